@@ -1,0 +1,312 @@
+"""FFT-based P_ell(k) and xi_ell(r) estimators, plain FP64 (oracle; test infrastructure only).
+
+Each function follows the paper's boxed estimator step by step on full complex
+grids, summing over every m and M:
+
+* ``pk_bisector``  Section 5.2 boxed estimator:
+  P_l(k) = (4pi/I) <Re sum_m Y_l^{m*}(k^) sum_{beta J1 J2 M} B F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)> - d_l0 S/I.
+* ``pk_midpoint``  Section 3.3 boxed parity-even estimator:
+  g^alpha_{JM} = (-1)^J IFT[d*(k) F[(2r)^-alpha Y_J^M d](k)]   (Section 3.2),
+  P_l(k) = (4pi/I) <Re sum_m Y_l^{m*}(k^) sum_{even alpha} sum Phi F[Y_J1^M(D^) D^alpha g^alpha_{J2,m-M}](k)> - d_l0 S/I.
+* ``pk_yamamoto``  Section 2.1 Yamamoto estimator,
+  P_l(k) = (4pi/I) <Re sum_m Y_l^{m*}(k^) F[Y_l^m d](k) d*(k)> - d_l0 S/I.
+* ``xi_midpoint``  Section 4.3 boxed parity-even estimator,
+  xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_{even alpha, J, M} F^{alpha,l}_J Y_J^{M*}(D^) D^alpha g^alpha_{JM}(D).
+* ``xi_bisector``  Section 6 boxed estimator,
+  h = IFT[F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)],
+  xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_m Y_l^{m*}(D^) sum B h.
+
+Normalisation (reading of Section 2.1): the substitution d -> w (n_g - alpha_r n_r) / I^{1/2}
+makes the 1/V of the definition inconsistent, so every estimator is divided by
+I = alpha_r sum_r w_r^2 nbar_r; alpha_r = sum w_g / sum w_r (the ratio that makes the
+weighted field vanish on average); the shot noise S/I, S = sum_g w_g^2 + alpha_r^2 sum_r w_r^2,
+is subtracted from the monopole only.  k-shell averages are means over the modes of
+the bin (the angular integral); r-bins divide by v_a = N_a H^3, the bin's volume on
+the grid, and exclude the zero separation.
+
+Series order K: midpoint keeps even alpha <= K; bisector keeps beta <= K // 2
+(the beta-th bisector term is O(theta^{2 beta})).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import coeffs
+from .mesh import (paint, node_positions, kgrid, separation_grid, window, neg_k,
+                   k_bin_index, r_bin_index)
+from .ylm import Ylm
+
+FOURPI = 4.0 * math.pi
+
+
+@dataclass
+class Config:
+    N: int
+    L: float
+    b0: tuple
+    assign: int = 3
+    ells: tuple = (0, 2, 4)
+    order: int = 4
+    compensate: bool = True
+    bin_lo: float = 0.01
+    bin_width: float = 0.01
+    n_bins: int = 20
+
+
+@dataclass
+class Result:
+    values: np.ndarray          # [n_ell, n_bins]
+    bin_mean: np.ndarray        # mean |k| or |r| per bin
+    counts: np.ndarray          # modes / separations per bin
+    alpha_r: float = 0.0
+    I: float = 0.0
+    S: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+
+def scalars(w_g, w_r, nbar_r):
+    """alpha_r, I, S (Section 2.1 with the readings listed in the module docstring)."""
+    w_g = np.asarray(w_g, dtype=np.float64)
+    w_r = np.asarray(w_r, dtype=np.float64)
+    nbar_r = np.asarray(nbar_r, dtype=np.float64)
+    alpha_r = w_g.sum() / w_r.sum()
+    I = alpha_r * np.sum(w_r * w_r * nbar_r)
+    S = np.sum(w_g * w_g) + alpha_r * alpha_r * np.sum(w_r * w_r)
+    return float(alpha_r), float(I), float(S)
+
+
+def density_masses(gal, ran, cfg: Config, alpha_r: float) -> np.ndarray:
+    """Node masses of w (n_g - alpha_r n_r)."""
+    mg = paint(gal["pos"], gal["w"], cfg.N, cfg.L, cfg.b0, cfg.assign)
+    mr = paint(ran["pos"], ran["w"], cfg.N, cfg.L, cfg.b0, cfg.assign)
+    return mg - alpha_r * mr
+
+
+def _prepare(gal, ran, cfg: Config, norm=None):
+    if norm is None:
+        alpha_r, I, S = scalars(gal["w"], ran["w"], ran["nbar"])
+    else:
+        alpha_r, I, S = norm
+    m = density_masses(gal, ran, cfg, alpha_r)
+    return m, alpha_r, I, S
+
+
+def _compensation(cfg: Config):
+    if cfg.compensate:
+        return 1.0 / window(cfg.N, cfg.assign)
+    return None
+
+
+def _fft(x, comp):
+    X = np.fft.fftn(x)
+    if comp is not None:
+        X *= comp
+    return X
+
+
+def _bin_k(E_list, cfg: Config):
+    """Shell means of Re E for each ell; k-bin from the integer |s|^2."""
+    b, kmag = k_bin_index(cfg.N, cfg.L, cfg.bin_lo, cfg.bin_width, cfg.n_bins)
+    bf = b.ravel()
+    sel = bf >= 0
+    counts = np.bincount(bf[sel], minlength=cfg.n_bins).astype(np.float64)
+    ksum = np.bincount(bf[sel], weights=kmag.ravel()[sel], minlength=cfg.n_bins)
+    vals = []
+    for E in E_list:
+        s = np.bincount(bf[sel], weights=np.real(E).ravel()[sel], minlength=cfg.n_bins)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            vals.append(np.where(counts > 0, s / np.where(counts > 0, counts, 1), 0.0))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kmean = np.where(counts > 0, ksum / np.where(counts > 0, counts, 1), 0.0)
+    return np.array(vals), kmean, counts
+
+
+def _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S, extra=None):
+    P = FOURPI / I * sums
+    for i, l in enumerate(cfg.ells):
+        if l == 0:
+            P[i] -= S / I
+    return Result(P, kmean, counts.astype(np.int64), alpha_r, I, S, extra or {})
+
+
+# ----------------------------------------------------------------------------
+# Power spectrum
+# ----------------------------------------------------------------------------
+
+def pk_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    if beta_max is None:
+        beta_max = cfg.order // 2
+    comp = _compensation(cfg)
+    xn = node_positions(cfg.N, cfg.L, cfg.b0)
+    _, kvec = kgrid(cfg.N, cfg.L)
+    Jmax = max(cfg.ells) + beta_max
+    Qt = {}
+    for J in range(Jmax + 1):
+        for M in range(-J, J + 1):
+            Qt[(J, M)] = _fft(m * Ylm(J, M, xn), comp)
+    Qneg = {key: neg_k(v) for key, v in Qt.items()}
+    E_list = []
+    for l in cfg.ells:
+        E = np.zeros_like(m, dtype=np.complex128)
+        for mm in range(-l, l + 1):
+            tab = coeffs.B_table(beta_max, l, mm)
+            inner = np.zeros_like(E)
+            for (J1, J2, M), c in tab.items():
+                inner += c * Qneg[(J1, M)] * Qt[(J2, mm - M)]
+            E += np.conj(Ylm(l, mm, kvec)) * inner
+        E_list.append(E)
+    sums, kmean, counts = _bin_k(E_list, cfg)
+    return _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S)
+
+
+def g_field(m, dtil, xn, alpha: int, J: int, M: int, comp):
+    """g^alpha_{JM}(D) = (-1)^J IFT[d*(k) F[(2r)^-alpha Y_J^M d](k)]  (Section 3.2), on the
+    separation grid (index n <-> D = H s(n)).  (2r)^-alpha is set to 0 at r = 0."""
+    r = np.sqrt(np.sum(xn * xn, axis=-1))
+    if alpha == 0:
+        rw = np.ones_like(r)
+    else:
+        with np.errstate(divide="ignore"):
+            rw = np.where(r > 0, (2.0 * r) ** (-float(alpha)), 0.0)
+    Q = m * rw * Ylm(J, M, xn)
+    Qt = _fft(Q, comp)
+    g = np.fft.ifftn(np.conj(dtil) * Qt)
+    return (-1) ** J * g
+
+
+def pk_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    comp = _compensation(cfg)
+    xn = node_positions(cfg.N, cfg.L, cfg.b0)
+    _, kvec = kgrid(cfg.N, cfg.L)
+    Dvec = separation_grid(cfg.N, cfg.L)
+    Dmag = np.sqrt(np.sum(Dvec * Dvec, axis=-1))
+    dtil = _fft(m, comp)
+    alphas = list(range(0, cfg.order + 1, 2))
+    # Phi tables per (l, m, alpha), and the g fields they need
+    tabs = {(l, mm, a): coeffs.Phi_table(a, l, mm)
+            for l in cfg.ells for mm in range(-l, l + 1) for a in alphas}
+    need = {}
+    for (l, mm, a), tab in tabs.items():
+        for (J1, J2, M), c in tab.items():
+            need.setdefault((a, J2, mm - M), []).append((l, mm, J1, M, c))
+    Ycache = {}
+
+    def YD(J, M):
+        if (J, M) not in Ycache:
+            Ycache[(J, M)] = Ylm(J, M, Dvec)
+        return Ycache[(J, M)]
+
+    A = {(l, mm): np.zeros(m.shape, dtype=np.complex128) for l in cfg.ells for mm in range(-l, l + 1)}
+    for (a, J2, M2), users in sorted(need.items()):
+        g = g_field(m, dtil, xn, a, J2, M2, comp)
+        Da = Dmag ** a if a > 0 else 1.0
+        for (l, mm, J1, M, c) in users:
+            A[(l, mm)] += c * YD(J1, M) * Da * g
+    E_list = []
+    for l in cfg.ells:
+        E = np.zeros(m.shape, dtype=np.complex128)
+        for mm in range(-l, l + 1):
+            E += np.conj(Ylm(l, mm, kvec)) * np.fft.fftn(A[(l, mm)])
+        E_list.append(E)
+    sums, kmean, counts = _bin_k(E_list, cfg)
+    return _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S)
+
+
+def pk_yamamoto(gal, ran, cfg: Config, norm=None) -> Result:
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    comp = _compensation(cfg)
+    xn = node_positions(cfg.N, cfg.L, cfg.b0)
+    _, kvec = kgrid(cfg.N, cfg.L)
+    dtil = _fft(m, comp)
+    E_list = []
+    for l in cfg.ells:
+        E = np.zeros(m.shape, dtype=np.complex128)
+        for mm in range(-l, l + 1):
+            E += np.conj(Ylm(l, mm, kvec)) * _fft(m * Ylm(l, mm, xn), comp) * np.conj(dtil)
+        E_list.append(E)
+    sums, kmean, counts = _bin_k(E_list, cfg)
+    return _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S)
+
+
+# ----------------------------------------------------------------------------
+# Correlation function
+# ----------------------------------------------------------------------------
+
+def _bin_r(X_list, cfg: Config):
+    b, rmag = r_bin_index(cfg.N, cfg.L, cfg.bin_lo, cfg.bin_width, cfg.n_bins)
+    bf = b.ravel()
+    sel = bf >= 0
+    counts = np.bincount(bf[sel], minlength=cfg.n_bins).astype(np.float64)
+    rsum = np.bincount(bf[sel], weights=rmag.ravel()[sel], minlength=cfg.n_bins)
+    vals = []
+    for X in X_list:
+        vals.append(np.bincount(bf[sel], weights=np.real(X).ravel()[sel], minlength=cfg.n_bins))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rmean = np.where(counts > 0, rsum / np.where(counts > 0, counts, 1), 0.0)
+    return np.array(vals), rmean, counts
+
+
+def _finish_xi(sums, rmean, counts, cfg, alpha_r, I, S):
+    H3 = (cfg.L / cfg.N) ** 3
+    with np.errstate(invalid="ignore", divide="ignore"):
+        vol = np.where(counts > 0, counts * H3, 1.0)
+    xi = FOURPI / I * sums / vol[None, :]
+    xi[:, counts == 0] = 0.0
+    return Result(xi, rmean, counts.astype(np.int64), alpha_r, I, S)
+
+
+def xi_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    comp = _compensation(cfg)
+    xn = node_positions(cfg.N, cfg.L, cfg.b0)
+    Dvec = separation_grid(cfg.N, cfg.L)
+    Dmag = np.sqrt(np.sum(Dvec * Dvec, axis=-1))
+    dtil = _fft(m, comp)
+    X = {l: np.zeros(m.shape, dtype=np.complex128) for l in cfg.ells}
+    for a in range(0, cfg.order + 1, 2):
+        Da = Dmag ** a if a > 0 else 1.0
+        for J in range(0, max(cfg.ells) + a + 1, 2):
+            Fs = {l: coeffs.F(a, l, J) for l in cfg.ells}
+            if all(v == 0.0 for v in Fs.values()):
+                continue
+            for M in range(-J, J + 1):
+                g = g_field(m, dtil, xn, a, J, M, comp)
+                t = np.conj(Ylm(J, M, Dvec)) * Da * g
+                for l, Fv in Fs.items():
+                    if Fv != 0.0:
+                        X[l] += Fv * t
+    sums, rmean, counts = _bin_r([X[l] for l in cfg.ells], cfg)
+    return _finish_xi(sums, rmean, counts, cfg, alpha_r, I, S)
+
+
+def xi_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    if beta_max is None:
+        beta_max = cfg.order // 2
+    comp = _compensation(cfg)
+    xn = node_positions(cfg.N, cfg.L, cfg.b0)
+    Dvec = separation_grid(cfg.N, cfg.L)
+    Jmax = max(cfg.ells) + beta_max
+    Qt = {}
+    for J in range(Jmax + 1):
+        for M in range(-J, J + 1):
+            Qt[(J, M)] = _fft(m * Ylm(J, M, xn), comp)
+    Qneg = {key: neg_k(v) for key, v in Qt.items()}
+    X_list = []
+    for l in cfg.ells:
+        X = np.zeros(m.shape, dtype=np.complex128)
+        for mm in range(-l, l + 1):
+            tab = coeffs.B_table(beta_max, l, mm)
+            Kprod = np.zeros(m.shape, dtype=np.complex128)
+            for (J1, J2, M), c in tab.items():
+                Kprod += c * Qneg[(J1, M)] * Qt[(J2, mm - M)]
+            Hlm = np.fft.ifftn(Kprod)
+            X += np.conj(Ylm(l, mm, Dvec)) * Hlm
+        X_list.append(X)
+    sums, rmean, counts = _bin_r(X_list, cfg)
+    return _finish_xi(sums, rmean, counts, cfg, alpha_r, I, S)

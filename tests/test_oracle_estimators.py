@@ -1,0 +1,207 @@
+"""Pins of the oracle's estimators: pair sums on node-placed tiny catalogs (exact equality),
+zeroth order = Yamamoto, monopole invariance, convergence to the exact line of sight,
+painting invariants."""
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle.estimators import (Config, scalars, pk_bisector, pk_midpoint, pk_yamamoto,
+                               xi_bisector, xi_midpoint)
+from oracle.mesh import paint, CIC, TSC
+from synthetic import tiny_node_catalog
+
+N, L, B0 = 16, 1000.0, (-500.0, -500.0, 1000.0)
+
+
+def _tiny(seed=5, **kw):
+    return tiny_node_catalog(seed, N, L, B0, **kw)
+
+
+def _cfg_pk(order, ells=(0, 2, 4)):
+    # 4 bins up to 0.045 < k_Nyq = 0.0503: no Nyquist-plane modes
+    return Config(N=N, L=L, b0=B0, assign=CIC, ells=ells, order=order, compensate=False,
+                  bin_lo=0.005, bin_width=0.01, n_bins=4)
+
+
+def _cfg_xi(order, ells=(0, 2, 4)):
+    return Config(N=N, L=L, b0=B0, assign=CIC, ells=ells, order=order, compensate=False,
+                  bin_lo=0.0, bin_width=100.0, n_bins=4)
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# ---------------------------------------------------------------- painting
+
+def test_paint_conserves_mass_and_node_particles_hit_one_node():
+    rng = np.random.default_rng(0)
+    pos = rng.uniform(-400, 400, size=(500, 3)) + np.array([0, 0, 1500.0])
+    w = rng.uniform(0.2, 2.0, 500)
+    for a in (CIC, TSC):
+        m = paint(pos, w, 32, 1000.0, (-500, -500, 1000), a)
+        assert m.sum() == pytest.approx(w.sum(), rel=1e-13)
+    gal, _ = _tiny()
+    m = paint(gal["pos"], gal["w"], N, L, B0, CIC)
+    idx = np.rint((gal["pos"] - np.array(B0)) / (L / N)).astype(int)
+    ref = np.zeros((N, N, N))
+    np.add.at(ref, (idx[:, 0], idx[:, 1], idx[:, 2]), gal["w"])
+    assert np.allclose(m, ref, atol=1e-14)
+    # TSC of a node particle: (1/8, 3/4, 1/8) per axis
+    one = {"pos": np.array([[B0[0] + 5 * L / N, B0[1] + 6 * L / N, B0[2] + 7 * L / N]])}
+    mt = paint(one["pos"], [1.0], N, L, B0, TSC)
+    k1 = np.array([0.125, 0.75, 0.125])
+    assert np.allclose(mt[4:7, 5:8, 6:9], k1[:, None, None] * k1[None, :, None] * k1[None, None, :])
+    assert mt.sum() == pytest.approx(1.0)
+
+
+def test_paint_periodic_wrap():
+    # a particle just below L - H/2 from b0 spreads onto node 0 (TSC) and node N-1
+    u = N - 0.3
+    pos = np.array([[B0[0] + u * L / N, B0[1] + 3 * L / N, B0[2] + 3 * L / N]])
+    m = paint(pos, [1.0], N, L, B0, TSC)
+    assert m[0].sum() > 0 and m[N - 1].sum() > 0 and m.sum() == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------- pair sums (exact)
+
+@pytest.mark.parametrize("order", [0, 2, 4])
+def test_bisector_pk_equals_series_pair_sum(order):
+    gal, ran = _tiny()
+    cfg = _cfg_pk(order)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = pk_bisector(gal, ran, cfg, norm)
+    bp, counts = brute.pk_pairs(gal, ran, cfg, "bis_series", norm)
+    assert np.array_equal(r.counts, counts.astype(int))
+    assert _rel(r.values, bp) < 1e-12
+
+
+@pytest.mark.parametrize("order", [0, 2, 4])
+def test_midpoint_pk_equals_series_pair_sum(order):
+    gal, ran = _tiny(seed=7)
+    cfg = _cfg_pk(order)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = pk_midpoint(gal, ran, cfg, norm)
+    bp, _ = brute.pk_pairs(gal, ran, cfg, "mid_series", norm)
+    assert _rel(r.values, bp) < 1e-12
+
+
+def test_yamamoto_pk_equals_pair_sum():
+    gal, ran = _tiny(seed=8)
+    cfg = _cfg_pk(0)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = pk_yamamoto(gal, ran, cfg, norm)
+    bp, _ = brute.pk_pairs(gal, ran, cfg, "yamamoto", norm)
+    assert _rel(r.values, bp) < 1e-12
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_bisector_xi_equals_series_pair_sum(order):
+    gal, ran = _tiny(seed=9)
+    cfg = _cfg_xi(order)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = xi_bisector(gal, ran, cfg, norm)
+    bp, counts = brute.xi_pairs(gal, ran, cfg, "bis_series", norm)
+    assert np.array_equal(r.counts, counts.astype(int))
+    assert _rel(r.values, bp) < 1e-12
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_midpoint_xi_equals_series_pair_sum(order):
+    gal, ran = _tiny(seed=10)
+    cfg = _cfg_xi(order)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = xi_midpoint(gal, ran, cfg, norm)
+    bp, _ = brute.xi_pairs(gal, ran, cfg, "mid_series", norm)
+    assert _rel(r.values, bp) < 1e-12
+
+
+# ---------------------------------------------------------------- structural identities
+
+def _generic(seed=3, n_gal=300, n_ran=900):
+    rng = np.random.default_rng(seed)
+    c = np.array([0.0, 0.0, 1200.0])
+    gal = {"pos": c + rng.uniform(-200, 200, (n_gal, 3)), "w": rng.uniform(0.5, 1.5, n_gal)}
+    ran = {"pos": c + rng.uniform(-200, 200, (n_ran, 3)), "w": rng.uniform(0.5, 1.5, n_ran)}
+    ran["nbar"] = np.full(n_ran, 2e-5)
+    gal["nbar"] = np.full(n_gal, 2e-5)
+    return gal, ran
+
+
+def test_midpoint_zeroth_order_is_yamamoto():
+    gal, ran = _generic()
+    cfg = Config(N=32, L=1000.0, b0=(-500, -500, 700), assign=TSC, ells=(0, 2, 4), order=0,
+                 compensate=True, bin_lo=0.005, bin_width=0.02, n_bins=7)
+    a = pk_midpoint(gal, ran, cfg)
+    b = pk_yamamoto(gal, ran, cfg)
+    assert np.max(np.abs(a.values - b.values)) < 1e-10 * np.max(np.abs(b.values))
+
+
+def test_monopole_identical_across_lines_of_sight_and_orders():
+    gal, ran = _generic(seed=4)
+    base = dict(N=32, L=1000.0, b0=(-500, -500, 700), assign=TSC, compensate=True,
+                bin_lo=0.005, bin_width=0.02, n_bins=7)
+    ref = pk_yamamoto(gal, ran, Config(ells=(0,), order=0, **base)).values[0]
+    for K in (0, 2, 4):
+        m = pk_midpoint(gal, ran, Config(ells=(0,), order=K, **base)).values[0]
+        b = pk_bisector(gal, ran, Config(ells=(0,), order=K, **base)).values[0]
+        assert np.max(np.abs(m - ref)) < 1e-10 * np.max(np.abs(ref))
+        assert np.max(np.abs(b - ref)) < 1e-10 * np.max(np.abs(ref))
+    xbase = dict(base, bin_lo=0.0, bin_width=60.0, n_bins=5)
+    x0 = xi_midpoint(gal, ran, Config(ells=(0,), order=0, **xbase)).values[0]
+    for K in (2, 4):
+        xm = xi_midpoint(gal, ran, Config(ells=(0,), order=K, **xbase)).values[0]
+        xb = xi_bisector(gal, ran, Config(ells=(0,), order=K, **xbase)).values[0]
+        assert np.max(np.abs(xm - x0)) < 1e-10 * np.max(np.abs(x0))
+        assert np.max(np.abs(xb - x0)) < 1e-10 * np.max(np.abs(x0))
+
+
+def test_bisector_zeroth_order_is_not_yamamoto():
+    gal, ran = _generic(seed=5)
+    cfg = Config(N=32, L=1000.0, b0=(-500, -500, 700), assign=TSC, ells=(2,), order=0,
+                 compensate=True, bin_lo=0.005, bin_width=0.02, n_bins=7)
+    a = pk_bisector(gal, ran, cfg).values
+    b = pk_yamamoto(gal, ran, cfg).values
+    assert np.max(np.abs(a - b)) > 1e-6 * np.max(np.abs(b))
+
+
+# ---------------------------------------------------------------- convergence to the exact LOS
+
+def test_series_converge_to_exact_line_of_sight():
+    """Tiny far catalog (theta_max ~ 0.1): the difference to the exact-LOS pair sum
+    shrinks by ~theta^2 per step of the series order."""
+    Nl, Ll = 16, 800.0
+    b0 = (-400.0, -400.0, 1800.0)
+    gal, ran = tiny_node_catalog(21, Nl, Ll, b0, n_gal=15, n_ran=45, lo=4, hi=11)
+    cfg0 = Config(N=Nl, L=Ll, b0=b0, assign=CIC, ells=(2,), order=0, compensate=False,
+                  bin_lo=0.005, bin_width=0.012, n_bins=4)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    for kind, fn, exact in (("mid", pk_midpoint, "mid_exact"), ("bis", pk_bisector, "bis_exact")):
+        ex, _ = brute.pk_pairs(gal, ran, cfg0, exact, norm)
+        errs = []
+        for K in (0, 2, 4):
+            cfg = Config(**{**cfg0.__dict__, "order": K})
+            errs.append(np.max(np.abs(fn(gal, ran, cfg, norm).values - ex)))
+        assert errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1], (kind, errs)
+
+
+def test_wide_angle_correction_shrinks_with_distance():
+    """Moving a catalog outward by a factor s shrinks the correction beyond zeroth order,
+    P_l(K=4) - P_l(K=0), roughly as s^-2 for both lines of sight (Section 6.2 shift test).
+    (The midpoint and bisector directions of one pair differ by an angle ~ theta^2, so their
+    difference is not used as a fourth-order pin.)"""
+    Nl, Ll = 16, 800.0
+    out = {"mid": [], "bis": []}
+    for shift in (1000.0, 2000.0):
+        b0 = (-400.0, -400.0, shift)
+        gal, ran = tiny_node_catalog(23, Nl, Ll, b0, n_gal=15, n_ran=45, lo=4, hi=11)
+        cfg = Config(N=Nl, L=Ll, b0=b0, assign=CIC, ells=(2,), order=4, compensate=False,
+                     bin_lo=0.005, bin_width=0.012, n_bins=4)
+        c0 = Config(**{**cfg.__dict__, "order": 0})
+        norm = scalars(gal["w"], ran["w"], ran["nbar"])
+        for kind, fn in (("mid", pk_midpoint), ("bis", pk_bisector)):
+            out[kind].append(np.max(np.abs(fn(gal, ran, cfg, norm).values - fn(gal, ran, c0, norm).values)))
+    s2 = ((2000.0 + 600.0) / (1000.0 + 600.0)) ** 2   # catalog centre distance ratio, squared
+    for kind, v in out.items():
+        ratio = v[0] / v[1]
+        assert 0.6 * s2 < ratio < 1.6 * s2, (kind, ratio, s2)
