@@ -1,0 +1,164 @@
+/*
+ * pw.h -- C ABI of libpw: pairwise line-of-sight power-spectrum and correlation-function
+ * multipole estimators on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Philcox & Slepian, "Beyond Yamamoto: Anisotropic Power Spectra and Correlation
+ * Functions with Pairwise Lines-of-Sight" (arXiv:2102.08384).
+ *   - midpoint P_l(k):  Section 3.3, boxed parity-even estimator (coefficients Phi, Appendix D)
+ *   - bisector P_l(k):  Section 5.2, boxed estimator (coefficients B, Appendix F)
+ *   - midpoint xi_l(r): Section 4.3, boxed parity-even estimator (coefficients F, Appendix E)
+ *   - bisector xi_l(r): Section 6, boxed estimator (coefficients B)
+ * The density field is w (n_g - alpha_r n_r) (Section 2.1); the estimators are normalised
+ * by I = alpha_r sum_r w_r^2 nbar_r with alpha_r = sum w_g / sum w_r, and the shot noise
+ * S / I, S = sum_g w_g^2 + alpha_r^2 sum_r w_r^2, is subtracted from the power-spectrum
+ * monopole only.
+ *
+ * Conventions
+ *   - Positions are comoving, observer at the coordinate origin.  Mesh nodes sit at
+ *     box_origin + n * H, H = box_len / n_mesh, n = 0 .. n_mesh-1 per axis, periodic.
+ *   - Every particle must satisfy 0 <= x_i - box_origin_i < box_len on every axis
+ *     (PW_ERANGE otherwise; particles are never wrapped).
+ *   - Series order K: the midpoint keeps even alpha <= K, the bisector keeps beta <= K/2
+ *     (the beta-th bisector term is O(theta^(2 beta))).
+ *   - Multipoles are the even ell = 0, 2, ..., ell_max; outputs are [n_ell][n_bins] row-major.
+ *   - k bins: bin b holds the modes with b = floor((|k| - bin_lo) / bin_width),
+ *     |k| = (2 pi / box_len) sqrt(n_x^2 + n_y^2 + n_z^2) on the signed FFT index
+ *     (n >= n_mesh/2 maps to n - n_mesh); decided in FP64 from the integer |n|^2.
+ *     r bins: the same with |r| = H sqrt(n^2) on the minimum-image separation; the zero
+ *     separation is in no bin.
+ *   - P_l values are shell means (the angular average); xi_l values are shell sums divided
+ *     by the bin volume N_a H^3 (N_a grid separations in the bin).
+ *
+ * Precision: PW_FP32 paints, weights and transforms in FP32 and accumulates every shell
+ * sum, normalisation and shot-noise term in FP64 on the GPU; PW_FP64 does everything in FP64.
+ *
+ * Errors: every call returns PW_OK (0) or a negative code; pw_last_error() gives a message.
+ * No exception crosses this ABI.  Outputs are written only on success.
+ * A pw_ctx is not thread-safe: use it from one thread at a time.
+ */
+#ifndef PW_H
+#define PW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PW_OK = 0,
+  PW_EINVAL = -1,    /* malformed configuration or arguments                     */
+  PW_ERANGE = -2,    /* a particle lies outside the box                           */
+  PW_ENOMEM = -3,    /* the request does not fit the context's HBM budget         */
+  PW_EDEVICE = -4,   /* a HIP runtime call failed                                 */
+  PW_EBUSY = -5,     /* the submission queue is full                              */
+  PW_EAGAIN = -6,    /* ticket still pending (pw_poll)                            */
+  PW_ECANCELED = -7  /* ticket was cancelled                                      */
+};
+
+enum pw_stat { PW_PK = 0, PW_XI = 1 };
+enum pw_los { PW_MIDPOINT = 0, PW_BISECTOR = 1 };
+enum pw_assign { PW_CIC = 2, PW_TSC = 3 };
+enum pw_prec { PW_FP32 = 0, PW_FP64 = 1 };
+
+typedef struct pw_ctx pw_ctx;
+
+/* Estimator configuration (the paper's problem statement: box, mesh, ell_max, series
+ * order, line of sight, bins). */
+typedef struct {
+  int stat;              /* PW_PK or PW_XI                                                */
+  int los;               /* PW_MIDPOINT or PW_BISECTOR                                    */
+  int assign;            /* PW_CIC or PW_TSC                                              */
+  int prec;              /* PW_FP32 or PW_FP64                                            */
+  int n_mesh;            /* N, a power of two in [16, 1024]                               */
+  double box_len;        /* L (same length unit as the positions, e.g. Mpc/h)             */
+  double box_origin[3];  /* b0, the corner of the box                                     */
+  int ell_max;           /* even, 0..8                                                    */
+  int order;             /* series order K, even, 0..8                                    */
+  int compensate;        /* 1: divide every k-space factor by the assignment window W(k)  */
+  double bin_lo;         /* lower edge of bin 0 (k in 1/length, r in length)              */
+  double bin_width;      /* > 0                                                           */
+  int n_bins;            /* 1..4096                                                       */
+} pw_config;
+
+/* A catalog: n particles as interleaved (x, y, z, w) records of dtype (PW_FP32 / PW_FP64).
+ * nbar (n values of the same dtype, or NULL) is the expected number density at each
+ * particle; it is read for the randoms only, to form I.  Pointers are host memory when
+ * on_device == 0 and device memory of the context's GPU when on_device == 1.  The caller
+ * owns the memory; the library never frees or retains it past the call (pw_estimate) or
+ * past the ticket's completion (pw_submit). */
+typedef struct {
+  const void *xyzw;
+  const void *nbar;
+  int64_t n;
+  int dtype;
+  int on_device;
+} pw_catalog;
+
+/* Normalisation scalars.  With use_given == 0 the library computes them (FP64 on the GPU)
+ * and writes them back; with use_given == 1 it uses the caller's values. */
+typedef struct {
+  double alpha_r;
+  double I;
+  double S;
+  int use_given;
+} pw_norm;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device memory the
+ * context may hold (0 = 90% of the device's free memory).  hip_stream (a hipStream_t, or
+ * NULL) is the stream pw_estimate runs on; NULL makes the context create its own. */
+int pw_create(pw_ctx **ctx, int device, size_t hbm_budget_bytes, void *hip_stream);
+
+/* Release every device allocation, stream and host resource of the context.  Pending
+ * submissions are cancelled first.  ctx may be NULL. */
+int pw_destroy(pw_ctx *ctx);
+
+/* Run one estimate synchronously.
+ *   out      [n_ell][n_bins] multipoles (host, FP64), n_ell = ell_max/2 + 1
+ *   bin_mean [n_bins] mean |k| (or |r|) of the modes in each bin (host, may be NULL)
+ *   counts   [n_bins] modes (or grid separations) per bin (host, may be NULL)
+ * Midpoint P_l with order > 0 requires the catalog extent on every axis to be at most
+ * box_len / 2 (the convolution grows to twice the survey width, Section 3.2): PW_EINVAL. */
+int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
+                const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
+                int64_t *counts);
+
+/* Continuous-batching submission: enqueue an estimate and return a ticket.  The inputs and
+ * output buffers must stay valid until the ticket completes or is cancelled.  Requests are
+ * admitted as their device-memory footprint fits the budget and run concurrently on the
+ * context's worker streams. */
+int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
+              const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
+              int64_t *counts, uint64_t *ticket);
+int pw_poll(pw_ctx *ctx, uint64_t ticket);   /* PW_OK done, PW_EAGAIN pending, <0 failed  */
+int pw_wait(pw_ctx *ctx, uint64_t ticket);   /* block until done; returns its status      */
+int pw_cancel(pw_ctx *ctx, uint64_t ticket); /* cancel a request not yet admitted         */
+
+/* Message of the last error on this context (thread-unsafe, valid until the next call). */
+const char *pw_last_error(const pw_ctx *ctx);
+
+/* Device-memory footprint (bytes) pw_estimate needs for cfg with the given catalog sizes;
+ * host-only, needs no device. */
+int pw_footprint(const pw_config *cfg, int64_t n_gal, int64_t n_ran, size_t *bytes);
+
+/* Coupling tables used by the kernels, in the real spherical-harmonic basis
+ *   y_l^0 = Y_l^0,  y_l^m = sqrt(2) (-1)^m Re Y_l^m,  y_l^-m = sqrt(2) (-1)^m Im Y_l^m  (m > 0),
+ * for inspection and tests; host-only, needs no device.  kind:
+ *   0  bisector: rows (l, nu, J1, mu1, J2, mu2, value) of the symmetrised real coupling
+ *      S with sum_{beta <= order/2} B folded in (Appendix F), such that
+ *      Re sum_m Y_l^{m*}(k^) sum B F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)
+ *        = sum_nu y_l^nu(k^) sum_{(J1,mu1) <= (J2,mu2)} S Re(conj(R_J1mu1(k)) R_J2mu2(k)),
+ *      R_Jmu = F[y_J^mu d].
+ *   1  midpoint: rows (l, nu, J1, mu1, J2, mu2, value) for alpha = `alpha` (Phi, Appendix D):
+ *      A_{l nu}(D) = sum Phi' y_J1^mu1(D^) |D|^alpha g_{alpha J2 mu2}(D).
+ *   2  midpoint Legendre: rows (l, 0, J, 0, 0, 0, F^{alpha,l}_J) (Appendix E).
+ * Writes at most max_rows rows of 7 doubles to rows (may be NULL) and the row count to
+ * n_rows. */
+int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,
+                      int64_t max_rows, int64_t *n_rows);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PW_H */

@@ -1,0 +1,427 @@
+// C ABI of libpw: context, planner and the synchronous estimate pipeline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pw.h"
+#include "coeffs.h"
+#include "dev_core.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace pw;
+
+namespace {
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Fail{code, buf};
+}
+
+#define HIPCHECK(x)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) fail(PW_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct pw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t used = 0;
+  std::string err;
+  std::map<PlanKey, std::unique_ptr<DevPlan>> plans;
+  // catalog staging (host pointers are copied here)
+  void *stage[2] = {nullptr, nullptr};
+  size_t stage_bytes[2] = {0, 0};
+  void *stage_nbar = nullptr;
+  size_t stage_nbar_bytes = 0;
+};
+
+namespace {
+
+void *dev_alloc(pw_ctx *ctx, size_t bytes) {
+  if (bytes == 0) return nullptr;
+  if (ctx->used + bytes > ctx->budget)
+    fail(PW_ENOMEM, "device memory budget exceeded: need %zu more bytes, %zu of %zu in use", bytes,
+         ctx->used, ctx->budget);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) fail(PW_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  ctx->used += bytes;
+  return p;
+}
+
+void dev_free(pw_ctx *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->used -= std::min(ctx->used, bytes);
+}
+
+template <typename T>
+T *upload(pw_ctx *ctx, DevPlan *dp, const std::vector<T> &v) {
+  if (v.empty()) return nullptr;
+  size_t bytes = v.size() * sizeof(T);
+  T *p = (T *)dev_alloc(ctx, bytes);
+  dp->allocs.push_back({p, bytes});
+  HIPCHECK(hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice));
+  return p;
+}
+
+void *alloc_plan(pw_ctx *ctx, DevPlan *dp, size_t bytes) {
+  void *p = dev_alloc(ctx, bytes);
+  dp->allocs.push_back({p, bytes});
+  return p;
+}
+
+void free_plan(pw_ctx *ctx, DevPlan *dp) {
+  for (auto &a : dp->allocs) dev_free(ctx, a.first, a.second);
+  dp->allocs.clear();
+}
+
+ShConst make_sh_const() {
+  ShConst c;
+  std::memset(&c, 0, sizeof(c));
+  const double pi = 3.14159265358979323846;
+  for (int l = 0; l <= kMaxJ; ++l)
+    for (int m = 0; m <= l; ++m) {
+      double a = (l - m) > 0 ? (2.0 * l - 1) / (double)(l - m) : 0.0;
+      double b = (l - m) > 0 ? (l + m - 1.0) / (double)(l - m) : 0.0;
+      // (l-m)!/(l+m)!
+      double ratio = 1.0;
+      for (int i = l - m + 1; i <= l + m; ++i) ratio /= (double)i;
+      double dfm = 1.0;
+      for (int i = 2 * m - 1; i > 1; i -= 2) dfm *= (double)i;
+      double nrm = std::sqrt((2.0 * l + 1) / (4.0 * pi) * ratio) * dfm * (m > 0 ? std::sqrt(2.0) : 1.0);
+      c.a[l][m] = (float)a; c.b[l][m] = (float)b; c.nrm[l][m] = (float)nrm;
+      c.a_d[l][m] = a; c.b_d[l][m] = b; c.nrm_d[l][m] = nrm;
+    }
+  return c;
+}
+
+std::mutex g_sh_mu;
+std::vector<int> g_sh_uploaded;  // devices with the constant table
+
+void ensure_sh(int device) {
+  std::lock_guard<std::mutex> lk(g_sh_mu);
+  if (std::find(g_sh_uploaded.begin(), g_sh_uploaded.end(), device) != g_sh_uploaded.end()) return;
+  ShConst c = make_sh_const();
+  upload_sh_const(c);
+  HIPCHECK(hipGetLastError());
+  g_sh_uploaded.push_back(device);
+}
+
+DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
+  PlanKey key = make_key(*cfg);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) return it->second.get();
+  std::unique_ptr<HostPlan> hp(new HostPlan(build_host_plan(*cfg)));
+  std::unique_ptr<DevPlan> dp(new DevPlan());
+  dp->host = std::move(hp);
+  HostPlan &h = *dp->host;
+  try {
+    size_t csz = h.prec == PW_FP32 ? 8 : 16;
+    // twiddles exp(-2 pi i e / N)
+    std::vector<double> tw(2 * h.N);
+    for (int e = 0; e < h.N; ++e) {
+      double ang = -2.0 * 3.14159265358979323846 * (double)e / (double)h.N;
+      tw[2 * e] = std::cos(ang);
+      tw[2 * e + 1] = std::sin(ang);
+    }
+    if (h.prec == PW_FP32) {
+      std::vector<float> twf(tw.begin(), tw.end());
+      dp->tw = upload(ctx, dp.get(), twf);
+    } else {
+      dp->tw = upload(ctx, dp.get(), tw);
+    }
+    dp->jobs = upload(ctx, dp.get(), h.jobs);
+    dp->ycnt = upload(ctx, dp.get(), h.ycnt);
+    dp->yoff = upload(ctx, dp.get(), h.yoff);
+    dp->pinfo = upload(ctx, dp.get(), h.pinfo);
+    dp->moff = upload(ctx, dp.get(), h.moff);
+    dp->modecoord = upload(ctx, dp.get(), h.modecoord);
+    dp->bin_of_s2 = upload(ctx, dp.get(), h.bin_of_s2);
+    dp->ells = upload(ctx, dp.get(), h.ells);
+    dp->t_start = upload(ctx, dp.get(), h.t_start);
+    dp->t_sh = upload(ctx, dp.get(), h.t_sh);
+    dp->t_ell = upload(ctx, dp.get(), h.t_ell);
+    dp->t_p1 = upload(ctx, dp.get(), h.t_p1);
+    dp->t_p2 = upload(ctx, dp.get(), h.t_p2);
+    if (h.prec == PW_FP32) {
+      std::vector<float> cf(h.t_coef.begin(), h.t_coef.end());
+      dp->t_coef = upload(ctx, dp.get(), cf);
+    } else {
+      dp->t_coef = upload(ctx, dp.get(), h.t_coef);
+    }
+    size_t rsz = h.prec == PW_FP32 ? 4 : 8;
+    dp->mesh = alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * h.N * rsz);
+    size_t x1 = (size_t)h.nfields * h.N * h.N * h.nkx * csz;
+    size_t x2 = (size_t)h.nfields * h.N * h.npen * csz;
+    size_t x3 = (size_t)h.nfields * h.nmodes * csz;
+    dp->bufA = alloc_plan(ctx, dp.get(), std::max(x1, x3));
+    dp->bufB = alloc_plan(ctx, dp.get(), std::max<size_t>(x2, 16));
+    dp->acc = (double *)alloc_plan(ctx, dp.get(), (size_t)(h.nell + 2) * h.n_bins * sizeof(double));
+    dp->out = (double *)alloc_plan(ctx, dp.get(), (size_t)(h.nell + 2) * h.n_bins * sizeof(double));
+    dp->part_g = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
+    dp->part_r = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
+    dp->norm = (DevNorm *)alloc_plan(ctx, dp.get(), sizeof(DevNorm));
+  } catch (...) {
+    free_plan(ctx, dp.get());
+    throw;
+  }
+  DevPlan *raw = dp.get();
+  ctx->plans[key] = std::move(dp);
+  return raw;
+}
+
+const void *stage_catalog(pw_ctx *ctx, const pw_catalog *c, int slot, const void **nbar_out) {
+  size_t rs = c->dtype == PW_FP32 ? 4 : 8;
+  *nbar_out = nullptr;
+  if (c->on_device) {
+    *nbar_out = c->nbar;
+    return c->xyzw;
+  }
+  size_t bytes = (size_t)c->n * 4 * rs;
+  if (ctx->stage_bytes[slot] < bytes) {
+    dev_free(ctx, ctx->stage[slot], ctx->stage_bytes[slot]);
+    ctx->stage[slot] = nullptr;
+    ctx->stage_bytes[slot] = 0;
+    ctx->stage[slot] = dev_alloc(ctx, bytes);
+    ctx->stage_bytes[slot] = bytes;
+  }
+  if (bytes) HIPCHECK(hipMemcpyAsync(ctx->stage[slot], c->xyzw, bytes, hipMemcpyHostToDevice, ctx->stream));
+  if (c->nbar && slot == 1) {
+    size_t nb = (size_t)c->n * rs;
+    if (ctx->stage_nbar_bytes < nb) {
+      dev_free(ctx, ctx->stage_nbar, ctx->stage_nbar_bytes);
+      ctx->stage_nbar = nullptr;
+      ctx->stage_nbar_bytes = 0;
+      ctx->stage_nbar = dev_alloc(ctx, nb);
+      ctx->stage_nbar_bytes = nb;
+    }
+    HIPCHECK(hipMemcpyAsync(ctx->stage_nbar, c->nbar, nb, hipMemcpyHostToDevice, ctx->stream));
+    *nbar_out = ctx->stage_nbar;
+  }
+  return ctx->stage[slot];
+}
+
+void check_catalog(const pw_catalog *c, const char *name) {
+  if (!c) fail(PW_EINVAL, "%s catalog is NULL", name);
+  if (c->n < 0) fail(PW_EINVAL, "%s catalog has n < 0", name);
+  if (c->n > 0 && !c->xyzw) fail(PW_EINVAL, "%s catalog has no xyzw array", name);
+  if (c->dtype != PW_FP32 && c->dtype != PW_FP64) fail(PW_EINVAL, "%s catalog dtype must be PW_FP32 or PW_FP64", name);
+}
+
+void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                  pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  validate_config(*cfg);
+  check_catalog(gal, "galaxy");
+  check_catalog(ran, "random");
+  if (!out) fail(PW_EINVAL, "out is NULL");
+  if (!(norm && norm->use_given) && !ran->nbar)
+    fail(PW_EINVAL, "random catalog needs nbar when the normalisation is not given");
+  HIPCHECK(hipSetDevice(ctx->device));
+  ensure_sh(ctx->device);
+  DevPlan *dp = get_plan(ctx, cfg);
+  HostPlan &h = *dp->host;
+  hipStream_t s = ctx->stream;
+  const void *gnb = nullptr, *rnb = nullptr;
+  const void *gx = stage_catalog(ctx, gal, 0, &gnb);
+  const void *rx = stage_catalog(ctx, ran, 1, &rnb);
+  // a1: FP64 scalars
+  launch_scalars(s, gx, nullptr, gal->n, gal->dtype, dp->part_g);
+  launch_scalars(s, rx, rnb, ran->n, ran->dtype, dp->part_r);
+  const bool use_given = norm && norm->use_given;
+  launch_finalize_norm(s, dp->part_g, dp->part_r, dp->norm, cfg->box_origin, cfg->box_len,
+                       h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
+                       use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
+  // a2: paint
+  const size_t ncell = (size_t)h.N * h.N * h.N;
+  launch_fill(s, dp->mesh, ncell, h.prec);
+  launch_paint(s, gx, gal->n, gal->dtype, h.prec, dp->mesh, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0);
+  launch_paint(s, rx, ran->n, ran->dtype, h.prec, dp->mesh, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1);
+  // a3 + a4: weighted fields and the forward transforms
+  launch_fx(s, h.prec, h.N, dp->mesh, dp->bufA, dp->jobs, (int)h.jobs.size(), h.nkx, cfg->box_origin, h.H, dp->tw);
+  if (h.npen > 0) {
+    launch_fy(s, h.prec, h.N, dp->bufA, dp->bufB, h.nfields, h.nkx, dp->ycnt, dp->yoff, h.npen, dp->tw);
+    launch_fz(s, h.prec, h.N, dp->bufB, dp->bufA, h.nfields, h.npen, dp->pinfo, dp->moff, h.nmodes, dp->tw);
+  }
+  // a7: contraction and FP64 binning
+  launch_fill(s, dp->acc, (size_t)(h.nell + 2) * h.n_bins, 1);
+  TermTable tab;
+  tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
+  tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
+  tab.ntargets = (int)h.t_sh.size();
+  launch_contract_bis(s, h.prec, h.ell_max, dp->bufA, h.nfields, h.nmodes, dp->modecoord, h.N,
+                      dp->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins, h.nell, tab, h.kf, dp->acc);
+  launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+  HIPCHECK(hipGetLastError());
+  std::vector<double> res((size_t)(h.nell + 2) * h.n_bins);
+  DevNorm dn;
+  HIPCHECK(hipMemcpyAsync(res.data(), dp->out, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(&dn, dp->norm, sizeof(DevNorm), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
+  if (dn.flags & 2)
+    fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
+  std::memcpy(out, res.data(), (size_t)h.nell * h.n_bins * sizeof(double));
+  if (bin_mean) std::memcpy(bin_mean, res.data() + (size_t)h.nell * h.n_bins, h.n_bins * sizeof(double));
+  if (counts)
+    for (int b = 0; b < h.n_bins; ++b) counts[b] = (int64_t)std::llround(res[(size_t)(h.nell + 1) * h.n_bins + b]);
+  if (norm && !norm->use_given) {
+    norm->alpha_r = dn.alpha_r;
+    norm->I = dn.I;
+    norm->S = dn.S;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_stream) {
+  if (!out) return PW_EINVAL;
+  *out = nullptr;
+  pw_ctx *ctx = new pw_ctx();
+  try {
+    int ndev = 0;
+    HIPCHECK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(PW_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    ctx->device = device;
+    HIPCHECK(hipSetDevice(device));
+    size_t free_b = 0, total_b = 0;
+    HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    if (hip_stream) {
+      ctx->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHECK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+      ctx->own_stream = true;
+    }
+    ensure_sh(device);
+  } catch (const Fail &f) {
+    delete ctx;
+    return f.code;
+  }
+  *out = ctx;
+  return PW_OK;
+}
+
+int pw_destroy(pw_ctx *ctx) {
+  if (!ctx) return PW_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto &kv : ctx->plans) free_plan(ctx, kv.second.get());
+  ctx->plans.clear();
+  for (int i = 0; i < 2; ++i) dev_free(ctx, ctx->stage[i], ctx->stage_bytes[i]);
+  dev_free(ctx, ctx->stage_nbar, ctx->stage_nbar_bytes);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return PW_OK;
+}
+
+int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  if (!ctx) return PW_EINVAL;
+  try {
+    if (!cfg) fail(PW_EINVAL, "cfg is NULL");
+    run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts);
+  } catch (const Fail &f) {
+    ctx->err = f.msg;
+    return f.code;
+  } catch (const std::exception &e) {
+    ctx->err = e.what();
+    return PW_EINVAL;
+  }
+  ctx->err.clear();
+  return PW_OK;
+}
+
+const char *pw_last_error(const pw_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int pw_footprint(const pw_config *cfg, int64_t n_gal, int64_t n_ran, size_t *bytes) {
+  if (!cfg || !bytes) return PW_EINVAL;
+  try {
+    validate_config(*cfg);
+    *bytes = footprint_bytes(*cfg, n_gal, n_ran);
+  } catch (const Fail &f) {
+    return f.code;
+  } catch (const std::exception &) {
+    return PW_EINVAL;
+  }
+  return PW_OK;
+}
+
+int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows, int64_t max_rows,
+                      int64_t *n_rows) {
+  if (!n_rows || ell_max < 0 || ell_max > 8 || (ell_max & 1) || order < 0 || order > 8) return PW_EINVAL;
+  std::vector<double> r;
+  try {
+    if (kind == 0) {
+      for (const Term &t : bisector_terms(ell_max, order / 2)) {
+        double v[7] = {(double)t.l, (double)t.nu, (double)t.J1, (double)t.mu1, (double)t.J2, (double)t.mu2, t.c};
+        r.insert(r.end(), v, v + 7);
+      }
+    } else if (kind == 1) {
+      if (alpha < 0 || (alpha & 1)) return PW_EINVAL;
+      for (const Term &t : midpoint_terms(ell_max, alpha)) {
+        double v[7] = {(double)t.l, (double)t.nu, (double)t.J1, (double)t.mu1, (double)t.J2, (double)t.mu2, t.c};
+        r.insert(r.end(), v, v + 7);
+      }
+    } else if (kind == 2) {
+      for (int l = 0; l <= ell_max; l += 2)
+        for (int J = 0; J <= l + alpha; J += 2) {
+          double F = legendre_F(alpha, l, J);
+          if (F == 0.0) continue;
+          double v[7] = {(double)l, 0.0, (double)J, 0.0, 0.0, 0.0, F};
+          r.insert(r.end(), v, v + 7);
+        }
+    } else {
+      return PW_EINVAL;
+    }
+  } catch (const std::exception &) {
+    return PW_EINVAL;
+  }
+  int64_t n = (int64_t)(r.size() / 7);
+  *n_rows = n;
+  if (rows) std::memcpy(rows, r.data(), (size_t)std::min(n, max_rows) * 7 * sizeof(double));
+  return PW_OK;
+}
+
+int pw_submit(pw_ctx *ctx, const pw_config *, const pw_catalog *, const pw_catalog *, pw_norm *,
+              double *, double *, int64_t *, uint64_t *) {
+  if (ctx) ctx->err = "pw_submit: not available in this build";
+  return PW_EINVAL;
+}
+int pw_poll(pw_ctx *, uint64_t) { return PW_EINVAL; }
+int pw_wait(pw_ctx *, uint64_t) { return PW_EINVAL; }
+int pw_cancel(pw_ctx *, uint64_t) { return PW_EINVAL; }
+
+}  // extern "C"
+
+namespace pw {
+[[noreturn]] void plan_fail(int code, const char *msg) { fail(code, "%s", msg); }
+}  // namespace pw

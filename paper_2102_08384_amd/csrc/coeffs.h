@@ -1,0 +1,38 @@
+// Host FP64 coupling-coefficient generator (complex basis from the paper's appendices,
+// then the real spherical-harmonic basis the kernels use).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace pw {
+
+// One term of a real-basis coupling: target (l, nu) <- coef * field p1 (x) field p2.
+// Real spherical-harmonic index p = J*J + J + mu, mu in [-J, J].
+struct Term {
+  int l, nu;
+  int J1, mu1, J2, mu2;
+  double c;
+};
+
+inline int sh_index(int J, int mu) { return J * J + J + mu; }
+
+// Bisector: S^{l nu}_{(J1mu1)(J2mu2)} with sum_{beta<=beta_max} B folded in and the pair
+// symmetrised ((J1,mu1) <= (J2,mu2) by index), for every even l <= ell_max.
+std::vector<Term> bisector_terms(int ell_max, int beta_max);
+
+// Midpoint parity-even real coupling Phi'^{alpha, l nu}_{(J1mu1)(J2mu2)} for one even alpha
+// (l even <= ell_max).  The (J2, mu2) index refers to the real field
+// (2r)^-alpha y_J2^mu2(x^) d of series order alpha.
+std::vector<Term> midpoint_terms(int ell_max, int alpha);
+
+// Parity-even Legendre coefficients F^{alpha,l}_J (Appendix E).
+double legendre_F(int alpha, int l, int J);
+
+// Building blocks (exposed for the table self-checks).
+double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3);
+double gaunt(int l1, int l2, int l3, int m1, int m2, int m3);
+double shift_phi(int alpha, int l, int m, int J1, int J2, int M);
+double bisector_B(int beta, int l, int m, int J1, int J2, int M);
+double legendre_f(int alpha, int l, int J);
+
+}  // namespace pw

@@ -1,0 +1,75 @@
+// Launch wrappers of the HIP kernels (host-callable).  All launches are asynchronous on the
+// given stream; shapes are validated by the caller (the planner) before any launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace pw {
+
+struct ShConst;
+
+// Per-catalog FP64 partial sums written by the scalars kernel (one row per block):
+// [0] sum w, [1] sum w^2, [2] sum w^2 nbar, [3..5] min x,y,z, [6..8] max x,y,z, [9] count
+constexpr int kScalarCols = 10;
+constexpr int kScalarBlocks = 512;
+
+// Device-resident normalisation, filled by the finalize kernel.
+struct DevNorm {
+  double alpha_r, I, S;
+  double sum_wg, sum_wr;
+  int flags;        // bit 0: particle outside the box, bit 1: extent > L/2 (midpoint P)
+  int pad;
+};
+
+// A pair job of the fused weighting + x-FFT pass: two real fields generated together as the
+// real and imaginary parts of one complex transform.
+// kind 0: fields (J, +m) and (J, -m), m > 0, of weight (2r)^-alpha;  pa / pb their indices.
+// kind 1: fields (Ja, 0) and (Jb, 0) (Jb < 0: single field, pb < 0).
+struct FieldJob {
+  int alpha, kind, Ja, m, Jb, pa, pb, pad;
+};
+
+struct PencilInfo {   // a retained (kx, ky) pencil of the z pass
+  int kx, ky, kzcnt, pad;
+};
+
+void upload_sh_const(const ShConst &c);
+
+void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n, int dtype,
+                    double *partial);
+void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
+                          const double *b0, double L, int check_extent, int use_given,
+                          double ga, double gI, double gS);
+void launch_fill(hipStream_t s, void *p, size_t n_elems, int prec);
+void launch_paint(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, void *mesh,
+                  int N, const double *b0, double H, int assign, const DevNorm *norm,
+                  int is_random);
+
+// Fused weighting + r2c along x: out[p][z][y][kx], kx < nkx.
+void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
+               int njobs, int nkx, const double *b0, double H, const void *tw);
+// c2c along y, pruned: out[p][z][yoff[ky] + kx] for kx < ycnt[ky].
+void launch_fy(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int nkx,
+               const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw);
+// c2c along z, pruned: out[p][moff[q] + j], j < pinfo[q].kzcnt.
+void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
+               int64_t npen, const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes,
+               const void *tw);
+
+// Bisector contraction + FP64 k-binning.
+struct TermTable {
+  const int *tstart;     // [ntargets + 1] term ranges per target
+  const int *tsh;        // [ntargets] real-SH index l*l+l+nu of each target
+  const int *tell;       // [ntargets] slot of l in the output
+  const int *p1, *p2;    // field indices
+  const void *coef;      // float or double
+  int ntargets;
+};
+void launch_contract_bis(hipStream_t s, int prec, int lmax, const void *spec, int nfields,
+                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
+                         int64_t n_s2, int nbins, int nell, TermTable tab, double kf, double *acc);
+void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, const int *ells,
+                        const DevNorm *norm, double *out);
+
+}  // namespace pw

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libpw (argument marshalling only; every step runs in libpw's kernels).
+
+The library must be built in-tree (``python -m paper_2102_08384_amd.build``); importing this
+module raises if ``libpw.so`` is missing.  Catalog arrays may be numpy arrays (host memory)
+or torch tensors on the context's GPU (device memory), shaped [n, 4] = (x, y, z, w).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpw.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pw.h")
+
+PW_OK, PW_EINVAL, PW_ERANGE, PW_ENOMEM, PW_EDEVICE, PW_EBUSY, PW_EAGAIN, PW_ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+PW_PK, PW_XI = 0, 1
+PW_MIDPOINT, PW_BISECTOR = 0, 1
+PW_CIC, PW_TSC = 2, 3
+PW_FP32, PW_FP64 = 0, 1
+
+_ERRNAMES = {PW_EINVAL: "PW_EINVAL", PW_ERANGE: "PW_ERANGE", PW_ENOMEM: "PW_ENOMEM",
+             PW_EDEVICE: "PW_EDEVICE", PW_EBUSY: "PW_EBUSY", PW_EAGAIN: "PW_EAGAIN",
+             PW_ECANCELED: "PW_ECANCELED"}
+
+
+class PwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Config(C.Structure):
+    _fields_ = [("stat", C.c_int), ("los", C.c_int), ("assign", C.c_int), ("prec", C.c_int),
+                ("n_mesh", C.c_int), ("box_len", C.c_double), ("box_origin", C.c_double * 3),
+                ("ell_max", C.c_int), ("order", C.c_int), ("compensate", C.c_int),
+                ("bin_lo", C.c_double), ("bin_width", C.c_double), ("n_bins", C.c_int)]
+
+
+class _Catalog(C.Structure):
+    _fields_ = [("xyzw", C.c_void_p), ("nbar", C.c_void_p), ("n", C.c_int64),
+                ("dtype", C.c_int), ("on_device", C.c_int)]
+
+
+class _Norm(C.Structure):
+    _fields_ = [("alpha_r", C.c_double), ("I", C.c_double), ("S", C.c_double), ("use_given", C.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpw.so not built at {LIB_PATH}; run python -m paper_2102_08384_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.pw_create.argtypes = [C.POINTER(P), C.c_int, C.c_size_t, P]
+    lib.pw_destroy.argtypes = [P]
+    lib.pw_estimate.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
+                                C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_int64)]
+    lib.pw_submit.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
+                              C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
+    lib.pw_poll.argtypes = [P, C.c_uint64]
+    lib.pw_wait.argtypes = [P, C.c_uint64]
+    lib.pw_cancel.argtypes = [P, C.c_uint64]
+    lib.pw_last_error.argtypes = [P]
+    lib.pw_last_error.restype = C.c_char_p
+    lib.pw_footprint.argtypes = [C.POINTER(_Config), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
+    lib.pw_coupling_table.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                      C.c_int64, C.POINTER(C.c_int64)]
+    return lib
+
+
+_lib = _load()
+
+
+def declared_symbols():
+    """Names of every function declared in include/pw.h."""
+    with open(HEADER) as fh:
+        txt = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(pw_[a-z_]+)\s*\(", txt, re.M)))
+
+
+@dataclass
+class Config:
+    stat: int = PW_PK
+    los: int = PW_BISECTOR
+    assign: int = PW_TSC
+    prec: int = PW_FP32
+    n_mesh: int = 64
+    box_len: float = 1000.0
+    box_origin: tuple = (-500.0, -500.0, 500.0)
+    ell_max: int = 4
+    order: int = 4
+    compensate: int = 1
+    bin_lo: float = 0.01
+    bin_width: float = 0.01
+    n_bins: int = 20
+
+    def _c(self):
+        c = _Config()
+        c.stat, c.los, c.assign, c.prec = self.stat, self.los, self.assign, self.prec
+        c.n_mesh = self.n_mesh
+        c.box_len = float(self.box_len)
+        for i in range(3):
+            c.box_origin[i] = float(self.box_origin[i])
+        c.ell_max, c.order, c.compensate = self.ell_max, self.order, int(self.compensate)
+        c.bin_lo, c.bin_width, c.n_bins = float(self.bin_lo), float(self.bin_width), self.n_bins
+        return c
+
+    @property
+    def n_ell(self):
+        return self.ell_max // 2 + 1
+
+
+def _catalog(xyzw, nbar, keep):
+    """Describe a catalog; keep references alive in `keep`."""
+    cat = _Catalog()
+    try:
+        import torch  # noqa: F401
+        is_torch = hasattr(xyzw, "data_ptr") and hasattr(xyzw, "is_cuda")
+    except ImportError:
+        is_torch = False
+    if is_torch:
+        t = xyzw.contiguous()
+        if t.dim() != 2 or t.shape[1] != 4:
+            raise ValueError("xyzw must be [n, 4]")
+        keep.append(t)
+        cat.xyzw = t.data_ptr() if t.numel() else None
+        cat.n = t.shape[0]
+        cat.dtype = PW_FP64 if str(t.dtype) == "torch.float64" else PW_FP32
+        if str(t.dtype) not in ("torch.float32", "torch.float64"):
+            raise ValueError("xyzw must be float32 or float64")
+        cat.on_device = 1 if t.is_cuda else 0
+        if nbar is not None:
+            nb = nbar.to(dtype=t.dtype, device=t.device).contiguous()
+            keep.append(nb)
+            cat.nbar = nb.data_ptr()
+        return cat
+    a = np.ascontiguousarray(xyzw)
+    if a.ndim != 2 or a.shape[1] != 4:
+        raise ValueError("xyzw must be [n, 4]")
+    if a.dtype not in (np.float32, np.float64):
+        raise ValueError("xyzw must be float32 or float64")
+    keep.append(a)
+    cat.xyzw = a.ctypes.data if a.size else None
+    cat.n = a.shape[0]
+    cat.dtype = PW_FP64 if a.dtype == np.float64 else PW_FP32
+    cat.on_device = 0
+    if nbar is not None:
+        nb = np.ascontiguousarray(nbar, dtype=a.dtype)
+        keep.append(nb)
+        cat.nbar = nb.ctypes.data
+    return cat
+
+
+class Context:
+    """A libpw context on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, stream=None):
+        self._h = C.c_void_p()
+        rc = _lib.pw_create(C.byref(self._h), device, hbm_budget,
+                            C.c_void_p(stream) if stream else None)
+        if rc != PW_OK:
+            raise PwError(rc, "pw_create failed")
+
+    def close(self):
+        if self._h:
+            _lib.pw_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self):
+        return _lib.pw_last_error(self._h).decode()
+
+    def estimate(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
+        """Run one estimate.  norm = (alpha_r, I, S) to impose the normalisation."""
+        keep = []
+        g = _catalog(gal_xyzw, None, keep)
+        r = _catalog(ran_xyzw, ran_nbar, keep)
+        nm = _Norm()
+        if norm is not None:
+            nm.alpha_r, nm.I, nm.S = (float(v) for v in norm)
+            nm.use_given = 1
+        out = np.zeros((cfg.n_ell, cfg.n_bins))
+        bm = np.zeros(cfg.n_bins)
+        cnt = np.zeros(cfg.n_bins, dtype=np.int64)
+        c = cfg._c()
+        rc = _lib.pw_estimate(self._h, C.byref(c), C.byref(g), C.byref(r), C.byref(nm),
+                              out.ctypes.data_as(C.POINTER(C.c_double)),
+                              bm.ctypes.data_as(C.POINTER(C.c_double)),
+                              cnt.ctypes.data_as(C.POINTER(C.c_int64)))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        return {"values": out, "bin_mean": bm, "counts": cnt, "norm": (nm.alpha_r, nm.I, nm.S)}
+
+
+def footprint(cfg: Config, n_gal: int, n_ran: int) -> int:
+    b = C.c_size_t()
+    c = cfg._c()
+    rc = _lib.pw_footprint(C.byref(c), n_gal, n_ran, C.byref(b))
+    if rc != PW_OK:
+        raise PwError(rc, "pw_footprint failed")
+    return b.value
+
+
+def coupling_table(kind: int, ell_max: int, order: int, alpha: int = 0) -> np.ndarray:
+    n = C.c_int64()
+    rc = _lib.pw_coupling_table(kind, ell_max, order, alpha, None, 0, C.byref(n))
+    if rc != PW_OK:
+        raise PwError(rc, "pw_coupling_table failed")
+    rows = np.zeros((n.value, 7))
+    rc = _lib.pw_coupling_table(kind, ell_max, order, alpha, rows.ctypes.data_as(C.POINTER(C.c_double)),
+                                n.value, C.byref(n))
+    if rc != PW_OK:
+        raise PwError(rc, "pw_coupling_table failed")
+    return rows

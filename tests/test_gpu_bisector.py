@@ -1,0 +1,98 @@
+"""GPU parity of the bisector P_l path (libpw through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle.estimators import pk_bisector
+from synthetic import make_workload_catalog
+
+from gpu_common import say, rounded, oracle_cfg, max_err_per_ell, uniform_catalog
+
+pytestmark = pytest.mark.gpu
+
+pw = pytest.importorskip("paper_2102_08384_amd.pw")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pw.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, cfg, gal, ran, dtype):
+    gx, g64 = rounded(gal, dtype)
+    rx, r64 = rounded(ran, dtype)
+    res = ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"].astype(dtype))
+    ref = pk_bisector(g64, r64, oracle_cfg(cfg))
+    return res, ref
+
+
+def test_bisector_fp64_small_mesh(ctx):
+    say("bisector P fp64 N=32 TSC uniform cube, ell<=4 order 4")
+    gal, ran = uniform_catalog(1, 3000, 9000, (0, 0, 1100), 400)
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=pw.PW_FP64,
+                    n_mesh=32, box_len=800.0, box_origin=(-400.0, -400.0, 700.0), ell_max=4,
+                    order=4, compensate=1, bin_lo=0.004, bin_width=0.02, n_bins=12)
+    res, ref = _run(ctx, cfg, gal, ran, np.float64)
+    assert np.array_equal(res["counts"], ref.counts)
+    assert np.allclose(res["bin_mean"], ref.bin_mean, rtol=1e-12)
+    err = max_err_per_ell(res["values"], ref.values)
+    say("fp64 err per ell", err)
+    assert np.all(err < 1e-9)
+    a, I, S = res["norm"]
+    assert a == pytest.approx(ref.alpha_r, rel=1e-12)
+    assert I == pytest.approx(ref.I, rel=1e-12)
+    assert S == pytest.approx(ref.S, rel=1e-12)
+
+
+@pytest.mark.parametrize("assign", [pw.PW_CIC, pw.PW_TSC] if hasattr(pw, "PW_CIC") else [])
+def test_bisector_fp32_ragged_bins(ctx, assign):
+    say("bisector P fp32 N=64 assign", assign, "bins past Nyquist (ragged pruning)")
+    gal, ran = uniform_catalog(2, 20000, 60000, (0, 0, 1200), 600)
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=assign, prec=pw.PW_FP32,
+                    n_mesh=64, box_len=1000.0, box_origin=(-500.0, -500.0, 700.0), ell_max=4,
+                    order=4, compensate=1, bin_lo=0.003, bin_width=0.0117, n_bins=27)
+    res, ref = _run(ctx, cfg, gal, ran, np.float32)
+    assert np.array_equal(res["counts"], ref.counts)
+    err = max_err_per_ell(res["values"], ref.values)
+    say("fp32 err per ell", err)
+    assert np.all(err < 1e-4)
+
+
+@pytest.mark.parametrize("ell_max,order", [(0, 0), (2, 0), (2, 2), (4, 2)])
+def test_bisector_orders(ctx, ell_max, order):
+    say("bisector P fp32 N=32 ell_max", ell_max, "order", order)
+    gal, ran = uniform_catalog(3, 5000, 15000, (100, -50, 900), 300)
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=pw.PW_FP32,
+                    n_mesh=32, box_len=700.0, box_origin=(-250.0, -400.0, 550.0), ell_max=ell_max,
+                    order=order, compensate=0, bin_lo=0.0, bin_width=0.025, n_bins=10)
+    res, ref = _run(ctx, cfg, gal, ran, np.float32)
+    err = max_err_per_ell(res["values"], ref.values)
+    say("err", err)
+    assert np.all(err < 1e-4)
+
+
+def test_bisector_lognormal_cone_n128(ctx):
+    say("bisector P fp32 N=128 lognormal cone (C3 geometry, 2e5 galaxies)")
+    gal, ran = make_workload_catalog("C3", index=7, n_gal=200_000)
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=pw.PW_FP32,
+                    n_mesh=128, box_len=2700.0, box_origin=(-1350.0, -1350.0, -200.0),
+                    ell_max=4, order=4, compensate=1, bin_lo=0.005, bin_width=0.005, n_bins=29)
+    res, ref = _run(ctx, cfg, gal, ran, np.float32)
+    assert np.array_equal(res["counts"], ref.counts)
+    err = max_err_per_ell(res["values"], ref.values)
+    say("err", err)
+    assert np.all(err < 1e-4)
+
+
+def test_out_of_box_particle_is_rejected(ctx):
+    say("bisector P out-of-box particle -> PW_ERANGE")
+    gal, ran = uniform_catalog(4, 100, 300, (0, 0, 1000), 200)
+    gal["pos"][5] = (0.0, 0.0, 5000.0)
+    cfg = pw.Config(n_mesh=16, box_len=400.0, box_origin=(-200.0, -200.0, 800.0), n_bins=4,
+                    bin_lo=0.01, bin_width=0.02)
+    gx, _ = rounded(gal, np.float32)
+    rx, _ = rounded(ran, np.float32)
+    with pytest.raises(pw.PwError) as e:
+        ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"].astype(np.float32))
+    assert e.value.code == pw.PW_ERANGE
