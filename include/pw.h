@@ -135,6 +135,17 @@ int pw_poll(pw_ctx *ctx, uint64_t ticket);   /* PW_OK done, PW_EAGAIN pending, <
 int pw_wait(pw_ctx *ctx, uint64_t ticket);   /* block until done; returns its status      */
 int pw_cancel(pw_ctx *ctx, uint64_t ticket); /* cancel a request not yet admitted         */
 
+/* Copy an internal buffer of the context's most recent pw_estimate to host memory (for
+ * per-stage checks).  what:
+ *   0  painted node masses, [N][N][N] (z, y, x order; FP32 or FP64 by prec)
+ *   1  retained half-spectrum values of the weighted fields, [nfields][nmodes] complex
+ *      (real-harmonic field index J*J + J + mu), bisector P_l only
+ *   2  coordinates of those modes, [nmodes] uint32 = kx | ky << 11 | kz << 22
+ *      (FFT indices; kx <= N/2)
+ * *needed receives the byte count; data are copied only when dst is not NULL and
+ * dst_bytes >= *needed.  Synchronises the context's stream. */
+int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed);
+
 /* Message of the last error on this context (thread-unsafe, valid until the next call). */
 const char *pw_last_error(const pw_ctx *ctx);
 

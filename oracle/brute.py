@@ -122,7 +122,7 @@ def pk_pairs(gal, ran, cfg, kind: str, norm):
         out = FOURPI / I * np.where(counts > 0, out / np.where(counts > 0, counts, 1), 0.0)
     for li, l in enumerate(cfg.ells):
         if l == 0:
-            out[li] -= S / I
+            out[li] -= np.where(counts > 0, S / I, 0.0)
     return out, counts
 
 

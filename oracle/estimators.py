@@ -125,10 +125,11 @@ def _bin_k(E_list, cfg: Config):
 
 
 def _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S, extra=None):
+    """An empty bin has no estimate and is reported as 0 for every ell (no shot-noise term)."""
     P = FOURPI / I * sums
     for i, l in enumerate(cfg.ells):
         if l == 0:
-            P[i] -= S / I
+            P[i] -= np.where(counts > 0, S / I, 0.0)
     return Result(P, kmean, counts.astype(np.int64), alpha_r, I, S, extra or {})
 
 

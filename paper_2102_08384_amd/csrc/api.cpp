@@ -59,6 +59,7 @@ struct pw_ctx {
   size_t stage_bytes[2] = {0, 0};
   void *stage_nbar = nullptr;
   size_t stage_nbar_bytes = 0;
+  DevPlan *last = nullptr;  // plan of the most recent estimate (pw_inspect)
 };
 
 namespace {
@@ -165,6 +166,14 @@ DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
     dp->modecoord = upload(ctx, dp.get(), h.modecoord);
     dp->bin_of_s2 = upload(ctx, dp.get(), h.bin_of_s2);
     dp->ells = upload(ctx, dp.get(), h.ells);
+    if (!h.winv.empty()) {
+      if (h.prec == PW_FP32) {
+        std::vector<float> wf(h.winv.begin(), h.winv.end());
+        dp->winv = upload(ctx, dp.get(), wf);
+      } else {
+        dp->winv = upload(ctx, dp.get(), h.winv);
+      }
+    }
     dp->t_start = upload(ctx, dp.get(), h.t_start);
     dp->t_sh = upload(ctx, dp.get(), h.t_sh);
     dp->t_ell = upload(ctx, dp.get(), h.t_ell);
@@ -248,6 +257,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   DevPlan *dp = get_plan(ctx, cfg);
   HostPlan &h = *dp->host;
   hipStream_t s = ctx->stream;
+  ctx->last = dp;
   const void *gnb = nullptr, *rnb = nullptr;
   const void *gx = stage_catalog(ctx, gal, 0, &gnb);
   const void *rx = stage_catalog(ctx, ran, 1, &rnb);
@@ -276,7 +286,8 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
   tab.ntargets = (int)h.t_sh.size();
   launch_contract_bis(s, h.prec, h.ell_max, dp->bufA, h.nfields, h.nmodes, dp->modecoord, h.N,
-                      dp->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins, h.nell, tab, h.kf, dp->acc);
+                      dp->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins, h.nell, tab, h.kf,
+                      dp->winv, dp->acc);
   launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
   HIPCHECK(hipGetLastError());
   std::vector<double> res((size_t)(h.nell + 2) * h.n_bins);
@@ -408,6 +419,33 @@ int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,
   int64_t n = (int64_t)(r.size() / 7);
   *n_rows = n;
   if (rows) std::memcpy(rows, r.data(), (size_t)std::min(n, max_rows) * 7 * sizeof(double));
+  return PW_OK;
+}
+
+int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed) {
+  if (!ctx || !needed) return PW_EINVAL;
+  try {
+    DevPlan *dp = ctx->last;
+    if (!dp) fail(PW_EINVAL, "pw_inspect: no estimate has run on this context");
+    const HostPlan &h = *dp->host;
+    size_t rsz = h.prec == PW_FP32 ? 4 : 8;
+    const void *src = nullptr;
+    size_t bytes = 0;
+    if (what == 0) { src = dp->mesh; bytes = (size_t)h.N * h.N * h.N * rsz; }
+    else if (what == 1) { src = dp->bufA; bytes = (size_t)h.nfields * h.nmodes * 2 * rsz; }
+    else if (what == 2) { src = dp->modecoord; bytes = (size_t)h.nmodes * 4; }
+    else fail(PW_EINVAL, "pw_inspect: unknown buffer %d", what);
+    *needed = bytes;
+    if (dst) {
+      if (dst_bytes < bytes) fail(PW_EINVAL, "pw_inspect: destination too small");
+      HIPCHECK(hipSetDevice(ctx->device));
+      HIPCHECK(hipStreamSynchronize(ctx->stream));
+      HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    }
+  } catch (const Fail &f) {
+    ctx->err = f.msg;
+    return f.code;
+  }
   return PW_OK;
 }
 

@@ -68,7 +68,8 @@ struct TermTable {
 };
 void launch_contract_bis(hipStream_t s, int prec, int lmax, const void *spec, int nfields,
                          int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
-                         int64_t n_s2, int nbins, int nell, TermTable tab, double kf, double *acc);
+                         int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
+                         const void *winv, double *acc);
 void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, const int *ells,
                         const DevNorm *norm, double *out);
 

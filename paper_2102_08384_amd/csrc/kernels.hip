@@ -419,7 +419,8 @@ template <typename R, int LMAX, int NTH>
 __global__ void __launch_bounds__(NTH)
 k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
                const uint32_t *__restrict__ modecoord, int N, const int *__restrict__ bin_of_s2,
-               int64_t n_s2, int nbins, int nell, TermTable tab, double kf, double *__restrict__ acc) {
+               int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
+               const R *__restrict__ winv, double *__restrict__ acc) {
   extern __shared__ unsigned char smem_raw[];
   cplx<R> *vals = reinterpret_cast<cplx<R> *>(smem_raw);          // [nfields][NTH]
   double *bacc = reinterpret_cast<double *>(vals + (size_t)nfields * NTH);  // [(nell + 2) * nbins]
@@ -485,6 +486,13 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
 #pragma unroll
       for (int i = 0; i <= LMAX / 2; ++i) if (i == li) E[i] += wd * a;
     }
+    if (winv) {
+      // assignment-window compensation: every spectrum value is divided by W(k)
+      const R iw = winv[kx] * winv[ky] * winv[kz];
+      const R iw2 = iw * iw;
+#pragma unroll
+      for (int i = 0; i <= LMAX / 2; ++i) E[i] *= iw2;
+    }
     const double mult = pair ? 2.0 : 1.0;
     for (int i = 0; i < nell; ++i) atomicAdd(&bacc[i * nbins + b], (double)E[i]);
     atomicAdd(&bacc[nell * nbins + b], mult);
@@ -497,7 +505,8 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
 
 void launch_contract_bis(hipStream_t s, int prec, int lmax, const void *spec, int nfields,
                          int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
-                         int64_t n_s2, int nbins, int nell, TermTable tab, double kf, double *acc) {
+                         int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
+                         const void *winv, double *acc) {
   int64_t want = (nmodes + 127) / 128;
   unsigned blocks = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
 #define PW_CONTRACT(R, L, NTH)                                                                     \
@@ -505,7 +514,7 @@ void launch_contract_bis(hipStream_t s, int prec, int lmax, const void *spec, in
     size_t sh = (size_t)nfields * NTH * sizeof(cplx<R>) + (size_t)(nell + 2) * nbins * sizeof(double); \
     hipLaunchKernelGGL((k_contract_bis<R, L, NTH>), dim3(blocks), dim3(NTH), sh, s,                \
                        (const cplx<R> *)spec, nfields, nmodes, modecoord, N, bin_of_s2, n_s2,      \
-                       nbins, nell, tab, kf, acc);                                                 \
+                       nbins, nell, tab, kf, (const R *)winv, acc);                                \
   }
   if (prec == 0) {
     switch (lmax) {

@@ -82,6 +82,16 @@ HostPlan build_host_plan(const pw_config &c) {
   }
   const int64_t K2 = std::max<int64_t>(h.K2, 0);
 
+  // assignment window W(k) = prod_i sinc(pi s_i / N)^p, p = 2 (CIC) or 3 (TSC)
+  if (c.compensate) {
+    h.winv.resize(N);
+    for (int i = 0; i < N; ++i) {
+      double x = 3.14159265358979323846 * (double)signed_idx(i, N) / (double)N;
+      double sn = (x == 0.0) ? 1.0 : std::sin(x) / x;
+      h.winv[i] = 1.0 / std::pow(sn, (double)c.assign);
+    }
+  }
+
   // fields: every real harmonic (J, mu) with J <= ell_max + order/2 (bisector)
   const int Jmax = c.ell_max + c.order / 2;
   h.nfields = (Jmax + 1) * (Jmax + 1);

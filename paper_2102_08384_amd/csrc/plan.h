@@ -42,6 +42,8 @@ struct HostPlan {
   std::vector<uint32_t> modecoord;
   // FP64 bin decision per integer |n|^2
   std::vector<int> bin_of_s2;
+  // 1 / sinc(pi s / N)^p per axis index (empty when compensation is off)
+  std::vector<double> winv;
   // coupling terms grouped by target
   std::vector<int> t_start, t_sh, t_ell, t_p1, t_p2;
   std::vector<double> t_coef;
@@ -62,6 +64,7 @@ struct DevPlan {
   uint32_t *modecoord = nullptr;
   int *bin_of_s2 = nullptr;
   int *ells = nullptr;
+  void *winv = nullptr;
   int *t_start = nullptr, *t_sh = nullptr, *t_ell = nullptr, *t_p1 = nullptr, *t_p2 = nullptr;
   void *t_coef = nullptr;
   void *mesh = nullptr, *bufA = nullptr, *bufB = nullptr;

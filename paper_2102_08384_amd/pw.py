@@ -66,6 +66,7 @@ def _load():
     lib.pw_poll.argtypes = [P, C.c_uint64]
     lib.pw_wait.argtypes = [P, C.c_uint64]
     lib.pw_cancel.argtypes = [P, C.c_uint64]
+    lib.pw_inspect.argtypes = [P, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.pw_last_error.argtypes = [P]
     lib.pw_last_error.restype = C.c_char_p
     lib.pw_footprint.argtypes = [C.POINTER(_Config), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
@@ -186,6 +187,20 @@ class Context:
 
     def last_error(self):
         return _lib.pw_last_error(self._h).decode()
+
+    def inspect(self, what: int, dtype=np.float32):
+        """Copy an internal buffer of the last estimate (see pw_inspect in pw.h)."""
+        need = C.c_size_t()
+        rc = _lib.pw_inspect(self._h, what, None, 0, C.byref(need))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        out = np.empty(need.value, dtype=np.uint8)
+        rc = _lib.pw_inspect(self._h, what, out.ctypes.data, need.value, C.byref(need))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        if what == 2:
+            return out.view(np.uint32)
+        return out.view(dtype)
 
     def estimate(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """Run one estimate.  norm = (alpha_r, I, S) to impose the normalisation."""

@@ -116,7 +116,7 @@ def gaussian_field(n_gen, L, rng, slope=-1.5, sigma=0.8):
     with np.errstate(divide="ignore"):
         amp = np.where(k2 > 0, k2 ** (slope / 4.0), 0.0)
     white = rng.standard_normal((n_gen, n_gen, n_gen))
-    G = np.fft.irfftn(np.fft.rfftn(white) * amp, s=(n_gen,) * 3)
+    G = np.fft.irfftn(np.fft.rfftn(white) * amp, s=(n_gen,) * 3, axes=(0, 1, 2))
     G *= sigma / G.std()
     return G
 

@@ -27,6 +27,52 @@ def _run(ctx, cfg, gal, ran, dtype):
     return res, ref
 
 
+def _real_sh(J, mu, v):
+    """y_J^mu from the oracle's complex harmonics: y^0 = Y^0, y^m = sqrt2 (-1)^m Re Y^m,
+    y^-m = sqrt2 (-1)^m Im Y^m."""
+    from oracle.ylm import Ylm
+    if mu == 0:
+        return Ylm(J, 0, v).real
+    Y = Ylm(J, abs(mu), v)
+    f = np.sqrt(2.0) * (-1) ** abs(mu)
+    return f * (Y.real if mu > 0 else Y.imag)
+
+
+def test_bisector_stages_fp64(ctx):
+    """Painted mesh and retained spectra against the oracle's paint and numpy FFTs."""
+    from oracle.estimators import density_masses, scalars
+    from oracle.mesh import node_positions
+    say("bisector stages fp64 N=32: paint + spectra")
+    gal, ran = uniform_catalog(11, 2000, 6000, (0, 0, 1100), 400)
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=pw.PW_FP64,
+                    n_mesh=32, box_len=800.0, box_origin=(-400.0, -400.0, 700.0), ell_max=2,
+                    order=2, compensate=0, bin_lo=0.004, bin_width=0.02, n_bins=6)
+    gx, g64 = rounded(gal, np.float64)
+    rx, r64 = rounded(ran, np.float64)
+    ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"])
+    oc = oracle_cfg(cfg)
+    a, I, S = scalars(g64["w"], r64["w"], r64["nbar"])
+    m = density_masses(g64, r64, oc, a)                     # [ix, iy, iz]
+    mesh = ctx.inspect(0, np.float64).reshape(32, 32, 32)    # [z, y, x]
+    err = np.max(np.abs(mesh - np.transpose(m, (2, 1, 0)))) / np.max(np.abs(m))
+    say("paint rel err", err)
+    assert err < 1e-12
+    spec = ctx.inspect(1, np.float64).view(np.complex128)
+    mc = ctx.inspect(2)
+    nf = 16
+    spec = spec.reshape(nf, -1)
+    kx, ky, kz = mc & 0x7FF, (mc >> 11) & 0x7FF, (mc >> 22) & 0x3FF
+    xn = node_positions(32, 800.0, cfg.box_origin)
+    for J in range(3):
+        for mu in range(-J, J + 1):
+            f = m * _real_sh(J, mu, xn)                   # [ix, iy, iz]
+            ref = np.fft.fftn(f)                          # [kx, ky, kz]
+            p = J * J + J + mu
+            e = np.max(np.abs(spec[p] - ref[kx, ky, kz])) / np.max(np.abs(ref))
+            say("spectrum", J, mu, "rel err", e)
+            assert e < 1e-12
+
+
 def test_bisector_fp64_small_mesh(ctx):
     say("bisector P fp64 N=32 TSC uniform cube, ell<=4 order 4")
     gal, ran = uniform_catalog(1, 3000, 9000, (0, 0, 1100), 400)
