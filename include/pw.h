@@ -146,6 +146,14 @@ int pw_cancel(pw_ctx *ctx, uint64_t ticket); /* cancel a request not yet admitte
  * dst_bytes >= *needed.  Synchronises the context's stream. */
 int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed);
 
+/* Stage timing.  With timing on, pw_estimate records a HIP event before each stage and after
+ * the last one on the context's stream; pw_stage_info then reports, for stage index
+ * 0 .. n-1 of the most recent estimate, its name, GPU time in milliseconds (-1 when timing
+ * was off) and its algorithmic HBM bytes (the bytes the stage must read and write: inputs
+ * once, outputs once).  pw_stage_info returns PW_EINVAL past the last stage. */
+int pw_set_timing(pw_ctx *ctx, int on);
+int pw_stage_info(pw_ctx *ctx, int stage, const char **name, double *ms, double *bytes);
+
 /* Message of the last error on this context (thread-unsafe, valid until the next call). */
 const char *pw_last_error(const pw_ctx *ctx);
 

@@ -46,6 +46,8 @@ struct Fail {
 
 }  // namespace
 
+constexpr int kMaxStages = 16;
+
 struct pw_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -60,6 +62,13 @@ struct pw_ctx {
   void *stage_nbar = nullptr;
   size_t stage_nbar_bytes = 0;
   DevPlan *last = nullptr;  // plan of the most recent estimate (pw_inspect)
+  // stage timing
+  bool timing = false;
+  hipEvent_t ev[kMaxStages + 1] = {};
+  int n_stages = 0;
+  const char *st_name[kMaxStages] = {};
+  double st_ms[kMaxStages] = {};
+  double st_bytes[kMaxStages] = {};
 };
 
 namespace {
@@ -261,25 +270,43 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   const void *gnb = nullptr, *rnb = nullptr;
   const void *gx = stage_catalog(ctx, gal, 0, &gnb);
   const void *rx = stage_catalog(ctx, ran, 1, &rnb);
+  const bool timing = ctx->timing;
+  int ns = 0;
+  auto mark = [&](const char *name, double bytes) {
+    if (timing) HIPCHECK(hipEventRecord(ctx->ev[ns], s));
+    if (name) { ctx->st_name[ns] = name; ctx->st_bytes[ns] = bytes; }
+    ++ns;
+  };
+  const double rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2.0 * rsz;
+  const double isz_g = gal->dtype == PW_FP32 ? 4.0 : 8.0, isz_r = ran->dtype == PW_FP32 ? 4.0 : 8.0;
+  const double ncell = (double)h.N * h.N * h.N;
+  const double x1 = (double)h.nfields * h.N * h.N * h.nkx * csz;
+  const double x2 = (double)h.nfields * h.N * h.npen * csz;
+  const double x3 = (double)h.nfields * h.nmodes * csz;
   // a1: FP64 scalars
+  mark("scalars", 4.0 * isz_g * gal->n + 5.0 * isz_r * ran->n);
   launch_scalars(s, gx, nullptr, gal->n, gal->dtype, dp->part_g);
   launch_scalars(s, rx, rnb, ran->n, ran->dtype, dp->part_r);
   const bool use_given = norm && norm->use_given;
   launch_finalize_norm(s, dp->part_g, dp->part_r, dp->norm, cfg->box_origin, cfg->box_len,
                        h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
                        use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
-  // a2: paint
-  const size_t ncell = (size_t)h.N * h.N * h.N;
-  launch_fill(s, dp->mesh, ncell, h.prec);
+  // a2: paint (particles read once, mesh written once)
+  mark("paint", 4.0 * isz_g * gal->n + 4.0 * isz_r * ran->n + ncell * rsz);
+  launch_fill(s, dp->mesh, (size_t)ncell, h.prec);
   launch_paint(s, gx, gal->n, gal->dtype, h.prec, dp->mesh, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0);
   launch_paint(s, rx, ran->n, ran->dtype, h.prec, dp->mesh, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1);
   // a3 + a4: weighted fields and the forward transforms
+  mark("fx", ncell * rsz + x1);
   launch_fx(s, h.prec, h.N, dp->mesh, dp->bufA, dp->jobs, (int)h.jobs.size(), h.nkx, cfg->box_origin, h.H, dp->tw);
-  if (h.npen > 0) {
+  mark("fy", x1 + x2);
+  if (h.npen > 0)
     launch_fy(s, h.prec, h.N, dp->bufA, dp->bufB, h.nfields, h.nkx, dp->ycnt, dp->yoff, h.npen, dp->tw);
+  mark("fz", x2 + x3);
+  if (h.npen > 0)
     launch_fz(s, h.prec, h.N, dp->bufB, dp->bufA, h.nfields, h.npen, dp->pinfo, dp->moff, h.nmodes, dp->tw);
-  }
   // a7: contraction and FP64 binning
+  mark("contract", x3 + 4.0 * h.nmodes);
   launch_fill(s, dp->acc, (size_t)(h.nell + 2) * h.n_bins, 1);
   TermTable tab;
   tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
@@ -288,13 +315,21 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   launch_contract_bis(s, h.prec, h.ell_max, dp->bufA, h.nfields, h.nmodes, dp->modecoord, h.N,
                       dp->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins, h.nell, tab, h.kf,
                       dp->winv, dp->acc);
+  mark("finalize", 0.0);
   launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+  mark(nullptr, 0.0);
+  ctx->n_stages = ns - 1;
   HIPCHECK(hipGetLastError());
   std::vector<double> res((size_t)(h.nell + 2) * h.n_bins);
   DevNorm dn;
   HIPCHECK(hipMemcpyAsync(res.data(), dp->out, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(&dn, dp->norm, sizeof(DevNorm), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < ctx->n_stages; ++i) {
+    float ms = -1.0f;
+    if (timing) HIPCHECK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+    ctx->st_ms[i] = timing ? (double)ms : -1.0;
+  }
   if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
   if (dn.flags & 2)
     fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
@@ -333,6 +368,7 @@ int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_strea
       ctx->own_stream = true;
     }
     ensure_sh(device);
+    for (int i = 0; i <= kMaxStages; ++i) HIPCHECK(hipEventCreate(&ctx->ev[i]));
   } catch (const Fail &f) {
     delete ctx;
     return f.code;
@@ -349,6 +385,8 @@ int pw_destroy(pw_ctx *ctx) {
   ctx->plans.clear();
   for (int i = 0; i < 2; ++i) dev_free(ctx, ctx->stage[i], ctx->stage_bytes[i]);
   dev_free(ctx, ctx->stage_nbar, ctx->stage_nbar_bytes);
+  for (int i = 0; i <= kMaxStages; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return PW_OK;
@@ -419,6 +457,20 @@ int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,
   int64_t n = (int64_t)(r.size() / 7);
   *n_rows = n;
   if (rows) std::memcpy(rows, r.data(), (size_t)std::min(n, max_rows) * 7 * sizeof(double));
+  return PW_OK;
+}
+
+int pw_set_timing(pw_ctx *ctx, int on) {
+  if (!ctx) return PW_EINVAL;
+  ctx->timing = on != 0;
+  return PW_OK;
+}
+
+int pw_stage_info(pw_ctx *ctx, int stage, const char **name, double *ms, double *bytes) {
+  if (!ctx || stage < 0 || stage >= ctx->n_stages) return PW_EINVAL;
+  if (name) *name = ctx->st_name[stage];
+  if (ms) *ms = ctx->st_ms[stage];
+  if (bytes) *bytes = ctx->st_bytes[stage];
   return PW_OK;
 }
 

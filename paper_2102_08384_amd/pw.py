@@ -67,6 +67,9 @@ def _load():
     lib.pw_wait.argtypes = [P, C.c_uint64]
     lib.pw_cancel.argtypes = [P, C.c_uint64]
     lib.pw_inspect.argtypes = [P, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.pw_set_timing.argtypes = [P, C.c_int]
+    lib.pw_stage_info.argtypes = [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
     lib.pw_last_error.argtypes = [P]
     lib.pw_last_error.restype = C.c_char_p
     lib.pw_footprint.argtypes = [C.POINTER(_Config), C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
@@ -187,6 +190,21 @@ class Context:
 
     def last_error(self):
         return _lib.pw_last_error(self._h).decode()
+
+    def set_timing(self, on: bool):
+        _lib.pw_set_timing(self._h, 1 if on else 0)
+
+    def stages(self):
+        """[(name, ms, algorithmic_bytes)] of the most recent estimate."""
+        out = []
+        i = 0
+        while True:
+            nm, ms, by = C.c_char_p(), C.c_double(), C.c_double()
+            if _lib.pw_stage_info(self._h, i, C.byref(nm), C.byref(ms), C.byref(by)) != PW_OK:
+                break
+            out.append((nm.value.decode(), ms.value, by.value))
+            i += 1
+        return out
 
     def inspect(self, what: int, dtype=np.float32):
         """Copy an internal buffer of the last estimate (see pw_inspect in pw.h)."""
