@@ -17,13 +17,13 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpw.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["coeffs.cpp", "plan.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["coeffs.cpp", "plan.cpp", "api.cpp", "kernels.hip", "paint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
-          "-I", os.path.join(ROOT, "include"),
+          "-I", os.path.join(ROOT, "include"), "-I", BUILD_DIR,
           # no packed-FP32 instructions in device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-ffp-contract=off", "-Wno-unused-command-line-argument"]
@@ -40,10 +40,24 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _generate():
+    """Build and run the host-only generator of the register-resident contraction."""
+    exe = os.path.join(BUILD_DIR, "gen_contract")
+    cmd = ["g++", "-O2", "-std=c++17", os.path.join(CSRC, "coeffs.cpp"),
+           os.path.join(CSRC, "gen_contract.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"generator build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    r = subprocess.run([exe, os.path.join(BUILD_DIR, "contract_gen.inc")], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"generator failed\n{r.stdout}\n{r.stderr}")
+
+
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     if not os.path.exists(HIPCC) and shutil.which("hipcc") is None:
         raise RuntimeError("hipcc not found")
     os.makedirs(BUILD_DIR, exist_ok=True)
+    _generate()
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -61,6 +61,9 @@ struct pw_ctx {
   size_t stage_bytes[2] = {0, 0};
   void *stage_nbar = nullptr;
   size_t stage_nbar_bytes = 0;
+  size_t lds_per_block = 65536;
+  void *records = nullptr;  // tile-sorted particle records of the current estimate
+  size_t records_bytes = 0;
   DevPlan *last = nullptr;  // plan of the most recent estimate (pw_inspect)
   // stage timing
   bool timing = false;
@@ -206,6 +209,18 @@ DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
     dp->part_g = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
     dp->part_r = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
     dp->norm = (DevNorm *)alloc_plan(ctx, dp.get(), sizeof(DevNorm));
+    {
+      const int ts = tile_size(h.N), nt = h.N / ts;
+      dp->ntiles = nt * nt * nt;
+      dp->tile_counts = (int *)alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * sizeof(int));
+      dp->tile_offsets = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
+      dp->tile_cursor = (int *)alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * sizeof(int));
+      dp->tile_slot = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
+      dp->tile_blocks = alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * (ts + 2) * (ts + 2) * (ts + 2) * 8);
+      if ((size_t)dp->ntiles * sizeof(int) > ctx->lds_per_block)
+        fail(PW_EINVAL, "n_mesh too large for the tile sort on this device (%zu bytes of LDS per block)",
+             ctx->lds_per_block);
+    }
   } catch (...) {
     free_plan(ctx, dp.get());
     throw;
@@ -293,9 +308,26 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
                        use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
   // a2: paint (particles read once, mesh written once)
   mark("paint", 4.0 * isz_g * gal->n + 4.0 * isz_r * ran->n + ncell * rsz);
-  launch_fill(s, dp->mesh, (size_t)ncell, h.prec);
-  launch_paint(s, gx, gal->n, gal->dtype, h.prec, dp->mesh, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0);
-  launch_paint(s, rx, ran->n, ran->dtype, h.prec, dp->mesh, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1);
+  {
+    const size_t need = (size_t)(gal->n + ran->n) * 4 * (size_t)rsz;
+    if (ctx->records_bytes < need) {
+      dev_free(ctx, ctx->records, ctx->records_bytes);
+      ctx->records = nullptr;
+      ctx->records_bytes = 0;
+      ctx->records = dev_alloc(ctx, need);
+      ctx->records_bytes = need;
+    }
+  }
+  launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
+  launch_tile_count(s, gx, gal->n, gal->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
+  launch_tile_count(s, rx, ran->n, ran->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
+  launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
+  launch_tile_scatter(s, gx, gal->n, gal->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0,
+                      dp->tile_cursor, ctx->records);
+  launch_tile_scatter(s, rx, ran->n, ran->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1,
+                      dp->tile_cursor, ctx->records);
+  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ctx->records,
+                    dp->norm, dp->tile_blocks, dp->mesh);
   // a3 + a4: weighted fields and the forward transforms
   mark("fx", ncell * rsz + x1);
   launch_fx(s, h.prec, h.N, dp->mesh, dp->bufA, dp->jobs, (int)h.jobs.size(), h.nkx, cfg->box_origin, h.H, dp->tw);
@@ -312,7 +344,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
   tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
   tab.ntargets = (int)h.t_sh.size();
-  launch_contract_bis(s, h.prec, h.ell_max, dp->bufA, h.nfields, h.nmodes, dp->modecoord, h.N,
+  launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, dp->bufA, h.nfields, h.nmodes, dp->modecoord, h.N,
                       dp->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins, h.nell, tab, h.kf,
                       dp->winv, dp->acc);
   mark("finalize", 0.0);
@@ -368,6 +400,11 @@ int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_strea
       ctx->own_stream = true;
     }
     ensure_sh(device);
+    {
+      int lds = 0;
+      HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+      ctx->lds_per_block = (size_t)lds;
+    }
     for (int i = 0; i <= kMaxStages; ++i) HIPCHECK(hipEventCreate(&ctx->ev[i]));
   } catch (const Fail &f) {
     delete ctx;

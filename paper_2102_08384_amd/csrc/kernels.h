@@ -10,24 +10,28 @@ namespace pw {
 struct ShConst;
 
 // Per-catalog FP64 partial sums written by the scalars kernel (one row per block):
-// [0] sum w, [1] sum w^2, [2] sum w^2 nbar, [3..5] min x,y,z, [6..8] max x,y,z, [9] count
-constexpr int kScalarCols = 10;
+// [0] sum w, [1] sum w^2, [2] sum w^2 nbar, [3..5] min x,y,z, [6..8] max x,y,z, [9] count,
+// [10] sum |w|
+constexpr int kScalarCols = 11;
 constexpr int kScalarBlocks = 512;
 
 // Device-resident normalisation, filled by the finalize kernel.
 struct DevNorm {
   double alpha_r, I, S;
   double sum_wg, sum_wr;
-  int flags;        // bit 0: particle outside the box, bit 1: extent > L/2 (midpoint P)
+  double fix_scale;  // 2^e: painting accumulates round(contribution * fix_scale) in int64
+  int flags;         // bit 0: particle outside the box, bit 1: extent > L/2 (midpoint P)
   int pad;
 };
 
 // A pair job of the fused weighting + x-FFT pass: two real fields generated together as the
 // real and imaginary parts of one complex transform.
 // kind 0: fields (J, +m) and (J, -m), m > 0, of weight (2r)^-alpha;  pa / pb their indices.
-// kind 1: fields (Ja, 0) and (Jb, 0) (Jb < 0: single field, pb < 0).
+// kind 1: fields (Ja, 0) of weight (2r)^-alpha and (Jb, 0) of weight (2r)^-alpha_b
+//         (Jb < 0: single field, pb < 0).
+// Jobs must be sorted by m, then by J (the x pass carries its recurrences across jobs).
 struct FieldJob {
-  int alpha, kind, Ja, m, Jb, pa, pb, pad;
+  int alpha, kind, Ja, m, Jb, pa, pb, alpha_b;
 };
 
 struct PencilInfo {   // a retained (kx, ky) pencil of the z pass
@@ -42,9 +46,24 @@ void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, Dev
                           const double *b0, double L, int check_extent, int use_given,
                           double ga, double gI, double gS);
 void launch_fill(hipStream_t s, void *p, size_t n_elems, int prec);
-void launch_paint(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, void *mesh,
-                  int N, const double *b0, double H, int assign, const DevNorm *norm,
-                  int is_random);
+
+// Tile-binned painting: particles are counting-sorted by the tile of their anchor node
+// (nearest for TSC, lower for CIC); each occupied tile (+ one-node halo) is accumulated in
+// LDS and stored as a block; a gather pass sums the blocks covering every node.  Tiles are
+// TS^3 nodes, TS = min(16, N).  Records are (l + d) per axis (l the node index inside the
+// tile, d the offset in cells) and the signed weight, in the mesh precision.  The sort
+// kernels keep one LDS counter per tile (ntiles * 4 bytes per workgroup).
+constexpr int kTile = 16;
+inline int tile_size(int N) { return N < kTile ? N : kTile; }
+void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,
+                       const double *b0, double H, int assign, int *counts);
+void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot);
+void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, int N,
+                         const double *b0, double H, int assign, const DevNorm *norm,
+                         int is_random, int *cursor, void *records);
+// blocks: scratch of ntiles * (TS+2)^3 int64 values; slot: [ntiles + 1] from the scan.
+void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
+                       const void *records, const DevNorm *norm, void *blocks, void *mesh);
 
 // Fused weighting + r2c along x: out[p][z][y][kx], kx < nkx.
 void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
@@ -66,7 +85,7 @@ struct TermTable {
   const void *coef;      // float or double
   int ntargets;
 };
-void launch_contract_bis(hipStream_t s, int prec, int lmax, const void *spec, int nfields,
+void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
                          int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                          const void *winv, double *acc);

@@ -1,9 +1,6 @@
 // HIP kernels of the estimator hot path (gfx950, wave64).
 //
-//   scalars      FP64 reductions over a catalog (sum w, sum w^2, sum w^2 nbar, bounding box)
-//   norm         alpha_r = sum w_g / sum w_r, I = alpha_r sum_r w_r^2 nbar_r,
-//                S = sum_g w_g^2 + alpha_r^2 sum_r w_r^2 (Section 2.1), range / extent flags
-//   paint        CIC / TSC mass assignment with FP32 (or FP64) atomics
+//   (catalog reductions and painting live in paint.hip)
 //   fx           fused field generation F (2r)^-alpha y_J^mu(x^) + real-to-complex FFT along x,
 //                two real fields per complex transform, output pruned to kx < nkx
 //   fy, fz       complex FFTs along y and z, output pruned to the retained k-sphere
@@ -20,193 +17,6 @@ __constant__ ShConst c_sh;
 
 void upload_sh_const(const ShConst &c) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sh), &c, sizeof(ShConst));
-}
-
-// ------------------------------------------------------------------------------ scalars
-template <typename R>
-__global__ void __launch_bounds__(256) k_scalars(const R *__restrict__ xyzw, const R *__restrict__ nbar,
-                                                 int64_t n, double *__restrict__ partial) {
-  double sw = 0, sw2 = 0, swn = 0;
-  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-  double cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double x = xyzw[4 * i], y = xyzw[4 * i + 1], z = xyzw[4 * i + 2], w = xyzw[4 * i + 3];
-    sw += w;
-    sw2 += w * w;
-    if (nbar) swn += w * w * (double)nbar[i];
-    mn[0] = fmin(mn[0], x); mn[1] = fmin(mn[1], y); mn[2] = fmin(mn[2], z);
-    mx[0] = fmax(mx[0], x); mx[1] = fmax(mx[1], y); mx[2] = fmax(mx[2], z);
-    cnt += 1;
-  }
-  __shared__ double red[256];
-  double vals[kScalarCols] = {sw, sw2, swn, mn[0], mn[1], mn[2], mx[0], mx[1], mx[2], cnt};
-  for (int c = 0; c < kScalarCols; ++c) {
-    red[threadIdx.x] = vals[c];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        double a = red[threadIdx.x], b = red[threadIdx.x + off];
-        red[threadIdx.x] = (c >= 3 && c < 6) ? fmin(a, b) : (c >= 6 && c < 9) ? fmax(a, b) : a + b;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x * kScalarCols + c] = red[0];
-    __syncthreads();
-  }
-}
-
-void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n, int dtype,
-                    double *partial) {
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_scalars<float>, dim3(kScalarBlocks), dim3(256), 0, s,
-                       (const float *)xyzw, (const float *)nbar, n, partial);
-  else
-    hipLaunchKernelGGL(k_scalars<double>, dim3(kScalarBlocks), dim3(256), 0, s,
-                       (const double *)xyzw, (const double *)nbar, n, partial);
-}
-
-__device__ void reduce_partials(const double *p, double out[kScalarCols]) {
-  // thread-0-only helper: deterministic sequential reduction over the block rows
-  for (int c = 0; c < kScalarCols; ++c) out[c] = (c >= 3 && c < 6) ? 1e300 : (c >= 6 && c < 9) ? -1e300 : 0.0;
-  for (int b = 0; b < kScalarBlocks; ++b)
-    for (int c = 0; c < kScalarCols; ++c) {
-      double v = p[b * kScalarCols + c];
-      if (c >= 3 && c < 6) out[c] = fmin(out[c], v);
-      else if (c >= 6 && c < 9) out[c] = fmax(out[c], v);
-      else out[c] += v;
-    }
-}
-
-__global__ void k_finalize_norm(const double *pg, const double *pr, DevNorm *norm, double b0x,
-                                double b0y, double b0z, double L, int check_extent, int use_given,
-                                double ga, double gI, double gS) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double g[kScalarCols], r[kScalarCols];
-  reduce_partials(pg, g);
-  reduce_partials(pr, r);
-  DevNorm n;
-  n.sum_wg = g[0];
-  n.sum_wr = r[0];
-  if (use_given) {
-    n.alpha_r = ga; n.I = gI; n.S = gS;
-  } else {
-    n.alpha_r = g[0] / r[0];
-    n.I = n.alpha_r * r[2];
-    n.S = g[1] + n.alpha_r * n.alpha_r * r[1];
-  }
-  int flags = 0;
-  const double b0[3] = {b0x, b0y, b0z};
-  for (int a = 0; a < 3; ++a) {
-    const double *cats[2] = {g, r};
-    for (int k = 0; k < 2; ++k) {
-      const double *c = cats[k];
-      if (c[9] > 0 && (c[3 + a] - b0[a] < 0.0 || c[6 + a] - b0[a] >= L)) flags |= 1;
-    }
-    if (check_extent) {
-      double lo = fmin(g[9] > 0 ? g[3 + a] : 1e300, r[9] > 0 ? r[3 + a] : 1e300);
-      double hi = fmax(g[9] > 0 ? g[6 + a] : -1e300, r[9] > 0 ? r[6 + a] : -1e300);
-      if (hi - lo > 0.5 * L) flags |= 2;
-    }
-  }
-  n.flags = flags;
-  n.pad = 0;
-  *norm = n;
-}
-
-void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
-                          const double *b0, double L, int check_extent, int use_given,
-                          double ga, double gI, double gS) {
-  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(64), 0, s, pg, pr, norm, b0[0], b0[1], b0[2],
-                     L, check_extent, use_given, ga, gI, gS);
-}
-
-// ------------------------------------------------------------------------------ fill
-template <typename T>
-__global__ void k_fill(T *p, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = (T)0;
-}
-
-void launch_fill(hipStream_t s, void *p, size_t n, int prec) {
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks == 0) return;
-  if (prec == 0) hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float *)p, n);
-  else hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double *)p, n);
-}
-
-// ------------------------------------------------------------------------------ paint
-// Node masses m_n += w W(u - n), u = (x - b0) / H, periodic indices (N is a power of two).
-// CIC: i0 = floor(u), weights (1-d, d).  TSC: i0 = floor(u + 1/2), d = u - i0,
-// weights (1/2 (1/2-d)^2, 3/4 - d^2, 1/2 (1/2+d)^2) at i0-1, i0, i0+1.  Positions are turned
-// into u in FP64 so that the cell decision does not depend on the storage precision.
-template <typename RI, typename RM, int ASSIGN>
-__global__ void __launch_bounds__(256) k_paint(const RI *__restrict__ xyzw, int64_t n, RM *__restrict__ mesh,
-                                               int N, double b0x, double b0y, double b0z, double H,
-                                               const DevNorm *__restrict__ norm, int is_random) {
-  const double wmul = is_random ? -norm->alpha_r : 1.0;
-  const int mask = N - 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double u[3];
-    u[0] = ((double)xyzw[4 * i] - b0x) / H;
-    u[1] = ((double)xyzw[4 * i + 1] - b0y) / H;
-    u[2] = ((double)xyzw[4 * i + 2] - b0z) / H;
-    const double w = (double)xyzw[4 * i + 3] * wmul;
-    if (!(u[0] >= 0.0 && u[0] < N && u[1] >= 0.0 && u[1] < N && u[2] >= 0.0 && u[2] < N)) continue;
-    int i0[3];
-    RM wt[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (ASSIGN == 2) {
-        double f = floor(u[a]);
-        double d = u[a] - f;
-        i0[a] = (int)f;
-        wt[a][0] = (RM)(1.0 - d);
-        wt[a][1] = (RM)d;
-      } else {
-        double f = floor(u[a] + 0.5);
-        double d = u[a] - f;
-        i0[a] = (int)f - 1;
-        wt[a][0] = (RM)(0.5 * (0.5 - d) * (0.5 - d));
-        wt[a][1] = (RM)(0.75 - d * d);
-        wt[a][2] = (RM)(0.5 * (0.5 + d) * (0.5 + d));
-      }
-    }
-    constexpr int NT = (ASSIGN == 2) ? 2 : 3;
-#pragma unroll
-    for (int a = 0; a < NT; ++a) {
-      const int iz = (i0[2] + a + N) & mask;
-      const RM wz = wt[2][a] * (RM)w;
-#pragma unroll
-      for (int b = 0; b < NT; ++b) {
-        const int iy = (i0[1] + b + N) & mask;
-        const RM wyz = wt[1][b] * wz;
-        const size_t rowb = ((size_t)iz * N + iy) * N;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-          const int ix = (i0[0] + c + N) & mask;
-          atomicAdd(&mesh[rowb + ix], wt[0][c] * wyz);
-        }
-      }
-    }
-  }
-}
-
-void launch_paint(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, void *mesh,
-                  int N, const double *b0, double H, int assign, const DevNorm *norm, int is_random) {
-  if (n <= 0) return;
-  int64_t blocks64 = (n + 255) / 256;
-  unsigned blocks = (unsigned)(blocks64 > 65536 ? 65536 : blocks64);
-#define PW_PAINT(RI, RM, A)                                                                        \
-  hipLaunchKernelGGL((k_paint<RI, RM, A>), dim3(blocks), dim3(256), 0, s, (const RI *)xyzw, n,     \
-                     (RM *)mesh, N, b0[0], b0[1], b0[2], H, norm, is_random)
-  if (dtype == 0 && prec == 0) { if (assign == 2) PW_PAINT(float, float, 2); else PW_PAINT(float, float, 3); }
-  else if (dtype == 0 && prec == 1) { if (assign == 2) PW_PAINT(float, double, 2); else PW_PAINT(float, double, 3); }
-  else if (dtype == 1 && prec == 0) { if (assign == 2) PW_PAINT(double, float, 2); else PW_PAINT(double, float, 3); }
-  else { if (assign == 2) PW_PAINT(double, double, 2); else PW_PAINT(double, double, 3); }
-#undef PW_PAINT
 }
 
 // ------------------------------------------------------------------------------ fx
@@ -248,23 +58,91 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
     }
   }
   const size_t fstride = (size_t)N * N * nkx;
+  // Recurrence state carried across jobs (jobs come sorted by m, then J): (x + i y)^m and
+  // Qt_J^m, Qt_{J-1}^m of the eight elements this lane holds.
+  R cr[8], ci[8], q0[8], q1[8];
+  int m_cur = 0, J_cur = 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) { cr[s] = 1; ci[s] = 0; q0[s] = 1; q1[s] = 0; }
+  auto set_m = [&](int m) {
+    if (m == m_cur + 1) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const R tr = cr[s] * ux[s] - ci[s] * uy[s];
+        ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
+        cr[s] = tr;
+      }
+    } else if (m != m_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        cr[s] = 1; ci[s] = 0;
+        for (int i = 0; i < m; ++i) {
+          const R tr = cr[s] * ux[s] - ci[s] * uy[s];
+          ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
+          cr[s] = tr;
+        }
+      }
+    }
+    if (m != m_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) { q0[s] = 1; q1[s] = 0; }
+      m_cur = m;
+      J_cur = m;
+    }
+  };
+  auto advance = [&](int Jt) {
+    if (Jt < J_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) { q0[s] = 1; q1[s] = 0; }
+      J_cur = m_cur;
+    }
+    while (J_cur < Jt) {
+      ++J_cur;
+      if (J_cur == m_cur + 1) {
+        const R c1 = (R)(2 * m_cur + 1);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) { q1[s] = q0[s]; q0[s] = c1 * uz[s] * q0[s]; }
+      } else {
+        const R a = sh_a<R>(c_sh, J_cur, m_cur), b = sh_b<R>(c_sh, J_cur, m_cur);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const R qn = a * uz[s] * q0[s] - b * q1[s];
+          q1[s] = q0[s];
+          q0[s] = qn;
+        }
+      }
+    }
+  };
   for (int jb = 0; jb < njobs; ++jb) {
     const FieldJob J = jobs[jb];
     cplx<R> v[8];
+    R wa[8], wb[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      R w = f[s];
-      for (int a = 0; a < J.alpha; ++a) w *= inv2r[s];
-      R ya, yb;
-      if (J.kind == 0) {
-        real_sh_pair<R>(c_sh, J.Ja, J.m, ux[s], uy[s], uz[s], &ya, &yb);
-      } else {
-        R dummy;
-        real_sh_pair<R>(c_sh, J.Ja, 0, ux[s], uy[s], uz[s], &ya, &dummy);
-        yb = 0;
-        if (J.Jb >= 0) real_sh_pair<R>(c_sh, J.Jb, 0, ux[s], uy[s], uz[s], &yb, &dummy);
+      R p = f[s], pb = f[s];
+      for (int a = 0; a < J.alpha; ++a) p *= inv2r[s];
+      for (int a = 0; a < J.alpha_b; ++a) pb *= inv2r[s];
+      wa[s] = p;
+      wb[s] = pb;
+    }
+    if (J.kind == 0) {
+      set_m(J.m);
+      advance(J.Ja);
+      const R n = sh_n<R>(c_sh, J.Ja, J.m);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) v[s] = mk<R>(wa[s] * n * q0[s] * cr[s], wa[s] * n * q0[s] * ci[s]);
+    } else {
+      set_m(0);
+      advance(J.Ja);
+      const R na = sh_n<R>(c_sh, J.Ja, 0);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) v[s] = mk<R>(wa[s] * na * q0[s], (R)0);
+      if (J.Jb >= 0) {
+        advance(J.Jb);
+        const R nb = sh_n<R>(c_sh, J.Jb, 0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s].y = wb[s] * nb * q0[s];
       }
-      v[s] = mk<R>(w * ya, w * yb);
     }
     fft_pencil<R, N, false>(v, t, tw, at, sync);
 #pragma unroll
@@ -421,7 +299,7 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
                const uint32_t *__restrict__ modecoord, int N, const int *__restrict__ bin_of_s2,
                int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                const R *__restrict__ winv, double *__restrict__ acc) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<R> *vals = reinterpret_cast<cplx<R> *>(smem_raw);          // [nfields][NTH]
   double *bacc = reinterpret_cast<double *>(vals + (size_t)nfields * NTH);  // [(nell + 2) * nbins]
   const int nacc = (nell + 2) * nbins;
@@ -503,10 +381,122 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
     if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
 }
 
-void launch_contract_bis(hipStream_t s, int prec, int lmax, const void *spec, int nfields,
+// Register-resident variant: the coupling for (LMAX, BMAX) is straight-line code generated at
+// build time (BisContract<L, B, R>::run), so all field values of a mode stay in VGPRs.
+template <int L, int B, typename R> struct BisContract {
+  static constexpr bool kGenerated = false;
+};
+#include "contract_gen.inc"
+
+template <typename R, int LMAX, int BMAX>
+__global__ void __launch_bounds__(256)
+k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, const uint32_t *__restrict__ modecoord,
+                   int N, const int *__restrict__ bin_of_s2, int64_t n_s2, int nbins, double kf,
+                   const R *__restrict__ winv, double *__restrict__ acc) {
+  using CT = BisContract<LMAX, BMAX, R>;
+  constexpr int NF = CT::NF;
+  constexpr int NSH = (LMAX + 1) * (LMAX + 1);
+  constexpr int NE = LMAX / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *bacc = reinterpret_cast<double *>(smem_raw);
+  const int nacc = (NE + 2) * nbins;
+  for (int i = threadIdx.x; i < nacc; i += blockDim.x) bacc[i] = 0.0;
+  __syncthreads();
+  const int half = N / 2;
+  for (int64_t mode = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mode < nmodes;
+       mode += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t mc = modecoord[mode];
+    const int kx = mc & 0x7ff, ky = (mc >> 11) & 0x7ff, kz = (mc >> 22) & 0x3ff;
+    const int sx = (kx == half) ? -half : kx;
+    const int sy = (ky < half) ? ky : ky - N;
+    const int sz = (kz < half) ? kz : kz - N;
+    const int64_t s2 = (int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz;
+    const int b = (s2 < n_s2) ? bin_of_s2[s2] : -1;
+    if (b < 0) continue;
+    cplx<R> a[NF];
+#pragma unroll
+    for (int p = 0; p < NF; ++p) a[p] = spec[(size_t)p * nmodes + mode];
+    const bool pair = (kx != 0 && kx != half);
+    R wdir[NSH];
+#pragma unroll
+    for (int i = 0; i < NSH; ++i) wdir[i] = 0;
+    {
+      R ux = 0, uy = 0, uz = 1;
+      const R ir = s2 > 0 ? (R)1 / sqrt((R)s2) : (R)0;
+      if (s2 > 0) { ux = (R)sx * ir; uy = (R)sy * ir; uz = (R)sz * ir; }
+      real_sh_even<R, LMAX>(c_sh, ux, uy, uz, wdir);
+      if (pair) {
+        const int my = (ky == half) ? sy : -sy;
+        const int mz = (kz == half) ? sz : -sz;
+        R wm[NSH];
+#pragma unroll
+        for (int i = 0; i < NSH; ++i) wm[i] = 0;
+        real_sh_even<R, LMAX>(c_sh, (R)(-sx) * ir, (R)my * ir, (R)mz * ir, wm);
+#pragma unroll
+        for (int i = 0; i < NSH; ++i) wdir[i] += wm[i];
+      }
+    }
+    R E[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) E[i] = 0;
+    CT::run(a, wdir, E);
+    if (winv) {
+      const R iw = winv[kx] * winv[ky] * winv[kz];
+      const R iw2 = iw * iw;
+#pragma unroll
+      for (int i = 0; i < NE; ++i) E[i] *= iw2;
+    }
+    const double mult = pair ? 2.0 : 1.0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) atomicAdd(&bacc[i * nbins + b], (double)E[i]);
+    atomicAdd(&bacc[NE * nbins + b], mult);
+    atomicAdd(&bacc[(NE + 1) * nbins + b], mult * kf * sqrt((double)s2));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nacc; i += blockDim.x)
+    if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
+}
+
+template <typename R, int L, int B>
+static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, const uint32_t *modecoord,
+                                int N, const int *bin_of_s2, int64_t n_s2, int nbins, double kf,
+                                const void *winv, double *acc) {
+  if constexpr (BisContract<L, B, R>::kGenerated) {
+    int64_t want = (nmodes + 255) / 256;
+    unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    size_t sh = (size_t)(L / 2 + 3) * nbins * sizeof(double);
+    hipLaunchKernelGGL((k_contract_bis_reg<R, L, B>), dim3(blocks), dim3(256), sh, s,
+                       (const cplx<R> *)spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf,
+                       (const R *)winv, acc);
+    return true;
+  } else {
+    return false;
+  }
+}
+
+template <typename R>
+static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void *spec, int64_t nmodes,
+                                  const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
+                                  int nbins, double kf, const void *winv, double *acc) {
+#define PW_CR(L, B)                                                                                \
+  if (lmax == L && bmax == B)                                                                      \
+    return contract_reg_launch<R, L, B>(s, spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, acc);
+  PW_CR(0, 0) PW_CR(0, 1) PW_CR(0, 2) PW_CR(2, 0) PW_CR(2, 1) PW_CR(2, 2)
+  PW_CR(4, 0) PW_CR(4, 1) PW_CR(4, 2) PW_CR(6, 0) PW_CR(6, 1) PW_CR(6, 2)
+#undef PW_CR
+  return false;
+}
+
+void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
                          int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                          const void *winv, double *acc) {
+  if (nmodes <= 0) return;
+  if (prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, modecoord, N, bin_of_s2, n_s2,
+                                               nbins, kf, winv, acc)
+                : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, modecoord, N, bin_of_s2, n_s2,
+                                                nbins, kf, winv, acc))
+    return;
   int64_t want = (nmodes + 127) / 128;
   unsigned blocks = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
 #define PW_CONTRACT(R, L, NTH)                                                                     \

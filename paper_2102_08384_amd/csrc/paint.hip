@@ -1,0 +1,442 @@
+// Catalog reductions, normalisation and mass assignment (gfx950).
+//
+//   scalars       FP64 reductions over a catalog (sum w, sum w^2, sum w^2 nbar, bounding box)
+//   norm          alpha_r = sum w_g / sum w_r, I = alpha_r sum_r w_r^2 nbar_r,
+//                 S = sum_g w_g^2 + alpha_r^2 sum_r w_r^2 (Section 2.1), range / extent flags
+//   tile_count    per-workgroup LDS histogram of the tile of every particle's anchor node
+//   tile_scan     exclusive scan of the tile counts, compact slots of the occupied tiles
+//   tile_scatter  particles -> tile-sorted records (node offset inside the tile, signed weight)
+//   tile_paint    CIC / TSC taps of one tile's particles accumulated in LDS (tile + halo),
+//                 written as a block to the tile's scratch slot
+//   tile_gather   every mesh node = sum of the (at most eight) blocks that cover it
+// No global atomics touch the mesh: each node is written once with a plain store.
+#include "kernels.h"
+
+namespace pw {
+
+// ------------------------------------------------------------------------------ scalars
+template <typename R>
+__global__ void __launch_bounds__(256) k_scalars(const R *__restrict__ xyzw, const R *__restrict__ nbar,
+                                                 int64_t n, double *__restrict__ partial) {
+  double sw = 0, sw2 = 0, swn = 0, swa = 0;
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  double cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double x = xyzw[4 * i], y = xyzw[4 * i + 1], z = xyzw[4 * i + 2], w = xyzw[4 * i + 3];
+    sw += w;
+    sw2 += w * w;
+    swa += fabs(w);
+    if (nbar) swn += w * w * (double)nbar[i];
+    mn[0] = fmin(mn[0], x); mn[1] = fmin(mn[1], y); mn[2] = fmin(mn[2], z);
+    mx[0] = fmax(mx[0], x); mx[1] = fmax(mx[1], y); mx[2] = fmax(mx[2], z);
+    cnt += 1;
+  }
+  __shared__ double red[256];
+  double vals[kScalarCols] = {sw, sw2, swn, mn[0], mn[1], mn[2], mx[0], mx[1], mx[2], cnt, swa};
+  for (int c = 0; c < kScalarCols; ++c) {
+    red[threadIdx.x] = vals[c];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+        double a = red[threadIdx.x], b = red[threadIdx.x + off];
+        red[threadIdx.x] = (c >= 3 && c < 6) ? fmin(a, b) : (c >= 6 && c < 9) ? fmax(a, b) : a + b;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x * kScalarCols + c] = red[0];
+    __syncthreads();
+  }
+}
+
+void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n, int dtype,
+                    double *partial) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_scalars<float>, dim3(kScalarBlocks), dim3(256), 0, s,
+                       (const float *)xyzw, (const float *)nbar, n, partial);
+  else
+    hipLaunchKernelGGL(k_scalars<double>, dim3(kScalarBlocks), dim3(256), 0, s,
+                       (const double *)xyzw, (const double *)nbar, n, partial);
+}
+
+__device__ void reduce_partials(const double *p, double out[kScalarCols]) {
+  // thread-0-only helper: deterministic sequential reduction over the block rows
+  for (int c = 0; c < kScalarCols; ++c) out[c] = (c >= 3 && c < 6) ? 1e300 : (c >= 6 && c < 9) ? -1e300 : 0.0;
+  for (int b = 0; b < kScalarBlocks; ++b)
+    for (int c = 0; c < kScalarCols; ++c) {
+      double v = p[b * kScalarCols + c];
+      if (c >= 3 && c < 6) out[c] = fmin(out[c], v);
+      else if (c >= 6 && c < 9) out[c] = fmax(out[c], v);
+      else out[c] += v;
+    }
+}
+
+__global__ void k_finalize_norm(const double *pg, const double *pr, DevNorm *norm, double b0x,
+                                double b0y, double b0z, double L, int check_extent, int use_given,
+                                double ga, double gI, double gS) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double g[kScalarCols], r[kScalarCols];
+  reduce_partials(pg, g);
+  reduce_partials(pr, r);
+  DevNorm n;
+  n.sum_wg = g[0];
+  n.sum_wr = r[0];
+  if (use_given) {
+    n.alpha_r = ga; n.I = gI; n.S = gS;
+  } else {
+    n.alpha_r = g[0] / r[0];
+    n.I = n.alpha_r * r[2];
+    n.S = g[1] + n.alpha_r * n.alpha_r * r[1];
+  }
+  int flags = 0;
+  const double b0[3] = {b0x, b0y, b0z};
+  for (int a = 0; a < 3; ++a) {
+    const double *cats[2] = {g, r};
+    for (int k = 0; k < 2; ++k) {
+      const double *c = cats[k];
+      if (c[9] > 0 && (c[3 + a] - b0[a] < 0.0 || c[6 + a] - b0[a] >= L)) flags |= 1;
+    }
+    if (check_extent) {
+      double lo = fmin(g[9] > 0 ? g[3 + a] : 1e300, r[9] > 0 ? r[3 + a] : 1e300);
+      double hi = fmax(g[9] > 0 ? g[6 + a] : -1e300, r[9] > 0 ? r[6 + a] : -1e300);
+      if (hi - lo > 0.5 * L) flags |= 2;
+    }
+  }
+  // fixed-point scale for painting: every node sum is bounded by sum |w_g| + |alpha_r| sum |w_r|,
+  // which must stay below 2^62 after scaling (int64 accumulators with headroom).
+  const double wabs = g[10] + fabs(n.alpha_r) * r[10];
+  int e = 40;
+  if (wabs > 0.0) {
+    int ex;
+    frexp(wabs, &ex);          // wabs < 2^ex
+    e = 61 - ex;
+  }
+  e = e > 1000 ? 1000 : (e < -1000 ? -1000 : e);
+  n.fix_scale = ldexp(1.0, e);
+  n.flags = flags;
+  n.pad = 0;
+  *norm = n;
+}
+
+void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
+                          const double *b0, double L, int check_extent, int use_given,
+                          double ga, double gI, double gS) {
+  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(64), 0, s, pg, pr, norm, b0[0], b0[1], b0[2],
+                     L, check_extent, use_given, ga, gI, gS);
+}
+
+// ------------------------------------------------------------------------------ fill
+template <typename T>
+__global__ void k_fill(T *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = (T)0;
+}
+
+void launch_fill(hipStream_t s, void *p, size_t n, int prec) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks == 0) return;
+  if (prec == 0) hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float *)p, n);
+  else hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double *)p, n);
+}
+
+// ------------------------------------------------------------------------------ tiled paint
+// Anchor node of a particle (decided in FP64): CIC i0 = floor(u) with taps i0, i0+1;
+// TSC i0 = floor(u + 1/2) with taps i0-1, i0, i0+1; d = u - i0; u = (x - b0) / H.
+// Particles outside [0, N) on some axis are skipped (the norm kernel flags them).
+__device__ __forceinline__ bool anchor3(const double u[3], int assign, int N, int i0[3], double d[3]) {
+  if (!(u[0] >= 0.0 && u[0] < N && u[1] >= 0.0 && u[1] < N && u[2] >= 0.0 && u[2] < N)) return false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double f = (assign == 2) ? floor(u[a]) : floor(u[a] + 0.5);
+    i0[a] = ((int)f) & (N - 1);
+    d[a] = u[a] - f;
+  }
+  return true;
+}
+
+template <typename R> struct Rec4;
+template <> struct Rec4<float> { typedef float4 T; };
+template <> struct Rec4<double> { typedef double4 T; };
+
+constexpr int kAggChunk = 65536;   // particles per workgroup of the sort kernels
+constexpr int kAggThreads = 1024;
+
+template <typename RI>
+__device__ __forceinline__ bool particle_tile(const RI *__restrict__ xyzw, int64_t i, int N, double b0x,
+                                              double b0y, double b0z, double H, int assign, int ts,
+                                              int i0[3], double d[3], int *tile) {
+  const double u[3] = {((double)xyzw[4 * i] - b0x) / H, ((double)xyzw[4 * i + 1] - b0y) / H,
+                       ((double)xyzw[4 * i + 2] - b0z) / H};
+  if (!anchor3(u, assign, N, i0, d)) return false;
+  const int nt = N / ts;
+  *tile = ((i0[2] / ts) * nt + i0[1] / ts) * nt + i0[0] / ts;
+  return true;
+}
+
+// Per-workgroup LDS histogram of a chunk; one global atomic per (chunk, occupied tile).
+template <typename RI>
+__global__ void __launch_bounds__(kAggThreads)
+k_tile_count(const RI *__restrict__ xyzw, int64_t n, int N, double b0x, double b0y, double b0z, double H,
+             int assign, int ts, int ntiles, int *__restrict__ counts) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int *hist = reinterpret_cast<int *>(smem_raw);
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kAggChunk;
+  const int64_t c1 = c0 + kAggChunk < n ? c0 + kAggChunk : n;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    int i0[3], tile;
+    double d[3];
+    if (particle_tile(xyzw, i, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
+    if (hist[t]) atomicAdd(&counts[t], hist[t]);
+}
+
+// offsets = exclusive scan of counts (offsets[ntiles] = total), cursor = offsets,
+// slot[t] = rank of tile t among the occupied tiles (-1 if empty), slots[ntiles] = count.
+__global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ counts, int ntiles,
+                                                    int *__restrict__ offsets, int *__restrict__ cursor,
+                                                    int *__restrict__ slot) {
+  __shared__ int part[1024];
+  __shared__ int occ[1024];
+  const int per = (ntiles + 1023) / 1024;
+  const int b = threadIdx.x * per, e = min(ntiles, b + per);
+  int s = 0, o = 0;
+  for (int i = b; i < e; ++i) {
+    s += counts[i];
+    o += counts[i] > 0;
+  }
+  part[threadIdx.x] = s;
+  occ[threadIdx.x] = o;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scans
+    int v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    int w = (int)threadIdx.x >= off ? occ[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    occ[threadIdx.x] += w;
+    __syncthreads();
+  }
+  int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  int orun = threadIdx.x > 0 ? occ[threadIdx.x - 1] : 0;
+  for (int i = b; i < e; ++i) {
+    offsets[i] = run;
+    cursor[i] = run;
+    run += counts[i];
+    slot[i] = counts[i] > 0 ? orun++ : -1;
+  }
+  if (threadIdx.x == 1023) {
+    offsets[ntiles] = part[1023];
+    slot[ntiles] = occ[1023];
+  }
+}
+
+// Reserve one run per (chunk, tile) and rank the chunk's particles inside it with LDS atomics.
+template <typename RI, typename RM>
+__global__ void __launch_bounds__(kAggThreads)
+k_tile_scatter(const RI *__restrict__ xyzw, int64_t n, int N, double b0x, double b0y, double b0z, double H,
+               int assign, int ts, int ntiles, const DevNorm *__restrict__ norm, int is_random,
+               int *__restrict__ cursor, typename Rec4<RM>::T *__restrict__ rec) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int *hist = reinterpret_cast<int *>(smem_raw);
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kAggChunk;
+  const int64_t c1 = c0 + kAggChunk < n ? c0 + kAggChunk : n;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    int i0[3], tile;
+    double d[3];
+    if (particle_tile(xyzw, i, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const int c = hist[t];
+    hist[t] = c ? atomicAdd(&cursor[t], c) : 0;  // base of this chunk's run in tile t
+  }
+  __syncthreads();
+  const double wmul = is_random ? -norm->alpha_r : 1.0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    int i0[3], tile;
+    double d[3];
+    if (!particle_tile(xyzw, i, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) continue;
+    const int pos = atomicAdd(&hist[tile], 1);
+    typename Rec4<RM>::T r;
+    r.x = (RM)((double)(i0[0] % ts) + d[0]);
+    r.y = (RM)((double)(i0[1] % ts) + d[1]);
+    r.z = (RM)((double)(i0[2] % ts) + d[2]);
+    r.w = (RM)((double)xyzw[4 * i + 3] * wmul);
+    rec[pos] = r;
+  }
+}
+
+// One workgroup per tile: the tile's nodes plus a one-node halo (local index -1 .. ts on each
+// axis, E = ts + 2) accumulated in LDS, then stored as block `slot[tile]` of the scratch.
+// Contributions are accumulated as 64-bit fixed point, round(c * fix_scale) with fix_scale a
+// power of two (integer LDS atomics run at full rate where floating-point LDS atomics are
+// serialised per lane); integer sums are exact, so the mesh does not depend on the order.
+template <typename RM, int ASSIGN>
+__global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restrict__ offsets,
+                                                    const int *__restrict__ slot,
+                                                    const typename Rec4<RM>::T *__restrict__ rec,
+                                                    const DevNorm *__restrict__ norm,
+                                                    unsigned long long *__restrict__ blocks) {
+  const int tile = blockIdx.x;
+  const int beg = offsets[tile], end = offsets[tile + 1];
+  if (beg == end) return;  // uniform for the block
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
+  const int E = ts + 2, E3 = E * E * E;
+  for (int c = threadIdx.x; c < E3; c += blockDim.x) acc[c] = 0ull;
+  const RM scale = (RM)norm->fix_scale;
+  __syncthreads();
+  constexpr int NTAP = (ASSIGN == 2) ? 2 : 3;
+  constexpr int O0 = (ASSIGN == 2) ? 1 : 0;   // LDS index of tap a on an axis: l + a + O0
+  for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    const typename Rec4<RM>::T r = rec[p];
+    const RM v[3] = {r.x, r.y, r.z};
+    int l[3];
+    RM wt[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int li = (ASSIGN == 2) ? (int)floor(v[a]) : (int)floor(v[a] + (RM)0.5);
+      li = li < 0 ? 0 : (li > ts - 1 ? ts - 1 : li);
+      const RM d = v[a] - (RM)li;
+      l[a] = li;
+      if (ASSIGN == 2) {
+        wt[a][0] = (RM)1 - d;
+        wt[a][1] = d;
+      } else {
+        wt[a][0] = (RM)0.5 * ((RM)0.5 - d) * ((RM)0.5 - d);
+        wt[a][1] = (RM)0.75 - d * d;
+        wt[a][2] = (RM)0.5 * ((RM)0.5 + d) * ((RM)0.5 + d);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NTAP; ++a) {
+      const RM wz = wt[2][a] * r.w * scale;
+      const int zz = l[2] + a + O0;
+#pragma unroll
+      for (int b = 0; b < NTAP; ++b) {
+        const RM wyz = wt[1][b] * wz;
+        const int base = (zz * E + l[1] + b + O0) * E + l[0] + O0;
+#pragma unroll
+        for (int c = 0; c < NTAP; ++c) {
+          const long long q = (long long)rint(wt[0][c] * wyz);
+          atomicAdd(&acc[base + c], (unsigned long long)q);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  unsigned long long *dst = blocks + (size_t)slot[tile] * E3;
+  for (int c = threadIdx.x; c < E3; c += blockDim.x) dst[c] = acc[c];
+}
+
+// Node (x, y, z) of tile T at local (lx, ly, lz) is covered by the block of tile T + d for
+// d in {-1, 0, 1}^3 where d_a = -1 needs l_a = 0 and d_a = +1 needs l_a = ts - 1; inside that
+// block it sits at local l - d ts, block index l - d ts + 1.  Empty tiles have no block.
+// N and ts are powers of two: index arithmetic by shifts and masks.
+template <typename RM>
+__global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const int *__restrict__ slot,
+                                                     const unsigned long long *__restrict__ blocks,
+                                                     const DevNorm *__restrict__ norm, RM *__restrict__ mesh) {
+  const int N = 1 << lgN, ts = 1 << lgts, nt = N >> lgts, E = ts + 2;
+  const size_t E3 = (size_t)E * E * E;
+  const size_t ncell = (size_t)1 << (3 * lgN);
+  const double inv = 1.0 / norm->fix_scale;
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < ncell; g += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(g & (N - 1)), y = (int)((g >> lgN) & (N - 1)), z = (int)(g >> (2 * lgN));
+    const int l[3] = {x & (ts - 1), y & (ts - 1), z & (ts - 1)};
+    const int t[3] = {x >> lgts, y >> lgts, z >> lgts};
+    int dlo[3], dhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dlo[a] = (l[a] == 0) ? -1 : 0;
+      dhi[a] = (l[a] == ts - 1) ? 1 : 0;
+    }
+    unsigned long long v = 0;
+    for (int dz = dlo[2]; dz <= dhi[2]; ++dz)
+      for (int dy = dlo[1]; dy <= dhi[1]; ++dy)
+        for (int dx = dlo[0]; dx <= dhi[0]; ++dx) {
+          const int tx = (t[0] + dx + nt) & (nt - 1), ty = (t[1] + dy + nt) & (nt - 1);
+          const int tz = (t[2] + dz + nt) & (nt - 1);
+          const int sl = slot[(tz * nt + ty) * nt + tx];
+          if (sl < 0) continue;
+          const int ex = l[0] - dx * ts + 1, ey = l[1] - dy * ts + 1, ez = l[2] - dz * ts + 1;
+          v += blocks[(size_t)sl * E3 + ((size_t)ez * E + ey) * E + ex];
+        }
+    mesh[g] = (RM)((double)(long long)v * inv);
+  }
+}
+
+void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,
+                       const double *b0, double H, int assign, int *counts) {
+  if (n <= 0) return;
+  const int ts = tile_size(N);
+  const int nt = N / ts, ntiles = nt * nt * nt;
+  const size_t lds = (size_t)ntiles * sizeof(int);
+  const unsigned chunks = (unsigned)((n + kAggChunk - 1) / kAggChunk);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_tile_count<float>, dim3(chunks), dim3(kAggThreads), lds, s, (const float *)xyzw, n, N,
+                       b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
+  else
+    hipLaunchKernelGGL(k_tile_count<double>, dim3(chunks), dim3(kAggThreads), lds, s, (const double *)xyzw, n,
+                       N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
+}
+
+void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot) {
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, offsets, cursor, slot);
+}
+
+void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, int N,
+                         const double *b0, double H, int assign, const DevNorm *norm,
+                         int is_random, int *cursor, void *records) {
+  if (n <= 0) return;
+  const int ts = tile_size(N);
+  const int nt = N / ts, ntiles = nt * nt * nt;
+  const size_t lds = (size_t)ntiles * sizeof(int);
+  const unsigned chunks = (unsigned)((n + kAggChunk - 1) / kAggChunk);
+#define PW_SCAT(RI, RM)                                                                            \
+  hipLaunchKernelGGL((k_tile_scatter<RI, RM>), dim3(chunks), dim3(kAggThreads), lds, s, (const RI *)xyzw, \
+                     n, N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, norm, is_random, cursor,    \
+                     (typename Rec4<RM>::T *)records)
+  if (dtype == 0 && prec == 0) PW_SCAT(float, float);
+  else if (dtype == 0) PW_SCAT(float, double);
+  else if (prec == 0) PW_SCAT(double, float);
+  else PW_SCAT(double, double);
+#undef PW_SCAT
+}
+
+static int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
+                       const void *records, const DevNorm *norm, void *blocks, void *mesh) {
+  const int ts = tile_size(N);
+  const int nt = N / ts;
+  const unsigned ntiles = (unsigned)(nt * nt * nt);
+  const size_t E3 = (size_t)(ts + 2) * (ts + 2) * (ts + 2);
+  const size_t ncell = (size_t)N * N * N;
+  const unsigned gblocks = (unsigned)std::min<size_t>((ncell + 255) / 256, 16384);
+  unsigned long long *b = (unsigned long long *)blocks;
+#define PW_TP(RM, A)                                                                              \
+  hipLaunchKernelGGL((k_tile_paint<RM, A>), dim3(ntiles), dim3(256), E3 * sizeof(unsigned long long), s, \
+                     ts, offsets, slot, (const typename Rec4<RM>::T *)records, norm, b)
+  if (prec == 0) { if (assign == 2) PW_TP(float, 2); else PW_TP(float, 3); }
+  else { if (assign == 2) PW_TP(double, 2); else PW_TP(double, 3); }
+#undef PW_TP
+  if (prec == 0)
+    hipLaunchKernelGGL(k_tile_gather<float>, dim3(gblocks), dim3(256), 0, s, ilog2(N), ilog2(ts), slot, b, norm,
+                       (float *)mesh);
+  else
+    hipLaunchKernelGGL(k_tile_gather<double>, dim3(gblocks), dim3(256), 0, s, ilog2(N), ilog2(ts), slot, b,
+                       norm, (double *)mesh);
+}
+
+}  // namespace pw
