@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpw.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["coeffs.cpp", "plan.cpp", "api.cpp", "kernels.hip", "paint.hip"]
+SOURCES = ["generated.hip", "kernels.hip", "inverse.hip", "paint.hip", "coeffs.cpp", "plan.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

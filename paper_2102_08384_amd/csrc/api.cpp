@@ -156,7 +156,6 @@ DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
   dp->host = std::move(hp);
   HostPlan &h = *dp->host;
   try {
-    size_t csz = h.prec == PW_FP32 ? 8 : 16;
     // twiddles exp(-2 pi i e / N)
     std::vector<double> tw(2 * h.N);
     for (int e = 0; e < h.N; ++e) {
@@ -171,39 +170,44 @@ DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
       dp->tw = upload(ctx, dp.get(), tw);
     }
     dp->jobs = upload(ctx, dp.get(), h.jobs);
-    dp->ycnt = upload(ctx, dp.get(), h.ycnt);
-    dp->yoff = upload(ctx, dp.get(), h.yoff);
-    dp->pinfo = upload(ctx, dp.get(), h.pinfo);
-    dp->moff = upload(ctx, dp.get(), h.moff);
-    dp->modecoord = upload(ctx, dp.get(), h.modecoord);
+    dp->ijobs = upload(ctx, dp.get(), h.ijobs);
+    dp->ajobs = upload(ctx, dp.get(), h.ajobs);
+    auto up_prune = [&](const Prune &p, DevPrune &d) {
+      d.ycnt = upload(ctx, dp.get(), p.ycnt);
+      d.yoff = upload(ctx, dp.get(), p.yoff);
+      d.pinfo = upload(ctx, dp.get(), p.pinfo);
+      d.moff = upload(ctx, dp.get(), p.moff);
+      d.modecoord = upload(ctx, dp.get(), p.modecoord);
+    };
+    up_prune(h.fwd, dp->fwd);
+    up_prune(h.sph, dp->sph);
     dp->bin_of_s2 = upload(ctx, dp.get(), h.bin_of_s2);
     dp->ells = upload(ctx, dp.get(), h.ells);
-    if (!h.winv.empty()) {
+    dp->zrank = upload(ctx, dp.get(), h.zrank);
+    dp->zidx = upload(ctx, dp.get(), h.zidx);
+    dp->yidx = upload(ctx, dp.get(), h.yidx);
+    dp->iycnt = upload(ctx, dp.get(), h.iycnt);
+    dp->iyoff = upload(ctx, dp.get(), h.iyoff);
+    auto up_real = [&](const std::vector<double> &v) -> void * {
       if (h.prec == PW_FP32) {
-        std::vector<float> wf(h.winv.begin(), h.winv.end());
-        dp->winv = upload(ctx, dp.get(), wf);
-      } else {
-        dp->winv = upload(ctx, dp.get(), h.winv);
+        std::vector<float> f(v.begin(), v.end());
+        return upload(ctx, dp.get(), f);
       }
-    }
+      return upload(ctx, dp.get(), v);
+    };
+    dp->winv = up_real(h.winv);
+    dp->icoef = up_real(h.icoef);
     dp->t_start = upload(ctx, dp.get(), h.t_start);
     dp->t_sh = upload(ctx, dp.get(), h.t_sh);
     dp->t_ell = upload(ctx, dp.get(), h.t_ell);
     dp->t_p1 = upload(ctx, dp.get(), h.t_p1);
     dp->t_p2 = upload(ctx, dp.get(), h.t_p2);
-    if (h.prec == PW_FP32) {
-      std::vector<float> cf(h.t_coef.begin(), h.t_coef.end());
-      dp->t_coef = upload(ctx, dp.get(), cf);
-    } else {
-      dp->t_coef = upload(ctx, dp.get(), h.t_coef);
-    }
+    dp->t_coef = up_real(h.t_coef);
     size_t rsz = h.prec == PW_FP32 ? 4 : 8;
     dp->mesh = alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * h.N * rsz);
-    size_t x1 = (size_t)h.nfields * h.N * h.N * h.nkx * csz;
-    size_t x2 = (size_t)h.nfields * h.N * h.npen * csz;
-    size_t x3 = (size_t)h.nfields * h.nmodes * csz;
-    dp->bufA = alloc_plan(ctx, dp.get(), std::max(x1, x3));
-    dp->bufB = alloc_plan(ctx, dp.get(), std::max<size_t>(x2, 16));
+    const size_t sb = spectrum_buffer_bytes(h);
+    dp->bufA = alloc_plan(ctx, dp.get(), sb);
+    dp->bufB = alloc_plan(ctx, dp.get(), sb);
     dp->acc = (double *)alloc_plan(ctx, dp.get(), (size_t)(h.nell + 2) * h.n_bins * sizeof(double));
     dp->out = (double *)alloc_plan(ctx, dp.get(), (size_t)(h.nell + 2) * h.n_bins * sizeof(double));
     dp->part_g = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
@@ -295,9 +299,6 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   const double rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2.0 * rsz;
   const double isz_g = gal->dtype == PW_FP32 ? 4.0 : 8.0, isz_r = ran->dtype == PW_FP32 ? 4.0 : 8.0;
   const double ncell = (double)h.N * h.N * h.N;
-  const double x1 = (double)h.nfields * h.N * h.N * h.nkx * csz;
-  const double x2 = (double)h.nfields * h.N * h.npen * csz;
-  const double x3 = (double)h.nfields * h.nmodes * csz;
   // a1: FP64 scalars
   mark("scalars", 4.0 * isz_g * gal->n + 5.0 * isz_r * ran->n);
   launch_scalars(s, gx, nullptr, gal->n, gal->dtype, dp->part_g);
@@ -329,26 +330,108 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ctx->records,
                     dp->norm, dp->tile_blocks, dp->mesh);
   // a3 + a4: weighted fields and the forward transforms
+  const int N = h.N;
+  const Prune &F = h.fwd;
+  const double x1 = (double)h.nfields * N * N * F.nkx * csz;
+  const double x2 = (double)h.nfields * N * F.npen * csz;
+  const double x3 = (double)h.nfields * F.nmodes * csz;
+  char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
   mark("fx", ncell * rsz + x1);
-  launch_fx(s, h.prec, h.N, dp->mesh, dp->bufA, dp->jobs, (int)h.jobs.size(), h.nkx, cfg->box_origin, h.H, dp->tw);
+  launch_fx(s, h.prec, N, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, cfg->box_origin, h.H, h.unit,
+            dp->tw);
   mark("fy", x1 + x2);
-  if (h.npen > 0)
-    launch_fy(s, h.prec, h.N, dp->bufA, dp->bufB, h.nfields, h.nkx, dp->ycnt, dp->yoff, h.npen, dp->tw);
+  if (F.npen > 0)
+    launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw);
   mark("fz", x2 + x3);
-  if (h.npen > 0)
-    launch_fz(s, h.prec, h.N, dp->bufB, dp->bufA, h.nfields, h.npen, dp->pinfo, dp->moff, h.nmodes, dp->tw);
-  // a7: contraction and FP64 binning
-  mark("contract", x3 + 4.0 * h.nmodes);
-  launch_fill(s, dp->acc, (size_t)(h.nell + 2) * h.n_bins, 1);
-  TermTable tab;
-  tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
-  tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
-  tab.ntargets = (int)h.t_sh.size();
-  launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, dp->bufA, h.nfields, h.nmodes, dp->modecoord, h.N,
-                      dp->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins, h.nell, tab, h.kf,
-                      dp->winv, dp->acc);
-  mark("finalize", 0.0);
-  launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+  if (F.npen > 0)
+    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, F.nmodes, dp->tw);
+  const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
+  const size_t nacc = (size_t)(h.nell + 2) * h.n_bins;
+  if (h.path == PATH_BIS_PK) {
+    // a7: contraction and FP64 binning
+    mark("contract", x3 + 4.0 * F.nmodes);
+    launch_fill(s, dp->acc, nacc, 1);
+    TermTable tab;
+    tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
+    tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
+    tab.ntargets = (int)h.t_sh.size();
+    launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, dp->fwd.modecoord, N,
+                        dp->bin_of_s2, n_s2, h.n_bins, h.nell, tab, h.kf, dp->winv, dp->acc);
+    mark("finalize", 0.0);
+    launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+  } else {
+    // Spectra after fz: full pencil-major A[p][q * N + kz], q = ky * nkx + kx.
+    const double sfull = (double)N * N * F.nkx * csz;  // one full spectrum
+    const size_t sfull_b = (size_t)N * N * F.nkx * (size_t)csz;
+    const double inv_n3 = 1.0 / ncell;
+    const int npl = h.nz;  // retained z planes (= y rows) of the inverse outputs
+    const double zpart = (double)h.n_inv * npl * F.npen * csz;
+    const double ypart = (double)h.n_inv * npl * h.ny * F.nkx * csz;
+    const bool xi = h.path != PATH_MID_PK;
+    if (xi) launch_fill(s, dp->acc, nacc, 1);
+    void *zin = A, *zout = B;
+    int real_in = 0;
+    if (h.path == PATH_BIS_XI) {
+      // a8 (bisector): T_{l nu}(k) = sum S Re(conj R_p1 R_p2) / W^2 on every mode
+      mark("targets", x3 + (double)h.n_targets * F.nmodes * rsz);
+      launch_targets(s, h.prec, N, h.ell_max, h.order / 2, A, F.nmodes, F.nkx, dp->winv, B);
+      zin = B;
+      zout = A;
+      real_in = 1;
+    }
+    // a5: conj(D) Q / W^2 (midpoint) and the inverse z pass; D = sqrt(4 pi) Q_{0,0,0}
+    const int nzf = h.path == PATH_BIS_XI ? h.n_targets : h.nfields;
+    // bytes: the input spectra (+ D once), the in-place products and the retained z planes
+    mark("iz", (real_in ? (double)nzf * F.nmodes * rsz : (double)(nzf + 1) * sfull) +
+                   (double)h.n_inplace * sfull + zpart);
+    const double sqrt4pi = std::sqrt(4.0 * 3.14159265358979323846);
+    launch_iz(s, h.prec, N, zin, zout, nzf, h.n_inplace, real_in, F.npen, F.nkx,
+              h.path == PATH_BIS_XI ? nullptr : A, sqrt4pi, h.path == PATH_BIS_XI ? nullptr : dp->winv,
+              dp->zrank, npl, dp->tw);
+    // inverse y pass into the other buffer (midpoint P: behind the alpha = 0 products)
+    void *yout = (zout == B) ? (void *)(A + (size_t)h.n_inplace * sfull_b) : (void *)B;
+    mark("iy", (double)h.n_inv * npl * N * F.nkx * csz + ypart);
+    launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, dp->iycnt, dp->iyoff, (int64_t)h.ny * F.nkx,
+              dp->tw);
+    if (xi) {
+      // a8: c2r along x fused with the |D|^alpha y(D^) weighting and FP64 r-binning
+      mark("ix_bin", ypart);
+      launch_ix(s, h.prec, N, 1, yout, nullptr, dp->ijobs, (int)h.ijobs.size(), dp->icoef, h.nell, h.nz, h.ny,
+                dp->zidx, dp->yidx, h.H, h.unit, inv_n3, dp->bin_of_s2, n_s2, h.n_bins, dp->acc, dp->tw);
+      mark("finalize", 0.0);
+      launch_finalize_xi(s, dp->acc, h.nell, h.n_bins, h.H * h.H * h.H, dp->norm, dp->out);
+    } else {
+      void *Aoff = A + (size_t)h.n_inplace * sfull_b;  // behind the alpha = 0 products
+      if (h.n_inv > 0) {
+        // g fields in real space (B), then a6: A_{l nu} = sum Phi' y(D^) |D|^alpha g (into Aoff)
+        mark("ix", ypart + (double)h.n_inv * ncell * rsz);
+        launch_ix(s, h.prec, N, 0, yout, B, dp->ijobs, (int)h.ijobs.size(), nullptr, h.nell, h.nz, h.ny,
+                  dp->zidx, dp->yidx, h.H, h.unit, inv_n3, nullptr, 0, 0, nullptr, dp->tw);
+        mark("reweight", (double)(h.n_inv + h.n_a) * ncell * rsz);
+        launch_reweight(s, h.prec, N, h.ell_max, h.order, B, Aoff, h.H / h.unit);
+        // forward transforms of A, pruned to the k-sphere of the bins
+        const Prune &P = h.sph;
+        const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
+                     a3 = (double)h.n_a * P.nmodes * csz;
+        mark("afx", (double)h.n_a * ncell * rsz + a1);
+        launch_fx(s, h.prec, N, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, cfg->box_origin, h.H, h.unit,
+                  dp->tw);
+        mark("afy", a1 + a2);
+        if (P.npen > 0)
+          launch_fy(s, h.prec, N, 0, B, Aoff, h.n_a, N, P.nkx, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw);
+        mark("afz", a2 + a3);
+        if (P.npen > 0)
+          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, P.nmodes, dp->tw);
+      }
+      // a7 (midpoint): sum_nu y_l^nu(k^) Re[G_{l nu} + A_{l nu}] and FP64 k-binning
+      mark("contract", (double)(h.n0 + h.n_a) * h.sph.nmodes * csz + 4.0 * h.sph.nmodes);
+      launch_fill(s, dp->acc, nacc, 1);
+      launch_contract_mid(s, h.prec, h.ell_max, A, F.nkx, h.n_a > 0 ? B : nullptr, h.sph.nmodes,
+                          dp->sph.modecoord, N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->acc);
+      mark("finalize", 0.0);
+      launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+    }
+  }
   mark(nullptr, 0.0);
   ctx->n_stages = ns - 1;
   HIPCHECK(hipGetLastError());
@@ -521,8 +604,12 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
     const void *src = nullptr;
     size_t bytes = 0;
     if (what == 0) { src = dp->mesh; bytes = (size_t)h.N * h.N * h.N * rsz; }
-    else if (what == 1) { src = dp->bufA; bytes = (size_t)h.nfields * h.nmodes * 2 * rsz; }
-    else if (what == 2) { src = dp->modecoord; bytes = (size_t)h.nmodes * 4; }
+    else if (what == 1) { src = dp->bufA; bytes = (size_t)h.nfields * h.fwd.nmodes * 2 * rsz; }
+    else if (what == 2) {
+      if (h.fwd.modecoord.empty()) fail(PW_EINVAL, "pw_inspect: this path keeps full spectra (no mode list)");
+      src = dp->fwd.modecoord;
+      bytes = (size_t)h.fwd.nmodes * 4;
+    }
     else fail(PW_EINVAL, "pw_inspect: unknown buffer %d", what);
     *needed = bytes;
     if (dst) {

@@ -139,6 +139,33 @@ __device__ __forceinline__ void fft_pencil(cplx<R> v[8], int t, const cplx<R> *_
   fft_stages<R, N, INV, 0, 1>(v, t, tw, at, sync);
 }
 
+// Row-mode pencils (x passes): ROWS rows of N elements per block, T = N/8 lanes per row.
+template <int N> struct FxShape {
+  static constexpr int T = N / 8;                          // lanes per pencil
+  static constexpr int ROWS = (T >= 64) ? (256 / T > 0 ? 256 / T : 1) : 64 / T * 2;
+  static constexpr int THREADS = ROWS * T;
+};
+
+// Column-mode pencils: C pencils adjacent in memory, lane (t, c) with c fastest so that every
+// global access of a wavefront covers C consecutive complex values.
+template <typename R, int N> struct ColShape {
+  static constexpr int T = N / 8;
+  static constexpr int C0 = (sizeof(R) == 4) ? 16 : 8;
+  static constexpr int C = (C0 * T > 1024) ? 1024 / T : C0;
+  static constexpr int THREADS = C * T;
+};
+
+#define PW_DISPATCH_N(FN, R, ...)                                                                  \
+  switch (N) {                                                                                     \
+    case 16: FN<R, 16>(__VA_ARGS__); break;                                                        \
+    case 32: FN<R, 32>(__VA_ARGS__); break;                                                        \
+    case 64: FN<R, 64>(__VA_ARGS__); break;                                                        \
+    case 128: FN<R, 128>(__VA_ARGS__); break;                                                      \
+    case 256: FN<R, 256>(__VA_ARGS__); break;                                                      \
+    case 512: FN<R, 512>(__VA_ARGS__); break;                                                      \
+    default: break;                                                                                \
+  }
+
 // ---------------------------------------------------------------------------------------
 // Real spherical harmonics y_J^mu(u) of a unit vector u, by the Cartesian recurrences
 //   Qt_m^m = 1, Qt_{m+1}^m = (2m+1) z, Qt_l^m = a_lm z Qt_{l-1}^m - b_lm Qt_{l-2}^m,
@@ -190,6 +217,71 @@ __device__ __forceinline__ void real_sh_pair(const ShConst &c, int J, int m, R x
   *yp = n * cr;
   *ym = n * ci;
 }
+
+// Recurrence state for the eight elements a lane holds, carried across a sequence of
+// harmonics (J, m) visited in order of m, then J: (x + i y)^m in (cr, ci) and Qt_J^m,
+// Qt_{J-1}^m in (q0, q1).  After set_m(m); advance(J) the harmonic of element s is
+// sh_n(J, m) * q0[s] * {cr[s], ci[s]}.  Any order is valid; a decreasing m or J restarts.
+template <typename R>
+struct ShRec8 {
+  R cr[8], ci[8], q0[8], q1[8];
+  int m_cur, J_cur;
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) { cr[s] = 1; ci[s] = 0; q0[s] = 1; q1[s] = 0; }
+    m_cur = 0;
+    J_cur = 0;
+  }
+  __device__ __forceinline__ void set_m(int m, const R *ux, const R *uy) {
+    if (m == m_cur + 1) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const R tr = cr[s] * ux[s] - ci[s] * uy[s];
+        ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
+        cr[s] = tr;
+      }
+    } else if (m != m_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        cr[s] = 1; ci[s] = 0;
+        for (int i = 0; i < m; ++i) {
+          const R tr = cr[s] * ux[s] - ci[s] * uy[s];
+          ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
+          cr[s] = tr;
+        }
+      }
+    }
+    if (m != m_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) { q0[s] = 1; q1[s] = 0; }
+      m_cur = m;
+      J_cur = m;
+    }
+  }
+  __device__ __forceinline__ void advance(const ShConst &c, int Jt, const R *uz) {
+    if (Jt < J_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) { q0[s] = 1; q1[s] = 0; }
+      J_cur = m_cur;
+    }
+    while (J_cur < Jt) {
+      ++J_cur;
+      if (J_cur == m_cur + 1) {
+        const R c1 = (R)(2 * m_cur + 1);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) { q1[s] = q0[s]; q0[s] = c1 * uz[s] * q0[s]; }
+      } else {
+        const R a = sh_a<R>(c, J_cur, m_cur), b = sh_b<R>(c, J_cur, m_cur);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const R qn = a * uz[s] * q0[s] - b * q1[s];
+          q1[s] = q0[s];
+          q0[s] = qn;
+        }
+      }
+    }
+  }
+};
 
 // All y_l^nu for even l <= LMAX (index sh_index(l, nu) - compact even-l layout given by
 // the caller through out[l*l + l + nu] with odd l left untouched).

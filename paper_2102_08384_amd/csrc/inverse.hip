@@ -1,0 +1,447 @@
+// HIP kernels of the inverse-transform paths (gfx950, wave64).
+//
+//   iz             inverse FFT along z of full pencil-major spectra, with the midpoint product
+//                  conj(D) Q / W^2 (Section 3.2, g fields) fused in front; output pruned to the
+//                  retained z planes
+//   ix             complex-to-real inverse FFT along x of field pairs; either stores the real
+//                  fields or, for xi_l, weights them by |D|^alpha y_J^mu(D^) times the per-field
+//                  multipole coefficient and bins the sums into r-shells in FP64
+//                  (Section 4.3 midpoint estimator, Section 6 bisector estimator)
+//   contract_mid   midpoint P_l contraction sum_nu y_l^nu(k^) Re[G + A] (Section 3.3 boxed
+//                  estimator in the real-harmonic basis) with FP64 shell sums
+//   finalize_xi    xi_l = (4 pi / I) sum / (N_a H^3)
+#include "kernels.h"
+
+#include "dev_core.h"
+
+namespace pw {
+
+__constant__ ShConst c_sh_inv;
+
+void upload_sh_const_inverse(const ShConst &c) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sh_inv), &c, sizeof(ShConst));
+}
+
+// ------------------------------------------------------------------------------ iz
+template <typename R, int N>
+__global__ void __launch_bounds__((ColShape<R, N>::THREADS))
+k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int n_inplace, int64_t npen,
+     int nkx, const cplx<R> *D, R d_scale, const R *__restrict__ winv, const int *__restrict__ zrank, int nz,
+     const cplx<R> *__restrict__ tw) {
+  constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
+  constexpr int LOGN = log2i(N);
+  __shared__ cplx<R> lds[N * (C + 1)];
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t q0 = (int64_t)blockIdx.x * C;
+  const int64_t q = q0 + c;
+  const int64_t left = npen - q0;
+  const int nval = (int)((left < C ? left : C) * N);  // valid values of this block's chunk
+  auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
+  auto sync = []() { __syncthreads(); };
+  const size_t fstride = (size_t)npen * N;
+  // the chunk of pencils q0 .. q0 + C - 1 is contiguous: element e = cc * N + kz
+  auto load_chunk = [&](const cplx<R> *src) {
+    for (int e = threadIdx.x; e < C * N; e += NT) {
+      const int cc = e >> LOGN, kz = e & (N - 1);
+      lds[kz * (C + 1) + cc] = (e < nval) ? src[(size_t)q0 * N + e] : mk<R>(0, 0);
+    }
+  };
+  cplx<R> dv[8];
+  if (D) {
+    load_chunk(D);
+    sync();
+    R iwxy = (R)1;
+    if (winv && q < npen) {
+      const int ky = (int)(q / nkx), kx = (int)(q - (int64_t)ky * nkx);
+      iwxy = winv[kx] * winv[ky];
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int kz = t + s * T;
+      R f = d_scale;
+      if (winv) {
+        const R iw = iwxy * winv[kz];
+        f *= iw * iw;
+      }
+      const cplx<R> d = at(kz);
+      dv[s] = mk<R>(d.x * f, -d.y * f);
+    }
+    sync();
+  }
+  for (int p = 0; p < nfields; ++p) {
+    if (in_real) {
+      const R *src = in_real + (size_t)p * fstride;
+      for (int e = threadIdx.x; e < C * N; e += NT) {
+        const int cc = e >> LOGN, kz = e & (N - 1);
+        lds[kz * (C + 1) + cc] = mk<R>((e < nval) ? src[(size_t)q0 * N + e] : (R)0, (R)0);
+      }
+    } else {
+      load_chunk(in + (size_t)p * fstride);
+    }
+    sync();
+    cplx<R> v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = at(t + s * T);
+    if (D) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) v[s] = cmul(dv[s], v[s]);
+    }
+    sync();
+    if (p < n_inplace) {
+      // the product stays in k-space: store it back in place, coalesced through LDS
+#pragma unroll
+      for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
+      sync();
+      cplx<R> *dst = in + (size_t)p * fstride;
+      for (int e = threadIdx.x; e < nval; e += NT) {
+        const int cc = e >> LOGN, kz = e & (N - 1);
+        dst[(size_t)q0 * N + e] = lds[kz * (C + 1) + cc];
+      }
+      sync();
+      continue;
+    }
+    fft_pencil<R, N, true>(v, t, tw, at, sync);
+    if (q < npen) {
+      cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * npen;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int zr = zrank[t + s * T];
+        if (zr >= 0) dst[(size_t)zr * npen + q] = v[s];
+      }
+    }
+  }
+}
+
+template <typename R, int N>
+static void iz_launch(hipStream_t s, void *in, void *out, int nfields, int n_inplace, int real_in, int64_t npen,
+                      int nkx, const void *D, double d_scale, const void *winv, const int *zrank, int nz,
+                      const void *tw) {
+  constexpr int C = ColShape<R, N>::C;
+  dim3 grid((unsigned)((npen + C - 1) / C));
+  hipLaunchKernelGGL((k_iz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s,
+                     real_in ? (cplx<R> *)nullptr : (cplx<R> *)in, real_in ? (const R *)in : (const R *)nullptr,
+                     (cplx<R> *)out, nfields, n_inplace, npen, nkx, (const cplx<R> *)D, (R)d_scale,
+                     (const R *)winv, zrank, nz, (const cplx<R> *)tw);
+}
+
+void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields, int n_inplace, int real_in,
+               int64_t npen, int nkx, const void *D, double d_scale, const void *winv, const int *zrank, int nz,
+               const void *tw) {
+  if (nfields <= 0 || npen <= 0) return;
+  if (prec == 0) {
+    PW_DISPATCH_N(iz_launch, float, s, in, out, nfields, n_inplace, real_in, npen, nkx, D, d_scale, winv, zrank,
+                  nz, tw)
+  } else {
+    PW_DISPATCH_N(iz_launch, double, s, in, out, nfields, n_inplace, real_in, npen, nkx, D, d_scale, winv,
+                  zrank, nz, tw)
+  }
+}
+
+// ------------------------------------------------------------------------------ ix
+constexpr int kMaxEll = 5;  // multipoles 0, 2, .., 8
+
+template <typename R, int N, int MODE>
+__global__ void __launch_bounds__(FxShape<N>::THREADS)
+k_ix(const cplx<R> *__restrict__ in, R *__restrict__ out, const FieldJob *__restrict__ jobs, int njobs,
+     const R *__restrict__ coef, int nell, int nz, int ny, const int *__restrict__ zidx,
+     const int *__restrict__ yidx, R Hu, double Hd, R scale, const int *__restrict__ bin_of_s2, int64_t n_s2,
+     int nbins, double *__restrict__ acc, const cplx<R> *__restrict__ tw) {
+  constexpr int T = FxShape<N>::T, ROWS = FxShape<N>::ROWS, NKX = N / 2 + 1;
+  constexpr int LN = N + N / 8;
+  __shared__ cplx<R> lds[ROWS * LN];
+  extern __shared__ double bacc[];  // mode 1: (nell + 2) * nbins
+  const int rl = threadIdx.x / T, t = threadIdx.x % T;
+  const int64_t nrows = (int64_t)nz * ny;
+  const int64_t row = (int64_t)blockIdx.x * ROWS + rl;
+  const bool live = row < nrows;
+  const int zr = live ? (int)(row / ny) : 0, yr = live ? (int)(row - (int64_t)zr * ny) : 0;
+  const int z = zidx[zr], y = yidx[yr];
+  cplx<R> *my = lds + rl * LN;
+  auto at = [my](int i) -> cplx<R> & { return my[i + (i >> 3)]; };
+  auto sync = []() { __syncthreads(); };
+  const int sy = y < N / 2 ? y : y - N, sz = z < N / 2 ? z : z - N;
+
+  // mode 1 geometry of the eight cells this lane holds
+  R ux[8], uy[8], uz[8], dm[8];
+  int bin[8];
+  R X[kMaxEll][8];
+  if constexpr (MODE == 1) {
+    const int nacc = (nell + 2) * nbins;
+    for (int i = threadIdx.x; i < nacc; i += blockDim.x) bacc[i] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int x = t + s * T;
+      const int sx = x < N / 2 ? x : x - N;
+      const int64_t s2 = (int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz;
+      bin[s] = (live && s2 < n_s2) ? bin_of_s2[s2] : -1;
+      dm[s] = Hu * sqrt((R)s2);  // |D| / unit
+      if (s2 > 0) {
+        const R ir = (R)1 / sqrt((R)s2);
+        ux[s] = (R)sx * ir; uy[s] = (R)sy * ir; uz[s] = (R)sz * ir;
+      } else {
+        ux[s] = 0; uy[s] = 0; uz[s] = 1;
+      }
+#pragma unroll
+      for (int l = 0; l < kMaxEll; ++l) X[l][s] = 0;
+    }
+  }
+  ShRec8<R> rec;
+  rec.init();
+  const size_t fstride = (size_t)nrows * NKX;
+  for (int jb = 0; jb < njobs; ++jb) {
+    const FieldJob J = jobs[jb];
+    const cplx<R> *ha = in + (size_t)J.pa * fstride + (size_t)row * NKX;
+    const cplx<R> *hb = in + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * NKX;
+    // Z = Ha + i Hb on the full x range from the half spectra (Ha(-k) = conj Ha(k) after the
+    // y and z inverse passes of a real field); the self-conjugate kx = 0, N/2 keep real parts.
+    for (int kx = t; kx < NKX; kx += T) {
+      const cplx<R> a = live ? ha[kx] : mk<R>(0, 0);
+      const cplx<R> b = (live && J.pb >= 0) ? hb[kx] : mk<R>(0, 0);
+      if (kx == 0 || kx == N / 2) {
+        at(kx) = mk<R>(a.x, b.x);
+      } else {
+        at(kx) = mk<R>(a.x - b.y, a.y + b.x);
+        at(N - kx) = mk<R>(a.x + b.y, b.x - a.y);
+      }
+    }
+    sync();
+    cplx<R> v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = at(t + s * T);
+    sync();
+    fft_pencil<R, N, true>(v, t, tw, at, sync);
+    if constexpr (MODE == 0) {
+      if (live) {
+        R *oa = out + (size_t)J.pa * N * N * N + ((size_t)z * N + y) * N;
+        R *ob = out + (size_t)(J.pb < 0 ? 0 : J.pb) * N * N * N + ((size_t)z * N + y) * N;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          oa[t + s * T] = v[s].x * scale;
+          if (J.pb >= 0) ob[t + s * T] = v[s].y * scale;
+        }
+      }
+    } else {
+      R ya[8], yb[8];
+      if (J.kind == 0) {
+        rec.set_m(J.m, ux, uy);
+        rec.advance(c_sh_inv, J.Ja, uz);
+        const R n = sh_n<R>(c_sh_inv, J.Ja, J.m);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          R w = n * rec.q0[s];
+          for (int a = 0; a < J.alpha; ++a) w *= dm[s];
+          ya[s] = w * rec.cr[s];
+          yb[s] = w * rec.ci[s];
+        }
+      } else {
+        rec.set_m(0, ux, uy);
+        rec.advance(c_sh_inv, J.Ja, uz);
+        const R na = sh_n<R>(c_sh_inv, J.Ja, 0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          R w = na * rec.q0[s];
+          for (int a = 0; a < J.alpha; ++a) w *= dm[s];
+          ya[s] = w;
+          yb[s] = 0;
+        }
+        if (J.Jb >= 0) {
+          rec.advance(c_sh_inv, J.Jb, uz);
+          const R nb = sh_n<R>(c_sh_inv, J.Jb, 0);
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            R w = nb * rec.q0[s];
+            for (int a = 0; a < J.alpha_b; ++a) w *= dm[s];
+            yb[s] = w;
+          }
+        }
+      }
+      const R *ca = coef + (size_t)jb * 2 * nell, *cb = ca + nell;
+#pragma unroll
+      for (int l = 0; l < kMaxEll; ++l) {
+        if (l < nell) {
+          const R fa = ca[l], fb = cb[l];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) X[l][s] += fa * ya[s] * v[s].x + fb * yb[s] * v[s].y;
+        }
+      }
+    }
+  }
+  if constexpr (MODE == 1) {
+    sync();  // bacc cleared by every thread before any accumulation
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int b = bin[s];
+      if (b < 0) continue;
+      const int x = t + s * T;
+      const int sx = x < N / 2 ? x : x - N;
+      const double s2 = (double)sx * sx + (double)sy * sy + (double)sz * sz;
+#pragma unroll
+      for (int l = 0; l < kMaxEll; ++l)
+        if (l < nell) atomicAdd(&bacc[l * nbins + b], (double)(X[l][s] * scale));
+      atomicAdd(&bacc[nell * nbins + b], 1.0);
+      atomicAdd(&bacc[(nell + 1) * nbins + b], Hd * sqrt(s2));
+    }
+    sync();
+    const int nacc = (nell + 2) * nbins;
+    for (int i = threadIdx.x; i < nacc; i += blockDim.x)
+      if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
+  }
+}
+
+template <typename R, int N>
+static void ix_launch(hipStream_t s, int mode, const void *in, void *out, const FieldJob *jobs, int njobs,
+                      const void *coef, int nell, int nz, int ny, const int *zidx, const int *yidx, double H,
+                      double unit, double scale, const int *bin_of_s2, int64_t n_s2, int nbins, double *acc,
+                      const void *tw) {
+  constexpr int ROWS = FxShape<N>::ROWS;
+  const int64_t nrows = (int64_t)nz * ny;
+  dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS));
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_ix<R, N, 0>), grid, dim3(FxShape<N>::THREADS), 0, s, (const cplx<R> *)in, (R *)out,
+                       jobs, njobs, (const R *)coef, nell, nz, ny, zidx, yidx, (R)(H / unit), H, (R)scale, bin_of_s2,
+                       n_s2, nbins, acc, (const cplx<R> *)tw);
+  } else {
+    size_t sh = (size_t)(nell + 2) * nbins * sizeof(double);
+    hipLaunchKernelGGL((k_ix<R, N, 1>), grid, dim3(FxShape<N>::THREADS), sh, s, (const cplx<R> *)in, (R *)out,
+                       jobs, njobs, (const R *)coef, nell, nz, ny, zidx, yidx, (R)(H / unit), H, (R)scale, bin_of_s2,
+                       n_s2, nbins, acc, (const cplx<R> *)tw);
+  }
+}
+
+void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *out, const FieldJob *jobs,
+               int njobs, const void *coef, int nell, int nz, int ny, const int *zidx, const int *yidx, double H,
+               double unit, double scale, const int *bin_of_s2, int64_t n_s2, int nbins, double *acc,
+               const void *tw) {
+  if (njobs <= 0 || nz <= 0 || ny <= 0 || nell > kMaxEll) return;
+  if (prec == 0) {
+    PW_DISPATCH_N(ix_launch, float, s, mode, in, out, jobs, njobs, coef, nell, nz, ny, zidx, yidx, H, unit, scale,
+                  bin_of_s2, n_s2, nbins, acc, tw)
+  } else {
+    PW_DISPATCH_N(ix_launch, double, s, mode, in, out, jobs, njobs, coef, nell, nz, ny, zidx, yidx, H, unit, scale,
+                  bin_of_s2, n_s2, nbins, acc, tw)
+  }
+}
+
+// ------------------------------------------------------------------------------ contract_mid
+// One thread per retained mode of the half spectrum; a mode with 0 < kx < N/2 also stands for
+// its mirror (conjugate values, same real parts) whose direction is that of (-n) mod N.
+template <typename R, int LMAX>
+__global__ void __launch_bounds__(256)
+k_contract_mid(const cplx<R> *__restrict__ G, int nkx_full, const cplx<R> *__restrict__ A, int64_t nmodes,
+               const uint32_t *__restrict__ modecoord, int N, const int *__restrict__ bin_of_s2, int64_t n_s2,
+               int nbins, double kf, double *__restrict__ acc) {
+  constexpr int NSH = (LMAX + 1) * (LMAX + 1);
+  constexpr int NE = LMAX / 2 + 1;
+  extern __shared__ double bacc[];
+  const int nacc = (NE + 2) * nbins;
+  for (int i = threadIdx.x; i < nacc; i += blockDim.x) bacc[i] = 0.0;
+  __syncthreads();
+  const int half = N / 2;
+  const size_t gstride = (size_t)N * nkx_full * N;
+  for (int64_t mode = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mode < nmodes;
+       mode += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t mc = modecoord[mode];
+    const int kx = mc & 0x7ff, ky = (mc >> 11) & 0x7ff, kz = (mc >> 22) & 0x3ff;
+    const int sx = (kx == half) ? -half : kx;
+    const int sy = (ky < half) ? ky : ky - N;
+    const int sz = (kz < half) ? kz : kz - N;
+    const int64_t s2 = (int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz;
+    const int b = (s2 < n_s2) ? bin_of_s2[s2] : -1;
+    if (b < 0) continue;
+    const bool pair = (kx != 0 && kx != half);
+    R wdir[NSH];
+#pragma unroll
+    for (int i = 0; i < NSH; ++i) wdir[i] = 0;
+    {
+      R ux = 0, uy = 0, uz = 1;
+      const R ir = s2 > 0 ? (R)1 / sqrt((R)s2) : (R)0;
+      if (s2 > 0) { ux = (R)sx * ir; uy = (R)sy * ir; uz = (R)sz * ir; }
+      real_sh_even<R, LMAX>(c_sh_inv, ux, uy, uz, wdir);
+      if (pair) {
+        const int my = (ky == half) ? sy : -sy;
+        const int mz = (kz == half) ? sz : -sz;
+        R wm[NSH];
+#pragma unroll
+        for (int i = 0; i < NSH; ++i) wm[i] = 0;
+        real_sh_even<R, LMAX>(c_sh_inv, (R)(-sx) * ir, (R)my * ir, (R)mz * ir, wm);
+#pragma unroll
+        for (int i = 0; i < NSH; ++i) wdir[i] += wm[i];
+      }
+    }
+    const size_t gi = ((size_t)ky * nkx_full + kx) * N + kz;
+    R E[NE];
+#pragma unroll
+    for (int l = 0, o = 0; l <= LMAX; l += 2) {
+      R e = 0;
+#pragma unroll
+      for (int nu = -l; nu <= l; ++nu, ++o) {
+        R v = G[(size_t)o * gstride + gi].x;
+        if (l >= 2 && A) v += A[(size_t)(o - 1) * nmodes + mode].x;
+        e += wdir[l * l + l + nu] * v;
+      }
+      E[l / 2] = e;
+    }
+    const double mult = pair ? 2.0 : 1.0;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) atomicAdd(&bacc[i * nbins + b], (double)E[i]);
+    atomicAdd(&bacc[NE * nbins + b], mult);
+    atomicAdd(&bacc[(NE + 1) * nbins + b], mult * kf * sqrt((double)s2));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nacc; i += blockDim.x)
+    if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
+}
+
+void launch_contract_mid(hipStream_t s, int prec, int lmax, const void *G, int nkx_full, const void *A,
+                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
+                         int nbins, double kf, double *acc) {
+  if (nmodes <= 0) return;
+  int64_t want = (nmodes + 255) / 256;
+  unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+  size_t sh = (size_t)(lmax / 2 + 3) * nbins * sizeof(double);
+#define PW_CM(R, L)                                                                                \
+  hipLaunchKernelGGL((k_contract_mid<R, L>), dim3(blocks), dim3(256), sh, s, (const cplx<R> *)G, nkx_full, \
+                     (const cplx<R> *)A, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf, acc);
+  if (prec == 0) {
+    switch (lmax) {
+      case 0: PW_CM(float, 0) break;
+      case 2: PW_CM(float, 2) break;
+      case 4: PW_CM(float, 4) break;
+      case 6: PW_CM(float, 6) break;
+      default: PW_CM(float, 8) break;
+    }
+  } else {
+    switch (lmax) {
+      case 0: PW_CM(double, 0) break;
+      case 2: PW_CM(double, 2) break;
+      case 4: PW_CM(double, 4) break;
+      case 6: PW_CM(double, 6) break;
+      default: PW_CM(double, 8) break;
+    }
+  }
+#undef PW_CM
+}
+
+// ------------------------------------------------------------------------------ finalize_xi
+__global__ void k_finalize_xi(const double *acc, int nell, int nbins, double cell_volume, const DevNorm *norm,
+                              double *out) {
+  const double fourpi = 12.566370614359172953850573533118;
+  const double I = norm->I;
+  for (int i = threadIdx.x; i < (nell + 1) * nbins; i += blockDim.x) {
+    const int l = i / nbins, b = i % nbins;
+    const double cnt = acc[nell * nbins + b];
+    if (l < nell) {
+      out[l * nbins + b] = (cnt > 0) ? fourpi / I * acc[l * nbins + b] / (cnt * cell_volume) : 0.0;
+    } else {
+      out[nell * nbins + b] = (cnt > 0) ? acc[(nell + 1) * nbins + b] / cnt : 0.0;  // mean |D|
+      out[(nell + 1) * nbins + b] = cnt;
+    }
+  }
+}
+
+void launch_finalize_xi(hipStream_t s, const double *acc, int nell, int nbins, double cell_volume,
+                        const DevNorm *norm, double *out) {
+  hipLaunchKernelGGL(k_finalize_xi, dim3(1), dim3(256), 0, s, acc, nell, nbins, cell_volume, norm, out);
+}
+
+}  // namespace pw

@@ -29,7 +29,9 @@ struct DevNorm {
 // kind 0: fields (J, +m) and (J, -m), m > 0, of weight (2r)^-alpha;  pa / pb their indices.
 // kind 1: fields (Ja, 0) of weight (2r)^-alpha and (Jb, 0) of weight (2r)^-alpha_b
 //         (Jb < 0: single field, pb < 0).
+// kind 2: no weighting: real input fields Ja and Jb (Jb < 0: none) of a field stack.
 // Jobs must be sorted by m, then by J (the x pass carries its recurrences across jobs).
+// The inverse x pass reads the same records with |D|^alpha y(D^) in place of (2r)^-alpha y(x^).
 struct FieldJob {
   int alpha, kind, Ja, m, Jb, pa, pb, alpha_b;
 };
@@ -39,6 +41,8 @@ struct PencilInfo {   // a retained (kx, ky) pencil of the z pass
 };
 
 void upload_sh_const(const ShConst &c);
+void upload_sh_const_inverse(const ShConst &c);
+void upload_sh_const_generated(const ShConst &c);
 
 void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n, int dtype,
                     double *partial);
@@ -65,12 +69,15 @@ void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, 
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
                        const void *records, const DevNorm *norm, void *blocks, void *mesh);
 
-// Fused weighting + r2c along x: out[p][z][y][kx], kx < nkx.
+// Fused weighting + r2c along x: out[p][z][y][kx], kx < nkx.  Radial weights are taken in the
+// length unit `unit`: (unit / 2r)^alpha (the inverse passes use (|D| / unit)^alpha, so every
+// product (2r)^-alpha |D|^alpha is unchanged while fields of every alpha stay O(1)).
 void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
-               int njobs, int nkx, const double *b0, double H, const void *tw);
-// c2c along y, pruned: out[p][z][yoff[ky] + kx] for kx < ycnt[ky].
-void launch_fy(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int nkx,
-               const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw);
+               int njobs, int nkx, const double *b0, double H, double unit, const void *tw);
+// c2c along y (forward, or inverse when inv), on nplanes planes per field:
+// in[p][plane][y][kx] -> out[p][plane][yoff[y'] + kx] for kx < ycnt[y'] (y' the output index).
+void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields,
+               int nplanes, int nkx, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw);
 // c2c along z, pruned: out[p][moff[q] + j], j < pinfo[q].kzcnt.
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
                int64_t npen, const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes,
@@ -90,6 +97,50 @@ void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                          const void *winv, double *acc);
 void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, const int *ells,
+                        const DevNorm *norm, double *out);
+
+// Register-resident bisector contraction when its coupling is generated; false otherwise.
+bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
+                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
+                                   int nbins, double kf, const void *winv, double *acc);
+// Which (ell_max, beta_max) / (ell_max, order) have build-time generated couplings.
+bool bis_contract_generated(int lmax, int bmax);
+bool mid_reweight_generated(int lmax, int order);
+// Number of g fields the generated re-weighting reads (-1: not generated).
+int mid_reweight_nfields(int lmax, int order);
+
+// ---- inverse path (inverse.hip) ----
+// Inverse z pass over full pencil-major spectra in[p][q * N + kz] (q = ky * nkx + kx):
+//   D != null: Z = conj(d_scale * D) * in / W(k)^2 (D is read before anything is written);
+//   fields p < n_inplace get Z written back in place and are not transformed;
+//   real_in: the input holds real values (imaginary part zero).
+// Other fields: inverse FFT along z, out[p - n_inplace][zrank[z]][q] for retained z.
+void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields, int n_inplace,
+               int real_in, int64_t npen, int nkx, const void *D, double d_scale, const void *winv,
+               const int *zrank, int nz, const void *tw);
+// Inverse x pass (complex-to-real) of pair jobs on the rows (zr, yr) of in[p][zr][yr][kx],
+// kx <= N/2, scaled by `scale`.
+//   mode 0: out[p][z][y][x] real fields (nz = ny = N).
+//   mode 1: X_l += coef[j][side][l] (|D| / unit)^alpha y_J^mu(D^) h, then FP64 r-binning of
+//           X_l into acc[l][b], acc[nell][b] (count), acc[nell + 1][b] (sum |D|).
+void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *out,
+               const FieldJob *jobs, int njobs, const void *coef, int nell, int nz, int ny,
+               const int *zidx, const int *yidx, double H, double unit, double scale, const int *bin_of_s2,
+               int64_t n_s2, int nbins, double *acc, const void *tw);
+// Midpoint real-space re-weighting: A_{l nu}(D) from the alpha > 0 g fields (generated),
+// with |D| in the length unit of the forward weights (Hu = H / unit).
+void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, const void *g, void *A, double Hu);
+// Bisector xi targets: T[t][i] = sum S Re(conj(R_p1) R_p2) / W(k)^2 over the full
+// pencil-major spectra (i = q * N + kz), written as real values (generated couplings).
+void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const void *spec, int64_t nmodes,
+                    int nkx, const void *winv, void *T);
+// Midpoint P contraction: E_l = sum_nu y_l^nu(k^) Re[G_{l nu}(k) + A_{l nu}(k)] on the k-sphere
+// modes; G: full pencil-major products (alpha = 0 fields, index even_index(l, nu)); A: pruned
+// spectra of the A fields (l >= 2, index even_index(l, nu) - 1; null when absent).
+void launch_contract_mid(hipStream_t s, int prec, int lmax, const void *G, int nkx_full, const void *A,
+                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
+                         int64_t n_s2, int nbins, double kf, double *acc);
+void launch_finalize_xi(hipStream_t s, const double *acc, int nell, int nbins, double cell_volume,
                         const DevNorm *norm, double *out);
 
 }  // namespace pw

@@ -17,19 +17,15 @@ __constant__ ShConst c_sh;
 
 void upload_sh_const(const ShConst &c) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sh), &c, sizeof(ShConst));
+  upload_sh_const_inverse(c);
+  upload_sh_const_generated(c);
 }
 
 // ------------------------------------------------------------------------------ fx
-template <int N> struct FxShape {
-  static constexpr int T = N / 8;                          // lanes per pencil
-  static constexpr int ROWS = (T >= 64) ? (256 / T > 0 ? 256 / T : 1) : 64 / T * 2;
-  static constexpr int THREADS = ROWS * T;
-};
-
 template <typename R, int N>
 __global__ void __launch_bounds__(FxShape<N>::THREADS)
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
-     int njobs, int nkx, R b0x, R b0y, R b0z, R H, const cplx<R> *__restrict__ tw) {
+     int njobs, int nkx, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw) {
   constexpr int T = FxShape<N>::T, ROWS = FxShape<N>::ROWS;
   constexpr int LN = N + N / 8;
   __shared__ cplx<R> lds[ROWS * LN];
@@ -51,97 +47,54 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
     if (r > (R)0) {
       const R ir = (R)1 / r;
       ux[s] = px * ir; uy[s] = py * ir; uz[s] = pz * ir;
-      inv2r[s] = (R)0.5 * ir;
+      inv2r[s] = uhalf * ir;  // u / (2r): lengths in the unit u
     } else {
       ux[s] = 0; uy[s] = 0; uz[s] = 1;
       inv2r[s] = 0;
     }
   }
   const size_t fstride = (size_t)N * N * nkx;
-  // Recurrence state carried across jobs (jobs come sorted by m, then J): (x + i y)^m and
-  // Qt_J^m, Qt_{J-1}^m of the eight elements this lane holds.
-  R cr[8], ci[8], q0[8], q1[8];
-  int m_cur = 0, J_cur = 0;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) { cr[s] = 1; ci[s] = 0; q0[s] = 1; q1[s] = 0; }
-  auto set_m = [&](int m) {
-    if (m == m_cur + 1) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const R tr = cr[s] * ux[s] - ci[s] * uy[s];
-        ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
-        cr[s] = tr;
-      }
-    } else if (m != m_cur) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        cr[s] = 1; ci[s] = 0;
-        for (int i = 0; i < m; ++i) {
-          const R tr = cr[s] * ux[s] - ci[s] * uy[s];
-          ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
-          cr[s] = tr;
-        }
-      }
-    }
-    if (m != m_cur) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) { q0[s] = 1; q1[s] = 0; }
-      m_cur = m;
-      J_cur = m;
-    }
-  };
-  auto advance = [&](int Jt) {
-    if (Jt < J_cur) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) { q0[s] = 1; q1[s] = 0; }
-      J_cur = m_cur;
-    }
-    while (J_cur < Jt) {
-      ++J_cur;
-      if (J_cur == m_cur + 1) {
-        const R c1 = (R)(2 * m_cur + 1);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) { q1[s] = q0[s]; q0[s] = c1 * uz[s] * q0[s]; }
-      } else {
-        const R a = sh_a<R>(c_sh, J_cur, m_cur), b = sh_b<R>(c_sh, J_cur, m_cur);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const R qn = a * uz[s] * q0[s] - b * q1[s];
-          q1[s] = q0[s];
-          q0[s] = qn;
-        }
-      }
-    }
-  };
+  // Recurrence state carried across jobs (jobs come sorted by m, then J).
+  ShRec8<R> rec;
+  rec.init();
   for (int jb = 0; jb < njobs; ++jb) {
     const FieldJob J = jobs[jb];
     cplx<R> v[8];
-    R wa[8], wb[8];
+    if (J.kind == 2) {
+      // plain pair of real input fields of the stack at `mesh`
+      const R *fa = mesh + (size_t)J.Ja * N * N * N + (size_t)row * N;
+      const R *fb = mesh + (size_t)(J.Jb < 0 ? 0 : J.Jb) * N * N * N + (size_t)row * N;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      R p = f[s], pb = f[s];
-      for (int a = 0; a < J.alpha; ++a) p *= inv2r[s];
-      for (int a = 0; a < J.alpha_b; ++a) pb *= inv2r[s];
-      wa[s] = p;
-      wb[s] = pb;
-    }
-    if (J.kind == 0) {
-      set_m(J.m);
-      advance(J.Ja);
-      const R n = sh_n<R>(c_sh, J.Ja, J.m);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) v[s] = mk<R>(wa[s] * n * q0[s] * cr[s], wa[s] * n * q0[s] * ci[s]);
+      for (int s = 0; s < 8; ++s) v[s] = mk<R>(fa[t + s * T], J.Jb >= 0 ? fb[t + s * T] : (R)0);
     } else {
-      set_m(0);
-      advance(J.Ja);
-      const R na = sh_n<R>(c_sh, J.Ja, 0);
+      R wa[8], wb[8];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) v[s] = mk<R>(wa[s] * na * q0[s], (R)0);
-      if (J.Jb >= 0) {
-        advance(J.Jb);
-        const R nb = sh_n<R>(c_sh, J.Jb, 0);
+      for (int s = 0; s < 8; ++s) {
+        R p = f[s], pb = f[s];
+        for (int a = 0; a < J.alpha; ++a) p *= inv2r[s];
+        for (int a = 0; a < J.alpha_b; ++a) pb *= inv2r[s];
+        wa[s] = p;
+        wb[s] = pb;
+      }
+      if (J.kind == 0) {
+        rec.set_m(J.m, ux, uy);
+        rec.advance(c_sh, J.Ja, uz);
+        const R n = sh_n<R>(c_sh, J.Ja, J.m);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v[s].y = wb[s] * nb * q0[s];
+        for (int s = 0; s < 8; ++s)
+          v[s] = mk<R>(wa[s] * n * rec.q0[s] * rec.cr[s], wa[s] * n * rec.q0[s] * rec.ci[s]);
+      } else {
+        rec.set_m(0, ux, uy);
+        rec.advance(c_sh, J.Ja, uz);
+        const R na = sh_n<R>(c_sh, J.Ja, 0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = mk<R>(wa[s] * na * rec.q0[s], (R)0);
+        if (J.Jb >= 0) {
+          rec.advance(c_sh, J.Jb, uz);
+          const R nb = sh_n<R>(c_sh, J.Jb, 0);
+#pragma unroll
+          for (int s = 0; s < 8; ++s) v[s].y = wb[s] * nb * rec.q0[s];
+        }
       }
     }
     fft_pencil<R, N, false>(v, t, tw, at, sync);
@@ -162,42 +115,22 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 
 template <typename R, int N>
 static void fx_launch(hipStream_t s, const void *mesh, void *out, const FieldJob *jobs, int njobs,
-                      int nkx, const double *b0, double H, const void *tw) {
+                      int nkx, const double *b0, double H, double unit, const void *tw) {
   constexpr int ROWS = FxShape<N>::ROWS;
   unsigned blocks = (unsigned)((size_t)N * N / ROWS);
   hipLaunchKernelGGL((k_fx<R, N>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
-                     (cplx<R> *)out, jobs, njobs, nkx, (R)b0[0], (R)b0[1], (R)b0[2], (R)H,
+                     (cplx<R> *)out, jobs, njobs, nkx, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
                      (const cplx<R> *)tw);
 }
 
-#define PW_DISPATCH_N(FN, R, ...)                                                                  \
-  switch (N) {                                                                                     \
-    case 16: FN<R, 16>(__VA_ARGS__); break;                                                        \
-    case 32: FN<R, 32>(__VA_ARGS__); break;                                                        \
-    case 64: FN<R, 64>(__VA_ARGS__); break;                                                        \
-    case 128: FN<R, 128>(__VA_ARGS__); break;                                                      \
-    case 256: FN<R, 256>(__VA_ARGS__); break;                                                      \
-    case 512: FN<R, 512>(__VA_ARGS__); break;                                                      \
-    default: break;                                                                                \
-  }
-
 void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
-               int njobs, int nkx, const double *b0, double H, const void *tw) {
-  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, mesh, out, jobs, njobs, nkx, b0, H, tw) }
-  else { PW_DISPATCH_N(fx_launch, double, s, mesh, out, jobs, njobs, nkx, b0, H, tw) }
+               int njobs, int nkx, const double *b0, double H, double unit, const void *tw) {
+  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, mesh, out, jobs, njobs, nkx, b0, H, unit, tw) }
+  else { PW_DISPATCH_N(fx_launch, double, s, mesh, out, jobs, njobs, nkx, b0, H, unit, tw) }
 }
 
 // ------------------------------------------------------------------------------ fy / fz
-// Column-mode pencils: C pencils adjacent in memory, lane (t, c) with c fastest so that every
-// global access of a wavefront covers C consecutive complex values.
-template <typename R, int N> struct ColShape {
-  static constexpr int T = N / 8;
-  static constexpr int C0 = (sizeof(R) == 4) ? 16 : 8;
-  static constexpr int C = (C0 * T > 1024) ? 1024 / T : C0;
-  static constexpr int THREADS = C * T;
-};
-
-template <typename R, int N>
+template <typename R, int N, bool INV>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, const int *__restrict__ ycnt,
      const int64_t *__restrict__ yoff, int64_t npen, const cplx<R> *__restrict__ tw) {
@@ -205,15 +138,15 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, const i
   __shared__ cplx<R> lds[N * (C + 1)];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + c;
-  const int z = blockIdx.y, p = blockIdx.z;
-  const cplx<R> *src = in + ((size_t)p * N + z) * N * nkx;
+  const size_t plane = (size_t)blockIdx.z * gridDim.y + blockIdx.y;  // field * nplanes + plane
+  const cplx<R> *src = in + plane * N * nkx;
   cplx<R> v[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) v[s] = (kx < nkx) ? src[(size_t)(t + s * T) * nkx + kx] : mk<R>(0, 0);
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
-  fft_pencil<R, N, false>(v, t, tw, at, sync);
-  cplx<R> *dst = out + ((size_t)p * N + z) * npen;
+  fft_pencil<R, N, INV>(v, t, tw, at, sync);
+  cplx<R> *dst = out + plane * npen;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int ky = t + s * T;
@@ -222,18 +155,23 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, const i
 }
 
 template <typename R, int N>
-static void fy_launch(hipStream_t s, const void *in, void *out, int nfields, int nkx, const int *ycnt,
-                      const int64_t *yoff, int64_t npen, const void *tw) {
+static void fy_launch(hipStream_t s, int inv, const void *in, void *out, int nfields, int nplanes, int nkx,
+                      const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw) {
   constexpr int C = ColShape<R, N>::C;
-  dim3 grid((nkx + C - 1) / C, N, nfields);
-  hipLaunchKernelGGL((k_fy<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                     (cplx<R> *)out, nkx, ycnt, yoff, npen, (const cplx<R> *)tw);
+  dim3 grid((nkx + C - 1) / C, nplanes, nfields);
+  if (inv)
+    hipLaunchKernelGGL((k_fy<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
+                       (cplx<R> *)out, nkx, ycnt, yoff, npen, (const cplx<R> *)tw);
+  else
+    hipLaunchKernelGGL((k_fy<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
+                       (cplx<R> *)out, nkx, ycnt, yoff, npen, (const cplx<R> *)tw);
 }
 
-void launch_fy(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int nkx,
-               const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw) {
-  if (prec == 0) { PW_DISPATCH_N(fy_launch, float, s, in, out, nfields, nkx, ycnt, yoff, npen, tw) }
-  else { PW_DISPATCH_N(fy_launch, double, s, in, out, nfields, nkx, ycnt, yoff, npen, tw) }
+void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields, int nplanes,
+               int nkx, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw) {
+  if (nfields <= 0 || nplanes <= 0) return;
+  if (prec == 0) { PW_DISPATCH_N(fy_launch, float, s, inv, in, out, nfields, nplanes, nkx, ycnt, yoff, npen, tw) }
+  else { PW_DISPATCH_N(fy_launch, double, s, inv, in, out, nfields, nplanes, nkx, ycnt, yoff, npen, tw) }
 }
 
 template <typename R, int N>
@@ -381,121 +319,13 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
     if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
 }
 
-// Register-resident variant: the coupling for (LMAX, BMAX) is straight-line code generated at
-// build time (BisContract<L, B, R>::run), so all field values of a mode stay in VGPRs.
-template <int L, int B, typename R> struct BisContract {
-  static constexpr bool kGenerated = false;
-};
-#include "contract_gen.inc"
-
-template <typename R, int LMAX, int BMAX>
-__global__ void __launch_bounds__(256)
-k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, const uint32_t *__restrict__ modecoord,
-                   int N, const int *__restrict__ bin_of_s2, int64_t n_s2, int nbins, double kf,
-                   const R *__restrict__ winv, double *__restrict__ acc) {
-  using CT = BisContract<LMAX, BMAX, R>;
-  constexpr int NF = CT::NF;
-  constexpr int NSH = (LMAX + 1) * (LMAX + 1);
-  constexpr int NE = LMAX / 2 + 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *bacc = reinterpret_cast<double *>(smem_raw);
-  const int nacc = (NE + 2) * nbins;
-  for (int i = threadIdx.x; i < nacc; i += blockDim.x) bacc[i] = 0.0;
-  __syncthreads();
-  const int half = N / 2;
-  for (int64_t mode = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mode < nmodes;
-       mode += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t mc = modecoord[mode];
-    const int kx = mc & 0x7ff, ky = (mc >> 11) & 0x7ff, kz = (mc >> 22) & 0x3ff;
-    const int sx = (kx == half) ? -half : kx;
-    const int sy = (ky < half) ? ky : ky - N;
-    const int sz = (kz < half) ? kz : kz - N;
-    const int64_t s2 = (int64_t)sx * sx + (int64_t)sy * sy + (int64_t)sz * sz;
-    const int b = (s2 < n_s2) ? bin_of_s2[s2] : -1;
-    if (b < 0) continue;
-    cplx<R> a[NF];
-#pragma unroll
-    for (int p = 0; p < NF; ++p) a[p] = spec[(size_t)p * nmodes + mode];
-    const bool pair = (kx != 0 && kx != half);
-    R wdir[NSH];
-#pragma unroll
-    for (int i = 0; i < NSH; ++i) wdir[i] = 0;
-    {
-      R ux = 0, uy = 0, uz = 1;
-      const R ir = s2 > 0 ? (R)1 / sqrt((R)s2) : (R)0;
-      if (s2 > 0) { ux = (R)sx * ir; uy = (R)sy * ir; uz = (R)sz * ir; }
-      real_sh_even<R, LMAX>(c_sh, ux, uy, uz, wdir);
-      if (pair) {
-        const int my = (ky == half) ? sy : -sy;
-        const int mz = (kz == half) ? sz : -sz;
-        R wm[NSH];
-#pragma unroll
-        for (int i = 0; i < NSH; ++i) wm[i] = 0;
-        real_sh_even<R, LMAX>(c_sh, (R)(-sx) * ir, (R)my * ir, (R)mz * ir, wm);
-#pragma unroll
-        for (int i = 0; i < NSH; ++i) wdir[i] += wm[i];
-      }
-    }
-    R E[NE];
-#pragma unroll
-    for (int i = 0; i < NE; ++i) E[i] = 0;
-    CT::run(a, wdir, E);
-    if (winv) {
-      const R iw = winv[kx] * winv[ky] * winv[kz];
-      const R iw2 = iw * iw;
-#pragma unroll
-      for (int i = 0; i < NE; ++i) E[i] *= iw2;
-    }
-    const double mult = pair ? 2.0 : 1.0;
-#pragma unroll
-    for (int i = 0; i < NE; ++i) atomicAdd(&bacc[i * nbins + b], (double)E[i]);
-    atomicAdd(&bacc[NE * nbins + b], mult);
-    atomicAdd(&bacc[(NE + 1) * nbins + b], mult * kf * sqrt((double)s2));
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nacc; i += blockDim.x)
-    if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
-}
-
-template <typename R, int L, int B>
-static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, const uint32_t *modecoord,
-                                int N, const int *bin_of_s2, int64_t n_s2, int nbins, double kf,
-                                const void *winv, double *acc) {
-  if constexpr (BisContract<L, B, R>::kGenerated) {
-    int64_t want = (nmodes + 255) / 256;
-    unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    size_t sh = (size_t)(L / 2 + 3) * nbins * sizeof(double);
-    hipLaunchKernelGGL((k_contract_bis_reg<R, L, B>), dim3(blocks), dim3(256), sh, s,
-                       (const cplx<R> *)spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf,
-                       (const R *)winv, acc);
-    return true;
-  } else {
-    return false;
-  }
-}
-
-template <typename R>
-static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void *spec, int64_t nmodes,
-                                  const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                  int nbins, double kf, const void *winv, double *acc) {
-#define PW_CR(L, B)                                                                                \
-  if (lmax == L && bmax == B)                                                                      \
-    return contract_reg_launch<R, L, B>(s, spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, acc);
-  PW_CR(0, 0) PW_CR(0, 1) PW_CR(0, 2) PW_CR(2, 0) PW_CR(2, 1) PW_CR(2, 2)
-  PW_CR(4, 0) PW_CR(4, 1) PW_CR(4, 2) PW_CR(6, 0) PW_CR(6, 1) PW_CR(6, 2)
-#undef PW_CR
-  return false;
-}
-
 void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
                          int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                          const void *winv, double *acc) {
   if (nmodes <= 0) return;
-  if (prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, modecoord, N, bin_of_s2, n_s2,
-                                               nbins, kf, winv, acc)
-                : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, modecoord, N, bin_of_s2, n_s2,
-                                                nbins, kf, winv, acc))
+  if (launch_contract_bis_generated(s, prec, lmax, bmax, spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins,
+                                    kf, winv, acc))
     return;
   int64_t want = (nmodes + 127) / 128;
   unsigned blocks = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);

@@ -12,6 +12,8 @@ namespace pw {
 
 namespace {
 
+constexpr double kPi = 3.14159265358979323846;
+
 int64_t isqrt64(int64_t v) {
   if (v <= 0) return 0;
   int64_t r = (int64_t)std::sqrt((double)v);
@@ -23,6 +25,96 @@ int64_t isqrt64(int64_t v) {
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 int signed_idx(int i, int N) { return i < N / 2 ? i : i - N; }
+
+int path_of(const pw_config &c) {
+  if (c.stat == PW_PK) return c.los == PW_BISECTOR ? PATH_BIS_PK : PATH_MID_PK;
+  return c.los == PW_BISECTOR ? PATH_BIS_XI : PATH_MID_XI;
+}
+
+// compact index of (l, nu) over even l = 0, 2, ..: l(l-1)/2 + l + nu
+int even_index(int l, int nu) { return l * (l - 1) / 2 + l + nu; }
+
+Prune make_prune(int N, int64_t K2, bool full, bool coords) {
+  Prune p;
+  p.full = full;
+  if (full) K2 = 3LL * (N / 2) * (N / 2);
+  K2 = std::max<int64_t>(K2, 0);
+  p.nkx = full ? N / 2 + 1 : (int)std::min<int64_t>(N / 2 + 1, isqrt64(K2) + 1);
+  p.ycnt.assign(N, 0);
+  p.yoff.assign(N, 0);
+  int64_t off = 0;
+  for (int ky = 0; ky < N; ++ky) {
+    int64_t sy = signed_idx(ky, N);
+    int cnt = 0;
+    if (full) cnt = p.nkx;
+    else if (sy * sy <= K2) cnt = (int)std::min<int64_t>(p.nkx, isqrt64(K2 - sy * sy) + 1);
+    p.ycnt[ky] = cnt;
+    p.yoff[ky] = off;
+    off += cnt;
+  }
+  p.npen = off;
+  int64_t moff = 0;
+  p.pinfo.reserve((size_t)p.npen);
+  p.moff.reserve((size_t)p.npen);
+  for (int ky = 0; ky < N; ++ky) {
+    int64_t sy = signed_idx(ky, N);
+    for (int kx = 0; kx < p.ycnt[ky]; ++kx) {
+      int cnt;
+      if (full) {
+        cnt = N;
+      } else {
+        int64_t rem = K2 - (int64_t)kx * kx - sy * sy;
+        int64_t kzm = rem < 0 ? 0 : isqrt64(rem);
+        cnt = (2 * kzm + 1 >= N) ? N : (int)(2 * kzm + 1);
+      }
+      p.pinfo.push_back(PencilInfo{kx, ky, cnt, 0});
+      p.moff.push_back(moff);
+      if (coords) {
+        const int half = (cnt - 1) / 2;
+        for (int j = 0; j < cnt; ++j) {
+          int kz = (cnt == N) ? j : (j <= half ? j : N - (cnt - j));
+          p.modecoord.push_back((uint32_t)kx | ((uint32_t)ky << 11) | ((uint32_t)kz << 22));
+        }
+      }
+      moff += cnt;
+    }
+  }
+  p.nmodes = moff;
+  return p;
+}
+
+// Pair jobs of one group of real fields.  fields: (alpha, J, mu) -> index.  m > 0 fields are
+// paired (J, +m) with (J, -m); the m = 0 fields are paired in order of J.
+void add_jobs(const std::map<std::tuple<int, int, int>, int> &fields, std::vector<FieldJob> &jobs) {
+  std::vector<std::pair<int, int>> zero;  // (J, alpha)
+  for (const auto &kv : fields) {
+    const int alpha = std::get<0>(kv.first), J = std::get<1>(kv.first), mu = std::get<2>(kv.first);
+    if (mu > 0) {
+      FieldJob j{alpha, 0, J, mu, -1, kv.second, fields.at(std::make_tuple(alpha, J, -mu)), alpha};
+      jobs.push_back(j);
+    } else if (mu == 0) {
+      zero.push_back({J, alpha});
+    }
+  }
+  std::stable_sort(zero.begin(), zero.end());
+  for (size_t i = 0; i < zero.size(); i += 2) {
+    const int Ja = zero[i].first, aa = zero[i].second;
+    const int pa = fields.at(std::make_tuple(aa, Ja, 0));
+    if (i + 1 < zero.size()) {
+      const int Jb = zero[i + 1].first, ab = zero[i + 1].second;
+      jobs.push_back(FieldJob{aa, 1, Ja, 0, Jb, pa, fields.at(std::make_tuple(ab, Jb, 0)), ab});
+    } else {
+      jobs.push_back(FieldJob{aa, 1, Ja, 0, -1, pa, -1, 0});
+    }
+  }
+}
+
+void sort_jobs(std::vector<FieldJob> &jobs) {
+  std::stable_sort(jobs.begin(), jobs.end(), [](const FieldJob &a, const FieldJob &b) {
+    if (a.m != b.m) return a.m < b.m;
+    return a.Ja < b.Ja;
+  });
+}
 
 }  // namespace
 
@@ -44,135 +136,259 @@ void validate_config(const pw_config &c) {
     if (!std::isfinite(c.box_origin[a])) plan_fail(PW_EINVAL, "box_origin must be finite");
   if (c.ell_max < 0 || c.ell_max > 8 || (c.ell_max & 1)) plan_fail(PW_EINVAL, "ell_max must be even, 0..8");
   if (c.order < 0 || c.order > 8 || (c.order & 1)) plan_fail(PW_EINVAL, "order must be even, 0..8");
-  if (!(c.bin_width > 0) || !std::isfinite(c.bin_lo)) plan_fail(PW_EINVAL, "bins must have bin_width > 0");
+  if (!(c.bin_width > 0) || !std::isfinite(c.bin_lo) || !std::isfinite(c.bin_width))
+    plan_fail(PW_EINVAL, "bins must have a finite bin_lo and bin_width > 0");
   if (c.n_bins < 1 || c.n_bins > 4096) plan_fail(PW_EINVAL, "n_bins must be in 1..4096");
-  if (c.stat != PW_PK || c.los != PW_BISECTOR)
-    plan_fail(PW_EINVAL, "this configuration (stat/los) is not built yet");
-  int Jmax = c.ell_max + c.order / 2;
-  int nf = (Jmax + 1) * (Jmax + 1);
-  size_t lds = (size_t)nf * (c.prec == PW_FP32 ? 128 * 8 : 64 * 16) +
-               (size_t)(c.ell_max / 2 + 3) * c.n_bins * 8;
-  if (lds > 65536)
-    plan_fail(PW_EINVAL, "ell_max + order/2 (or n_bins) too large for the contraction kernel's LDS");
+  const int path = path_of(c);
+  const int nell = c.ell_max / 2 + 1;
+  if (path == PATH_BIS_PK) {
+    int Jmax = c.ell_max + c.order / 2;
+    int nf = (Jmax + 1) * (Jmax + 1);
+    bool gen = bis_contract_generated(c.ell_max, c.order / 2);
+    size_t lds = gen ? (size_t)(nell + 2) * c.n_bins * 8
+                     : (size_t)nf * (c.prec == PW_FP32 ? 128 * 8 : 64 * 16) + (size_t)(nell + 2) * c.n_bins * 8;
+    if (lds > 65536)
+      plan_fail(PW_EINVAL, "ell_max + order/2 (or n_bins) too large for the contraction kernel's LDS");
+  } else if (path == PATH_MID_PK) {
+    if (c.ell_max >= 2 && c.order >= 2 && !mid_reweight_generated(c.ell_max, c.order))
+      plan_fail(PW_EINVAL,
+                "midpoint P_l: (ell_max, order) has no re-weighting kernel (built: ell_max 2..6 with "
+                "order 2..4, and order 6 for ell_max <= 4)");
+    if ((size_t)(nell + 2) * c.n_bins * 8 > 65536) plan_fail(PW_EINVAL, "n_bins too large");
+  } else {
+    const double r_hi = c.bin_lo + c.n_bins * c.bin_width;
+    if (r_hi > 0.5 * c.box_len)
+      plan_fail(PW_EINVAL, "xi_l: the r-bins must end at or below box_len / 2 (periodic images beyond)");
+    // the fused x pass keeps ROWS rows of N complex values and the bins in LDS
+    const int T = c.n_mesh / 8;
+    const int rows = (T >= 64) ? (256 / T > 0 ? 256 / T : 1) : 64 / T * 2;
+    const size_t lds = (size_t)rows * (c.n_mesh + c.n_mesh / 8) * (c.prec == PW_FP32 ? 8 : 16) +
+                       (size_t)(nell + 2) * c.n_bins * 8;
+    if (lds > 65536) plan_fail(PW_EINVAL, "n_bins too large for xi_l (LDS of the fused x pass)");
+    if (path == PATH_BIS_XI && !bis_contract_generated(c.ell_max, c.order / 2))
+      plan_fail(PW_EINVAL, "bisector xi_l is built for ell_max <= 6 and order <= 4");
+  }
 }
 
 HostPlan build_host_plan(const pw_config &c) {
   HostPlan h;
+  h.path = path_of(c);
   h.stat = c.stat; h.los = c.los; h.prec = c.prec; h.N = c.n_mesh;
   h.ell_max = c.ell_max; h.order = c.order; h.n_bins = c.n_bins;
-  h.L = c.box_len; h.H = c.box_len / c.n_mesh; h.kf = 2.0 * 3.14159265358979323846 / c.box_len;
+  h.L = c.box_len; h.H = c.box_len / c.n_mesh; h.kf = 2.0 * kPi / c.box_len;
+  {
+    // (2r)^-alpha and |D|^alpha are evaluated in the unit u ~ 2 |box centre| (at least L/2):
+    // fields of different alpha then have comparable magnitudes, which the two-real-fields-per-
+    // complex-transform packing needs (a field 1e13 times smaller than its partner would keep
+    // no significant digits).
+    double cx = c.box_origin[0] + 0.5 * c.box_len, cy = c.box_origin[1] + 0.5 * c.box_len,
+           cz = c.box_origin[2] + 0.5 * c.box_len;
+    h.unit = std::max(2.0 * std::sqrt(cx * cx + cy * cy + cz * cz), 0.5 * c.box_len);
+  }
   h.nell = c.ell_max / 2 + 1;
   for (int l = 0; l <= c.ell_max; l += 2) h.ells.push_back(l);
-  h.check_extent = (c.stat == PW_PK && c.los == PW_MIDPOINT && c.order > 0) ? 1 : 0;
+  h.check_extent = (h.path == PATH_MID_PK && c.order > 0 && c.ell_max > 0) ? 1 : 0;
+  h.n0 = 0; h.n_inv = 0; h.n_inplace = 0; h.nz = 0; h.ny = 0; h.n_targets = 0; h.n_a = 0;
   const int N = h.N;
+  const bool is_pk = c.stat == PW_PK;
 
-  // FP64 bin decision from the integer |n|^2 (same expression order as the definition:
-  // |k| = (2 pi / L) sqrt(s2), b = floor((|k| - lo) / width)).
+  // FP64 bin decision from the integer |n|^2 (same expression order as the definition):
+  //   P:  |k| = (2 pi / L) sqrt(s2),  b = floor((|k| - lo) / width)
+  //   xi: |D| = (L / N) sqrt(s2),     b = floor((|D| - lo) / width), D = 0 excluded
   const int64_t smax = 3LL * (N / 2) * (N / 2);
   h.bin_of_s2.assign((size_t)smax + 1, -1);
   h.K2 = -1;
   for (int64_t s2 = 0; s2 <= smax; ++s2) {
-    double kmag = (2.0 * 3.14159265358979323846 / c.box_len) * std::sqrt((double)s2);
-    double t = kmag - c.bin_lo;
-    double b = std::floor(t / c.bin_width);
+    double mag = is_pk ? (2.0 * kPi / c.box_len) * std::sqrt((double)s2)
+                       : (c.box_len / N) * std::sqrt((double)s2);
+    double b = std::floor((mag - c.bin_lo) / c.bin_width);
+    if (!is_pk && s2 == 0) continue;
     if (b >= 0 && b < c.n_bins) {
       h.bin_of_s2[(size_t)s2] = (int)b;
       h.K2 = s2;
     }
   }
-  const int64_t K2 = std::max<int64_t>(h.K2, 0);
 
   // assignment window W(k) = prod_i sinc(pi s_i / N)^p, p = 2 (CIC) or 3 (TSC)
   if (c.compensate) {
     h.winv.resize(N);
     for (int i = 0; i < N; ++i) {
-      double x = 3.14159265358979323846 * (double)signed_idx(i, N) / (double)N;
+      double x = kPi * (double)signed_idx(i, N) / (double)N;
       double sn = (x == 0.0) ? 1.0 : std::sin(x) / x;
       h.winv[i] = 1.0 / std::pow(sn, (double)c.assign);
     }
   }
 
-  // fields: every real harmonic (J, mu) with J <= ell_max + order/2 (bisector)
-  const int Jmax = c.ell_max + c.order / 2;
-  h.nfields = (Jmax + 1) * (Jmax + 1);
-  for (int J = 0; J <= Jmax; J += 2) {
-    FieldJob j{0, 1, J, 0, (J + 1 <= Jmax) ? J + 1 : -1, sh_index(J, 0),
-               (J + 1 <= Jmax) ? sh_index(J + 1, 0) : -1, 0};
-    h.jobs.push_back(j);
-  }
-  for (int m = 1; m <= Jmax; ++m)
-    for (int J = m; J <= Jmax; ++J) {
-      FieldJob j{0, 0, J, m, -1, sh_index(J, m), sh_index(J, -m), 0};
+  // ------------------------------------------------------------------ forward fields
+  std::map<std::tuple<int, int, int>, int> fields;  // (alpha, J, mu) -> index
+  if (c.los == PW_BISECTOR) {
+    // every real harmonic (J, mu), J <= ell_max + order/2, at index J*J + J + mu
+    const int Jmax = c.ell_max + c.order / 2;
+    h.nfields = (Jmax + 1) * (Jmax + 1);
+    for (int J = 0; J <= Jmax; J += 2) {
+      FieldJob j{0, 1, J, 0, (J + 1 <= Jmax) ? J + 1 : -1, sh_index(J, 0),
+                 (J + 1 <= Jmax) ? sh_index(J + 1, 0) : -1, 0};
       h.jobs.push_back(j);
     }
-
-  // pruned index sets: keep |n|^2 <= K2
-  h.nkx = (int)std::min<int64_t>(N / 2 + 1, isqrt64(K2) + 1);
-  h.ycnt.assign(N, 0);
-  h.yoff.assign(N, 0);
-  int64_t off = 0;
-  for (int ky = 0; ky < N; ++ky) {
-    int64_t sy = signed_idx(ky, N);
-    int cnt = 0;
-    if (sy * sy <= K2) cnt = (int)std::min<int64_t>(h.nkx, isqrt64(K2 - sy * sy) + 1);
-    h.ycnt[ky] = cnt;
-    h.yoff[ky] = off;
-    off += cnt;
+    for (int m = 1; m <= Jmax; ++m)
+      for (int J = m; J <= Jmax; ++J) {
+        FieldJob j{0, 0, J, m, -1, sh_index(J, m), sh_index(J, -m), 0};
+        h.jobs.push_back(j);
+      }
+  } else {
+    // alpha = 0: y_J^mu d, J = 0, 2, .., ell_max (index even_index(J, mu));
+    // alpha = 2, 4, .., order (only when ell_max >= 2: the monopole has no alpha > 0 term):
+    //   (2r)^-alpha y_J^mu d, J even <= ell_max + alpha, in (alpha, J, mu) order after them.
+    std::map<std::tuple<int, int, int>, int> f0, fa;
+    int p = 0;
+    for (int J = 0; J <= c.ell_max; J += 2)
+      for (int mu = -J; mu <= J; ++mu) f0[std::make_tuple(0, J, mu)] = p++;
+    h.n0 = p;
+    if (c.ell_max >= 2)
+      for (int alpha = 2; alpha <= c.order; alpha += 2)
+        for (int J = 0; J <= c.ell_max + alpha; J += 2)
+          for (int mu = -J; mu <= J; ++mu) fa[std::make_tuple(alpha, J, mu)] = p++;
+    h.nfields = p;
+    add_jobs(f0, h.jobs);
+    add_jobs(fa, h.jobs);
+    fields = f0;
+    fields.insert(fa.begin(), fa.end());
+    h.n_inv = (h.path == PATH_MID_PK) ? h.nfields - h.n0 : h.nfields;
+    h.n_inplace = (h.path == PATH_MID_PK) ? h.n0 : 0;
   }
-  h.npen = off;
-  int64_t moff = 0;
-  h.pinfo.reserve((size_t)h.npen);
-  h.moff.reserve((size_t)h.npen);
-  for (int ky = 0; ky < N; ++ky) {
-    int64_t sy = signed_idx(ky, N);
-    for (int kx = 0; kx < h.ycnt[ky]; ++kx) {
-      int64_t rem = K2 - (int64_t)kx * kx - sy * sy;
-      int cnt;
-      if (rem < 0) cnt = 1;  // cannot happen for retained pencils; keep kz = 0 slot
-      else {
-        int64_t kzm = isqrt64(rem);
-        cnt = (2 * kzm + 1 >= N) ? N : (int)(2 * kzm + 1);
+  sort_jobs(h.jobs);
+
+  // ------------------------------------------------------------------ retention
+  h.fwd = make_prune(N, h.K2, h.path != PATH_BIS_PK, h.path == PATH_BIS_PK);
+  if (h.path == PATH_MID_PK) h.sph = make_prune(N, h.K2, false, true);
+
+  // ------------------------------------------------------------------ inverse transforms
+  if (h.path != PATH_BIS_PK) {
+    int R;
+    if (h.path == PATH_MID_PK) R = N / 2;
+    else R = (int)isqrt64(std::max<int64_t>(h.K2, 0));
+    const int n = std::min(N, 2 * R + 1);
+    h.nz = n;
+    h.ny = n;
+    h.zrank.assign(N, -1);
+    h.zidx.assign(n, 0);
+    for (int j = 0; j < n; ++j) {
+      const int half = (n - 1) / 2;
+      const int z = (n == N) ? j : (j <= half ? j : N - (n - j));
+      h.zidx[j] = z;
+      h.zrank[z] = j;
+    }
+    h.yidx = h.zidx;
+    const int nkx = h.fwd.nkx;
+    h.iycnt.assign(N, 0);
+    h.iyoff.assign(N, 0);
+    for (int y = 0; y < N; ++y)
+      if (h.zrank[y] >= 0) {
+        h.iycnt[y] = nkx;
+        h.iyoff[y] = (int64_t)h.zrank[y] * nkx;
       }
-      PencilInfo pi{kx, ky, cnt, 0};
-      h.pinfo.push_back(pi);
-      h.moff.push_back(moff);
-      const int half = (cnt - 1) / 2;
-      for (int j = 0; j < cnt; ++j) {
-        int kz = (cnt == N) ? j : (j <= half ? j : N - (cnt - j));
-        h.modecoord.push_back((uint32_t)kx | ((uint32_t)ky << 11) | ((uint32_t)kz << 22));
-      }
-      moff += cnt;
+  }
+  if (h.path == PATH_MID_PK || h.path == PATH_MID_XI) {
+    for (const FieldJob &j : h.jobs) {
+      const bool a0 = j.pa < h.n0;
+      if (h.path == PATH_MID_PK && a0) continue;  // alpha = 0: stays in k-space
+      FieldJob k = j;
+      k.pa -= h.n_inplace;
+      if (k.pb >= 0) k.pb -= h.n_inplace;
+      h.ijobs.push_back(k);
     }
   }
-  h.nmodes = moff;
-
-  // coupling terms grouped by target (l, nu)
-  std::vector<Term> terms = bisector_terms(c.ell_max, c.order / 2);
-  std::map<std::pair<int, int>, std::vector<Term>> by;
-  for (const Term &t : terms) by[{t.l, t.nu}].push_back(t);
-  h.t_start.push_back(0);
-  for (auto &kv : by) {
-    for (const Term &t : kv.second) {
-      h.t_p1.push_back(sh_index(t.J1, t.mu1));
-      h.t_p2.push_back(sh_index(t.J2, t.mu2));
-      h.t_coef.push_back(t.c);
+  if (h.path == PATH_BIS_XI) {
+    // targets T_{l nu} at even_index(l, nu); pair jobs as for fields (alpha = 0)
+    std::map<std::tuple<int, int, int>, int> tg;
+    for (int l = 0; l <= c.ell_max; l += 2)
+      for (int nu = -l; nu <= l; ++nu) tg[std::make_tuple(0, l, nu)] = even_index(l, nu);
+    h.n_targets = (int)tg.size();
+    h.n_inv = h.n_targets;
+    add_jobs(tg, h.ijobs);
+  }
+  sort_jobs(h.ijobs);
+  // xi: per-field multipole coefficients of every inverse job, [job][side][l]
+  //   midpoint: F^{alpha,l}_J (Appendix E); bisector: the target's own l.
+  if (h.path == PATH_MID_XI || h.path == PATH_BIS_XI) {
+    for (const FieldJob &j : h.ijobs) {
+      const int Jb = j.kind == 0 ? j.Ja : j.Jb;
+      for (int side = 0; side < 2; ++side)
+        for (int l : h.ells) {
+          double F = 0.0;
+          if (h.path == PATH_MID_XI) {
+            if (side == 0) F = legendre_F(j.alpha, l, j.Ja);
+            else if (j.pb >= 0) F = legendre_F(j.alpha_b, l, Jb);
+          } else {
+            F = side == 0 ? (l == j.Ja ? 1.0 : 0.0) : (j.pb >= 0 && l == Jb ? 1.0 : 0.0);
+          }
+          h.icoef.push_back(F);
+        }
     }
-    h.t_start.push_back((int)h.t_p1.size());
-    h.t_sh.push_back(kv.first.first * kv.first.first + kv.first.first + kv.first.second);
-    h.t_ell.push_back(kv.first.first / 2);
+  }
+
+  // ------------------------------------------------------------------ midpoint P: A fields
+  if (h.path == PATH_MID_PK) {
+    // alpha = 0 couplings: (l, nu) <- y_0^0(D^) g_{0 l nu} with coefficient sqrt(4 pi), so the
+    // k-space term is conj(D) Q_{0 l nu} / W^2 with unit weight.
+    for (const Term &t : midpoint_terms(c.ell_max, 0)) {
+      const bool ok = t.J1 == 0 && t.mu1 == 0 && t.J2 == t.l && t.mu2 == t.nu &&
+                      std::fabs(t.c - std::sqrt(4.0 * kPi)) < 1e-12;
+      if (!ok) plan_fail(PW_EINVAL, "midpoint alpha = 0 coupling is not the identity");
+    }
+    if (h.n_inv > 0) {
+      if (mid_reweight_nfields(c.ell_max, c.order) != h.n_inv)
+        plan_fail(PW_EINVAL, "internal: midpoint field set differs from the re-weighting kernel's");
+      for (int l = 2; l <= c.ell_max; l += 2) h.n_a += 2 * l + 1;
+      for (int i = 0; i < h.n_a; i += 2)
+        h.ajobs.push_back(FieldJob{0, 2, i, 0, (i + 1 < h.n_a) ? i + 1 : -1, i,
+                                   (i + 1 < h.n_a) ? i + 1 : -1, 0});
+    }
+  }
+
+  // ------------------------------------------------------------------ bisector P tables
+  if (h.path == PATH_BIS_PK) {
+    std::vector<Term> terms = bisector_terms(c.ell_max, c.order / 2);
+    std::map<std::pair<int, int>, std::vector<Term>> by;
+    for (const Term &t : terms) by[{t.l, t.nu}].push_back(t);
+    h.t_start.push_back(0);
+    for (auto &kv : by) {
+      for (const Term &t : kv.second) {
+        h.t_p1.push_back(sh_index(t.J1, t.mu1));
+        h.t_p2.push_back(sh_index(t.J2, t.mu2));
+        h.t_coef.push_back(t.c);
+      }
+      h.t_start.push_back((int)h.t_p1.size());
+      h.t_sh.push_back(kv.first.first * kv.first.first + kv.first.first + kv.first.second);
+      h.t_ell.push_back(kv.first.first / 2);
+    }
+  }
+  const size_t rsz = h.prec == PW_FP32 ? 4 : 8, csz = 2 * rsz;
+  if (h.path == PATH_MID_PK && h.n_a > 0) {
+    const size_t sfull = (size_t)N * N * h.fwd.nkx * csz;
+    if ((size_t)h.n_a * N * N * N * rsz > (size_t)h.n_inv * sfull)
+      plan_fail(PW_EINVAL, "internal: A fields do not fit the spectrum buffer");
   }
   return h;
 }
 
+size_t spectrum_buffer_bytes(const HostPlan &h) {
+  const size_t csz = h.prec == PW_FP32 ? 8 : 16;
+  const size_t x1 = (size_t)h.nfields * h.N * h.N * h.fwd.nkx * csz;
+  const size_t x2 = (size_t)h.nfields * h.N * h.fwd.npen * csz;
+  const size_t x3 = (size_t)h.nfields * h.fwd.nmodes * csz;
+  return std::max<size_t>(std::max(x1, std::max(x2, x3)), 16);
+}
+
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
   HostPlan h = build_host_plan(c);
-  size_t csz = c.prec == PW_FP32 ? 8 : 16, rsz = c.prec == PW_FP32 ? 4 : 8;
-  size_t x1 = (size_t)h.nfields * h.N * h.N * h.nkx * csz;
-  size_t x2 = (size_t)h.nfields * h.N * h.npen * csz;
-  size_t x3 = (size_t)h.nfields * h.nmodes * csz;
-  size_t b = (size_t)h.N * h.N * h.N * rsz + std::max(x1, x3) + x2;
-  b += h.modecoord.size() * 4 + h.bin_of_s2.size() * 4 + h.pinfo.size() * 24;
-  b += (size_t)(n_gal + n_ran) * 4 * rsz + (size_t)n_ran * rsz;
+  const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
+  const int ts = tile_size(h.N), nt = h.N / ts;
+  size_t b = (size_t)h.N * h.N * h.N * rsz + 2 * spectrum_buffer_bytes(h);
+  b += h.fwd.modecoord.size() * 4 + h.sph.modecoord.size() * 4 + h.bin_of_s2.size() * 4 +
+       (h.fwd.pinfo.size() + h.sph.pinfo.size()) * 24;
+  b += (size_t)nt * nt * nt * ((ts + 2) * (ts + 2) * (ts + 2) * 8 + 16);
+  b += (size_t)(n_gal + n_ran) * 4 * rsz * 2 + (size_t)n_ran * rsz;
   return b;
 }
 

@@ -1,6 +1,16 @@
 // Planner: validates a configuration and derives everything the kernels need — the real
 // fields of each series order, the pair jobs of the fused x pass, the pruned index sets of the
 // y and z passes, the per-mode coordinates, the FP64 bin decisions and the coupling tables.
+//
+// Four paths share the forward passes:
+//   bisector P_l   forward transforms pruned to the k-sphere of the bins, contraction.
+//   midpoint P_l   full forward transforms; conj(D) Q / W^2 fused into an inverse z pass;
+//                  alpha = 0 products stay in k-space; alpha > 0 ones go back to real space,
+//                  are re-weighted into A_{l nu}, and A is transformed forward (pruned).
+//   midpoint xi_l  full forward transforms; product + inverse transforms output-pruned to the
+//                  separations of the r-bins; weighting and binning fused into the x pass.
+//   bisector xi_l  full forward transforms; per-mode targets T_{l nu}; inverse transforms
+//                  output-pruned as above; y_l^nu(D^) weighting and binning fused.
 #pragma once
 #include <cstdint>
 #include <memory>
@@ -22,51 +32,82 @@ typedef std::tuple<int, int, int, int, int, double, double, double, double, int,
 PlanKey make_key(const pw_config &c);
 void validate_config(const pw_config &c);
 
-struct HostPlan {
-  int stat, los, prec, N, ell_max, order, n_bins, nell;
-  double L, H, kf;
-  int check_extent;
-  std::vector<int> ells;
-  // fields / jobs
-  int nfields;
-  std::vector<FieldJob> jobs;
-  // pruned spectra
-  int64_t K2;            // largest retained |n|^2
-  int nkx;
+enum Path { PATH_BIS_PK = 0, PATH_MID_PK = 1, PATH_MID_XI = 2, PATH_BIS_XI = 3 };
+
+// Retained modes of a forward transform: |n|^2 <= K2 (all modes when `full`).
+struct Prune {
+  bool full = false;
+  int nkx = 0;
   std::vector<int> ycnt;
   std::vector<int64_t> yoff;
-  int64_t npen;
+  int64_t npen = 0;
   std::vector<PencilInfo> pinfo;
   std::vector<int64_t> moff;
-  int64_t nmodes;
-  std::vector<uint32_t> modecoord;
-  // FP64 bin decision per integer |n|^2
-  std::vector<int> bin_of_s2;
-  // 1 / sinc(pi s / N)^p per axis index (empty when compensation is off)
-  std::vector<double> winv;
-  // coupling terms grouped by target
+  int64_t nmodes = 0;
+  std::vector<uint32_t> modecoord;  // kx | ky << 11 | kz << 22 (pruned sets only)
+};
+
+struct HostPlan {
+  int path;
+  int stat, los, prec, N, ell_max, order, n_bins, nell;
+  double L, H, kf;
+  double unit;               // length unit of the radial weights (about twice the box-centre distance)
+  int check_extent;
+  std::vector<int> ells;
+  // forward fields and the pair jobs of the x pass
+  int nfields;
+  std::vector<FieldJob> jobs;
+  int n0;                    // midpoint: number of alpha = 0 fields (stored first)
+  Prune fwd;                 // forward retention
+  Prune sph;                 // midpoint P: the k-sphere of the bins (A fields, contraction)
+  int64_t K2;                // largest |n|^2 in a k-bin (P) ; largest |s|^2 in an r-bin (xi)
+  std::vector<int> bin_of_s2;  // FP64 bin decision per integer |n|^2 (k for P, r for xi)
+  std::vector<double> winv;    // 1 / sinc(pi s / N)^p per axis index (empty: no compensation)
+  // bisector P: coupling terms grouped by target (table-driven contraction)
   std::vector<int> t_start, t_sh, t_ell, t_p1, t_p2;
   std::vector<double> t_coef;
+  // inverse transforms (midpoint, xi)
+  int n_inv;                 // fields of the inverse stack
+  int n_inplace;             // fields kept in k-space by the inverse z pass (midpoint P)
+  int nz, ny;                // retained z planes / y rows of the inverse outputs
+  std::vector<int> zrank, zidx, yidx;   // index -> rank (-1: dropped) ; rank -> index
+  std::vector<int> iycnt;    // per y index: nkx if retained else 0
+  std::vector<int64_t> iyoff;  // per y index: rank * nkx
+  std::vector<FieldJob> ijobs;   // pair jobs of the inverse x pass (indices into the stack)
+  std::vector<double> icoef;     // xi: [ijob][2][nell] per-field multipole coefficients
+  int n_targets;             // bisector xi: T_{l nu} spectra
+  // midpoint P: A_{l nu} fields (l >= 2) and their forward pair jobs
+  int n_a;
+  std::vector<FieldJob> ajobs;
 };
 
 HostPlan build_host_plan(const pw_config &c);
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
+// bytes of each of the two spectrum buffers
+size_t spectrum_buffer_bytes(const HostPlan &h);
 
-struct DevPlan {
-  std::unique_ptr<HostPlan> host;
-  std::vector<std::pair<void *, size_t>> allocs;
-  void *tw = nullptr;
-  FieldJob *jobs = nullptr;
+struct DevPrune {
   int *ycnt = nullptr;
   int64_t *yoff = nullptr;
   PencilInfo *pinfo = nullptr;
   int64_t *moff = nullptr;
   uint32_t *modecoord = nullptr;
+};
+
+struct DevPlan {
+  std::unique_ptr<HostPlan> host;
+  std::vector<std::pair<void *, size_t>> allocs;
+  void *tw = nullptr;
+  FieldJob *jobs = nullptr, *ijobs = nullptr, *ajobs = nullptr;
+  DevPrune fwd, sph;
   int *bin_of_s2 = nullptr;
   int *ells = nullptr;
   void *winv = nullptr;
   int *t_start = nullptr, *t_sh = nullptr, *t_ell = nullptr, *t_p1 = nullptr, *t_p2 = nullptr;
   void *t_coef = nullptr;
+  int *zrank = nullptr, *zidx = nullptr, *yidx = nullptr, *iycnt = nullptr;
+  int64_t *iyoff = nullptr;
+  void *icoef = nullptr;
   void *mesh = nullptr, *bufA = nullptr, *bufB = nullptr;
   double *acc = nullptr, *out = nullptr, *part_g = nullptr, *part_r = nullptr;
   DevNorm *norm = nullptr;
