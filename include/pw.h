@@ -71,7 +71,7 @@ typedef struct {
   int los;               /* PW_MIDPOINT or PW_BISECTOR                                    */
   int assign;            /* PW_CIC or PW_TSC                                              */
   int prec;              /* PW_FP32 or PW_FP64                                            */
-  int n_mesh;            /* N, a power of two in [16, 1024]                               */
+  int n_mesh;            /* N, a power of two in [16, 512]                                */
   double box_len;        /* L (same length unit as the positions, e.g. Mpc/h)             */
   double box_origin[3];  /* b0, the corner of the box                                     */
   int ell_max;           /* even, 0..8                                                    */
@@ -119,29 +119,51 @@ int pw_destroy(pw_ctx *ctx);
  *   bin_mean [n_bins] mean |k| (or |r|) of the modes in each bin (host, may be NULL)
  *   counts   [n_bins] modes (or grid separations) per bin (host, may be NULL)
  * Midpoint P_l with order > 0 requires the catalog extent on every axis to be at most
- * box_len / 2 (the convolution grows to twice the survey width, Section 3.2): PW_EINVAL. */
+ * box_len / 2 (the convolution grows to twice the survey width, Section 3.2): PW_EINVAL.
+ * xi_l requires the r-bins to end at or below box_len / 2 (separations beyond alias with
+ * their periodic images): PW_EINVAL.
+ * Built couplings: bisector xi_l for ell_max <= 6 and order <= 4; midpoint P_l for
+ * ell_max <= 6 with order <= 4, and order 6 for ell_max <= 4 (PW_EINVAL otherwise); bisector
+ * P_l and midpoint xi_l for every ell_max <= 8, order <= 8. */
 int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
                 const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
                 int64_t *counts);
 
-/* Continuous-batching submission: enqueue an estimate and return a ticket.  The inputs and
- * output buffers must stay valid until the ticket completes or is cancelled.  Requests are
- * admitted as their device-memory footprint fits the budget and run concurrently on the
- * context's worker streams. */
+/* Serving.  pw_submit validates a request, enqueues it and returns a ticket at once; a
+ * worker thread of the context admits pending requests in arrival order as soon as one of the
+ * context's serving lanes is free and the request's device memory fits the HBM budget (plans
+ * and work buffers of idle lanes are evicted, least recently used first, to make room; a
+ * plan stays resident on its lane for later requests of the same configuration).  Each lane
+ * has its own HIP stream, so admitted requests of any size, mesh and estimator run
+ * concurrently on the device.  The inputs and output buffers must stay valid until the ticket
+ * completes or is cancelled; outputs are written when the request finishes.
+ *   pw_submit   PW_OK and *ticket, or an error for a malformed request / one that can never
+ *               fit the budget (PW_ENOMEM); nothing is enqueued then.
+ *   pw_poll     PW_EAGAIN while pending or running; otherwise the request's final status
+ *               (PW_OK, PW_ECANCELED or the error of pw_estimate), after which the ticket is
+ *               released (a later call on it returns PW_EINVAL).
+ *   pw_wait     blocks until the request is final, returns and releases like pw_poll.
+ *   pw_cancel   removes a request that has not been admitted (its status becomes
+ *               PW_ECANCELED); PW_EBUSY if it is already running.
+ * Submission functions may be called from one thread at a time; they may run concurrently
+ * with pw_estimate calls on the same context. */
 int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
               const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
               int64_t *counts, uint64_t *ticket);
-int pw_poll(pw_ctx *ctx, uint64_t ticket);   /* PW_OK done, PW_EAGAIN pending, <0 failed  */
-int pw_wait(pw_ctx *ctx, uint64_t ticket);   /* block until done; returns its status      */
-int pw_cancel(pw_ctx *ctx, uint64_t ticket); /* cancel a request not yet admitted         */
+int pw_poll(pw_ctx *ctx, uint64_t ticket);
+int pw_wait(pw_ctx *ctx, uint64_t ticket);
+int pw_cancel(pw_ctx *ctx, uint64_t ticket);
+/* Number of serving lanes (1..8, default 2); only before the first pw_submit (PW_EBUSY
+ * after). */
+int pw_set_lanes(pw_ctx *ctx, int n_lanes);
 
 /* Copy an internal buffer of the context's most recent pw_estimate to host memory (for
  * per-stage checks).  what:
  *   0  painted node masses, [N][N][N] (z, y, x order; FP32 or FP64 by prec)
- *   1  retained half-spectrum values of the weighted fields, [nfields][nmodes] complex
- *      (real-harmonic field index J*J + J + mu), bisector P_l only
- *   2  coordinates of those modes, [nmodes] uint32 = kx | ky << 11 | kz << 22
- *      (FFT indices; kx <= N/2)
+ *   1  bisector P_l: retained half-spectrum values of the weighted fields, [nfields][nmodes]
+ *      complex (real-harmonic field index J*J + J + mu)
+ *   2  bisector P_l: coordinates of those modes, [nmodes] uint32 = kx | ky << 11 | kz << 22
+ *      (FFT indices; kx <= N/2); PW_EINVAL for paths that keep full spectra
  * *needed receives the byte count; data are copied only when dst is not NULL and
  * dst_bytes >= *needed.  Synchronises the context's stream. */
 int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed);

@@ -1,16 +1,28 @@
-// C ABI of libpw: context, planner and the synchronous estimate pipeline.
+// C ABI of libpw: context, planner, the estimate pipeline and the serving loop.
+//
+// A context owns lanes.  Each lane has its own HIP stream, plan cache (tables and work
+// buffers per configuration), catalog staging and pinned result buffers.  Lane 0 runs the
+// synchronous pw_estimate on the caller's (or the context's) stream; lanes 1..n serve
+// pw_submit requests: a worker thread admits pending requests as a lane and enough of the HBM
+// budget free up (evicting the plans of idle lanes, least recently used first), enqueues their
+// whole pipeline on the lane's stream, and finishes them when the lane's completion event
+// fires, so requests of different sizes and meshes overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -44,54 +56,114 @@ struct Fail {
     if (e_ != hipSuccess) fail(PW_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e_)); \
   } while (0)
 
-}  // namespace
+constexpr int kMaxStages = 24;
+constexpr int kMaxLanes = 8;
 
-constexpr int kMaxStages = 16;
-
-struct pw_ctx {
-  int device = 0;
+struct Lane {
+  int id = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  size_t budget = 0;
-  size_t used = 0;
-  std::string err;
   std::map<PlanKey, std::unique_ptr<DevPlan>> plans;
-  // catalog staging (host pointers are copied here)
+  std::map<PlanKey, uint64_t> plan_stamp;  // last use (LRU eviction)
+  std::map<PlanKey, size_t> plan_bytes;
   void *stage[2] = {nullptr, nullptr};
   size_t stage_bytes[2] = {0, 0};
   void *stage_nbar = nullptr;
   size_t stage_nbar_bytes = 0;
-  size_t lds_per_block = 65536;
-  void *records = nullptr;  // tile-sorted particle records of the current estimate
+  void *records = nullptr;  // tile-sorted particle records
   size_t records_bytes = 0;
-  DevPlan *last = nullptr;  // plan of the most recent estimate (pw_inspect)
-  // stage timing
+  double *host_res = nullptr;  // pinned: [(nell + 2) * nbins] results + DevNorm
+  size_t host_res_bytes = 0;
+  hipEvent_t done = nullptr;
+  DevPlan *last = nullptr;
+  // stage timing (lane 0)
   bool timing = false;
   hipEvent_t ev[kMaxStages + 1] = {};
   int n_stages = 0;
   const char *st_name[kMaxStages] = {};
   double st_ms[kMaxStages] = {};
   double st_bytes[kMaxStages] = {};
+  struct Req *cur = nullptr;  // serving lanes: the request in flight
+};
+
+struct Req {
+  uint64_t ticket = 0;
+  pw_config cfg;
+  pw_catalog gal, ran;
+  pw_norm norm_in;
+  pw_norm *norm_out = nullptr;
+  double *out = nullptr, *bin_mean = nullptr;
+  int64_t *counts = nullptr;
+  size_t need = 0;     // device bytes of a plan for cfg plus catalog staging (admission)
+  int status = PW_EAGAIN;
+  std::string err;
+  DevPlan *dp = nullptr;
+};
+
+}  // namespace
+
+struct pw_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  std::mutex mem_mu;  // guards `used`
+  std::string err;
+  size_t lds_per_block = 65536;
+  uint64_t stamp = 0;
+  std::unique_ptr<Lane> main;                 // lane 0: pw_estimate
+  std::vector<std::unique_ptr<Lane>> lanes;   // serving lanes
+  int n_lanes = 2;
+  // serving state (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Req *> pending;
+  std::map<uint64_t, std::unique_ptr<Req>> reqs;
+  uint64_t next_ticket = 1;
+  std::thread worker;
+  bool worker_started = false;
+  bool stop = false;
 };
 
 namespace {
 
 void *dev_alloc(pw_ctx *ctx, size_t bytes) {
   if (bytes == 0) return nullptr;
-  if (ctx->used + bytes > ctx->budget)
-    fail(PW_ENOMEM, "device memory budget exceeded: need %zu more bytes, %zu of %zu in use", bytes,
-         ctx->used, ctx->budget);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    if (ctx->used + bytes > ctx->budget)
+      fail(PW_ENOMEM, "device memory budget exceeded: need %zu more bytes, %zu of %zu in use", bytes,
+           ctx->used, ctx->budget);
+    ctx->used += bytes;
+  }
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) fail(PW_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-  ctx->used += bytes;
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    ctx->used -= bytes;
+    fail(PW_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
   return p;
 }
 
 void dev_free(pw_ctx *ctx, void *p, size_t bytes) {
   if (!p) return;
   (void)hipFree(p);
+  std::lock_guard<std::mutex> lk(ctx->mem_mu);
   ctx->used -= std::min(ctx->used, bytes);
+}
+
+size_t mem_used(pw_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mem_mu);
+  return ctx->used;
+}
+
+void ensure_buffer(pw_ctx *ctx, void **p, size_t *have, size_t need) {
+  if (*have >= need) return;
+  dev_free(ctx, *p, *have);
+  *p = nullptr;
+  *have = 0;
+  *p = dev_alloc(ctx, need);
+  *have = need;
 }
 
 template <typename T>
@@ -147,10 +219,7 @@ void ensure_sh(int device) {
   g_sh_uploaded.push_back(device);
 }
 
-DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
-  PlanKey key = make_key(*cfg);
-  auto it = ctx->plans.find(key);
-  if (it != ctx->plans.end()) return it->second.get();
+std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
   std::unique_ptr<HostPlan> hp(new HostPlan(build_host_plan(*cfg)));
   std::unique_ptr<DevPlan> dp(new DevPlan());
   dp->host = std::move(hp);
@@ -229,12 +298,38 @@ DevPlan *get_plan(pw_ctx *ctx, const pw_config *cfg) {
     free_plan(ctx, dp.get());
     throw;
   }
-  DevPlan *raw = dp.get();
-  ctx->plans[key] = std::move(dp);
-  return raw;
+  return dp;
 }
 
-const void *stage_catalog(pw_ctx *ctx, const pw_catalog *c, int slot, const void **nbar_out) {
+size_t plan_alloc_bytes(const DevPlan *dp) {
+  size_t b = 0;
+  for (auto &a : dp->allocs) b += a.second;
+  return b;
+}
+
+DevPlan *get_plan(pw_ctx *ctx, Lane &ln, const pw_config *cfg) {
+  PlanKey key = make_key(*cfg);
+  auto it = ln.plans.find(key);
+  if (it == ln.plans.end()) {
+    std::unique_ptr<DevPlan> dp = build_dev_plan(ctx, cfg);
+    ln.plan_bytes[key] = plan_alloc_bytes(dp.get());
+    it = ln.plans.emplace(key, std::move(dp)).first;
+  }
+  ln.plan_stamp[key] = ++ctx->stamp;
+  return it->second.get();
+}
+
+void evict_plan(pw_ctx *ctx, Lane &ln, const PlanKey &key) {
+  auto it = ln.plans.find(key);
+  if (it == ln.plans.end()) return;
+  if (ln.last == it->second.get()) ln.last = nullptr;
+  free_plan(ctx, it->second.get());
+  ln.plans.erase(it);
+  ln.plan_stamp.erase(key);
+  ln.plan_bytes.erase(key);
+}
+
+const void *stage_catalog(pw_ctx *ctx, Lane &ln, const pw_catalog *c, int slot, const void **nbar_out) {
   size_t rs = c->dtype == PW_FP32 ? 4 : 8;
   *nbar_out = nullptr;
   if (c->on_device) {
@@ -242,27 +337,15 @@ const void *stage_catalog(pw_ctx *ctx, const pw_catalog *c, int slot, const void
     return c->xyzw;
   }
   size_t bytes = (size_t)c->n * 4 * rs;
-  if (ctx->stage_bytes[slot] < bytes) {
-    dev_free(ctx, ctx->stage[slot], ctx->stage_bytes[slot]);
-    ctx->stage[slot] = nullptr;
-    ctx->stage_bytes[slot] = 0;
-    ctx->stage[slot] = dev_alloc(ctx, bytes);
-    ctx->stage_bytes[slot] = bytes;
-  }
-  if (bytes) HIPCHECK(hipMemcpyAsync(ctx->stage[slot], c->xyzw, bytes, hipMemcpyHostToDevice, ctx->stream));
+  ensure_buffer(ctx, &ln.stage[slot], &ln.stage_bytes[slot], bytes);
+  if (bytes) HIPCHECK(hipMemcpyAsync(ln.stage[slot], c->xyzw, bytes, hipMemcpyHostToDevice, ln.stream));
   if (c->nbar && slot == 1) {
     size_t nb = (size_t)c->n * rs;
-    if (ctx->stage_nbar_bytes < nb) {
-      dev_free(ctx, ctx->stage_nbar, ctx->stage_nbar_bytes);
-      ctx->stage_nbar = nullptr;
-      ctx->stage_nbar_bytes = 0;
-      ctx->stage_nbar = dev_alloc(ctx, nb);
-      ctx->stage_nbar_bytes = nb;
-    }
-    HIPCHECK(hipMemcpyAsync(ctx->stage_nbar, c->nbar, nb, hipMemcpyHostToDevice, ctx->stream));
-    *nbar_out = ctx->stage_nbar;
+    ensure_buffer(ctx, &ln.stage_nbar, &ln.stage_nbar_bytes, nb);
+    HIPCHECK(hipMemcpyAsync(ln.stage_nbar, c->nbar, nb, hipMemcpyHostToDevice, ln.stream));
+    *nbar_out = ln.stage_nbar;
   }
-  return ctx->stage[slot];
+  return ln.stage[slot];
 }
 
 void check_catalog(const pw_catalog *c, const char *name) {
@@ -272,28 +355,36 @@ void check_catalog(const pw_catalog *c, const char *name) {
   if (c->dtype != PW_FP32 && c->dtype != PW_FP64) fail(PW_EINVAL, "%s catalog dtype must be PW_FP32 or PW_FP64", name);
 }
 
-void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
-                  pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+void check_request(const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran, const pw_norm *norm,
+                   const double *out) {
+  if (!cfg) fail(PW_EINVAL, "cfg is NULL");
   validate_config(*cfg);
   check_catalog(gal, "galaxy");
   check_catalog(ran, "random");
   if (!out) fail(PW_EINVAL, "out is NULL");
   if (!(norm && norm->use_given) && !ran->nbar)
     fail(PW_EINVAL, "random catalog needs nbar when the normalisation is not given");
+}
+
+// Enqueue the whole estimate on the lane's stream, ending with the copy of the results into
+// the lane's pinned buffer and the lane's completion event.  Returns the plan used.
+DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_catalog *gal,
+                         const pw_catalog *ran, const pw_norm *norm) {
   HIPCHECK(hipSetDevice(ctx->device));
   ensure_sh(ctx->device);
-  DevPlan *dp = get_plan(ctx, cfg);
+  DevPlan *dp = get_plan(ctx, ln, cfg);
   HostPlan &h = *dp->host;
-  hipStream_t s = ctx->stream;
-  ctx->last = dp;
+  hipStream_t s = ln.stream;
+  ln.last = dp;
   const void *gnb = nullptr, *rnb = nullptr;
-  const void *gx = stage_catalog(ctx, gal, 0, &gnb);
-  const void *rx = stage_catalog(ctx, ran, 1, &rnb);
-  const bool timing = ctx->timing;
+  const void *gx = stage_catalog(ctx, ln, gal, 0, &gnb);
+  const void *rx = stage_catalog(ctx, ln, ran, 1, &rnb);
+  const bool timing = ln.timing;
   int ns = 0;
   auto mark = [&](const char *name, double bytes) {
-    if (timing) HIPCHECK(hipEventRecord(ctx->ev[ns], s));
-    if (name) { ctx->st_name[ns] = name; ctx->st_bytes[ns] = bytes; }
+    if (ns > kMaxStages) fail(PW_EINVAL, "internal: too many stages");
+    if (timing) HIPCHECK(hipEventRecord(ln.ev[ns], s));
+    if (name && ns < kMaxStages) { ln.st_name[ns] = name; ln.st_bytes[ns] = bytes; }
     ++ns;
   };
   const double rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2.0 * rsz;
@@ -309,25 +400,16 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
                        use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
   // a2: paint (particles read once, mesh written once)
   mark("paint", 4.0 * isz_g * gal->n + 4.0 * isz_r * ran->n + ncell * rsz);
-  {
-    const size_t need = (size_t)(gal->n + ran->n) * 4 * (size_t)rsz;
-    if (ctx->records_bytes < need) {
-      dev_free(ctx, ctx->records, ctx->records_bytes);
-      ctx->records = nullptr;
-      ctx->records_bytes = 0;
-      ctx->records = dev_alloc(ctx, need);
-      ctx->records_bytes = need;
-    }
-  }
+  ensure_buffer(ctx, &ln.records, &ln.records_bytes, (size_t)(gal->n + ran->n) * 4 * (size_t)rsz);
   launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
   launch_tile_count(s, gx, gal->n, gal->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
   launch_tile_count(s, rx, ran->n, ran->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
   launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
   launch_tile_scatter(s, gx, gal->n, gal->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0,
-                      dp->tile_cursor, ctx->records);
+                      dp->tile_cursor, ln.records);
   launch_tile_scatter(s, rx, ran->n, ran->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1,
-                      dp->tile_cursor, ctx->records);
-  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ctx->records,
+                      dp->tile_cursor, ln.records);
+  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ln.records,
                     dp->norm, dp->tile_blocks, dp->mesh);
   // a3 + a4: weighted fields and the forward transforms
   const int N = h.N;
@@ -433,23 +515,37 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     }
   }
   mark(nullptr, 0.0);
-  ctx->n_stages = ns - 1;
+  ln.n_stages = ns - 1;
   HIPCHECK(hipGetLastError());
-  std::vector<double> res((size_t)(h.nell + 2) * h.n_bins);
-  DevNorm dn;
-  HIPCHECK(hipMemcpyAsync(res.data(), dp->out, res.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync(&dn, dp->norm, sizeof(DevNorm), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  for (int i = 0; i < ctx->n_stages; ++i) {
-    float ms = -1.0f;
-    if (timing) HIPCHECK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
-    ctx->st_ms[i] = timing ? (double)ms : -1.0;
+  const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+  const size_t need = nres * sizeof(double) + sizeof(DevNorm);
+  if (ln.host_res_bytes < need) {
+    if (ln.host_res) (void)hipHostFree(ln.host_res);
+    ln.host_res = nullptr;
+    ln.host_res_bytes = 0;
+    HIPCHECK(hipHostMalloc((void **)&ln.host_res, need, hipHostMallocDefault));
+    ln.host_res_bytes = need;
   }
+  HIPCHECK(hipMemcpyAsync(ln.host_res, dp->out, nres * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync((char *)ln.host_res + nres * sizeof(double), dp->norm, sizeof(DevNorm),
+                          hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipEventRecord(ln.done, s));
+  return dp;
+}
+
+// After the lane's completion event: check the flags and write the caller's outputs.
+void finish_estimate(Lane &ln, const DevPlan *dp, pw_norm *norm, double *out, double *bin_mean,
+                     int64_t *counts) {
+  const HostPlan &h = *dp->host;
+  const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+  const double *res = ln.host_res;
+  DevNorm dn;
+  std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
   if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
   if (dn.flags & 2)
     fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
-  std::memcpy(out, res.data(), (size_t)h.nell * h.n_bins * sizeof(double));
-  if (bin_mean) std::memcpy(bin_mean, res.data() + (size_t)h.nell * h.n_bins, h.n_bins * sizeof(double));
+  std::memcpy(out, res, (size_t)h.nell * h.n_bins * sizeof(double));
+  if (bin_mean) std::memcpy(bin_mean, res + (size_t)h.nell * h.n_bins, h.n_bins * sizeof(double));
   if (counts)
     for (int b = 0; b < h.n_bins; ++b) counts[b] = (int64_t)std::llround(res[(size_t)(h.nell + 1) * h.n_bins + b]);
   if (norm && !norm->use_given) {
@@ -457,6 +553,226 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     norm->I = dn.I;
     norm->S = dn.S;
   }
+}
+
+// Make room for a plan on lane 0 by evicting cached plans (lane 0's other plans, then idle
+// serving lanes'), least recently used first.
+void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran) {
+  Lane &ln = *ctx->main;
+  const PlanKey key = make_key(*cfg);
+  if (ln.plans.count(key)) return;
+  const size_t need = footprint_bytes(*cfg, gal->n, ran->n);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  while (mem_used(ctx) + need > ctx->budget) {
+    Lane *vl = nullptr;
+    PlanKey vk;
+    uint64_t oldest = (uint64_t)-1;
+    for (auto &kv : ln.plan_stamp)
+      if (kv.second < oldest) { oldest = kv.second; vl = &ln; vk = kv.first; }
+    for (auto &lp : ctx->lanes) {
+      if (lp->cur) continue;
+      for (auto &kv : lp->plan_stamp)
+        if (kv.second < oldest) { oldest = kv.second; vl = lp.get(); vk = kv.first; }
+    }
+    if (!vl) break;
+    evict_plan(ctx, *vl, vk);
+  }
+}
+
+void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                  pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  check_request(cfg, gal, ran, norm, out);
+  make_room_main(ctx, cfg, gal, ran);
+  Lane &ln = *ctx->main;
+  DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm);
+  HIPCHECK(hipEventSynchronize(ln.done));
+  for (int i = 0; i < ln.n_stages; ++i) {
+    float ms = -1.0f;
+    if (ln.timing) HIPCHECK(hipEventElapsedTime(&ms, ln.ev[i], ln.ev[i + 1]));
+    ln.st_ms[i] = ln.timing ? (double)ms : -1.0;
+  }
+  finish_estimate(ln, dp, norm, out, bin_mean, counts);
+}
+
+Lane *make_lane(int id, hipStream_t user_stream) {
+  std::unique_ptr<Lane> ln(new Lane());
+  ln->id = id;
+  if (user_stream) {
+    ln->stream = user_stream;
+  } else {
+    HIPCHECK(hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking));  // default priority
+    ln->own_stream = true;
+  }
+  HIPCHECK(hipEventCreateWithFlags(&ln->done, hipEventDisableTiming));
+  if (id == 0)
+    for (int i = 0; i <= kMaxStages; ++i) HIPCHECK(hipEventCreate(&ln->ev[i]));
+  return ln.release();
+}
+
+void destroy_lane(pw_ctx *ctx, Lane *ln) {
+  if (!ln) return;
+  if (ln->stream) (void)hipStreamSynchronize(ln->stream);
+  for (auto &kv : ln->plans) free_plan(ctx, kv.second.get());
+  ln->plans.clear();
+  for (int i = 0; i < 2; ++i) dev_free(ctx, ln->stage[i], ln->stage_bytes[i]);
+  dev_free(ctx, ln->stage_nbar, ln->stage_nbar_bytes);
+  dev_free(ctx, ln->records, ln->records_bytes);
+  if (ln->host_res) (void)hipHostFree(ln->host_res);
+  for (int i = 0; i <= kMaxStages; ++i)
+    if (ln->ev[i]) (void)hipEventDestroy(ln->ev[i]);
+  if (ln->done) (void)hipEventDestroy(ln->done);
+  if (ln->own_stream && ln->stream) (void)hipStreamDestroy(ln->stream);
+}
+
+// ------------------------------------------------------------------------------ serving
+// Bytes a lane still has to allocate to run `r` (0 when its plan and buffers are resident).
+size_t lane_extra_bytes(const Lane &ln, const Req &r) {
+  size_t extra = 0;
+  if (ln.plans.find(make_key(r.cfg)) == ln.plans.end()) extra += r.need;
+  const size_t rs = r.cfg.prec == PW_FP32 ? 4 : 8;
+  const size_t rec = (size_t)(r.gal.n + r.ran.n) * 4 * rs;
+  if (ln.records_bytes < rec) extra += rec;
+  auto stg = [&](const pw_catalog &c, size_t have) -> size_t {
+    if (c.on_device) return 0;
+    size_t b = (size_t)c.n * 4 * (c.dtype == PW_FP32 ? 4 : 8);
+    return have >= b ? 0 : b;
+  };
+  extra += stg(r.gal, ln.stage_bytes[0]) + stg(r.ran, ln.stage_bytes[1]);
+  return extra;
+}
+
+// Try to admit the oldest pending request that can run now.  Called with ctx->mu held.
+// Returns the (request, lane) to launch, or (nullptr, nullptr).
+std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
+  for (auto it = ctx->pending.begin(); it != ctx->pending.end(); ++it) {
+    Req *r = *it;
+    // free lanes, preferring one whose plan for this configuration is resident
+    Lane *best = nullptr;
+    size_t best_extra = (size_t)-1;
+    for (auto &lp : ctx->lanes) {
+      if (lp->cur) continue;
+      size_t e = lane_extra_bytes(*lp, *r);
+      if (e < best_extra) { best = lp.get(); best_extra = e; }
+    }
+    if (!best) return {nullptr, nullptr};  // every lane busy
+    // make room: evict idle lanes' plans, least recently used first
+    while (mem_used(ctx) + best_extra > ctx->budget) {
+      Lane *vl = nullptr;
+      const PlanKey *vk = nullptr;
+      uint64_t oldest = (uint64_t)-1;
+      for (auto &lp : ctx->lanes) {
+        if (lp->cur) continue;
+        for (auto &kv : lp->plan_stamp) {
+          if (lp.get() == best && kv.first == make_key(r->cfg)) continue;
+          if (kv.second < oldest) { oldest = kv.second; vl = lp.get(); vk = &kv.first; }
+        }
+      }
+      if (!vl) break;
+      PlanKey k = *vk;
+      evict_plan(ctx, *vl, k);
+      best_extra = lane_extra_bytes(*best, *r);
+    }
+    if (mem_used(ctx) + best_extra <= ctx->budget) {
+      ctx->pending.erase(it);
+      return {r, best};
+    }
+    bool running = false;
+    for (auto &lp : ctx->lanes) running = running || lp->cur != nullptr;
+    if (!running) {
+      // can never fit: fail it and look at the next one
+      r->status = PW_ENOMEM;
+      r->err = "request does not fit the context's HBM budget";
+      ctx->pending.erase(it);
+      ctx->cv.notify_all();
+      return pick_admission(ctx);
+    }
+    // wait for memory: keep arrival order for requests that need more memory
+    return {nullptr, nullptr};
+  }
+  return {nullptr, nullptr};
+}
+
+void worker_loop(pw_ctx *ctx) {
+  (void)hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  for (;;) {
+    bool any_running = false;
+    // completions
+    for (auto &lp : ctx->lanes) {
+      Lane &ln = *lp;
+      if (!ln.cur) continue;
+      hipError_t q = hipEventQuery(ln.done);
+      if (q == hipErrorNotReady) { any_running = true; continue; }
+      Req *r = ln.cur;
+      if (q != hipSuccess) {
+        r->status = PW_EDEVICE;
+        r->err = std::string("device error: ") + hipGetErrorString(q);
+      } else {
+        try {
+          finish_estimate(ln, r->dp, r->norm_out, r->out, r->bin_mean, r->counts);
+          r->status = PW_OK;
+        } catch (const Fail &f) {
+          r->status = f.code;
+          r->err = f.msg;
+        }
+      }
+      ln.cur = nullptr;
+      ctx->cv.notify_all();
+    }
+    // admissions
+    for (;;) {
+      std::pair<Req *, Lane *> a = pick_admission(ctx);
+      if (!a.first) break;
+      Req *r = a.first;
+      Lane &ln = *a.second;
+      ln.cur = r;
+      lk.unlock();
+      int code = PW_OK;
+      std::string msg;
+      try {
+        r->dp = launch_estimate(ctx, ln, &r->cfg, &r->gal, &r->ran, &r->norm_in);
+      } catch (const Fail &f) {
+        code = f.code;
+        msg = f.msg;
+      } catch (const std::exception &e) {
+        code = PW_EINVAL;
+        msg = e.what();
+      }
+      lk.lock();
+      if (code != PW_OK) {
+        r->status = code;
+        r->err = msg;
+        ln.cur = nullptr;
+        ctx->cv.notify_all();
+      } else {
+        any_running = true;
+      }
+    }
+    if (ctx->stop && ctx->pending.empty() && !any_running) break;
+    if (any_running) {
+      ctx->cv.wait_for(lk, std::chrono::microseconds(100));
+    } else {
+      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty(); });
+    }
+  }
+}
+
+void start_worker(pw_ctx *ctx) {
+  if (ctx->worker_started) return;
+  for (int i = 0; i < ctx->n_lanes; ++i) ctx->lanes.emplace_back(make_lane(i + 1, nullptr));
+  ctx->worker = std::thread(worker_loop, ctx);
+  ctx->worker_started = true;
+}
+
+int req_final(pw_ctx *ctx, uint64_t ticket, bool erase) {
+  auto it = ctx->reqs.find(ticket);
+  if (it == ctx->reqs.end()) return PW_EINVAL;
+  int st = it->second->status;
+  if (st != PW_EAGAIN) {
+    ctx->err = it->second->err;
+    if (erase) ctx->reqs.erase(it);
+  }
+  return st;
 }
 
 }  // namespace
@@ -476,20 +792,15 @@ int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_strea
     size_t free_b = 0, total_b = 0;
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
-    if (hip_stream) {
-      ctx->stream = (hipStream_t)hip_stream;
-    } else {
-      HIPCHECK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-      ctx->own_stream = true;
-    }
     ensure_sh(device);
     {
       int lds = 0;
       HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
       ctx->lds_per_block = (size_t)lds;
     }
-    for (int i = 0; i <= kMaxStages; ++i) HIPCHECK(hipEventCreate(&ctx->ev[i]));
+    ctx->main.reset(make_lane(0, (hipStream_t)hip_stream));
   } catch (const Fail &f) {
+    if (ctx->main) destroy_lane(ctx, ctx->main.release());
     delete ctx;
     return f.code;
   }
@@ -500,14 +811,25 @@ int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_strea
 int pw_destroy(pw_ctx *ctx) {
   if (!ctx) return PW_OK;
   (void)hipSetDevice(ctx->device);
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  for (auto &kv : ctx->plans) free_plan(ctx, kv.second.get());
-  ctx->plans.clear();
-  for (int i = 0; i < 2; ++i) dev_free(ctx, ctx->stage[i], ctx->stage_bytes[i]);
-  dev_free(ctx, ctx->stage_nbar, ctx->stage_nbar_bytes);
-  for (int i = 0; i <= kMaxStages; ++i)
-    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
-  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->worker_started) {
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      for (Req *r : ctx->pending) {
+        r->status = PW_ECANCELED;
+        r->err = "context destroyed";
+      }
+      ctx->pending.clear();
+      ctx->stop = true;
+    }
+    ctx->cv.notify_all();
+    ctx->worker.join();
+  }
+  for (auto &lp : ctx->lanes) {
+    destroy_lane(ctx, lp.get());
+  }
+  ctx->lanes.clear();
+  if (ctx->main) destroy_lane(ctx, ctx->main.get());
+  ctx->main.reset();
   delete ctx;
   return PW_OK;
 }
@@ -516,7 +838,6 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const 
                 pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
   if (!ctx) return PW_EINVAL;
   try {
-    if (!cfg) fail(PW_EINVAL, "cfg is NULL");
     run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts);
   } catch (const Fail &f) {
     ctx->err = f.msg;
@@ -529,8 +850,93 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const 
   return PW_OK;
 }
 
-const char *pw_last_error(const pw_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+int pw_set_lanes(pw_ctx *ctx, int n_lanes) {
+  if (!ctx) return PW_EINVAL;
+  if (n_lanes < 1 || n_lanes > kMaxLanes) {
+    ctx->err = "n_lanes must be in 1..8";
+    return PW_EINVAL;
+  }
+  if (ctx->worker_started) {
+    ctx->err = "pw_set_lanes: the serving loop has already started";
+    return PW_EBUSY;
+  }
+  ctx->n_lanes = n_lanes;
+  return PW_OK;
+}
 
+int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran, pw_norm *norm,
+              double *out, double *bin_mean, int64_t *counts, uint64_t *ticket) {
+  if (!ctx || !ticket) return PW_EINVAL;
+  std::unique_ptr<Req> r(new Req());
+  try {
+    check_request(cfg, gal, ran, norm, out);
+    r->cfg = *cfg;
+    r->gal = *gal;
+    r->ran = *ran;
+    if (norm) r->norm_in = *norm;
+    else std::memset(&r->norm_in, 0, sizeof(pw_norm));
+    r->norm_out = norm;
+    r->out = out;
+    r->bin_mean = bin_mean;
+    r->counts = counts;
+    r->need = footprint_bytes(*cfg, 0, 0);
+    size_t whole = footprint_bytes(*cfg, gal->n, ran->n);
+    if (whole > ctx->budget) fail(PW_ENOMEM, "request needs %zu bytes, budget is %zu", whole, ctx->budget);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    start_worker(ctx);
+    r->ticket = ctx->next_ticket++;
+    *ticket = r->ticket;
+    ctx->pending.push_back(r.get());
+    ctx->reqs[r->ticket] = std::move(r);
+  } catch (const Fail &f) {
+    ctx->err = f.msg;
+    return f.code;
+  } catch (const std::exception &e) {
+    ctx->err = e.what();
+    return PW_EINVAL;
+  }
+  ctx->cv.notify_all();
+  return PW_OK;
+}
+
+int pw_poll(pw_ctx *ctx, uint64_t ticket) {
+  if (!ctx) return PW_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return req_final(ctx, ticket, true);
+}
+
+int pw_wait(pw_ctx *ctx, uint64_t ticket) {
+  if (!ctx) return PW_EINVAL;
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(ticket);
+  if (it == ctx->reqs.end()) return PW_EINVAL;
+  Req *r = it->second.get();
+  ctx->cv.wait(lk, [&] { return r->status != PW_EAGAIN; });
+  return req_final(ctx, ticket, true);
+}
+
+int pw_cancel(pw_ctx *ctx, uint64_t ticket) {
+  if (!ctx) return PW_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->reqs.find(ticket);
+  if (it == ctx->reqs.end()) return PW_EINVAL;
+  Req *r = it->second.get();
+  auto pit = std::find(ctx->pending.begin(), ctx->pending.end(), r);
+  if (pit == ctx->pending.end()) {
+    if (r->status == PW_EAGAIN) {
+      ctx->err = "pw_cancel: the request is already running";
+      return PW_EBUSY;
+    }
+    return PW_OK;  // already finished; the ticket keeps its status
+  }
+  ctx->pending.erase(pit);
+  r->status = PW_ECANCELED;
+  r->err = "cancelled";
+  ctx->cv.notify_all();
+  return PW_OK;
+}
+
+const char *pw_last_error(const pw_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 int pw_footprint(const pw_config *cfg, int64_t n_gal, int64_t n_ran, size_t *bytes) {
   if (!cfg || !bytes) return PW_EINVAL;
   try {
@@ -582,22 +988,22 @@ int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,
 
 int pw_set_timing(pw_ctx *ctx, int on) {
   if (!ctx) return PW_EINVAL;
-  ctx->timing = on != 0;
+  ctx->main->timing = on != 0;
   return PW_OK;
 }
 
 int pw_stage_info(pw_ctx *ctx, int stage, const char **name, double *ms, double *bytes) {
-  if (!ctx || stage < 0 || stage >= ctx->n_stages) return PW_EINVAL;
-  if (name) *name = ctx->st_name[stage];
-  if (ms) *ms = ctx->st_ms[stage];
-  if (bytes) *bytes = ctx->st_bytes[stage];
+  if (!ctx || stage < 0 || stage >= ctx->main->n_stages) return PW_EINVAL;
+  if (name) *name = ctx->main->st_name[stage];
+  if (ms) *ms = ctx->main->st_ms[stage];
+  if (bytes) *bytes = ctx->main->st_bytes[stage];
   return PW_OK;
 }
 
 int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed) {
   if (!ctx || !needed) return PW_EINVAL;
   try {
-    DevPlan *dp = ctx->last;
+    DevPlan *dp = ctx->main->last;
     if (!dp) fail(PW_EINVAL, "pw_inspect: no estimate has run on this context");
     const HostPlan &h = *dp->host;
     size_t rsz = h.prec == PW_FP32 ? 4 : 8;
@@ -615,7 +1021,7 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
     if (dst) {
       if (dst_bytes < bytes) fail(PW_EINVAL, "pw_inspect: destination too small");
       HIPCHECK(hipSetDevice(ctx->device));
-      HIPCHECK(hipStreamSynchronize(ctx->stream));
+      HIPCHECK(hipStreamSynchronize(ctx->main->stream));
       HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
     }
   } catch (const Fail &f) {
@@ -624,15 +1030,6 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
   }
   return PW_OK;
 }
-
-int pw_submit(pw_ctx *ctx, const pw_config *, const pw_catalog *, const pw_catalog *, pw_norm *,
-              double *, double *, int64_t *, uint64_t *) {
-  if (ctx) ctx->err = "pw_submit: not available in this build";
-  return PW_EINVAL;
-}
-int pw_poll(pw_ctx *, uint64_t) { return PW_EINVAL; }
-int pw_wait(pw_ctx *, uint64_t) { return PW_EINVAL; }
-int pw_cancel(pw_ctx *, uint64_t) { return PW_EINVAL; }
 
 }  // extern "C"
 

@@ -51,6 +51,13 @@ class _Norm(C.Structure):
 
 
 def _load():
+    # One HIP runtime per process: PyTorch-ROCm ships its own libamdhip64 (same soname as the
+    # system one libpw links).  Loading torch first makes libpw bind to that same runtime; loading
+    # libpw first would make torch load a second runtime, which then finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libpw.so not built at {LIB_PATH}; run python -m paper_2102_08384_amd.build")
     lib = C.CDLL(LIB_PATH)
@@ -66,6 +73,7 @@ def _load():
     lib.pw_poll.argtypes = [P, C.c_uint64]
     lib.pw_wait.argtypes = [P, C.c_uint64]
     lib.pw_cancel.argtypes = [P, C.c_uint64]
+    lib.pw_set_lanes.argtypes = [P, C.c_int]
     lib.pw_inspect.argtypes = [P, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.pw_set_timing.argtypes = [P, C.c_int]
     lib.pw_stage_info.argtypes = [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
@@ -240,6 +248,74 @@ class Context:
         if rc != PW_OK:
             raise PwError(rc, self.last_error())
         return {"values": out, "bin_mean": bm, "counts": cnt, "norm": (nm.alpha_r, nm.I, nm.S)}
+
+
+    # ---------------------------------------------------------------- serving
+    def set_lanes(self, n: int):
+        rc = _lib.pw_set_lanes(self._h, n)
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+
+    def submit(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
+        """Enqueue an estimate; returns a Ticket (inputs are kept alive by it)."""
+        t = Ticket(self, cfg)
+        g = _catalog(gal_xyzw, None, t._keep)
+        r = _catalog(ran_xyzw, ran_nbar, t._keep)
+        t._cats = (g, r)
+        if norm is not None:
+            t._norm.alpha_r, t._norm.I, t._norm.S = (float(v) for v in norm)
+            t._norm.use_given = 1
+        t._cfg_c = cfg._c()
+        tk = C.c_uint64()
+        rc = _lib.pw_submit(self._h, C.byref(t._cfg_c), C.byref(g), C.byref(r), C.byref(t._norm),
+                            t.out.ctypes.data_as(C.POINTER(C.c_double)),
+                            t.bin_mean.ctypes.data_as(C.POINTER(C.c_double)),
+                            t.counts.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(tk))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        t.id = tk.value
+        return t
+
+
+class Ticket:
+    """A submitted request: its result buffers and the inputs they depend on."""
+
+    def __init__(self, ctx: Context, cfg: Config):
+        self._ctx = ctx
+        self._keep = []
+        self._norm = _Norm()
+        self.id = 0
+        self.status = PW_EAGAIN
+        self.out = np.zeros((cfg.n_ell, cfg.n_bins))
+        self.bin_mean = np.zeros(cfg.n_bins)
+        self.counts = np.zeros(cfg.n_bins, dtype=np.int64)
+
+    def _final(self, rc):
+        self.status = rc
+        if rc == PW_OK:
+            self._keep = []
+            return {"values": self.out, "bin_mean": self.bin_mean, "counts": self.counts,
+                    "norm": (self._norm.alpha_r, self._norm.I, self._norm.S)}
+        raise PwError(rc, self._ctx.last_error())
+
+    def poll(self):
+        """None while pending, else the result dict (raises PwError on failure)."""
+        if self.status != PW_EAGAIN:
+            return self._final(self.status)
+        rc = _lib.pw_poll(self._ctx._h, self.id)
+        if rc == PW_EAGAIN:
+            return None
+        return self._final(rc)
+
+    def wait(self):
+        if self.status != PW_EAGAIN:
+            return self._final(self.status)
+        return self._final(_lib.pw_wait(self._ctx._h, self.id))
+
+    def cancel(self):
+        rc = _lib.pw_cancel(self._ctx._h, self.id)
+        if rc not in (PW_OK,):
+            raise PwError(rc, self._ctx.last_error())
 
 
 def footprint(cfg: Config, n_gal: int, n_ran: int) -> int:
