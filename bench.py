@@ -1,16 +1,26 @@
-"""Benchmark: bisector P_l on the 512^3 headline workload, one catalog per step.
+"""Benchmark: bisector P_l on the 512^3 headline workload (catalogs/s, served vs plain).
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--workload C3]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--lanes 2] [--workload C3]
+                [--no-cpu-baseline] [--no-served] [--copy-calibration]
 
 A step is one pass of the whole hot path (FP64 scalars, paint, weighted fields, pruned forward
-FFTs, contraction and FP64 binning) over one synthetic catalog already resident in HBM, through
-the C ABI (pw_estimate).  Prints one JSON line.
+FFTs, contraction and FP64 binning) over one synthetic catalog already resident in HBM,
+through the C ABI.
+  plain   one synchronous pw_estimate per catalog on one stream
+  served  K catalogs submitted at once to the serving loop (pw_submit), which runs them on
+          `--lanes` concurrent lanes; latency = submit -> result on the host
+`value` is the served throughput; the plain one is reported beside it.  The roofline entry is
+for the dominant kernel of the plain run (HIP events on its stream).  --copy-calibration also
+runs one device-to-device copy of known size, the reference for the HBM traffic counters.
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -21,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bisector P_ℓ 512³ catalogs/s, served vs plain; p50/p99 latency; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
+KERNEL_NAMES = {"fx": "k_fx", "fy": "k_fy", "fz": "k_fz", "contract": "k_contract_bis_reg"}
 
 
 def log(*a):
@@ -59,7 +71,78 @@ def cpu_baseline(name, frac=0.25, n_mesh=96):
             "sample": f"{name} catalog subsampled to {frac:g} of its particles "
                       f"({len(g['pos'])} galaxies + {len(r['pos'])} randoms) on a {n_mesh}^3 mesh "
                       f"(full workload: {wl.N}^3), same l<=4, order {wl.order}, bins; numpy FP64, "
-                      f"single-threaded FFTs"}
+                      f"single-threaded FFTs (one catalog per value^-1 seconds)"}
+
+
+def source_digest():
+    """Digest of the kernel sources; counter-based traffic is reported only for this digest."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2102_08384_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "bisector_pk_512_traffic.txt")
+    if not os.path.exists(path):
+        return None, None
+    txt = open(path).read()
+    m = re.search(r"^source_digest\s*=\s*(\S+)", txt, re.M)
+    if not m or m.group(1) != source_digest():
+        return None, "counters taken on other kernel sources"
+    m = re.search(rf"^{re.escape(kernel)}\s+traffic_bytes_per_launch\s*=\s*(\S+)", txt, re.M)
+    if not m:
+        return None, None
+    return float(m.group(1)), path
+
+
+def plain_run(ctx, cfg, gx, rx, rn, steps, warmup, torch):
+    for _ in range(warmup):
+        ctx.estimate(cfg, gx, rx, ran_nbar=rn)
+    torch.cuda.synchronize()
+    lat, stage_ms, stage_bytes = [], {}, {}
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        res = ctx.estimate(cfg, gx, rx, ran_nbar=rn)
+        lat.append((time.perf_counter() - t1) * 1e3)
+        for name, ms, by in ctx.stages():
+            stage_ms.setdefault(name, []).append(ms)
+            stage_bytes[name] = by
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, lat, stage_ms, stage_bytes, res
+
+
+def served_run(ctx, cfg, gx, rx, rn, steps, warmup, torch):
+    for t in [ctx.submit(cfg, gx, rx, ran_nbar=rn) for _ in range(warmup)]:
+        t.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sub, tickets = [], []
+    for _ in range(steps):
+        sub.append(time.perf_counter())
+        tickets.append(ctx.submit(cfg, gx, rx, ran_nbar=rn))
+    done = [None] * steps
+    res = None
+    while any(d is None for d in done):
+        for i, t in enumerate(tickets):
+            if done[i] is None:
+                r = t.poll()
+                if r is not None:
+                    done[i] = time.perf_counter()
+                    res = r
+        time.sleep(2e-4)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = [(d - s) * 1e3 for s, d in zip(sub, done)]
+    return elapsed, lat, res
 
 
 def main():
@@ -67,8 +150,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--lanes", type=int, default=2)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -90,36 +176,45 @@ def main():
     rn = torch.from_numpy(ran["nbar"].astype(np.float32)).to(dev)
     cfg = workload_config(pw, a.workload)
     stream = torch.cuda.current_stream(dev)
+    if a.copy_calibration:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {COPY_BYTES} bytes done")
+        del src, dst
     ctx = pw.Context(0, stream=stream.cuda_stream)
     ctx.set_timing(True)
-    log("warmup", a.warmup)
-    for _ in range(a.warmup):
-        ctx.estimate(cfg, gx, rx, ran_nbar=rn)
-    torch.cuda.synchronize()
-    lat = []
-    stage_ms = {}
-    stage_bytes = {}
-    log("timing", a.steps, "steps")
-    t_start = time.perf_counter()
-    for _ in range(a.steps):
-        t1 = time.perf_counter()
-        res = ctx.estimate(cfg, gx, rx, ran_nbar=rn)
-        lat.append((time.perf_counter() - t1) * 1e3)
-        for name, ms, by in ctx.stages():
-            stage_ms.setdefault(name, []).append(ms)
-            stage_bytes[name] = by
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    log(f"timed {a.steps} steps in {elapsed:.3f}s")
-    value = a.steps / elapsed
+    ctx.set_lanes(a.lanes)
+
+    log("plain: warmup", a.warmup, "then", a.steps, "steps")
+    p_el, p_lat, stage_ms, stage_bytes, res = plain_run(ctx, cfg, gx, rx, rn, a.steps, a.warmup, torch)
+    plain_value = a.steps / p_el
+    log(f"plain {plain_value:.2f} catalogs/s")
+    served = None
+    if not a.no_served:
+        log("served:", a.lanes, "lanes, warmup", a.warmup, "then", a.steps, "catalogs")
+        s_el, s_lat, s_res = served_run(ctx, cfg, gx, rx, rn, a.steps, a.warmup, torch)
+        served = {"value": a.steps / s_el, "ms_per_catalog": s_el * 1e3 / a.steps, "lanes": a.lanes,
+                  "latency_ms": {"p50": float(np.percentile(s_lat, 50)),
+                                 "p99": float(np.percentile(s_lat, 99))},
+                  "arrivals": f"{a.steps} catalogs submitted at once (saturated queue)",
+                  "max_abs_diff_vs_plain": float(np.max(np.abs(s_res["values"] - res["values"])))}
+        log(f"served {served['value']:.2f} catalogs/s")
+
     stages = {n: {"ms": float(np.mean(v)), "GB": stage_bytes[n] / 1e9,
                   "GBps": (stage_bytes[n] / 1e9) / (np.mean(v) / 1e3) if np.mean(v) > 0 else None}
               for n, v in stage_ms.items()}
-    dom = max(stages, key=lambda n: stages[n]["ms"])
+    dom = max((n for n in stages if n in KERNEL_NAMES), key=lambda n: stages[n]["ms"])
     ach = stages[dom]["GBps"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_GB_per_launch": stages[dom]["GB"], "avg_ms": stages[dom]["ms"]}
+    traffic, tsrc = counter_traffic(KERNEL_NAMES[dom])
+    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": KERNEL_NAMES[dom], "algorithmic_bytes_per_launch": stage_bytes[dom],
+                "avg_ms": stages[dom]["ms"], "traffic_source": tsrc}
+    value = served["value"] if served else plain_value
+    elapsed = (a.steps / value)
     out = {
         "metric": METRIC, "value": value, "unit": "catalogs/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": elapsed * 1e3 / a.steps, "higher_is_better": True,
@@ -128,8 +223,14 @@ def main():
                                f"galaxies + {wl.n_gal * wl.ran_ratio:.0e} randoms in a 1/8-sky cone "
                                f"r in [{wl.rmin:g},{wl.rmax:g}], l<=4, order {wl.order} (beta<=2), "
                                f"k {wl.bin_lo}-{wl.bin_lo + wl.n_bins * wl.bin_width:.3f} dk {wl.bin_width}",
-                   "mode": "plain (one pw_estimate per catalog, inputs resident in HBM)"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                   "mode": "served" if served else "plain",
+                   "inputs": "resident in HBM (device pointers)"},
+        "plain": {"value": plain_value, "ms_per_catalog": p_el * 1e3 / a.steps,
+                  "latency_ms": {"p50": float(np.percentile(p_lat, 50)),
+                                 "p99": float(np.percentile(p_lat, 99))}},
+        "served": served,
+        "latency_ms": served["latency_ms"] if served else
+        {"p50": float(np.percentile(p_lat, 50)), "p99": float(np.percentile(p_lat, 99))},
         "roofline": roofline,
         "stages": stages,
         "monopole_first_bins": res["values"][0][:3].tolist(),

@@ -29,8 +29,19 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-ffp-contract=off", "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str) -> str:
+def _deps_mtime() -> float:
+    """Newest mtime of the headers every translation unit may include."""
+    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    paths += [os.path.join(ROOT, "include", "pw.h"), os.path.join(BUILD_DIR, "contract_gen.inc")]
+    return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(os.path.join(CSRC, src)), _deps_mtime())
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
@@ -48,19 +59,28 @@ def _generate():
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"generator build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    r = subprocess.run([exe, os.path.join(BUILD_DIR, "contract_gen.inc")], capture_output=True, text=True)
+    out = os.path.join(BUILD_DIR, "contract_gen.inc")
+    tmp = out + ".new"
+    r = subprocess.run([exe, tmp], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"generator failed\n{r.stdout}\n{r.stderr}")
+    # keep the old file (and its mtime) when nothing changed
+    if os.path.exists(out) and open(out).read() == open(tmp).read():
+        os.remove(tmp)
+    else:
+        os.replace(tmp, out)
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source for gfx950 and link libpw.so (incremental: reuse up-to-date
+    objects; the default rebuilds everything)."""
     if not os.path.exists(HIPCC) and shutil.which("hipcc") is None:
         raise RuntimeError("hipcc not found")
     os.makedirs(BUILD_DIR, exist_ok=True)
     _generate()
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -75,6 +95,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, incremental=a.incremental)
     sys.exit(0)

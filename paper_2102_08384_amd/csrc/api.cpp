@@ -84,6 +84,7 @@ struct Lane {
   double st_ms[kMaxStages] = {};
   double st_bytes[kMaxStages] = {};
   struct Req *cur = nullptr;  // serving lanes: the request in flight
+  int occ_rows = 0, occ_planes = 0;  // occupancy of the most recent estimate (lane 0)
 };
 
 struct Req {
@@ -119,6 +120,7 @@ struct pw_ctx {
   std::deque<Req *> pending;
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
   uint64_t next_ticket = 1;
+  std::map<PlanKey, size_t> plan_bytes_cache;  // plan footprint per configuration
   std::thread worker;
   bool worker_started = false;
   bool stop = false;
@@ -290,6 +292,9 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
       dp->tile_cursor = (int *)alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * sizeof(int));
       dp->tile_slot = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
       dp->tile_blocks = alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * (ts + 2) * (ts + 2) * (ts + 2) * 8);
+      dp->rowmask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
+      dp->rowlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
+      dp->planemask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
       if ((size_t)dp->ntiles * sizeof(int) > ctx->lds_per_block)
         fail(PW_EINVAL, "n_mesh too large for the tile sort on this device (%zu bytes of LDS per block)",
              ctx->lds_per_block);
@@ -402,6 +407,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   mark("paint", 4.0 * isz_g * gal->n + 4.0 * isz_r * ran->n + ncell * rsz);
   ensure_buffer(ctx, &ln.records, &ln.records_bytes, (size_t)(gal->n + ran->n) * 4 * (size_t)rsz);
   launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
+  launch_fill(s, dp->rowmask, (size_t)h.N * h.N, 0);
   launch_tile_count(s, gx, gal->n, gal->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
   launch_tile_count(s, rx, ran->n, ran->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
   launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
@@ -410,23 +416,26 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   launch_tile_scatter(s, rx, ran->n, ran->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1,
                       dp->tile_cursor, ln.records);
   launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ln.records,
-                    dp->norm, dp->tile_blocks, dp->mesh);
+                    dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
+  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->norm);
   // a3 + a4: weighted fields and the forward transforms
   const int N = h.N;
   const Prune &F = h.fwd;
-  const double x1 = (double)h.nfields * N * N * F.nkx * csz;
+  const double x1 = (double)h.nfields * N * N * F.nkx * csz;  // algorithmic (unpadded)
   const double x2 = (double)h.nfields * N * F.npen * csz;
   const double x3 = (double)h.nfields * F.nmodes * csz;
   char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
   mark("fx", ncell * rsz + x1);
-  launch_fx(s, h.prec, N, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, cfg->box_origin, h.H, h.unit,
-            dp->tw);
+  launch_fx(s, h.prec, N, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
+            h.unit, dp->tw, dp->rowlist, dp->norm);
   mark("fy", x1 + x2);
   if (F.npen > 0)
-    launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw);
+    launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
+              dp->rowmask, dp->planemask);
   mark("fz", x2 + x3);
   if (F.npen > 0)
-    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, F.nmodes, dp->tw);
+    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, F.nmodes, dp->tw,
+              dp->planemask);
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
   const size_t nacc = (size_t)(h.nell + 2) * h.n_bins;
   if (h.path == PATH_BIS_PK) {
@@ -467,18 +476,18 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     mark("iz", (real_in ? (double)nzf * F.nmodes * rsz : (double)(nzf + 1) * sfull) +
                    (double)h.n_inplace * sfull + zpart);
     const double sqrt4pi = std::sqrt(4.0 * 3.14159265358979323846);
-    launch_iz(s, h.prec, N, zin, zout, nzf, h.n_inplace, real_in, F.npen, F.nkx,
+    launch_iz(s, h.prec, N, zin, zout, nzf, h.n_inplace, real_in, F.npen, F.nkx, F.rs,
               h.path == PATH_BIS_XI ? nullptr : A, sqrt4pi, h.path == PATH_BIS_XI ? nullptr : dp->winv,
               dp->zrank, npl, dp->tw);
     // inverse y pass into the other buffer (midpoint P: behind the alpha = 0 products)
     void *yout = (zout == B) ? (void *)(A + (size_t)h.n_inplace * sfull_b) : (void *)B;
     mark("iy", (double)h.n_inv * npl * N * F.nkx * csz + ypart);
-    launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, dp->iycnt, dp->iyoff, (int64_t)h.ny * F.nkx,
-              dp->tw);
+    launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, F.rs, dp->iycnt, dp->iyoff,
+              (int64_t)h.ny * F.rs, dp->tw, nullptr, nullptr);
     if (xi) {
       // a8: c2r along x fused with the |D|^alpha y(D^) weighting and FP64 r-binning
       mark("ix_bin", ypart);
-      launch_ix(s, h.prec, N, 1, yout, nullptr, dp->ijobs, (int)h.ijobs.size(), dp->icoef, h.nell, h.nz, h.ny,
+      launch_ix(s, h.prec, N, 1, yout, nullptr, F.rs, dp->ijobs, (int)h.ijobs.size(), dp->icoef, h.nell, h.nz, h.ny,
                 dp->zidx, dp->yidx, h.H, h.unit, inv_n3, dp->bin_of_s2, n_s2, h.n_bins, dp->acc, dp->tw);
       mark("finalize", 0.0);
       launch_finalize_xi(s, dp->acc, h.nell, h.n_bins, h.H * h.H * h.H, dp->norm, dp->out);
@@ -487,7 +496,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
       if (h.n_inv > 0) {
         // g fields in real space (B), then a6: A_{l nu} = sum Phi' y(D^) |D|^alpha g (into Aoff)
         mark("ix", ypart + (double)h.n_inv * ncell * rsz);
-        launch_ix(s, h.prec, N, 0, yout, B, dp->ijobs, (int)h.ijobs.size(), nullptr, h.nell, h.nz, h.ny,
+        launch_ix(s, h.prec, N, 0, yout, B, F.rs, dp->ijobs, (int)h.ijobs.size(), nullptr, h.nell, h.nz, h.ny,
                   dp->zidx, dp->yidx, h.H, h.unit, inv_n3, nullptr, 0, 0, nullptr, dp->tw);
         mark("reweight", (double)(h.n_inv + h.n_a) * ncell * rsz);
         launch_reweight(s, h.prec, N, h.ell_max, h.order, B, Aoff, h.H / h.unit);
@@ -496,14 +505,15 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
                      a3 = (double)h.n_a * P.nmodes * csz;
         mark("afx", (double)h.n_a * ncell * rsz + a1);
-        launch_fx(s, h.prec, N, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, cfg->box_origin, h.H, h.unit,
-                  dp->tw);
+        launch_fx(s, h.prec, N, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
+                  h.unit, dp->tw, nullptr, nullptr);
         mark("afy", a1 + a2);
         if (P.npen > 0)
-          launch_fy(s, h.prec, N, 0, B, Aoff, h.n_a, N, P.nkx, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw);
+          launch_fy(s, h.prec, N, 0, B, Aoff, h.n_a, N, P.nkx, P.rs, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw,
+                    nullptr, nullptr);
         mark("afz", a2 + a3);
         if (P.npen > 0)
-          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, P.nmodes, dp->tw);
+          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, P.nmodes, dp->tw, nullptr);
       }
       // a7 (midpoint): sum_nu y_l^nu(k^) Re[G_{l nu} + A_{l nu}] and FP64 k-binning
       mark("contract", (double)(h.n0 + h.n_a) * h.sph.nmodes * csz + 4.0 * h.sph.nmodes);
@@ -561,8 +571,10 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
   Lane &ln = *ctx->main;
   const PlanKey key = make_key(*cfg);
   if (ln.plans.count(key)) return;
-  const size_t need = footprint_bytes(*cfg, gal->n, ran->n);
   std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->plan_bytes_cache.find(key);
+  if (it == ctx->plan_bytes_cache.end()) it = ctx->plan_bytes_cache.emplace(key, plan_bytes(*cfg)).first;
+  const size_t need = it->second + catalog_bytes(*cfg, gal->n, ran->n);
   while (mem_used(ctx) + need > ctx->budget) {
     Lane *vl = nullptr;
     PlanKey vk;
@@ -590,6 +602,26 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     float ms = -1.0f;
     if (ln.timing) HIPCHECK(hipEventElapsedTime(&ms, ln.ev[i], ln.ev[i + 1]));
     ln.st_ms[i] = ln.timing ? (double)ms : -1.0;
+  }
+  {
+    // forward passes touch only the occupied rows / planes: scale their algorithmic bytes
+    const HostPlan &h = *dp->host;
+    const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+    DevNorm dn;
+    std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
+    const double N = h.N, rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2 * rsz;
+    const double fr = dn.nrows_occ / (N * N), fp = dn.nplanes_occ / N;
+    const double x1 = (double)h.nfields * N * N * h.fwd.nkx * csz;
+    const double x2 = (double)h.nfields * N * h.fwd.npen * csz;
+    const double x3 = (double)h.nfields * h.fwd.nmodes * csz;
+    for (int i = 0; i < ln.n_stages; ++i) {
+      const std::string nm = ln.st_name[i] ? ln.st_name[i] : "";
+      if (nm == "fx") ln.st_bytes[i] = fr * (N * N * N * rsz + x1);
+      else if (nm == "fy") ln.st_bytes[i] = fr * x1 + fp * x2;
+      else if (nm == "fz") ln.st_bytes[i] = fp * x2 + x3;
+    }
+    ln.occ_rows = dn.nrows_occ;
+    ln.occ_planes = dn.nplanes_occ;
   }
   finish_estimate(ln, dp, norm, out, bin_mean, counts);
 }
@@ -879,8 +911,20 @@ int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw
     r->out = out;
     r->bin_mean = bin_mean;
     r->counts = counts;
-    r->need = footprint_bytes(*cfg, 0, 0);
-    size_t whole = footprint_bytes(*cfg, gal->n, ran->n);
+    const PlanKey key = make_key(*cfg);
+    size_t pb = 0;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      auto it = ctx->plan_bytes_cache.find(key);
+      if (it != ctx->plan_bytes_cache.end()) pb = it->second;
+    }
+    if (!pb) {
+      pb = plan_bytes(*cfg);
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->plan_bytes_cache[key] = pb;
+    }
+    r->need = pb;
+    size_t whole = pb + catalog_bytes(*cfg, gal->n, ran->n);
     if (whole > ctx->budget) fail(PW_ENOMEM, "request needs %zu bytes, budget is %zu", whole, ctx->budget);
     std::lock_guard<std::mutex> lk(ctx->mu);
     start_worker(ctx);

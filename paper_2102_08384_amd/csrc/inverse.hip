@@ -26,7 +26,7 @@ void upload_sh_const_inverse(const ShConst &c) {
 template <typename R, int N>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int n_inplace, int64_t npen,
-     int nkx, const cplx<R> *D, R d_scale, const R *__restrict__ winv, const int *__restrict__ zrank, int nz,
+     int nkx, int rs, const cplx<R> *D, R d_scale, const R *__restrict__ winv, const int *__restrict__ zrank, int nz,
      const cplx<R> *__restrict__ tw) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
   constexpr int LOGN = log2i(N);
@@ -46,15 +46,16 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
       lds[kz * (C + 1) + cc] = (e < nval) ? src[(size_t)q0 * N + e] : mk<R>(0, 0);
     }
   };
+  // output position of this lane's pencil in a padded plane: ky * rs + kx
+  const int qky = (int)(q / nkx), qkx = (int)(q - (int64_t)qky * nkx);
+  const int64_t qo = (int64_t)qky * rs + qkx;
+  const int64_t plane_o = (int64_t)N * rs;
   cplx<R> dv[8];
   if (D) {
     load_chunk(D);
     sync();
     R iwxy = (R)1;
-    if (winv && q < npen) {
-      const int ky = (int)(q / nkx), kx = (int)(q - (int64_t)ky * nkx);
-      iwxy = winv[kx] * winv[ky];
-    }
+    if (winv && q < npen) iwxy = winv[qkx] * winv[qky];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int kz = t + s * T;
@@ -102,11 +103,11 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
     }
     fft_pencil<R, N, true>(v, t, tw, at, sync);
     if (q < npen) {
-      cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * npen;
+      cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * plane_o;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int zr = zrank[t + s * T];
-        if (zr >= 0) dst[(size_t)zr * npen + q] = v[s];
+        if (zr >= 0) dst[(size_t)zr * plane_o + qo] = v[s];
       }
     }
   }
@@ -114,25 +115,25 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
 
 template <typename R, int N>
 static void iz_launch(hipStream_t s, void *in, void *out, int nfields, int n_inplace, int real_in, int64_t npen,
-                      int nkx, const void *D, double d_scale, const void *winv, const int *zrank, int nz,
+                      int nkx, int rs, const void *D, double d_scale, const void *winv, const int *zrank, int nz,
                       const void *tw) {
   constexpr int C = ColShape<R, N>::C;
   dim3 grid((unsigned)((npen + C - 1) / C));
   hipLaunchKernelGGL((k_iz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s,
                      real_in ? (cplx<R> *)nullptr : (cplx<R> *)in, real_in ? (const R *)in : (const R *)nullptr,
-                     (cplx<R> *)out, nfields, n_inplace, npen, nkx, (const cplx<R> *)D, (R)d_scale,
+                     (cplx<R> *)out, nfields, n_inplace, npen, nkx, rs, (const cplx<R> *)D, (R)d_scale,
                      (const R *)winv, zrank, nz, (const cplx<R> *)tw);
 }
 
 void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields, int n_inplace, int real_in,
-               int64_t npen, int nkx, const void *D, double d_scale, const void *winv, const int *zrank, int nz,
-               const void *tw) {
+               int64_t npen, int nkx, int rs, const void *D, double d_scale, const void *winv, const int *zrank,
+               int nz, const void *tw) {
   if (nfields <= 0 || npen <= 0) return;
   if (prec == 0) {
-    PW_DISPATCH_N(iz_launch, float, s, in, out, nfields, n_inplace, real_in, npen, nkx, D, d_scale, winv, zrank,
-                  nz, tw)
+    PW_DISPATCH_N(iz_launch, float, s, in, out, nfields, n_inplace, real_in, npen, nkx, rs, D, d_scale, winv,
+                  zrank, nz, tw)
   } else {
-    PW_DISPATCH_N(iz_launch, double, s, in, out, nfields, n_inplace, real_in, npen, nkx, D, d_scale, winv,
+    PW_DISPATCH_N(iz_launch, double, s, in, out, nfields, n_inplace, real_in, npen, nkx, rs, D, d_scale, winv,
                   zrank, nz, tw)
   }
 }
@@ -142,7 +143,7 @@ constexpr int kMaxEll = 5;  // multipoles 0, 2, .., 8
 
 template <typename R, int N, int MODE>
 __global__ void __launch_bounds__(FxShape<N>::THREADS)
-k_ix(const cplx<R> *__restrict__ in, R *__restrict__ out, const FieldJob *__restrict__ jobs, int njobs,
+k_ix(const cplx<R> *__restrict__ in, R *__restrict__ out, int rs, const FieldJob *__restrict__ jobs, int njobs,
      const R *__restrict__ coef, int nell, int nz, int ny, const int *__restrict__ zidx,
      const int *__restrict__ yidx, R Hu, double Hd, R scale, const int *__restrict__ bin_of_s2, int64_t n_s2,
      int nbins, double *__restrict__ acc, const cplx<R> *__restrict__ tw) {
@@ -187,11 +188,11 @@ k_ix(const cplx<R> *__restrict__ in, R *__restrict__ out, const FieldJob *__rest
   }
   ShRec8<R> rec;
   rec.init();
-  const size_t fstride = (size_t)nrows * NKX;
+  const size_t fstride = (size_t)nrows * rs;  // rows padded to rs
   for (int jb = 0; jb < njobs; ++jb) {
     const FieldJob J = jobs[jb];
-    const cplx<R> *ha = in + (size_t)J.pa * fstride + (size_t)row * NKX;
-    const cplx<R> *hb = in + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * NKX;
+    const cplx<R> *ha = in + (size_t)J.pa * fstride + (size_t)row * rs;
+    const cplx<R> *hb = in + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * rs;
     // Z = Ha + i Hb on the full x range from the half spectra (Ha(-k) = conj Ha(k) after the
     // y and z inverse passes of a real field); the self-conjugate kx = 0, N/2 keep real parts.
     for (int kx = t; kx < NKX; kx += T) {
@@ -289,7 +290,7 @@ k_ix(const cplx<R> *__restrict__ in, R *__restrict__ out, const FieldJob *__rest
 }
 
 template <typename R, int N>
-static void ix_launch(hipStream_t s, int mode, const void *in, void *out, const FieldJob *jobs, int njobs,
+static void ix_launch(hipStream_t s, int mode, const void *in, void *out, int rs, const FieldJob *jobs, int njobs,
                       const void *coef, int nell, int nz, int ny, const int *zidx, const int *yidx, double H,
                       double unit, double scale, const int *bin_of_s2, int64_t n_s2, int nbins, double *acc,
                       const void *tw) {
@@ -298,26 +299,26 @@ static void ix_launch(hipStream_t s, int mode, const void *in, void *out, const 
   dim3 grid((unsigned)((nrows + ROWS - 1) / ROWS));
   if (mode == 0) {
     hipLaunchKernelGGL((k_ix<R, N, 0>), grid, dim3(FxShape<N>::THREADS), 0, s, (const cplx<R> *)in, (R *)out,
-                       jobs, njobs, (const R *)coef, nell, nz, ny, zidx, yidx, (R)(H / unit), H, (R)scale, bin_of_s2,
+                       rs, jobs, njobs, (const R *)coef, nell, nz, ny, zidx, yidx, (R)(H / unit), H, (R)scale, bin_of_s2,
                        n_s2, nbins, acc, (const cplx<R> *)tw);
   } else {
     size_t sh = (size_t)(nell + 2) * nbins * sizeof(double);
     hipLaunchKernelGGL((k_ix<R, N, 1>), grid, dim3(FxShape<N>::THREADS), sh, s, (const cplx<R> *)in, (R *)out,
-                       jobs, njobs, (const R *)coef, nell, nz, ny, zidx, yidx, (R)(H / unit), H, (R)scale, bin_of_s2,
+                       rs, jobs, njobs, (const R *)coef, nell, nz, ny, zidx, yidx, (R)(H / unit), H, (R)scale, bin_of_s2,
                        n_s2, nbins, acc, (const cplx<R> *)tw);
   }
 }
 
-void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *out, const FieldJob *jobs,
+void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *out, int rs, const FieldJob *jobs,
                int njobs, const void *coef, int nell, int nz, int ny, const int *zidx, const int *yidx, double H,
                double unit, double scale, const int *bin_of_s2, int64_t n_s2, int nbins, double *acc,
                const void *tw) {
   if (njobs <= 0 || nz <= 0 || ny <= 0 || nell > kMaxEll) return;
   if (prec == 0) {
-    PW_DISPATCH_N(ix_launch, float, s, mode, in, out, jobs, njobs, coef, nell, nz, ny, zidx, yidx, H, unit, scale,
+    PW_DISPATCH_N(ix_launch, float, s, mode, in, out, rs, jobs, njobs, coef, nell, nz, ny, zidx, yidx, H, unit, scale,
                   bin_of_s2, n_s2, nbins, acc, tw)
   } else {
-    PW_DISPATCH_N(ix_launch, double, s, mode, in, out, jobs, njobs, coef, nell, nz, ny, zidx, yidx, H, unit, scale,
+    PW_DISPATCH_N(ix_launch, double, s, mode, in, out, rs, jobs, njobs, coef, nell, nz, ny, zidx, yidx, H, unit, scale,
                   bin_of_s2, n_s2, nbins, acc, tw)
   }
 }

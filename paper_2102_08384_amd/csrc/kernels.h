@@ -21,6 +21,8 @@ struct DevNorm {
   double sum_wg, sum_wr;
   double fix_scale;  // 2^e: painting accumulates round(contribution * fix_scale) in int64
   int flags;         // bit 0: particle outside the box, bit 1: extent > L/2 (midpoint P)
+  int nrows_occ;     // x-rows (z, y) of the mesh with a non-zero node
+  int nplanes_occ;   // z-planes of the mesh with a non-zero node
   int pad;
 };
 
@@ -66,22 +68,44 @@ void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, 
                          const double *b0, double H, int assign, const DevNorm *norm,
                          int is_random, int *cursor, void *records);
 // blocks: scratch of ntiles * (TS+2)^3 int64 values; slot: [ntiles + 1] from the scan.
+// rowmask (N*N ints, zeroed by the caller; may be null) receives 1 for every x-row (z, y)
+// holding a non-zero node.
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
-                       const void *records, const DevNorm *norm, void *blocks, void *mesh);
+                       const void *records, const DevNorm *norm, void *blocks, void *mesh, int *rowmask);
+// Survey occupancy: rowlist = the non-empty rows in increasing order, planemask[z] = 1 for
+// z-planes with a non-empty row; counts into norm->nrows_occ / nplanes_occ.  Every field of
+// the forward transforms is the mesh times a weight, so it vanishes exactly on empty rows.
+void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, DevNorm *norm);
 
-// Fused weighting + r2c along x: out[p][z][y][kx], kx < nkx.  Radial weights are taken in the
+// Row strides: every row of a half spectrum (kx = 0 .. nkx-1) starts at a multiple of `rs`
+// complex values, rs >= nkx rounded up to 128 bytes, so that column-pencil passes read whole
+// cache lines.
+inline int row_stride(int nkx, int prec) {
+  const int q = prec == 0 ? 16 : 8;
+  return (nkx + q - 1) / q * q;
+}
+
+// Fused weighting + r2c along x: out[p][z][y * rs + kx], kx < nkx.  Radial weights are taken in the
 // length unit `unit`: (unit / 2r)^alpha (the inverse passes use (|D| / unit)^alpha, so every
 // product (2r)^-alpha |D|^alpha is unchanged while fields of every alpha stay O(1)).
+// rowlist (may be null: every row) restricts the pass to the non-empty rows; the output rows of
+// empty ones are not written (the y pass reads them as zeros).
 void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
-               int njobs, int nkx, const double *b0, double H, double unit, const void *tw);
+               int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
+               const int *rowlist, const DevNorm *norm);
 // c2c along y (forward, or inverse when inv), on nplanes planes per field:
-// in[p][plane][y][kx] -> out[p][plane][yoff[y'] + kx] for kx < ycnt[y'] (y' the output index).
+// in[p][plane][y * rs + kx] -> out[p][plane][yoff[y'] + kx] for kx < ycnt[y'] (y' the output
+// index, npen values per output plane).
+// rowmask / planemask (forward pass only; may be null): empty input rows are read as zeros and
+// empty planes are skipped (their output is not written; the z pass reads them as zeros).
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields,
-               int nplanes, int nkx, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw);
+               int nplanes, int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen,
+               const void *tw, const int *rowmask, const int *planemask);
 // c2c along z, pruned: out[p][moff[q] + j], j < pinfo[q].kzcnt.
+// planemask (may be null): empty z-planes of the input are read as zeros.
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
                int64_t npen, const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes,
-               const void *tw);
+               const void *tw, const int *planemask);
 
 // Bisector contraction + FP64 k-binning.
 struct TermTable {
@@ -114,16 +138,17 @@ int mid_reweight_nfields(int lmax, int order);
 //   D != null: Z = conj(d_scale * D) * in / W(k)^2 (D is read before anything is written);
 //   fields p < n_inplace get Z written back in place and are not transformed;
 //   real_in: the input holds real values (imaginary part zero).
-// Other fields: inverse FFT along z, out[p - n_inplace][zrank[z]][q] for retained z.
+// Other fields: inverse FFT along z, out[p - n_inplace][zrank[z]][ky * rs + kx] for retained z
+// (N * rs values per output plane).
 void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields, int n_inplace,
-               int real_in, int64_t npen, int nkx, const void *D, double d_scale, const void *winv,
-               const int *zrank, int nz, const void *tw);
-// Inverse x pass (complex-to-real) of pair jobs on the rows (zr, yr) of in[p][zr][yr][kx],
+               int real_in, int64_t npen, int nkx, int rs, const void *D, double d_scale,
+               const void *winv, const int *zrank, int nz, const void *tw);
+// Inverse x pass (complex-to-real) of pair jobs on the rows (zr, yr) of in[p][zr][yr * rs + kx],
 // kx <= N/2, scaled by `scale`.
 //   mode 0: out[p][z][y][x] real fields (nz = ny = N).
 //   mode 1: X_l += coef[j][side][l] (|D| / unit)^alpha y_J^mu(D^) h, then FP64 r-binning of
 //           X_l into acc[l][b], acc[nell][b] (count), acc[nell + 1][b] (sum |D|).
-void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *out,
+void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *out, int rs,
                const FieldJob *jobs, int njobs, const void *coef, int nell, int nz, int ny,
                const int *zidx, const int *yidx, double H, double unit, double scale, const int *bin_of_s2,
                int64_t n_s2, int nbins, double *acc, const void *tw);

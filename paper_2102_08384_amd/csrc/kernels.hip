@@ -25,12 +25,21 @@ void upload_sh_const(const ShConst &c) {
 template <typename R, int N>
 __global__ void __launch_bounds__(FxShape<N>::THREADS)
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
-     int njobs, int nkx, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw) {
+     int njobs, int nkx, int rs, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw,
+     const int *__restrict__ rowlist, const DevNorm *__restrict__ norm) {
   constexpr int T = FxShape<N>::T, ROWS = FxShape<N>::ROWS;
   constexpr int LN = N + N / 8;
   __shared__ cplx<R> lds[ROWS * LN];
   const int rl = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = blockIdx.x * ROWS + rl;  // row = z * N + y (grid covers N*N exactly)
+  // row = z * N + y: every row (grid covers N*N exactly), or the non-empty rows in order
+  int row = blockIdx.x * ROWS + rl;
+  bool live = true;
+  if (rowlist) {
+    const int nr = norm->nrows_occ;
+    if ((int)blockIdx.x * ROWS >= nr) return;  // uniform for the block: before any barrier
+    live = row < nr;
+    row = live ? rowlist[row] : 0;
+  }
   const int y = row & (N - 1), z = row / N;
   cplx<R> *my = lds + rl * LN;
   auto at = [my](int i) -> cplx<R> & { return my[i + (i >> 3)]; };
@@ -41,7 +50,7 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int x = t + s * T;
-    f[s] = mesh[(size_t)row * N + x];
+    f[s] = live ? mesh[(size_t)row * N + x] : (R)0;
     const R px = b0x + (R)x * H;
     const R r = sqrt(px * px + py * py + pz * pz);
     if (r > (R)0) {
@@ -53,7 +62,7 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
       inv2r[s] = 0;
     }
   }
-  const size_t fstride = (size_t)N * N * nkx;
+  const size_t fstride = (size_t)N * N * rs;  // rows padded to rs (128-byte aligned)
   // Recurrence state carried across jobs (jobs come sorted by m, then J).
   ShRec8<R> rec;
   rec.init();
@@ -65,7 +74,7 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
       const R *fa = mesh + (size_t)J.Ja * N * N * N + (size_t)row * N;
       const R *fb = mesh + (size_t)(J.Jb < 0 ? 0 : J.Jb) * N * N * N + (size_t)row * N;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) v[s] = mk<R>(fa[t + s * T], J.Jb >= 0 ? fb[t + s * T] : (R)0);
+      for (int s = 0; s < 8; ++s) v[s] = mk<R>(fa[t + s * T], J.Jb >= 0 ? fb[t + s * T] : (R)0);  // dense
     } else {
       R wa[8], wb[8];
 #pragma unroll
@@ -101,9 +110,9 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 #pragma unroll
     for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
     __syncthreads();
-    cplx<R> *oa = out + (size_t)J.pa * fstride + (size_t)row * nkx;
-    cplx<R> *ob = out + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * nkx;
-    for (int kx = t; kx < nkx; kx += T) {
+    cplx<R> *oa = out + (size_t)J.pa * fstride + (size_t)row * rs;
+    cplx<R> *ob = out + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * rs;
+    for (int kx = t; live && kx < nkx; kx += T) {
       const cplx<R> a = at(kx), b = at((N - kx) & (N - 1));
       // A = (Z(k) + conj Z(N-k)) / 2,  B = (Z(k) - conj Z(N-k)) / (2i)
       oa[kx] = mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y));
@@ -115,34 +124,43 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 
 template <typename R, int N>
 static void fx_launch(hipStream_t s, const void *mesh, void *out, const FieldJob *jobs, int njobs,
-                      int nkx, const double *b0, double H, double unit, const void *tw) {
+                      int nkx, int rs, const double *b0, double H, double unit, const void *tw,
+                      const int *rowlist, const DevNorm *norm) {
   constexpr int ROWS = FxShape<N>::ROWS;
   unsigned blocks = (unsigned)((size_t)N * N / ROWS);
   hipLaunchKernelGGL((k_fx<R, N>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
-                     (cplx<R> *)out, jobs, njobs, nkx, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
-                     (const cplx<R> *)tw);
+                     (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
+                     (const cplx<R> *)tw, rowlist, norm);
 }
 
 void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
-               int njobs, int nkx, const double *b0, double H, double unit, const void *tw) {
-  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, mesh, out, jobs, njobs, nkx, b0, H, unit, tw) }
-  else { PW_DISPATCH_N(fx_launch, double, s, mesh, out, jobs, njobs, nkx, b0, H, unit, tw) }
+               int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
+               const int *rowlist, const DevNorm *norm) {
+  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
+  else { PW_DISPATCH_N(fx_launch, double, s, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
 }
 
 // ------------------------------------------------------------------------------ fy / fz
 template <typename R, int N, bool INV>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
-k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, const int *__restrict__ ycnt,
-     const int64_t *__restrict__ yoff, int64_t npen, const cplx<R> *__restrict__ tw) {
+k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, int rs, const int *__restrict__ ycnt,
+     const int64_t *__restrict__ yoff, int64_t npen, const cplx<R> *__restrict__ tw,
+     const int *__restrict__ rowmask, const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C;
   __shared__ cplx<R> lds[N * (C + 1)];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + c;
-  const size_t plane = (size_t)blockIdx.z * gridDim.y + blockIdx.y;  // field * nplanes + plane
-  const cplx<R> *src = in + plane * N * nkx;
+  const int z = blockIdx.y;
+  if (planemask && !planemask[z]) return;  // uniform for the block: before any barrier
+  const size_t plane = (size_t)blockIdx.z * gridDim.y + z;  // field * nplanes + plane
+  const cplx<R> *src = in + plane * N * rs;  // input rows padded to rs
   cplx<R> v[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) v[s] = (kx < nkx) ? src[(size_t)(t + s * T) * nkx + kx] : mk<R>(0, 0);
+  for (int s = 0; s < 8; ++s) {
+    const int y = t + s * T;
+    const bool ok = kx < nkx && (!rowmask || rowmask[z * N + y]);
+    v[s] = ok ? src[(size_t)y * rs + kx] : mk<R>(0, 0);
+  }
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
   fft_pencil<R, N, INV>(v, t, tw, at, sync);
@@ -156,29 +174,36 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, const i
 
 template <typename R, int N>
 static void fy_launch(hipStream_t s, int inv, const void *in, void *out, int nfields, int nplanes, int nkx,
-                      const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw) {
+                      int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
+                      const int *rowmask, const int *planemask) {
   constexpr int C = ColShape<R, N>::C;
   dim3 grid((nkx + C - 1) / C, nplanes, nfields);
   if (inv)
     hipLaunchKernelGGL((k_fy<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                       (cplx<R> *)out, nkx, ycnt, yoff, npen, (const cplx<R> *)tw);
+                       (cplx<R> *)out, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw, rowmask, planemask);
   else
     hipLaunchKernelGGL((k_fy<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                       (cplx<R> *)out, nkx, ycnt, yoff, npen, (const cplx<R> *)tw);
+                       (cplx<R> *)out, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw, rowmask, planemask);
 }
 
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields, int nplanes,
-               int nkx, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw) {
+               int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
+               const int *rowmask, const int *planemask) {
   if (nfields <= 0 || nplanes <= 0) return;
-  if (prec == 0) { PW_DISPATCH_N(fy_launch, float, s, inv, in, out, nfields, nplanes, nkx, ycnt, yoff, npen, tw) }
-  else { PW_DISPATCH_N(fy_launch, double, s, inv, in, out, nfields, nplanes, nkx, ycnt, yoff, npen, tw) }
+  if (prec == 0) {
+    PW_DISPATCH_N(fy_launch, float, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
+                  planemask)
+  } else {
+    PW_DISPATCH_N(fy_launch, double, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
+                  planemask)
+  }
 }
 
 template <typename R, int N>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int64_t npen,
      const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, int64_t nmodes,
-     const cplx<R> *__restrict__ tw) {
+     const cplx<R> *__restrict__ tw, const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
   __shared__ cplx<R> lds[N * (C + 1)];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
@@ -188,7 +213,10 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int64_t npen,
   const cplx<R> *src = in + (size_t)p * N * npen;
   cplx<R> v[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) v[s] = (q < npen) ? src[(size_t)(t + s * T) * npen + q] : mk<R>(0, 0);
+  for (int s = 0; s < 8; ++s) {
+    const int z = t + s * T;
+    v[s] = (q < npen && (!planemask || planemask[z])) ? src[(size_t)z * npen + q] : mk<R>(0, 0);
+  }
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
   fft_pencil<R, N, false>(v, t, tw, at, sync);
@@ -211,17 +239,19 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int64_t npen,
 
 template <typename R, int N>
 static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int64_t npen,
-                      const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes, const void *tw) {
+                      const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes, const void *tw,
+                      const int *planemask) {
   constexpr int C = ColShape<R, N>::C;
   dim3 grid((unsigned)((npen + C - 1) / C), nfields);
   hipLaunchKernelGGL((k_fz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                     (cplx<R> *)out, npen, pinfo, moff, nmodes, (const cplx<R> *)tw);
+                     (cplx<R> *)out, npen, pinfo, moff, nmodes, (const cplx<R> *)tw, planemask);
 }
 
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int64_t npen,
-               const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes, const void *tw) {
-  if (prec == 0) { PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, nmodes, tw) }
-  else { PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, nmodes, tw) }
+               const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes, const void *tw,
+               const int *planemask) {
+  if (prec == 0) { PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, nmodes, tw, planemask) }
+  else { PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, nmodes, tw, planemask) }
 }
 
 // ------------------------------------------------------------------------------ contraction

@@ -114,6 +114,8 @@ __global__ void k_finalize_norm(const double *pg, const double *pr, DevNorm *nor
   e = e > 1000 ? 1000 : (e < -1000 ? -1000 : e);
   n.fix_scale = ldexp(1.0, e);
   n.flags = flags;
+  n.nrows_occ = 0;
+  n.nplanes_occ = 0;
   n.pad = 0;
   *norm = n;
 }
@@ -342,7 +344,8 @@ __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restric
 template <typename RM>
 __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const int *__restrict__ slot,
                                                      const unsigned long long *__restrict__ blocks,
-                                                     const DevNorm *__restrict__ norm, RM *__restrict__ mesh) {
+                                                     const DevNorm *__restrict__ norm, RM *__restrict__ mesh,
+                                                     int *__restrict__ rowmask) {
   const int N = 1 << lgN, ts = 1 << lgts, nt = N >> lgts, E = ts + 2;
   const size_t E3 = (size_t)E * E * E;
   const size_t ncell = (size_t)1 << (3 * lgN);
@@ -369,7 +372,50 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const in
           v += blocks[(size_t)sl * E3 + ((size_t)ez * E + ey) * E + ex];
         }
     mesh[g] = (RM)((double)(long long)v * inv);
+    if (rowmask && v != 0) rowmask[g >> lgN] = 1;  // every writer stores the same value
   }
+}
+
+// One block: compact the non-empty rows (in order) and mark the non-empty planes.
+constexpr int kOccThreads = 1024;
+__global__ void __launch_bounds__(kOccThreads) k_occupancy(int N, const int *__restrict__ rowmask,
+                                                           int *__restrict__ rowlist, int *__restrict__ planemask,
+                                                           DevNorm *__restrict__ norm) {
+  __shared__ int part[kOccThreads];
+  __shared__ int nplanes;
+  const int nrows = N * N;
+  const int chunk = (nrows + kOccThreads - 1) / kOccThreads;
+  const int lo = threadIdx.x * chunk, hi = min(lo + chunk, nrows);
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) cnt += rowmask[i] != 0;
+  part[threadIdx.x] = cnt;
+  if (threadIdx.x == 0) nplanes = 0;
+  __syncthreads();
+  // inclusive scan of the per-thread counts (Hillis-Steele in LDS)
+  for (int off = 1; off < kOccThreads; off <<= 1) {
+    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int o = part[threadIdx.x] - cnt;
+  for (int i = lo; i < hi; ++i)
+    if (rowmask[i] != 0) rowlist[o++] = i;
+  for (int z = threadIdx.x; z < N; z += kOccThreads) {
+    int any = 0;
+    for (int y = 0; y < N; ++y) any |= rowmask[z * N + y];
+    planemask[z] = any != 0;
+    if (any) atomicAdd(&nplanes, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    norm->nrows_occ = part[kOccThreads - 1];
+    norm->nplanes_occ = nplanes;
+  }
+}
+
+void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, DevNorm *norm) {
+  hipLaunchKernelGGL(k_occupancy, dim3(1), dim3(kOccThreads), 0, s, N, rowmask, rowlist, planemask, norm);
 }
 
 void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,
@@ -417,7 +463,7 @@ static int ilog2(int v) {
 }
 
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
-                       const void *records, const DevNorm *norm, void *blocks, void *mesh) {
+                       const void *records, const DevNorm *norm, void *blocks, void *mesh, int *rowmask) {
   const int ts = tile_size(N);
   const int nt = N / ts;
   const unsigned ntiles = (unsigned)(nt * nt * nt);
@@ -433,10 +479,10 @@ void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *of
 #undef PW_TP
   if (prec == 0)
     hipLaunchKernelGGL(k_tile_gather<float>, dim3(gblocks), dim3(256), 0, s, ilog2(N), ilog2(ts), slot, b, norm,
-                       (float *)mesh);
+                       (float *)mesh, rowmask);
   else
     hipLaunchKernelGGL(k_tile_gather<double>, dim3(gblocks), dim3(256), 0, s, ilog2(N), ilog2(ts), slot, b,
-                       norm, (double *)mesh);
+                       norm, (double *)mesh, rowmask);
 }
 
 }  // namespace pw

@@ -34,12 +34,13 @@ int path_of(const pw_config &c) {
 // compact index of (l, nu) over even l = 0, 2, ..: l(l-1)/2 + l + nu
 int even_index(int l, int nu) { return l * (l - 1) / 2 + l + nu; }
 
-Prune make_prune(int N, int64_t K2, bool full, bool coords) {
+Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
   Prune p;
   p.full = full;
   if (full) K2 = 3LL * (N / 2) * (N / 2);
   K2 = std::max<int64_t>(K2, 0);
   p.nkx = full ? N / 2 + 1 : (int)std::min<int64_t>(N / 2 + 1, isqrt64(K2) + 1);
+  p.rs = row_stride(p.nkx, prec);
   p.ycnt.assign(N, 0);
   p.yoff.assign(N, 0);
   int64_t off = 0;
@@ -259,8 +260,8 @@ HostPlan build_host_plan(const pw_config &c) {
   sort_jobs(h.jobs);
 
   // ------------------------------------------------------------------ retention
-  h.fwd = make_prune(N, h.K2, h.path != PATH_BIS_PK, h.path == PATH_BIS_PK);
-  if (h.path == PATH_MID_PK) h.sph = make_prune(N, h.K2, false, true);
+  h.fwd = make_prune(N, h.K2, h.path != PATH_BIS_PK, h.path == PATH_BIS_PK, c.prec);
+  if (h.path == PATH_MID_PK) h.sph = make_prune(N, h.K2, false, true, c.prec);
 
   // ------------------------------------------------------------------ inverse transforms
   if (h.path != PATH_BIS_PK) {
@@ -279,13 +280,13 @@ HostPlan build_host_plan(const pw_config &c) {
       h.zrank[z] = j;
     }
     h.yidx = h.zidx;
-    const int nkx = h.fwd.nkx;
+    const int nkx = h.fwd.nkx, rs = h.fwd.rs;
     h.iycnt.assign(N, 0);
     h.iyoff.assign(N, 0);
     for (int y = 0; y < N; ++y)
       if (h.zrank[y] >= 0) {
         h.iycnt[y] = nkx;
-        h.iyoff[y] = (int64_t)h.zrank[y] * nkx;
+        h.iyoff[y] = (int64_t)h.zrank[y] * rs;
       }
   }
   if (h.path == PATH_MID_PK || h.path == PATH_MID_XI) {
@@ -366,7 +367,8 @@ HostPlan build_host_plan(const pw_config &c) {
   const size_t rsz = h.prec == PW_FP32 ? 4 : 8, csz = 2 * rsz;
   if (h.path == PATH_MID_PK && h.n_a > 0) {
     const size_t sfull = (size_t)N * N * h.fwd.nkx * csz;
-    if ((size_t)h.n_a * N * N * N * rsz > (size_t)h.n_inv * sfull)
+    if ((size_t)h.n_a * N * N * N * rsz > (size_t)h.n_inv * sfull ||
+        (size_t)h.n_a * N * N * h.sph.rs * csz > spectrum_buffer_bytes(h))
       plan_fail(PW_EINVAL, "internal: A fields do not fit the spectrum buffer");
   }
   return h;
@@ -374,13 +376,13 @@ HostPlan build_host_plan(const pw_config &c) {
 
 size_t spectrum_buffer_bytes(const HostPlan &h) {
   const size_t csz = h.prec == PW_FP32 ? 8 : 16;
-  const size_t x1 = (size_t)h.nfields * h.N * h.N * h.fwd.nkx * csz;
+  const size_t x1 = (size_t)h.nfields * h.N * h.N * h.fwd.rs * csz;
   const size_t x2 = (size_t)h.nfields * h.N * h.fwd.npen * csz;
   const size_t x3 = (size_t)h.nfields * h.fwd.nmodes * csz;
   return std::max<size_t>(std::max(x1, std::max(x2, x3)), 16);
 }
 
-size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
+size_t plan_bytes(const pw_config &c) {
   HostPlan h = build_host_plan(c);
   const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
   const int ts = tile_size(h.N), nt = h.N / ts;
@@ -388,8 +390,17 @@ size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
   b += h.fwd.modecoord.size() * 4 + h.sph.modecoord.size() * 4 + h.bin_of_s2.size() * 4 +
        (h.fwd.pinfo.size() + h.sph.pinfo.size()) * 24;
   b += (size_t)nt * nt * nt * ((ts + 2) * (ts + 2) * (ts + 2) * 8 + 16);
-  b += (size_t)(n_gal + n_ran) * 4 * rsz * 2 + (size_t)n_ran * rsz;
   return b;
+}
+
+size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
+  const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
+  // tile-sorted records + staging of host catalogs (+ nbar)
+  return (size_t)(n_gal + n_ran) * 4 * rsz * 2 + (size_t)n_ran * rsz;
+}
+
+size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
+  return plan_bytes(c) + catalog_bytes(c, n_gal, n_ran);
 }
 
 }  // namespace pw

@@ -38,6 +38,7 @@ enum Path { PATH_BIS_PK = 0, PATH_MID_PK = 1, PATH_MID_XI = 2, PATH_BIS_XI = 3 }
 struct Prune {
   bool full = false;
   int nkx = 0;
+  int rs = 0;                       // padded row stride of the x-pass output (complex values)
   std::vector<int> ycnt;
   std::vector<int64_t> yoff;
   int64_t npen = 0;
@@ -72,7 +73,7 @@ struct HostPlan {
   int nz, ny;                // retained z planes / y rows of the inverse outputs
   std::vector<int> zrank, zidx, yidx;   // index -> rank (-1: dropped) ; rank -> index
   std::vector<int> iycnt;    // per y index: nkx if retained else 0
-  std::vector<int64_t> iyoff;  // per y index: rank * nkx
+  std::vector<int64_t> iyoff;  // per y index: rank * rs
   std::vector<FieldJob> ijobs;   // pair jobs of the inverse x pass (indices into the stack)
   std::vector<double> icoef;     // xi: [ijob][2][nell] per-field multipole coefficients
   int n_targets;             // bisector xi: T_{l nu} spectra
@@ -83,6 +84,8 @@ struct HostPlan {
 
 HostPlan build_host_plan(const pw_config &c);
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
+size_t plan_bytes(const pw_config &c);       // device bytes of one plan (tables + work buffers)
+size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);  // records + staging
 // bytes of each of the two spectrum buffers
 size_t spectrum_buffer_bytes(const HostPlan &h);
 
@@ -114,6 +117,7 @@ struct DevPlan {
   int *tile_counts = nullptr, *tile_offsets = nullptr, *tile_cursor = nullptr, *tile_slot = nullptr;
   void *tile_blocks = nullptr;
   int ntiles = 0;
+  int *rowmask = nullptr, *rowlist = nullptr, *planemask = nullptr;  // survey occupancy
 };
 
 }  // namespace pw
