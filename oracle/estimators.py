@@ -3,7 +3,8 @@
 Each function follows the paper's boxed estimator step by step on full complex
 grids, summing over every m and M:
 
-* ``pk_bisector``  Section 5.2 boxed estimator:
+* ``pk_bisector``  Section 5.2 boxed estimator (``pk_bisector_shells``: the same, keeping
+  only the modes of the k-bins of every transform, for large meshes):
   P_l(k) = (4pi/I) <Re sum_m Y_l^{m*}(k^) sum_{beta J1 J2 M} B F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)> - d_l0 S/I.
 * ``pk_midpoint``  Section 3.3 boxed parity-even estimator:
   g^alpha_{JM} = (-1)^J IFT[d*(k) F[(2r)^-alpha Y_J^M d](k)]   (Section 3.2),
@@ -33,10 +34,11 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
+import scipy.fft
 
 from . import coeffs
 from .mesh import (paint, node_positions, kgrid, separation_grid, window, neg_k,
-                   k_bin_index, r_bin_index)
+                   k_bin_index, r_bin_index, signed_index)
 from .ylm import Ylm
 
 FOURPI = 4.0 * math.pi
@@ -100,8 +102,18 @@ def _compensation(cfg: Config):
     return None
 
 
+def fftn(x):
+    """Unnormalised forward n-D DFT, numpy's sign convention (pocketfft, every host core)."""
+    return scipy.fft.fftn(x, workers=-1)
+
+
+def ifftn(x):
+    """Inverse n-D DFT with the 1/N^3 factor, numpy's convention."""
+    return scipy.fft.ifftn(x, workers=-1)
+
+
 def _fft(x, comp):
-    X = np.fft.fftn(x)
+    X = fftn(x)
     if comp is not None:
         X *= comp
     return X
@@ -164,6 +176,61 @@ def pk_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
     return _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S)
 
 
+def pk_bisector_shells(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
+    """pk_bisector with the memory of the retained modes only: the same steps (Section 5.2
+    boxed estimator), but each transform is reduced to the modes of the k-bins right after it
+    is computed.  Q(-k) of a retained mode is read at the index (-n) mod N, which is retained
+    too (same |k|).  For meshes whose full set of transforms does not fit in host memory."""
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    if beta_max is None:
+        beta_max = cfg.order // 2
+    N = cfg.N
+    b, kmag = k_bin_index(N, cfg.L, cfg.bin_lo, cfg.bin_width, cfg.n_bins)
+    sel = np.flatnonzero(b.ravel() >= 0)
+    b_sel = b.ravel()[sel]
+    k_sel = kmag.ravel()[sel]
+    del b, kmag
+    ix, iy, iz = np.unravel_index(sel, (N, N, N))
+    neg = np.ravel_multi_index(((-ix) % N, (-iy) % N, (-iz) % N), (N, N, N))
+    perm = np.searchsorted(sel, neg)          # Q(-k) of retained mode i is Q_sel[perm[i]]
+    assert np.array_equal(sel[perm], neg)
+    s = signed_index(N)
+    kf = 2.0 * np.pi / cfg.L
+    kvec_sel = np.stack([s[ix], s[iy], s[iz]], axis=-1) * kf
+    del ix, iy, iz, neg
+    comp_sel = None
+    if cfg.compensate:
+        comp_sel = (1.0 / window(N, cfg.assign)).ravel()[sel]
+    xn = node_positions(N, cfg.L, cfg.b0)
+    Jmax = max(cfg.ells) + beta_max
+    Qs = {}
+    for J in range(Jmax + 1):
+        for M in range(-J, J + 1):
+            X = fftn(m * Ylm(J, M, xn)).ravel()[sel]
+            Qs[(J, M)] = X * comp_sel if comp_sel is not None else X
+    del xn
+    E_list = []
+    for l in cfg.ells:
+        E = np.zeros(len(sel), dtype=np.complex128)
+        for mm in range(-l, l + 1):
+            tab = coeffs.B_table(beta_max, l, mm)
+            inner = np.zeros(len(sel), dtype=np.complex128)
+            for (J1, J2, M), c in tab.items():
+                inner += c * Qs[(J1, M)][perm] * Qs[(J2, mm - M)]
+            E += np.conj(Ylm(l, mm, kvec_sel)) * inner
+        E_list.append(E)
+    counts = np.bincount(b_sel, minlength=cfg.n_bins).astype(np.float64)
+    ksum = np.bincount(b_sel, weights=k_sel, minlength=cfg.n_bins)
+    vals = []
+    for E in E_list:
+        sm = np.bincount(b_sel, weights=np.real(E), minlength=cfg.n_bins)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            vals.append(np.where(counts > 0, sm / np.where(counts > 0, counts, 1), 0.0))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kmean = np.where(counts > 0, ksum / np.where(counts > 0, counts, 1), 0.0)
+    return _finish_pk(np.array(vals), kmean, counts, cfg, alpha_r, I, S)
+
+
 def g_field(m, dtil, xn, alpha: int, J: int, M: int, comp):
     """g^alpha_{JM}(D) = (-1)^J IFT[d*(k) F[(2r)^-alpha Y_J^M d](k)]  (Section 3.2), on the
     separation grid (index n <-> D = H s(n)).  (2r)^-alpha is set to 0 at r = 0."""
@@ -175,7 +242,7 @@ def g_field(m, dtil, xn, alpha: int, J: int, M: int, comp):
             rw = np.where(r > 0, (2.0 * r) ** (-float(alpha)), 0.0)
     Q = m * rw * Ylm(J, M, xn)
     Qt = _fft(Q, comp)
-    g = np.fft.ifftn(np.conj(dtil) * Qt)
+    g = ifftn(np.conj(dtil) * Qt)
     return (-1) ** J * g
 
 
@@ -212,7 +279,7 @@ def pk_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
     for l in cfg.ells:
         E = np.zeros(m.shape, dtype=np.complex128)
         for mm in range(-l, l + 1):
-            E += np.conj(Ylm(l, mm, kvec)) * np.fft.fftn(A[(l, mm)])
+            E += np.conj(Ylm(l, mm, kvec)) * fftn(A[(l, mm)])
         E_list.append(E)
     sums, kmean, counts = _bin_k(E_list, cfg)
     return _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S)
@@ -306,7 +373,7 @@ def xi_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
             Kprod = np.zeros(m.shape, dtype=np.complex128)
             for (J1, J2, M), c in tab.items():
                 Kprod += c * Qneg[(J1, M)] * Qt[(J2, mm - M)]
-            Hlm = np.fft.ifftn(Kprod)
+            Hlm = ifftn(Kprod)
             X += np.conj(Ylm(l, mm, Dvec)) * Hlm
         X_list.append(X)
     sums, rmean, counts = _bin_r(X_list, cfg)

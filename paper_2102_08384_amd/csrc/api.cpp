@@ -295,6 +295,7 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
       dp->rowmask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
       dp->rowlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
       dp->planemask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
+      dp->zlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
       if ((size_t)dp->ntiles * sizeof(int) > ctx->lds_per_block)
         fail(PW_EINVAL, "n_mesh too large for the tile sort on this device (%zu bytes of LDS per block)",
              ctx->lds_per_block);
@@ -417,13 +418,15 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
                       dp->tile_cursor, ln.records);
   launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ln.records,
                     dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
-  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->norm);
+  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->norm);
   // a3 + a4: weighted fields and the forward transforms
   const int N = h.N;
   const Prune &F = h.fwd;
-  const double x1 = (double)h.nfields * N * N * F.nkx * csz;  // algorithmic (unpadded)
-  const double x2 = (double)h.nfields * N * F.npen * csz;
-  const double x3 = (double)h.nfields * F.nmodes * csz;
+  // algorithmic bytes (retained values only, no padding)
+  const double modes_real = F.full ? (double)N * F.npen_real : (double)F.nmodes;
+  const double x1 = (double)h.nfields * N * N * F.nkx * csz;
+  const double x2 = (double)h.nfields * N * F.npen_real * csz;
+  const double x3 = (double)h.nfields * modes_real * csz;
   char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
   mark("fx", ncell * rsz + x1);
   launch_fx(s, h.prec, N, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
@@ -431,10 +434,10 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   mark("fy", x1 + x2);
   if (F.npen > 0)
     launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
-              dp->rowmask, dp->planemask);
+              dp->rowmask, dp->zlist, dp->norm);
   mark("fz", x2 + x3);
   if (F.npen > 0)
-    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, F.nmodes, dp->tw,
+    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, F.mstride, dp->tw,
               dp->planemask);
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
   const size_t nacc = (size_t)(h.nell + 2) * h.n_bins;
@@ -446,17 +449,17 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
     tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
     tab.ntargets = (int)h.t_sh.size();
-    launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, dp->fwd.modecoord, N,
+    launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, F.mstride, dp->fwd.modecoord, N,
                         dp->bin_of_s2, n_s2, h.n_bins, h.nell, tab, h.kf, dp->winv, dp->acc);
     mark("finalize", 0.0);
     launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
   } else {
-    // Spectra after fz: full pencil-major A[p][q * N + kz], q = ky * nkx + kx.
-    const double sfull = (double)N * N * F.nkx * csz;  // one full spectrum
-    const size_t sfull_b = (size_t)N * N * F.nkx * (size_t)csz;
+    // Spectra after fz: full pencil-major A[p][q * N + kz], q = ky * rs + kx.
+    const double sfull = (double)N * N * F.nkx * csz;  // one full half spectrum (algorithmic)
+    const size_t sfull_b = (size_t)N * F.npen * (size_t)csz;  // one full pencil-major spectrum
     const double inv_n3 = 1.0 / ncell;
     const int npl = h.nz;  // retained z planes (= y rows) of the inverse outputs
-    const double zpart = (double)h.n_inv * npl * F.npen * csz;
+    const double zpart = (double)h.n_inv * npl * F.npen_real * csz;
     const double ypart = (double)h.n_inv * npl * h.ny * F.nkx * csz;
     const bool xi = h.path != PATH_MID_PK;
     if (xi) launch_fill(s, dp->acc, nacc, 1);
@@ -464,8 +467,8 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     int real_in = 0;
     if (h.path == PATH_BIS_XI) {
       // a8 (bisector): T_{l nu}(k) = sum S Re(conj R_p1 R_p2) / W^2 on every mode
-      mark("targets", x3 + (double)h.n_targets * F.nmodes * rsz);
-      launch_targets(s, h.prec, N, h.ell_max, h.order / 2, A, F.nmodes, F.nkx, dp->winv, B);
+      mark("targets", x3 + (double)h.n_targets * modes_real * rsz);
+      launch_targets(s, h.prec, N, h.ell_max, h.order / 2, A, F.nmodes, F.rs, dp->winv, B);
       zin = B;
       zout = A;
       real_in = 1;
@@ -473,7 +476,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     // a5: conj(D) Q / W^2 (midpoint) and the inverse z pass; D = sqrt(4 pi) Q_{0,0,0}
     const int nzf = h.path == PATH_BIS_XI ? h.n_targets : h.nfields;
     // bytes: the input spectra (+ D once), the in-place products and the retained z planes
-    mark("iz", (real_in ? (double)nzf * F.nmodes * rsz : (double)(nzf + 1) * sfull) +
+    mark("iz", (real_in ? (double)nzf * modes_real * rsz : (double)(nzf + 1) * sfull) +
                    (double)h.n_inplace * sfull + zpart);
     const double sqrt4pi = std::sqrt(4.0 * 3.14159265358979323846);
     launch_iz(s, h.prec, N, zin, zout, nzf, h.n_inplace, real_in, F.npen, F.nkx, F.rs,
@@ -483,7 +486,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     void *yout = (zout == B) ? (void *)(A + (size_t)h.n_inplace * sfull_b) : (void *)B;
     mark("iy", (double)h.n_inv * npl * N * F.nkx * csz + ypart);
     launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, F.rs, dp->iycnt, dp->iyoff,
-              (int64_t)h.ny * F.rs, dp->tw, nullptr, nullptr);
+              (int64_t)h.ny * F.rs, dp->tw, nullptr, nullptr, nullptr);
     if (xi) {
       // a8: c2r along x fused with the |D|^alpha y(D^) weighting and FP64 r-binning
       mark("ix_bin", ypart);
@@ -510,15 +513,15 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         mark("afy", a1 + a2);
         if (P.npen > 0)
           launch_fy(s, h.prec, N, 0, B, Aoff, h.n_a, N, P.nkx, P.rs, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw,
-                    nullptr, nullptr);
+                    nullptr, nullptr, nullptr);
         mark("afz", a2 + a3);
         if (P.npen > 0)
-          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, P.nmodes, dp->tw, nullptr);
+          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, P.mstride, dp->tw, nullptr);
       }
       // a7 (midpoint): sum_nu y_l^nu(k^) Re[G_{l nu} + A_{l nu}] and FP64 k-binning
       mark("contract", (double)(h.n0 + h.n_a) * h.sph.nmodes * csz + 4.0 * h.sph.nmodes);
       launch_fill(s, dp->acc, nacc, 1);
-      launch_contract_mid(s, h.prec, h.ell_max, A, F.nkx, h.n_a > 0 ? B : nullptr, h.sph.nmodes,
+      launch_contract_mid(s, h.prec, h.ell_max, A, F.rs, h.n_a > 0 ? B : nullptr, h.sph.nmodes, h.sph.mstride,
                           dp->sph.modecoord, N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->acc);
       mark("finalize", 0.0);
       launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
@@ -611,9 +614,10 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
     const double N = h.N, rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2 * rsz;
     const double fr = dn.nrows_occ / (N * N), fp = dn.nplanes_occ / N;
+    const double modes_real = h.fwd.full ? N * (double)h.fwd.npen_real : (double)h.fwd.nmodes;
     const double x1 = (double)h.nfields * N * N * h.fwd.nkx * csz;
-    const double x2 = (double)h.nfields * N * h.fwd.npen * csz;
-    const double x3 = (double)h.nfields * h.fwd.nmodes * csz;
+    const double x2 = (double)h.nfields * N * h.fwd.npen_real * csz;
+    const double x3 = (double)h.nfields * modes_real * csz;
     for (int i = 0; i < ln.n_stages; ++i) {
       const std::string nm = ln.st_name[i] ? ln.st_name[i] : "";
       if (nm == "fx") ln.st_bytes[i] = fr * (N * N * N * rsz + x1);
@@ -1054,7 +1058,7 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
     const void *src = nullptr;
     size_t bytes = 0;
     if (what == 0) { src = dp->mesh; bytes = (size_t)h.N * h.N * h.N * rsz; }
-    else if (what == 1) { src = dp->bufA; bytes = (size_t)h.nfields * h.fwd.nmodes * 2 * rsz; }
+    else if (what == 1) { src = dp->bufA; bytes = (size_t)h.nfields * h.fwd.nmodes * 2 * rsz; }  // compact copy
     else if (what == 2) {
       if (h.fwd.modecoord.empty()) fail(PW_EINVAL, "pw_inspect: this path keeps full spectra (no mode list)");
       src = dp->fwd.modecoord;
@@ -1066,7 +1070,14 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
       if (dst_bytes < bytes) fail(PW_EINVAL, "pw_inspect: destination too small");
       HIPCHECK(hipSetDevice(ctx->device));
       HIPCHECK(hipStreamSynchronize(ctx->main->stream));
-      HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+      if (what == 1) {
+        // fields are stored with the padded stride mstride: copy them out compactly
+        const size_t w = (size_t)h.fwd.nmodes * 2 * rsz;
+        HIPCHECK(hipMemcpy2D(dst, w, src, (size_t)h.fwd.mstride * 2 * rsz, w, (size_t)h.nfields,
+                             hipMemcpyDeviceToHost));
+      } else {
+        HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+      }
     }
   } catch (const Fail &f) {
     ctx->err = f.msg;

@@ -29,7 +29,8 @@ template <int L, int K, typename R> struct MidReweight {
 
 template <typename R, int LMAX, int BMAX>
 __global__ void __launch_bounds__(256)
-k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, const uint32_t *__restrict__ modecoord,
+k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, int64_t mstride,
+                   const uint32_t *__restrict__ modecoord,
                    int N, const int *__restrict__ bin_of_s2, int64_t n_s2, int nbins, double kf,
                    const R *__restrict__ winv, double *__restrict__ acc) {
   using CT = BisContract<LMAX, BMAX, R>;
@@ -54,7 +55,7 @@ k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, const uint3
     if (b < 0) continue;
     cplx<R> a[NF];
 #pragma unroll
-    for (int p = 0; p < NF; ++p) a[p] = spec[(size_t)p * nmodes + mode];
+    for (int p = 0; p < NF; ++p) a[p] = spec[(size_t)p * mstride + mode];
     const bool pair = (kx != 0 && kx != half);
     R wdir[NSH];
 #pragma unroll
@@ -97,7 +98,8 @@ k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, const uint3
 }
 
 template <typename R, int L, int B>
-static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, const uint32_t *modecoord,
+static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, int64_t mstride,
+                                const uint32_t *modecoord,
                                 int N, const int *bin_of_s2, int64_t n_s2, int nbins, double kf,
                                 const void *winv, double *acc) {
   if constexpr (BisContract<L, B, R>::kGenerated) {
@@ -105,7 +107,7 @@ static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes,
     unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
     size_t sh = (size_t)(L / 2 + 3) * nbins * sizeof(double);
     hipLaunchKernelGGL((k_contract_bis_reg<R, L, B>), dim3(blocks), dim3(256), sh, s,
-                       (const cplx<R> *)spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf,
+                       (const cplx<R> *)spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf,
                        (const R *)winv, acc);
     return true;
   } else {
@@ -115,11 +117,13 @@ static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes,
 
 template <typename R>
 static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void *spec, int64_t nmodes,
+                                  int64_t mstride,
                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
                                   int nbins, double kf, const void *winv, double *acc) {
 #define PW_CR(L, B)                                                                                \
   if (lmax == L && bmax == B)                                                                      \
-    return contract_reg_launch<R, L, B>(s, spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, acc);
+    return contract_reg_launch<R, L, B>(s, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, \
+                                        acc);
   PW_CR(0, 0) PW_CR(0, 1) PW_CR(0, 2) PW_CR(2, 0) PW_CR(2, 1) PW_CR(2, 2)
   PW_CR(4, 0) PW_CR(4, 1) PW_CR(4, 2) PW_CR(6, 0) PW_CR(6, 1) PW_CR(6, 2)
 #undef PW_CR
@@ -127,12 +131,12 @@ static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void 
 }
 
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
-                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
+                                   int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
                                    int nbins, double kf, const void *winv, double *acc) {
-  return prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, modecoord, N, bin_of_s2, n_s2,
-                                                  nbins, kf, winv, acc)
-                   : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, modecoord, N, bin_of_s2, n_s2,
-                                                   nbins, kf, winv, acc);
+  return prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
+                                                  n_s2, nbins, kf, winv, acc)
+                   : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
+                                                   n_s2, nbins, kf, winv, acc);
 }
 
 // ------------------------------------------------------------------------------ generated
@@ -161,7 +165,7 @@ bool mid_reweight_generated(int lmax, int order) {
 // Bisector xi targets over the full pencil-major spectra: one thread per mode.
 template <typename R, int LMAX, int BMAX>
 __global__ void __launch_bounds__(256)
-k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int nkx, const R *__restrict__ winv,
+k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int rs, const R *__restrict__ winv,
           R *__restrict__ T) {
   using CT = BisContract<LMAX, BMAX, R>;
   constexpr int NF = CT::NF;
@@ -177,7 +181,7 @@ k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int nkx, cons
     R iw2 = (R)1;
     if (winv) {
       const int64_t q = i / N;
-      const int kz = (int)(i - q * N), ky = (int)(q / nkx), kx = (int)(q - (int64_t)ky * nkx);
+      const int kz = (int)(i - q * N), ky = (int)(q / rs), kx = (int)(q - (int64_t)ky * rs);
       const R iw = winv[kx] * winv[ky] * winv[kz];
       iw2 = iw * iw;
     }
@@ -190,13 +194,13 @@ k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int nkx, cons
 }
 
 template <typename R, int L, int B>
-static bool targets_launch(hipStream_t s, const void *spec, int64_t nmodes, int N, int nkx, const void *winv,
+static bool targets_launch(hipStream_t s, const void *spec, int64_t nmodes, int N, int rs, const void *winv,
                            void *T) {
   if constexpr (BisContract<L, B, R>::kGenerated) {
     int64_t want = (nmodes + 255) / 256;
     unsigned blocks = (unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536);
     hipLaunchKernelGGL((k_targets<R, L, B>), dim3(blocks), dim3(256), 0, s, (const cplx<R> *)spec, nmodes, N,
-                       nkx, (const R *)winv, (R *)T);
+                       rs, (const R *)winv, (R *)T);
     return true;
   } else {
     return false;
@@ -204,11 +208,11 @@ static bool targets_launch(hipStream_t s, const void *spec, int64_t nmodes, int 
 }
 
 void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const void *spec, int64_t nmodes,
-                    int nkx, const void *winv, void *T) {
+                    int rs, const void *winv, void *T) {
 #define PW_TG(L, B)                                                                               \
   if (lmax == L && bmax == B) {                                                                   \
-    if (prec == 0) targets_launch<float, L, B>(s, spec, nmodes, N, nkx, winv, T);                 \
-    else targets_launch<double, L, B>(s, spec, nmodes, N, nkx, winv, T);                          \
+    if (prec == 0) targets_launch<float, L, B>(s, spec, nmodes, N, rs, winv, T);                  \
+    else targets_launch<double, L, B>(s, spec, nmodes, N, rs, winv, T);                           \
     return;                                                                                       \
   }
   PW_TG(0, 0) PW_TG(0, 1) PW_TG(0, 2) PW_TG(2, 0) PW_TG(2, 1) PW_TG(2, 2)

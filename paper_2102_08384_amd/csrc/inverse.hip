@@ -46,10 +46,10 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
       lds[kz * (C + 1) + cc] = (e < nval) ? src[(size_t)q0 * N + e] : mk<R>(0, 0);
     }
   };
-  // output position of this lane's pencil in a padded plane: ky * rs + kx
-  const int qky = (int)(q / nkx), qkx = (int)(q - (int64_t)qky * nkx);
-  const int64_t qo = (int64_t)qky * rs + qkx;
-  const int64_t plane_o = (int64_t)N * rs;
+  // full retention: pencil q = ky * rs + kx (kx >= nkx: all-zero padding pencils)
+  const int qky = (int)(q / rs), qkx = (int)(q - (int64_t)qky * rs);
+  const int64_t qo = q;
+  const int64_t plane_o = npen;
   cplx<R> dv[8];
   if (D) {
     load_chunk(D);
@@ -328,7 +328,8 @@ void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *o
 // its mirror (conjugate values, same real parts) whose direction is that of (-n) mod N.
 template <typename R, int LMAX>
 __global__ void __launch_bounds__(256)
-k_contract_mid(const cplx<R> *__restrict__ G, int nkx_full, const cplx<R> *__restrict__ A, int64_t nmodes,
+k_contract_mid(const cplx<R> *__restrict__ G, int rs_full, const cplx<R> *__restrict__ A, int64_t nmodes,
+               int64_t mstride,
                const uint32_t *__restrict__ modecoord, int N, const int *__restrict__ bin_of_s2, int64_t n_s2,
                int nbins, double kf, double *__restrict__ acc) {
   constexpr int NSH = (LMAX + 1) * (LMAX + 1);
@@ -338,7 +339,7 @@ k_contract_mid(const cplx<R> *__restrict__ G, int nkx_full, const cplx<R> *__res
   for (int i = threadIdx.x; i < nacc; i += blockDim.x) bacc[i] = 0.0;
   __syncthreads();
   const int half = N / 2;
-  const size_t gstride = (size_t)N * nkx_full * N;
+  const size_t gstride = (size_t)N * rs_full * N;
   for (int64_t mode = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mode < nmodes;
        mode += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t mc = modecoord[mode];
@@ -369,7 +370,7 @@ k_contract_mid(const cplx<R> *__restrict__ G, int nkx_full, const cplx<R> *__res
         for (int i = 0; i < NSH; ++i) wdir[i] += wm[i];
       }
     }
-    const size_t gi = ((size_t)ky * nkx_full + kx) * N + kz;
+    const size_t gi = ((size_t)ky * rs_full + kx) * N + kz;
     R E[NE];
 #pragma unroll
     for (int l = 0, o = 0; l <= LMAX; l += 2) {
@@ -377,7 +378,7 @@ k_contract_mid(const cplx<R> *__restrict__ G, int nkx_full, const cplx<R> *__res
 #pragma unroll
       for (int nu = -l; nu <= l; ++nu, ++o) {
         R v = G[(size_t)o * gstride + gi].x;
-        if (l >= 2 && A) v += A[(size_t)(o - 1) * nmodes + mode].x;
+        if (l >= 2 && A) v += A[(size_t)(o - 1) * mstride + mode].x;
         e += wdir[l * l + l + nu] * v;
       }
       E[l / 2] = e;
@@ -393,16 +394,16 @@ k_contract_mid(const cplx<R> *__restrict__ G, int nkx_full, const cplx<R> *__res
     if (bacc[i] != 0.0) atomicAdd(&acc[i], bacc[i]);
 }
 
-void launch_contract_mid(hipStream_t s, int prec, int lmax, const void *G, int nkx_full, const void *A,
-                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
+void launch_contract_mid(hipStream_t s, int prec, int lmax, const void *G, int rs_full, const void *A,
+                         int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
                          int nbins, double kf, double *acc) {
   if (nmodes <= 0) return;
   int64_t want = (nmodes + 255) / 256;
   unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
   size_t sh = (size_t)(lmax / 2 + 3) * nbins * sizeof(double);
 #define PW_CM(R, L)                                                                                \
-  hipLaunchKernelGGL((k_contract_mid<R, L>), dim3(blocks), dim3(256), sh, s, (const cplx<R> *)G, nkx_full, \
-                     (const cplx<R> *)A, nmodes, modecoord, N, bin_of_s2, n_s2, nbins, kf, acc);
+  hipLaunchKernelGGL((k_contract_mid<R, L>), dim3(blocks), dim3(256), sh, s, (const cplx<R> *)G, rs_full, \
+                     (const cplx<R> *)A, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf, acc);
   if (prec == 0) {
     switch (lmax) {
       case 0: PW_CM(float, 0) break;

@@ -73,9 +73,11 @@ void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, 
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
                        const void *records, const DevNorm *norm, void *blocks, void *mesh, int *rowmask);
 // Survey occupancy: rowlist = the non-empty rows in increasing order, planemask[z] = 1 for
-// z-planes with a non-empty row; counts into norm->nrows_occ / nplanes_occ.  Every field of
-// the forward transforms is the mesh times a weight, so it vanishes exactly on empty rows.
-void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, DevNorm *norm);
+// z-planes with a non-empty row, zlist = those planes in increasing order; counts into
+// norm->nrows_occ / nplanes_occ.  Every field of the forward transforms is the mesh times a
+// weight, so it vanishes exactly on empty rows.
+void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, int *zlist,
+                      DevNorm *norm);
 
 // Row strides: every row of a half spectrum (kx = 0 .. nkx-1) starts at a multiple of `rs`
 // complex values, rs >= nkx rounded up to 128 bytes, so that column-pencil passes read whole
@@ -96,11 +98,12 @@ void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, cons
 // c2c along y (forward, or inverse when inv), on nplanes planes per field:
 // in[p][plane][y * rs + kx] -> out[p][plane][yoff[y'] + kx] for kx < ycnt[y'] (y' the output
 // index, npen values per output plane).
-// rowmask / planemask (forward pass only; may be null): empty input rows are read as zeros and
-// empty planes are skipped (their output is not written; the z pass reads them as zeros).
+// rowmask / zlist (forward pass only; may be null): only the planes zlist[0 .. norm->nplanes_occ)
+// are transformed (the others are not written; the z pass reads them as zeros) and empty
+// input rows are read as zeros.
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields,
                int nplanes, int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen,
-               const void *tw, const int *rowmask, const int *planemask);
+               const void *tw, const int *rowmask, const int *zlist, const DevNorm *norm);
 // c2c along z, pruned: out[p][moff[q] + j], j < pinfo[q].kzcnt.
 // planemask (may be null): empty z-planes of the input are read as zeros.
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
@@ -117,7 +120,7 @@ struct TermTable {
   int ntargets;
 };
 void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
-                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
+                         int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                          const void *winv, double *acc);
 void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, const int *ells,
@@ -125,7 +128,7 @@ void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, c
 
 // Register-resident bisector contraction when its coupling is generated; false otherwise.
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
-                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
+                                   int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
                                    int nbins, double kf, const void *winv, double *acc);
 // Which (ell_max, beta_max) / (ell_max, order) have build-time generated couplings.
 bool bis_contract_generated(int lmax, int bmax);
@@ -156,14 +159,14 @@ void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *o
 // with |D| in the length unit of the forward weights (Hu = H / unit).
 void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, const void *g, void *A, double Hu);
 // Bisector xi targets: T[t][i] = sum S Re(conj(R_p1) R_p2) / W(k)^2 over the full
-// pencil-major spectra (i = q * N + kz), written as real values (generated couplings).
+// pencil-major spectra (i = q * N + kz, q = ky * rs + kx), written as real values (generated).
 void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const void *spec, int64_t nmodes,
-                    int nkx, const void *winv, void *T);
+                    int rs, const void *winv, void *T);
 // Midpoint P contraction: E_l = sum_nu y_l^nu(k^) Re[G_{l nu}(k) + A_{l nu}(k)] on the k-sphere
 // modes; G: full pencil-major products (alpha = 0 fields, index even_index(l, nu)); A: pruned
 // spectra of the A fields (l >= 2, index even_index(l, nu) - 1; null when absent).
-void launch_contract_mid(hipStream_t s, int prec, int lmax, const void *G, int nkx_full, const void *A,
-                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
+void launch_contract_mid(hipStream_t s, int prec, int lmax, const void *G, int rs_full, const void *A,
+                         int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, double kf, double *acc);
 void launch_finalize_xi(hipStream_t s, const double *acc, int nell, int nbins, double cell_volume,
                         const DevNorm *norm, double *out);

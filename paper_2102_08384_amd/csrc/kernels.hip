@@ -9,6 +9,8 @@
 //   finalize_pk  P_l = (4 pi / I) <..>_shell - d_l0 S / I
 #include "kernels.h"
 
+#include <algorithm>
+
 #include "dev_core.h"
 
 namespace pw {
@@ -112,7 +114,12 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
     __syncthreads();
     cplx<R> *oa = out + (size_t)J.pa * fstride + (size_t)row * rs;
     cplx<R> *ob = out + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * rs;
-    for (int kx = t; live && kx < nkx; kx += T) {
+    for (int kx = t; live && kx < rs; kx += T) {
+      if (kx >= nkx) {  // padding to the 128-byte row stride: whole-line writes
+        oa[kx] = mk<R>(0, 0);
+        if (J.pb >= 0) ob[kx] = mk<R>(0, 0);
+        continue;
+      }
       const cplx<R> a = at(kx), b = at((N - kx) & (N - 1));
       // A = (Z(k) + conj Z(N-k)) / 2,  B = (Z(k) - conj Z(N-k)) / (2i)
       oa[kx] = mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y));
@@ -141,117 +148,184 @@ void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, cons
 }
 
 // ------------------------------------------------------------------------------ fy / fz
+// Column-pencil passes are software-pipelined: a block owns one plane (y pass) or one group of
+// C pencils (z pass) and loops over a group of fields, issuing the global loads of the next
+// field before transforming the current one (barriers do not wait for global loads), so memory
+// latency hides behind the FFT.  Occupancy masks live in LDS, loaded once per block.
+inline int field_groups(int nfields, int nblocks_other) {
+  int g = (8 * 512 + nblocks_other - 1) / (nblocks_other > 0 ? nblocks_other : 1);
+  return g < 1 ? 1 : (g > nfields ? nfields : g);
+}
+
 template <typename R, int N, bool INV>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
-k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nkx, int rs, const int *__restrict__ ycnt,
-     const int64_t *__restrict__ yoff, int64_t npen, const cplx<R> *__restrict__ tw,
-     const int *__restrict__ rowmask, const int *__restrict__ planemask) {
-  constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C;
+k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int fpb, int nplanes, int nkx, int rs,
+     const int *__restrict__ ycnt, const int64_t *__restrict__ yoff, int64_t npen, const cplx<R> *__restrict__ tw,
+     const int *__restrict__ rowmask, const int *__restrict__ zlist, const DevNorm *__restrict__ norm) {
+  constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
+  constexpr int Q = 128 / (int)sizeof(cplx<R>);
   __shared__ cplx<R> lds[N * (C + 1)];
+  __shared__ int msk[N];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = blockIdx.x * C + c;
-  const int z = blockIdx.y;
-  if (planemask && !planemask[z]) return;  // uniform for the block: before any barrier
-  const size_t plane = (size_t)blockIdx.z * gridDim.y + z;  // field * nplanes + plane
-  const cplx<R> *src = in + plane * N * rs;  // input rows padded to rs
-  cplx<R> v[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int y = t + s * T;
-    const bool ok = kx < nkx && (!rowmask || rowmask[z * N + y]);
-    v[s] = ok ? src[(size_t)y * rs + kx] : mk<R>(0, 0);
+  int z = blockIdx.x;
+  if (zlist) {
+    if ((int)blockIdx.x >= norm->nplanes_occ) return;  // uniform: before any barrier
+    z = zlist[blockIdx.x];
   }
+  for (int i = threadIdx.x; i < N; i += NT) msk[i] = rowmask ? rowmask[z * N + i] : 1;
+  __syncthreads();
+  const int ncb = (nkx + C - 1) / C;
+  const int p0 = blockIdx.y * fpb;
+  const int p1 = min(nfields, p0 + fpb);
+  const int nitems = (p1 - p0) * ncb;
+  if (nitems <= 0) return;
+  auto load = [&](int it, cplx<R> *v) {
+    const int p = p0 + it / ncb, kx = (it % ncb) * C + c;
+    const cplx<R> *src = in + ((size_t)p * nplanes + z) * N * rs;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int y = t + s * T;
+      v[s] = (kx < nkx && msk[y]) ? src[(size_t)y * rs + kx] : mk<R>(0, 0);
+    }
+  };
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
-  fft_pencil<R, N, INV>(v, t, tw, at, sync);
-  cplx<R> *dst = out + plane * npen;
+  cplx<R> nxt[8];
+  load(0, nxt);
+  for (int it = 0; it < nitems; ++it) {
+    cplx<R> v[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int ky = t + s * T;
-    if (kx < ycnt[ky]) dst[yoff[ky] + kx] = v[s];
+    for (int s = 0; s < 8; ++s) v[s] = nxt[s];
+    if (it + 1 < nitems) load(it + 1, nxt);
+    fft_pencil<R, N, INV>(v, t, tw, at, sync);
+    const int p = p0 + it / ncb, kx = (it % ncb) * C + c;
+    cplx<R> *dst = out + ((size_t)p * nplanes + z) * npen;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      // whole 128-byte lines: the row's padding slots are written too (never read as modes)
+      const int ky = t + s * T;
+      const int cnt = ycnt[ky];
+      if (kx < (cnt + Q - 1) / Q * Q) dst[yoff[ky] + kx] = v[s];
+    }
   }
 }
 
 template <typename R, int N>
 static void fy_launch(hipStream_t s, int inv, const void *in, void *out, int nfields, int nplanes, int nkx,
                       int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
-                      const int *rowmask, const int *planemask) {
-  constexpr int C = ColShape<R, N>::C;
-  dim3 grid((nkx + C - 1) / C, nplanes, nfields);
+                      const int *rowmask, const int *zlist, const DevNorm *norm) {
+  const int G = field_groups(nfields, nplanes);
+  const int fpb = (nfields + G - 1) / G;
+  dim3 grid(nplanes, (nfields + fpb - 1) / fpb);
   if (inv)
     hipLaunchKernelGGL((k_fy<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                       (cplx<R> *)out, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw, rowmask, planemask);
+                       (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw,
+                       rowmask, zlist, norm);
   else
     hipLaunchKernelGGL((k_fy<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                       (cplx<R> *)out, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw, rowmask, planemask);
+                       (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw,
+                       rowmask, zlist, norm);
 }
 
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields, int nplanes,
                int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
-               const int *rowmask, const int *planemask) {
+               const int *rowmask, const int *zlist, const DevNorm *norm) {
   if (nfields <= 0 || nplanes <= 0) return;
   if (prec == 0) {
     PW_DISPATCH_N(fy_launch, float, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
-                  planemask)
+                  zlist, norm)
   } else {
     PW_DISPATCH_N(fy_launch, double, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
-                  planemask)
+                  zlist, norm)
   }
 }
 
 template <typename R, int N>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
-k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int64_t npen,
-     const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, int64_t nmodes,
+k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int fpb, int64_t npen,
+     const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, int64_t mstride,
      const cplx<R> *__restrict__ tw, const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
+  constexpr int Q = 128 / (int)sizeof(cplx<R>);  // complex values per 128-byte line
   __shared__ cplx<R> lds[N * (C + 1)];
+  __shared__ int st[C + 1];                      // first output mode of each pencil, relative
+  __shared__ int msk[N];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int64_t q0 = (int64_t)blockIdx.x * C;
   const int64_t q = q0 + c;
-  const int p = blockIdx.y;
-  const cplx<R> *src = in + (size_t)p * N * npen;
-  cplx<R> v[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int z = t + s * T;
-    v[s] = (q < npen && (!planemask || planemask[z])) ? src[(size_t)z * npen + q] : mk<R>(0, 0);
+  const int p0 = blockIdx.y * fpb;
+  const int p1 = min(nfields, p0 + fpb);
+  if (p0 >= p1) return;  // uniform
+  for (int i = threadIdx.x; i < N; i += NT) msk[i] = planemask ? planemask[i] : 1;
+  const int64_t m0 = moff[q0];
+  if (threadIdx.x <= C) {
+    const int64_t qq = q0 + threadIdx.x;
+    const int64_t e = (qq < npen) ? moff[qq] : moff[npen - 1] + pinfo[npen - 1].kzcnt;
+    st[threadIdx.x] = (int)(e - m0);
   }
+  __syncthreads();
+  const bool has = q < npen && pinfo[q].kzcnt > 0;  // padding pencils hold no modes
+  auto load = [&](int p, cplx<R> *v) {
+    const cplx<R> *src = in + (size_t)p * N * npen;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int z = t + s * T;
+      v[s] = (has && msk[z]) ? src[(size_t)z * npen + q] : mk<R>(0, 0);
+    }
+  };
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
-  fft_pencil<R, N, false>(v, t, tw, at, sync);
+  const int len = st[C];
+  const int64_t a0 = m0 / Q * Q;
+  cplx<R> nxt[8];
+  load(p0, nxt);
+  for (int p = p0; p < p1; ++p) {
+    cplx<R> v[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
-  __syncthreads();
-  cplx<R> *dst = out + (size_t)p * nmodes;
-  for (int cc = 0; cc < C; ++cc) {
-    const int64_t qq = q0 + cc;
-    if (qq >= npen) break;
-    const int cnt = pinfo[qq].kzcnt;
-    const int half = (cnt - 1) / 2;
-    const int64_t base = moff[qq];
-    for (int j = threadIdx.x; j < cnt; j += NT) {
+    for (int s = 0; s < 8; ++s) v[s] = nxt[s];
+    if (p + 1 < p1) load(p + 1, nxt);
+    fft_pencil<R, N, false>(v, t, tw, at, sync);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
+    __syncthreads();
+    // the block's pencils own one contiguous run of modes [m0, m0 + len): write it with
+    // wavefront accesses aligned to 128-byte lines
+    cplx<R> *dst = out + (size_t)p * mstride;
+    for (int64_t e = a0 + threadIdx.x; e < m0 + len; e += NT) {
+      if (e < m0) continue;
+      const int r = (int)(e - m0);
+      int cc = 0;
+#pragma unroll
+      for (int i = 1; i < C; ++i) cc += (r >= st[i]) ? 1 : 0;
+      const int j = r - st[cc];
+      const int cnt = st[cc + 1] - st[cc];
+      const int half = (cnt - 1) / 2;
       const int kz = (cnt == N) ? j : (j <= half ? j : N - (cnt - j));
-      dst[base + j] = lds[kz * (C + 1) + cc];
+      dst[e] = lds[kz * (C + 1) + cc];
     }
+    __syncthreads();  // LDS reads done before the next transform writes
   }
 }
 
 template <typename R, int N>
 static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int64_t npen,
-                      const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes, const void *tw,
+                      const PencilInfo *pinfo, const int64_t *moff, int64_t mstride, const void *tw,
                       const int *planemask) {
   constexpr int C = ColShape<R, N>::C;
-  dim3 grid((unsigned)((npen + C - 1) / C), nfields);
+  const unsigned ng = (unsigned)((npen + C - 1) / C);
+  const int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
+  const int fpb = (nfields + G - 1) / G;
+  dim3 grid(ng, (nfields + fpb - 1) / fpb);
   hipLaunchKernelGGL((k_fz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                     (cplx<R> *)out, npen, pinfo, moff, nmodes, (const cplx<R> *)tw, planemask);
+                     (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, mstride, (const cplx<R> *)tw, planemask);
 }
 
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int64_t npen,
-               const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes, const void *tw,
+               const PencilInfo *pinfo, const int64_t *moff, int64_t mstride, const void *tw,
                const int *planemask) {
-  if (prec == 0) { PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, nmodes, tw, planemask) }
-  else { PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, nmodes, tw, planemask) }
+  if (nfields <= 0 || npen <= 0) return;
+  if (prec == 0) { PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, mstride, tw, planemask) }
+  else { PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, mstride, tw, planemask) }
 }
 
 // ------------------------------------------------------------------------------ contraction
@@ -263,7 +337,7 @@ constexpr int kMaxVals = 4096;
 
 template <typename R, int LMAX, int NTH>
 __global__ void __launch_bounds__(NTH)
-k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
+k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes, int64_t mstride,
                const uint32_t *__restrict__ modecoord, int N, const int *__restrict__ bin_of_s2,
                int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                const R *__restrict__ winv, double *__restrict__ acc) {
@@ -281,7 +355,7 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
     const bool live = mode < nmodes;
     __syncthreads();
     for (int p = 0; p < nfields; ++p)
-      vals[p * NTH + threadIdx.x] = live ? spec[(size_t)p * nmodes + mode] : mk<R>(0, 0);
+      vals[p * NTH + threadIdx.x] = live ? spec[(size_t)p * mstride + mode] : mk<R>(0, 0);
     __syncthreads();
     if (!live) continue;
     const uint32_t mc = modecoord[mode];
@@ -350,11 +424,11 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes,
 }
 
 void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
-                         int64_t nmodes, const uint32_t *modecoord, int N, const int *bin_of_s2,
+                         int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
                          const void *winv, double *acc) {
   if (nmodes <= 0) return;
-  if (launch_contract_bis_generated(s, prec, lmax, bmax, spec, nmodes, modecoord, N, bin_of_s2, n_s2, nbins,
+  if (launch_contract_bis_generated(s, prec, lmax, bmax, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins,
                                     kf, winv, acc))
     return;
   int64_t want = (nmodes + 127) / 128;
@@ -363,7 +437,7 @@ void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void
   {                                                                                                \
     size_t sh = (size_t)nfields * NTH * sizeof(cplx<R>) + (size_t)(nell + 2) * nbins * sizeof(double); \
     hipLaunchKernelGGL((k_contract_bis<R, L, NTH>), dim3(blocks), dim3(NTH), sh, s,                \
-                       (const cplx<R> *)spec, nfields, nmodes, modecoord, N, bin_of_s2, n_s2,      \
+                       (const cplx<R> *)spec, nfields, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, \
                        nbins, nell, tab, kf, (const R *)winv, acc);                                \
   }
   if (prec == 0) {

@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const in
 constexpr int kOccThreads = 1024;
 __global__ void __launch_bounds__(kOccThreads) k_occupancy(int N, const int *__restrict__ rowmask,
                                                            int *__restrict__ rowlist, int *__restrict__ planemask,
-                                                           DevNorm *__restrict__ norm) {
+                                                           int *__restrict__ zlist, DevNorm *__restrict__ norm) {
   __shared__ int part[kOccThreads];
   __shared__ int nplanes;
   const int nrows = N * N;
@@ -411,11 +411,15 @@ __global__ void __launch_bounds__(kOccThreads) k_occupancy(int N, const int *__r
   if (threadIdx.x == 0) {
     norm->nrows_occ = part[kOccThreads - 1];
     norm->nplanes_occ = nplanes;
+    int k = 0;
+    for (int z = 0; z < N; ++z)
+      if (planemask[z]) zlist[k++] = z;
   }
 }
 
-void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, DevNorm *norm) {
-  hipLaunchKernelGGL(k_occupancy, dim3(1), dim3(kOccThreads), 0, s, N, rowmask, rowlist, planemask, norm);
+void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, int *zlist,
+                      DevNorm *norm) {
+  hipLaunchKernelGGL(k_occupancy, dim3(1), dim3(kOccThreads), 0, s, N, rowmask, rowlist, planemask, zlist, norm);
 }
 
 void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,

@@ -37,6 +37,8 @@ int even_index(int l, int nu) { return l * (l - 1) / 2 + l + nu; }
 Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
   Prune p;
   p.full = full;
+  const int Q = prec == PW_FP32 ? 16 : 8;  // complex values per 128 bytes
+  auto padq = [Q](int64_t v) { return (v + Q - 1) / Q * Q; };
   if (full) K2 = 3LL * (N / 2) * (N / 2);
   K2 = std::max<int64_t>(K2, 0);
   p.nkx = full ? N / 2 + 1 : (int)std::min<int64_t>(N / 2 + 1, isqrt64(K2) + 1);
@@ -51,7 +53,8 @@ Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
     else if (sy * sy <= K2) cnt = (int)std::min<int64_t>(p.nkx, isqrt64(K2 - sy * sy) + 1);
     p.ycnt[ky] = cnt;
     p.yoff[ky] = off;
-    off += cnt;
+    off += full ? p.rs : padq(cnt);
+    p.npen_real += cnt;
   }
   p.npen = off;
   int64_t moff = 0;
@@ -59,10 +62,13 @@ Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
   p.moff.reserve((size_t)p.npen);
   for (int ky = 0; ky < N; ++ky) {
     int64_t sy = signed_idx(ky, N);
-    for (int kx = 0; kx < p.ycnt[ky]; ++kx) {
+    const int slots = full ? p.rs : (int)padq(p.ycnt[ky]);
+    for (int kx = 0; kx < slots; ++kx) {
       int cnt;
       if (full) {
-        cnt = N;
+        cnt = N;  // kx >= nkx: an all-zero padding pencil, transformed like the others
+      } else if (kx >= p.ycnt[ky]) {
+        cnt = 0;  // padding slot: no modes
       } else {
         int64_t rem = K2 - (int64_t)kx * kx - sy * sy;
         int64_t kzm = rem < 0 ? 0 : isqrt64(rem);
@@ -70,7 +76,7 @@ Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
       }
       p.pinfo.push_back(PencilInfo{kx, ky, cnt, 0});
       p.moff.push_back(moff);
-      if (coords) {
+      if (coords && cnt > 0) {
         const int half = (cnt - 1) / 2;
         for (int j = 0; j < cnt; ++j) {
           int kz = (cnt == N) ? j : (j <= half ? j : N - (cnt - j));
@@ -81,6 +87,7 @@ Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
     }
   }
   p.nmodes = moff;
+  p.mstride = padq(moff);
   return p;
 }
 
@@ -366,9 +373,10 @@ HostPlan build_host_plan(const pw_config &c) {
   }
   const size_t rsz = h.prec == PW_FP32 ? 4 : 8, csz = 2 * rsz;
   if (h.path == PATH_MID_PK && h.n_a > 0) {
-    const size_t sfull = (size_t)N * N * h.fwd.nkx * csz;
+    const size_t sfull = (size_t)N * h.fwd.npen * csz;
     if ((size_t)h.n_a * N * N * N * rsz > (size_t)h.n_inv * sfull ||
-        (size_t)h.n_a * N * N * h.sph.rs * csz > spectrum_buffer_bytes(h))
+        (size_t)h.n_a * N * N * h.sph.rs * csz > spectrum_buffer_bytes(h) ||
+        (size_t)h.n_a * h.sph.mstride * csz > spectrum_buffer_bytes(h))
       plan_fail(PW_EINVAL, "internal: A fields do not fit the spectrum buffer");
   }
   return h;
@@ -378,7 +386,7 @@ size_t spectrum_buffer_bytes(const HostPlan &h) {
   const size_t csz = h.prec == PW_FP32 ? 8 : 16;
   const size_t x1 = (size_t)h.nfields * h.N * h.N * h.fwd.rs * csz;
   const size_t x2 = (size_t)h.nfields * h.N * h.fwd.npen * csz;
-  const size_t x3 = (size_t)h.nfields * h.fwd.nmodes * csz;
+  const size_t x3 = (size_t)h.nfields * h.fwd.mstride * csz;
   return std::max<size_t>(std::max(x1, std::max(x2, x3)), 16);
 }
 

@@ -34,17 +34,23 @@ void validate_config(const pw_config &c);
 
 enum Path { PATH_BIS_PK = 0, PATH_MID_PK = 1, PATH_MID_XI = 2, PATH_BIS_XI = 3 };
 
-// Retained modes of a forward transform: |n|^2 <= K2 (all modes when `full`).
+// Retained modes of a forward transform: |n|^2 <= K2 (all modes when `full`).  Every row and
+// field start is padded to 128 bytes (Q = 16 FP32 / 8 FP64 complex values) so that the column
+// passes move whole cache lines: x-pass rows have stride rs; each ky row of a y-pass plane
+// starts at a multiple of Q (padding pencils have kzcnt = 0, or for full retention are
+// ordinary all-zero pencils q = ky * rs + kx, kx >= nkx); z-pass fields have stride mstride.
 struct Prune {
   bool full = false;
   int nkx = 0;
   int rs = 0;                       // padded row stride of the x-pass output (complex values)
   std::vector<int> ycnt;
   std::vector<int64_t> yoff;
-  int64_t npen = 0;
-  std::vector<PencilInfo> pinfo;
-  std::vector<int64_t> moff;
-  int64_t nmodes = 0;
+  int64_t npen = 0;                 // pencils per y-pass plane, padding included
+  int64_t npen_real = 0;            // retained pencils (sum of ycnt)
+  std::vector<PencilInfo> pinfo;    // [npen]
+  std::vector<int64_t> moff;        // [npen]
+  int64_t nmodes = 0;               // modes per field (pencil-major), padding pencils included
+  int64_t mstride = 0;              // field stride of the z-pass output
   std::vector<uint32_t> modecoord;  // kx | ky << 11 | kz << 22 (pruned sets only)
 };
 
@@ -117,7 +123,7 @@ struct DevPlan {
   int *tile_counts = nullptr, *tile_offsets = nullptr, *tile_cursor = nullptr, *tile_slot = nullptr;
   void *tile_blocks = nullptr;
   int ntiles = 0;
-  int *rowmask = nullptr, *rowlist = nullptr, *planemask = nullptr;  // survey occupancy
+  int *rowmask = nullptr, *rowlist = nullptr, *planemask = nullptr, *zlist = nullptr;  // survey occupancy
 };
 
 }  // namespace pw

@@ -205,3 +205,21 @@ def test_wide_angle_correction_shrinks_with_distance():
     for kind, v in out.items():
         ratio = v[0] / v[1]
         assert 0.6 * s2 < ratio < 1.6 * s2, (kind, ratio, s2)
+
+
+def test_bisector_shell_path_equals_full_grid_path():
+    """The memory-lean bisector (retained modes only) is the full-grid estimator."""
+    from oracle.estimators import pk_bisector_shells
+    rng = np.random.default_rng(71)
+    gal = {"pos": np.array([0.0, 0.0, 1000.0]) + rng.uniform(-200, 200, (400, 3)),
+           "w": rng.uniform(0.5, 1.5, 400), "nbar": np.full(400, 1e-4)}
+    ran = {"pos": np.array([0.0, 0.0, 1000.0]) + rng.uniform(-200, 200, (1200, 3)),
+           "w": rng.uniform(0.5, 1.5, 1200), "nbar": np.full(1200, 1e-4)}
+    cfg = Config(N=32, L=900.0, b0=(-450.0, -450.0, 700.0), assign=3, ells=(0, 2, 4), order=4,
+                 compensate=True, bin_lo=0.01, bin_width=0.03, n_bins=7)
+    a = pk_bisector(gal, ran, cfg)
+    b = pk_bisector_shells(gal, ran, cfg)
+    assert np.array_equal(a.counts, b.counts)
+    assert np.allclose(a.bin_mean, b.bin_mean, rtol=1e-14, atol=0)
+    scale = np.max(np.abs(a.values[0]))
+    assert np.max(np.abs(a.values - b.values)) < 1e-12 * scale
