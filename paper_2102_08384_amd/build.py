@@ -26,13 +26,14 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-I", BUILD_DIR,
           # no packed-FP32 instructions in device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-ffp-contract=off", "-Wno-unused-command-line-argument"]
+          "-Wno-unused-command-line-argument"]
 
 
 def _deps_mtime() -> float:
     """Newest mtime of the headers every translation unit may include."""
     paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    paths += [os.path.join(ROOT, "include", "pw.h"), os.path.join(BUILD_DIR, "contract_gen.inc")]
+    paths += [os.path.join(ROOT, "include", "pw.h"), os.path.join(BUILD_DIR, "contract_gen.inc"),
+              os.path.abspath(__file__)]  # compile flags live here
     return max(os.path.getmtime(p) for p in paths if os.path.exists(p))
 
 

@@ -296,6 +296,7 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
       dp->rowlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
       dp->planemask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
       dp->zlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
+      dp->occ_blockcnt = (int *)alloc_plan(ctx, dp.get(), (size_t)occupancy_blocks(h.N) * sizeof(int));
       if ((size_t)dp->ntiles * sizeof(int) > ctx->lds_per_block)
         fail(PW_EINVAL, "n_mesh too large for the tile sort on this device (%zu bytes of LDS per block)",
              ctx->lds_per_block);
@@ -418,7 +419,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
                       dp->tile_cursor, ln.records);
   launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ln.records,
                     dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
-  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->norm);
+  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->occ_blockcnt, dp->norm);
   // a3 + a4: weighted fields and the forward transforms
   const int N = h.N;
   const Prune &F = h.fwd;

@@ -162,6 +162,7 @@ k_ix(const cplx<R> *__restrict__ in, R *__restrict__ out, int rs, const FieldJob
   auto sync = []() { __syncthreads(); };
   const int sy = y < N / 2 ? y : y - N, sz = z < N / 2 ? z : z - N;
 
+
   // mode 1 geometry of the eight cells this lane holds
   R ux[8], uy[8], uz[8], dm[8];
   int bin[8];

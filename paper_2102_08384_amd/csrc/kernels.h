@@ -51,6 +51,7 @@ void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n
 void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
                           const double *b0, double L, int check_extent, int use_given,
                           double ga, double gI, double gS);
+// Zero n_elems values: prec 0 float, 1 double, 2 int.
 void launch_fill(hipStream_t s, void *p, size_t n_elems, int prec);
 
 // Tile-binned painting: particles are counting-sorted by the tile of their anchor node
@@ -76,8 +77,10 @@ void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *of
 // z-planes with a non-empty row, zlist = those planes in increasing order; counts into
 // norm->nrows_occ / nplanes_occ.  Every field of the forward transforms is the mesh times a
 // weight, so it vanishes exactly on empty rows.
+// blockcnt: occupancy_blocks(N) ints of scratch.
+int occupancy_blocks(int N);
 void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, int *zlist,
-                      DevNorm *norm);
+                      int *blockcnt, DevNorm *norm);
 
 // Row strides: every row of a half spectrum (kx = 0 .. nkx-1) starts at a multiple of `rs`
 // complex values, rs >= nkx rounded up to 128 bytes, so that column-pencil passes read whole

@@ -59,25 +59,39 @@ void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n
                        (const double *)xyzw, (const double *)nbar, n, partial);
 }
 
-__device__ void reduce_partials(const double *p, double out[kScalarCols]) {
-  // thread-0-only helper: deterministic sequential reduction over the block rows
-  for (int c = 0; c < kScalarCols; ++c) out[c] = (c >= 3 && c < 6) ? 1e300 : (c >= 6 && c < 9) ? -1e300 : 0.0;
-  for (int b = 0; b < kScalarBlocks; ++b)
-    for (int c = 0; c < kScalarCols; ++c) {
-      double v = p[b * kScalarCols + c];
-      if (c >= 3 && c < 6) out[c] = fmin(out[c], v);
-      else if (c >= 6 && c < 9) out[c] = fmax(out[c], v);
-      else out[c] += v;
-    }
+
+constexpr int kNormThreads = 256;
+__device__ __forceinline__ double combine(int c, double a, double b) {
+  return (c >= 3 && c < 6) ? fmin(a, b) : (c >= 6 && c < 9) ? fmax(a, b) : a + b;
 }
 
-__global__ void k_finalize_norm(const double *pg, const double *pr, DevNorm *norm, double b0x,
-                                double b0y, double b0z, double L, int check_extent, int use_given,
-                                double ga, double gI, double gS) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(kNormThreads)
+k_finalize_norm(const double *pg, const double *pr, DevNorm *norm, double b0x, double b0y, double b0z, double L,
+                int check_extent, int use_given, double ga, double gI, double gS) {
+  // fixed-order (deterministic) reduction of the per-block partial rows: thread t folds rows
+  // t, t + 256, ..., then a tree in LDS
+  __shared__ double red[2 * kScalarCols][kNormThreads];
+  for (int k = 0; k < 2; ++k) {
+    const double *p = k ? pr : pg;
+    for (int c = 0; c < kScalarCols; ++c) {
+      double v = (c >= 3 && c < 6) ? 1e300 : (c >= 6 && c < 9) ? -1e300 : 0.0;
+      for (int b = threadIdx.x; b < kScalarBlocks; b += kNormThreads) v = combine(c, v, p[b * kScalarCols + c]);
+      red[k * kScalarCols + c][threadIdx.x] = v;
+    }
+  }
+  __syncthreads();
+  for (int off = kNormThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int q = 0; q < 2 * kScalarCols; ++q)
+        red[q][threadIdx.x] = combine(q % kScalarCols, red[q][threadIdx.x], red[q][threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   double g[kScalarCols], r[kScalarCols];
-  reduce_partials(pg, g);
-  reduce_partials(pr, r);
+  for (int c = 0; c < kScalarCols; ++c) {
+    g[c] = red[c][0];
+    r[c] = red[kScalarCols + c][0];
+  }
   DevNorm n;
   n.sum_wg = g[0];
   n.sum_wr = r[0];
@@ -123,7 +137,7 @@ __global__ void k_finalize_norm(const double *pg, const double *pr, DevNorm *nor
 void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
                           const double *b0, double L, int check_extent, int use_given,
                           double ga, double gI, double gS) {
-  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(64), 0, s, pg, pr, norm, b0[0], b0[1], b0[2],
+  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kNormThreads), 0, s, pg, pr, norm, b0[0], b0[1], b0[2],
                      L, check_extent, use_given, ga, gI, gS);
 }
 
@@ -139,6 +153,7 @@ void launch_fill(hipStream_t s, void *p, size_t n, int prec) {
   if (blocks > 8192) blocks = 8192;
   if (blocks == 0) return;
   if (prec == 0) hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float *)p, n);
+  else if (prec == 2) hipLaunchKernelGGL(k_fill<int>, dim3((unsigned)blocks), dim3(256), 0, s, (int *)p, n);
   else hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double *)p, n);
 }
 
@@ -376,50 +391,76 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const in
   }
 }
 
-// One block: compact the non-empty rows (in order) and mark the non-empty planes.
+// Occupancy in two passes over blocks of 1024 rows: (1) per-block counts and the plane flags,
+// (2) each block's offset (sum of the earlier blocks' counts), an in-block scan by wavefront
+// ballots, and the writes of the row list; block 0 also compacts the plane list and stores the
+// counts.
 constexpr int kOccThreads = 1024;
-__global__ void __launch_bounds__(kOccThreads) k_occupancy(int N, const int *__restrict__ rowmask,
-                                                           int *__restrict__ rowlist, int *__restrict__ planemask,
-                                                           int *__restrict__ zlist, DevNorm *__restrict__ norm) {
-  __shared__ int part[kOccThreads];
-  __shared__ int nplanes;
+__global__ void __launch_bounds__(kOccThreads) k_occ_count(int N, const int *__restrict__ rowmask,
+                                                           int *__restrict__ blockcnt, int *__restrict__ planemask) {
+  __shared__ int wsum[kOccThreads / 64];
   const int nrows = N * N;
-  const int chunk = (nrows + kOccThreads - 1) / kOccThreads;
-  const int lo = threadIdx.x * chunk, hi = min(lo + chunk, nrows);
-  int cnt = 0;
-  for (int i = lo; i < hi; ++i) cnt += rowmask[i] != 0;
-  part[threadIdx.x] = cnt;
-  if (threadIdx.x == 0) nplanes = 0;
-  __syncthreads();
-  // inclusive scan of the per-thread counts (Hillis-Steele in LDS)
-  for (int off = 1; off < kOccThreads; off <<= 1) {
-    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  int o = part[threadIdx.x] - cnt;
-  for (int i = lo; i < hi; ++i)
-    if (rowmask[i] != 0) rowlist[o++] = i;
-  for (int z = threadIdx.x; z < N; z += kOccThreads) {
-    int any = 0;
-    for (int y = 0; y < N; ++y) any |= rowmask[z * N + y];
-    planemask[z] = any != 0;
-    if (any) atomicAdd(&nplanes, 1);
-  }
+  const int i = blockIdx.x * kOccThreads + threadIdx.x;
+  const bool f = i < nrows && rowmask[i] != 0;
+  if (f) planemask[i / N] = 1;  // every writer stores the same value
+  const unsigned long long bal = __ballot(f);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
   __syncthreads();
   if (threadIdx.x == 0) {
-    norm->nrows_occ = part[kOccThreads - 1];
-    norm->nplanes_occ = nplanes;
-    int k = 0;
-    for (int z = 0; z < N; ++z)
-      if (planemask[z]) zlist[k++] = z;
+    int c = 0;
+    for (int w = 0; w < kOccThreads / 64; ++w) c += wsum[w];
+    blockcnt[blockIdx.x] = c;
   }
 }
 
+__global__ void __launch_bounds__(kOccThreads) k_occ_write(int N, int nblocks, const int *__restrict__ rowmask,
+                                                           const int *__restrict__ blockcnt,
+                                                           const int *__restrict__ planemask,
+                                                           int *__restrict__ rowlist, int *__restrict__ zlist,
+                                                           DevNorm *__restrict__ norm) {
+  __shared__ int wsum[kOccThreads / 64];
+  __shared__ int part[kOccThreads];
+  const int nrows = N * N;
+  // offset of this block: sum of blockcnt[0 .. blockIdx.x)
+  int acc = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kOccThreads) acc += blockcnt[b];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kOccThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  const int base = part[0];
+  const int i = blockIdx.x * kOccThreads + threadIdx.x;
+  const bool f = i < nrows && rowmask[i] != 0;
+  const unsigned long long bal = __ballot(f);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wsum[w] = __popcll(bal);
+  __syncthreads();
+  int wo = 0;
+  for (int k = 0; k < w; ++k) wo += wsum[k];
+  const unsigned long long below = lane ? (bal & ((1ull << lane) - 1ull)) : 0ull;
+  if (f) rowlist[base + wo + __popcll(below)] = i;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int tot = 0;
+    for (int b = 0; b < nblocks; ++b) tot += blockcnt[b];
+    int k = 0;
+    for (int z = 0; z < N; ++z)
+      if (planemask[z]) zlist[k++] = z;
+    norm->nrows_occ = tot;
+    norm->nplanes_occ = k;
+  }
+}
+
+int occupancy_blocks(int N) { return (N * N + kOccThreads - 1) / kOccThreads; }
+
 void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, int *planemask, int *zlist,
-                      DevNorm *norm) {
-  hipLaunchKernelGGL(k_occupancy, dim3(1), dim3(kOccThreads), 0, s, N, rowmask, rowlist, planemask, zlist, norm);
+                      int *blockcnt, DevNorm *norm) {
+  const int nb = occupancy_blocks(N);
+  launch_fill(s, planemask, (size_t)N, 2);
+  hipLaunchKernelGGL(k_occ_count, dim3(nb), dim3(kOccThreads), 0, s, N, rowmask, blockcnt, planemask);
+  hipLaunchKernelGGL(k_occ_write, dim3(nb), dim3(kOccThreads), 0, s, N, nb, rowmask, blockcnt, planemask, rowlist,
+                     zlist, norm);
 }
 
 void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,

@@ -170,7 +170,8 @@ void validate_config(const pw_config &c) {
     // the fused x pass keeps ROWS rows of N complex values and the bins in LDS
     const int T = c.n_mesh / 8;
     const int rows = (T >= 64) ? (256 / T > 0 ? 256 / T : 1) : 64 / T * 2;
-    const size_t lds = (size_t)rows * (c.n_mesh + c.n_mesh / 8) * (c.prec == PW_FP32 ? 8 : 16) +
+    const size_t csz = c.prec == PW_FP32 ? 8 : 16;
+    const size_t lds = (size_t)rows * (c.n_mesh + c.n_mesh / 8) * csz + (size_t)c.n_mesh * csz +
                        (size_t)(nell + 2) * c.n_bins * 8;
     if (lds > 65536) plan_fail(PW_EINVAL, "n_bins too large for xi_l (LDS of the fused x pass)");
     if (path == PATH_BIS_XI && !bis_contract_generated(c.ell_max, c.order / 2))

@@ -124,6 +124,7 @@ struct DevPlan {
   void *tile_blocks = nullptr;
   int ntiles = 0;
   int *rowmask = nullptr, *rowlist = nullptr, *planemask = nullptr, *zlist = nullptr;  // survey occupancy
+  int *occ_blockcnt = nullptr;
 };
 
 }  // namespace pw
