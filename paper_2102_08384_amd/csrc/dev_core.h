@@ -74,12 +74,47 @@ __host__ __device__ constexpr int stage_radix(int N, int s) {
   return (s < log2i(N) / 3) ? 8 : (log2i(N) % 3 == 2 ? 4 : 2);
 }
 
-// One Stockham stage (radix RADIX, current span NS) for lane t (0 <= t < N/8) holding
+// Span of stage S: product of the radices of the stages before it.
+__host__ __device__ constexpr int stage_span(int N, int S) { return S == 0 ? 1 : stage_span(N, S - 1) * stage_radix(N, S - 1); }
+
+// Twiddle sources: a table tw[e] = exp(-2 pi i e / N) in global memory, or the twiddles of one
+// lane held in registers (FftTw, filled once per kernel).
+template <typename R, int N> struct GlobalTw {
+  const cplx<R> *__restrict__ tw;
+  template <int S, int RADIX>
+  __device__ __forceinline__ cplx<R> get(int c, int r, int k) const {
+    return tw[(r * k * (N / (stage_span(N, S) * RADIX))) & (N - 1)];
+  }
+};
+template <typename R, int N> struct FftTw {
+  static constexpr int NSTAGE = n_stages(N);
+  cplx<R> w[NSTAGE > 1 ? (NSTAGE - 1) * 7 : 1];
+  // twiddles of lane t for every stage after the first
+  __device__ __forceinline__ void load(int t, const cplx<R> *__restrict__ tw) { load_from<1>(t, tw); }
+  template <int S>
+  __device__ __forceinline__ void load_from(int t, const cplx<R> *__restrict__ tw) {
+    if constexpr (S < NSTAGE) {
+      constexpr int RADIX = stage_radix(N, S), NB = 8 / RADIX, NS = stage_span(N, S);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const int k = (t + c * (N / 8)) % NS;
+#pragma unroll
+        for (int r = 1; r < RADIX; ++r)
+          w[(S - 1) * 7 + c * (RADIX - 1) + r - 1] = tw[(r * k * (N / (NS * RADIX))) & (N - 1)];
+      }
+      load_from<S + 1>(t, tw);
+    }
+  }
+  template <int S, int RADIX>
+  __device__ __forceinline__ cplx<R> get(int c, int r, int) const { return w[(S - 1) * 7 + c * (RADIX - 1) + r - 1]; }
+};
+
+// One Stockham stage S (radix RADIX, current span NS) for lane t (0 <= t < N/8) holding
 // v[s] = x[t + s*N/8].  The stage outputs go either back into v (LAST: natural order) or to
 // LDS at their Stockham positions (j/NS)*NS*RADIX + j%NS + r*NS through the accessor `at`.
-// tw[e] = exp(-2 pi i e / N) (conjugated for the inverse).
-template <typename R, int N, bool INV, int RADIX, int NS, bool LAST, typename At>
-__device__ __forceinline__ void fft_stage(cplx<R> v[8], int t, const cplx<R> *__restrict__ tw, At at) {
+// Twiddles exp(-2 pi i e / N) come from `tw` (conjugated for the inverse).
+template <typename R, int N, bool INV, int S, int RADIX, int NS, bool LAST, typename Tw, typename At>
+__device__ __forceinline__ void fft_stage(cplx<R> v[8], int t, const Tw &tw, At at) {
   constexpr int NB = 8 / RADIX;        // butterflies per lane
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
@@ -89,10 +124,9 @@ __device__ __forceinline__ void fft_stage(cplx<R> v[8], int t, const cplx<R> *__
     for (int r = 0; r < RADIX; ++r) u[r] = v[c + NB * r];
     const int k = j % NS;
     if constexpr (NS > 1) {
-      const int step = k * (N / (NS * RADIX));
 #pragma unroll
       for (int r = 1; r < RADIX; ++r) {
-        cplx<R> w = tw[(r * step) & (N - 1)];
+        cplx<R> w = tw.template get<S, RADIX>(c, r, k);
         if (INV) w.y = -w.y;
         u[r] = cmul(u[r], w);
       }
@@ -115,13 +149,13 @@ __device__ __forceinline__ void fft_stage(cplx<R> v[8], int t, const cplx<R> *__
   }
 }
 
-template <typename R, int N, bool INV, int S, int NS, typename At, typename Sync>
-__device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const cplx<R> *__restrict__ tw, At at, Sync sync) {
+template <typename R, int N, bool INV, int S, int NS, typename Tw, typename At, typename Sync>
+__device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const Tw &tw, At at, Sync sync) {
   constexpr int RAD = stage_radix(N, S);
   if constexpr (S == n_stages(N) - 1) {
-    fft_stage<R, N, INV, RAD, NS, true>(v, t, tw, at);
+    fft_stage<R, N, INV, S, RAD, NS, true>(v, t, tw, at);
   } else {
-    fft_stage<R, N, INV, RAD, NS, false>(v, t, tw, at);
+    fft_stage<R, N, INV, S, RAD, NS, false>(v, t, tw, at);
     sync();
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = at(t + q * (N / 8));
@@ -136,8 +170,19 @@ __device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const cplx<R> *_
 // of the block must call it (it contains barriers).
 template <typename R, int N, bool INV, typename At, typename Sync>
 __device__ __forceinline__ void fft_pencil(cplx<R> v[8], int t, const cplx<R> *__restrict__ tw, At at, Sync sync) {
+  GlobalTw<R, N> g{tw};
+  fft_stages<R, N, INV, 0, 1>(v, t, g, at, sync);
+}
+// The same with the lane's twiddles in registers (FftTw::load once per kernel).  Kernels that
+// prefetch the next pencil group's data across transforms use this form, with an explicit
+// vmcnt(0) wait after FftTw::load: the compiler then never waits on the prefetched loads to
+// read a twiddle.
+template <typename R, int N, bool INV, typename At, typename Sync>
+__device__ __forceinline__ void fft_pencil(cplx<R> v[8], int t, const FftTw<R, N> &tw, At at, Sync sync) {
   fft_stages<R, N, INV, 0, 1>(v, t, tw, at, sync);
 }
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited on)
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Row-mode pencils (x passes): ROWS rows of N elements per block, T = N/8 lanes per row.
 template <int N> struct FxShape {

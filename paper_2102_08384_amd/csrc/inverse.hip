@@ -38,6 +38,9 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
   const int nval = (int)((left < C ? left : C) * N);  // valid values of this block's chunk
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
+  FftTw<R, N> twr;
+  twr.load(t, tw);
+  wait_vmem();
   const size_t fstride = (size_t)npen * N;
   // the chunk of pencils q0 .. q0 + C - 1 is contiguous: element e = cc * N + kz
   auto load_chunk = [&](const cplx<R> *src) {
@@ -101,7 +104,7 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
       sync();
       continue;
     }
-    fft_pencil<R, N, true>(v, t, tw, at, sync);
+    fft_pencil<R, N, true>(v, t, twr, at, sync);
     if (q < npen) {
       cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * plane_o;
 #pragma unroll

@@ -172,7 +172,18 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
     if ((int)blockIdx.x >= norm->nplanes_occ) return;  // uniform: before any barrier
     z = zlist[blockIdx.x];
   }
+  FftTw<R, N> twr;
+  twr.load(t, tw);
+  // output rows of this lane (ky = t + s*T) and their padded lengths, fixed for the block
+  int64_t yo[8];
+  int yl[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    yo[s] = yoff[t + s * T];
+    yl[s] = (ycnt[t + s * T] + Q - 1) / Q * Q;
+  }
   for (int i = threadIdx.x; i < N; i += NT) msk[i] = rowmask ? rowmask[z * N + i] : 1;
+  wait_vmem();
   __syncthreads();
   const int ncb = (nkx + C - 1) / C;
   const int p0 = blockIdx.y * fpb;
@@ -197,15 +208,13 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
     if (it + 1 < nitems) load(it + 1, nxt);
-    fft_pencil<R, N, INV>(v, t, tw, at, sync);
+    fft_pencil<R, N, INV>(v, t, twr, at, sync);
     const int p = p0 + it / ncb, kx = (it % ncb) * C + c;
     cplx<R> *dst = out + ((size_t)p * nplanes + z) * npen;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       // whole 128-byte lines: the row's padding slots are written too (never read as modes)
-      const int ky = t + s * T;
-      const int cnt = ycnt[ky];
-      if (kx < (cnt + Q - 1) / Q * Q) dst[yoff[ky] + kx] = v[s];
+      if (kx < yl[s]) dst[yo[s] + kx] = v[s];
     }
   }
 }
@@ -256,6 +265,8 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
   const int p0 = blockIdx.y * fpb;
   const int p1 = min(nfields, p0 + fpb);
   if (p0 >= p1) return;  // uniform
+  FftTw<R, N> twr;
+  twr.load(t, tw);
   for (int i = threadIdx.x; i < N; i += NT) msk[i] = planemask ? planemask[i] : 1;
   const int64_t m0 = moff[q0];
   if (threadIdx.x <= C) {
@@ -263,8 +274,9 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
     const int64_t e = (qq < npen) ? moff[qq] : moff[npen - 1] + pinfo[npen - 1].kzcnt;
     st[threadIdx.x] = (int)(e - m0);
   }
-  __syncthreads();
   const bool has = q < npen && pinfo[q].kzcnt > 0;  // padding pencils hold no modes
+  wait_vmem();
+  __syncthreads();
   auto load = [&](int p, cplx<R> *v) {
     const cplx<R> *src = in + (size_t)p * N * npen;
 #pragma unroll
@@ -284,7 +296,7 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
     if (p + 1 < p1) load(p + 1, nxt);
-    fft_pencil<R, N, false>(v, t, tw, at, sync);
+    fft_pencil<R, N, false>(v, t, twr, at, sync);
 #pragma unroll
     for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
     __syncthreads();

@@ -355,20 +355,35 @@ __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restric
 // Node (x, y, z) of tile T at local (lx, ly, lz) is covered by the block of tile T + d for
 // d in {-1, 0, 1}^3 where d_a = -1 needs l_a = 0 and d_a = +1 needs l_a = ts - 1; inside that
 // block it sits at local l - d ts, block index l - d ts + 1.  Empty tiles have no block.
-// N and ts are powers of two: index arithmetic by shifts and masks.
+// One workgroup per group of GX tiles along x (GX = 2 for FP32 with at least two tiles per
+// axis, so mesh rows are written as whole 128-byte lines); the slots of the group's
+// neighbourhood are read into LDS once.  N and ts are powers of two.
 template <typename RM>
-__global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const int *__restrict__ slot,
+__global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx, const int *__restrict__ slot,
                                                      const unsigned long long *__restrict__ blocks,
                                                      const DevNorm *__restrict__ norm, RM *__restrict__ mesh,
                                                      int *__restrict__ rowmask) {
-  const int N = 1 << lgN, ts = 1 << lgts, nt = N >> lgts, E = ts + 2;
+  const int N = 1 << lgN, ts = 1 << lgts, nt = N >> lgts, E = ts + 2, GX = 1 << lggx;
   const size_t E3 = (size_t)E * E * E;
-  const size_t ncell = (size_t)1 << (3 * lgN);
+  __shared__ int sl[3][3][4];  // [dz + 1][dy + 1][tile offset along x + 1], offsets -1 .. GX
+  const int ngx = nt >> lggx;
+  const int gx = (int)blockIdx.x % ngx, ty = ((int)blockIdx.x / ngx) % nt, tz = (int)blockIdx.x / (ngx * nt);
+  const int tx0 = gx << lggx;
+  if ((int)threadIdx.x < 9 * (GX + 2)) {
+    const int i = threadIdx.x;
+    const int dxi = i % (GX + 2), dy = (i / (GX + 2)) % 3 - 1, dz = i / (3 * (GX + 2)) - 1;
+    const int tx = (tx0 + dxi - 1 + nt) & (nt - 1), tyy = (ty + dy + nt) & (nt - 1), tzz = (tz + dz + nt) & (nt - 1);
+    sl[dz + 1][dy + 1][dxi] = slot[(tzz * nt + tyy) * nt + tx];
+  }
+  __syncthreads();
   const double inv = 1.0 / norm->fix_scale;
-  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < ncell; g += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(g & (N - 1)), y = (int)((g >> lgN) & (N - 1)), z = (int)(g >> (2 * lgN));
-    const int l[3] = {x & (ts - 1), y & (ts - 1), z & (ts - 1)};
-    const int t[3] = {x >> lgts, y >> lgts, z >> lgts};
+  const int lgW = lggx + lgts;  // nodes per row of the group: W = GX * ts
+  const int nnode = 1 << (lgW + 2 * lgts);
+#pragma unroll 4
+  for (int n = threadIdx.x; n < nnode; n += 256) {
+    const int lxg = n & ((1 << lgW) - 1), ly = (n >> lgW) & (ts - 1), lz = n >> (lgW + lgts);
+    const int txl = lxg >> lgts, lx = lxg & (ts - 1);
+    const int l[3] = {lx, ly, lz};
     int dlo[3], dhi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -379,13 +394,13 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, const in
     for (int dz = dlo[2]; dz <= dhi[2]; ++dz)
       for (int dy = dlo[1]; dy <= dhi[1]; ++dy)
         for (int dx = dlo[0]; dx <= dhi[0]; ++dx) {
-          const int tx = (t[0] + dx + nt) & (nt - 1), ty = (t[1] + dy + nt) & (nt - 1);
-          const int tz = (t[2] + dz + nt) & (nt - 1);
-          const int sl = slot[(tz * nt + ty) * nt + tx];
-          if (sl < 0) continue;
-          const int ex = l[0] - dx * ts + 1, ey = l[1] - dy * ts + 1, ez = l[2] - dz * ts + 1;
-          v += blocks[(size_t)sl * E3 + ((size_t)ez * E + ey) * E + ex];
+          const int s = sl[dz + 1][dy + 1][txl + dx + 1];
+          if (s < 0) continue;
+          const int ex = lx - dx * ts + 1, ey = ly - dy * ts + 1, ez = lz - dz * ts + 1;
+          v += blocks[(size_t)s * E3 + ((size_t)ez * E + ey) * E + ex];
         }
+    const int x = (tx0 << lgts) + lxg, y = (ty << lgts) + ly, z = (tz << lgts) + lz;
+    const size_t g = ((size_t)z * N + y) * N + x;
     mesh[g] = (RM)((double)(long long)v * inv);
     if (rowmask && v != 0) rowmask[g >> lgN] = 1;  // every writer stores the same value
   }
@@ -513,8 +528,7 @@ void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *of
   const int nt = N / ts;
   const unsigned ntiles = (unsigned)(nt * nt * nt);
   const size_t E3 = (size_t)(ts + 2) * (ts + 2) * (ts + 2);
-  const size_t ncell = (size_t)N * N * N;
-  const unsigned gblocks = (unsigned)std::min<size_t>((ncell + 255) / 256, 16384);
+  const int lggx_f = nt >= 2 ? 1 : 0;  // FP32: two tiles per workgroup along x (128-byte rows)
   unsigned long long *b = (unsigned long long *)blocks;
 #define PW_TP(RM, A)                                                                              \
   hipLaunchKernelGGL((k_tile_paint<RM, A>), dim3(ntiles), dim3(256), E3 * sizeof(unsigned long long), s, \
@@ -523,10 +537,10 @@ void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *of
   else { if (assign == 2) PW_TP(double, 2); else PW_TP(double, 3); }
 #undef PW_TP
   if (prec == 0)
-    hipLaunchKernelGGL(k_tile_gather<float>, dim3(gblocks), dim3(256), 0, s, ilog2(N), ilog2(ts), slot, b, norm,
-                       (float *)mesh, rowmask);
+    hipLaunchKernelGGL(k_tile_gather<float>, dim3(ntiles >> lggx_f), dim3(256), 0, s, ilog2(N), ilog2(ts), lggx_f,
+                       slot, b, norm, (float *)mesh, rowmask);
   else
-    hipLaunchKernelGGL(k_tile_gather<double>, dim3(gblocks), dim3(256), 0, s, ilog2(N), ilog2(ts), slot, b,
+    hipLaunchKernelGGL(k_tile_gather<double>, dim3(ntiles), dim3(256), 0, s, ilog2(N), ilog2(ts), 0, slot, b,
                        norm, (double *)mesh, rowmask);
 }
 
