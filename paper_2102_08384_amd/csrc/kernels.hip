@@ -255,7 +255,6 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
      const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, int64_t mstride,
      const cplx<R> *__restrict__ tw, const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
-  constexpr int Q = 128 / (int)sizeof(cplx<R>);  // complex values per 128-byte line
   __shared__ cplx<R> lds[N * (C + 1)];
   __shared__ int st[C + 1];                      // first output mode of each pencil, relative
   __shared__ int msk[N];
@@ -287,8 +286,11 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
   };
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
-  const int len = st[C];
-  const int64_t a0 = m0 / Q * Q;
+  // output of pencil cc goes out through its own T lanes (a whole wavefront when T = 64):
+  // one contiguous run of modes per lane group, no search over the block's pencils
+  const int oc = threadIdx.x / T, oj = threadIdx.x % T;
+  const int obase = st[oc], ocnt = st[oc + 1] - obase;
+  const int ohalf = (ocnt - 1) / 2;
   cplx<R> nxt[8];
   load(p0, nxt);
   for (int p = p0; p < p1; ++p) {
@@ -300,20 +302,12 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 #pragma unroll
     for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
     __syncthreads();
-    // the block's pencils own one contiguous run of modes [m0, m0 + len): write it with
-    // wavefront accesses aligned to 128-byte lines
-    cplx<R> *dst = out + (size_t)p * mstride;
-    for (int64_t e = a0 + threadIdx.x; e < m0 + len; e += NT) {
-      if (e < m0) continue;
-      const int r = (int)(e - m0);
-      int cc = 0;
-#pragma unroll
-      for (int i = 1; i < C; ++i) cc += (r >= st[i]) ? 1 : 0;
-      const int j = r - st[cc];
-      const int cnt = st[cc + 1] - st[cc];
-      const int half = (cnt - 1) / 2;
-      const int kz = (cnt == N) ? j : (j <= half ? j : N - (cnt - j));
-      dst[e] = lds[kz * (C + 1) + cc];
+    // the block's pencils own one contiguous run of modes starting at m0; pencil oc holds the
+    // kz of its count in the order 0, 1, .., half, -(cnt-1-half), .., -1
+    cplx<R> *dst = out + (size_t)p * mstride + m0 + obase;
+    for (int j = oj; j < ocnt; j += T) {
+      const int kz = (ocnt == N) ? j : (j <= ohalf ? j : N - (ocnt - j));
+      dst[j] = lds[kz * (C + 1) + oc];
     }
     __syncthreads();  // LDS reads done before the next transform writes
   }
