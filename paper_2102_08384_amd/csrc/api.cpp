@@ -430,7 +430,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const double x3 = (double)h.nfields * modes_real * csz;
   char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
   mark("fx", ncell * rsz + x1);
-  launch_fx(s, h.prec, N, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
+  launch_fx(s, h.prec, N, false, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
             h.unit, dp->tw, dp->rowlist, dp->norm);
   mark("fy", x1 + x2);
   if (F.npen > 0)
@@ -509,7 +509,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
                      a3 = (double)h.n_a * P.nmodes * csz;
         mark("afx", (double)h.n_a * ncell * rsz + a1);
-        launch_fx(s, h.prec, N, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
+        launch_fx(s, h.prec, N, true, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
                   h.unit, dp->tw, nullptr, nullptr);
         mark("afy", a1 + a2);
         if (P.npen > 0)

@@ -95,7 +95,8 @@ inline int row_stride(int nkx, int prec) {
 // product (2r)^-alpha |D|^alpha is unchanged while fields of every alpha stay O(1)).
 // rowlist (may be null: every row) restricts the pass to the non-empty rows; the output rows of
 // empty ones are not written (the y pass reads them as zeros).
-void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
+// plain: every job is kind 2 (pairs of real input fields, no weighting); else kinds 0 and 1.
+void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                const int *rowlist, const DevNorm *norm);
 // c2c along y (forward, or inverse when inv), on nplanes planes per field:

@@ -24,12 +24,108 @@ void upload_sh_const(const ShConst &c) {
 }
 
 // ------------------------------------------------------------------------------ fx
-template <typename R, int N>
+// Legendre part of the real harmonics for the 8 values of a lane, stepped in J at fixed m
+// (the Cartesian recurrence of ShRec8) with the last two orders in qa / qb: a step overwrites the
+// older one in place and flips `b_cur`, so no register copies happen; callers read the current
+// order through `with_cur`, which hands the right array to a generic lambda (both versions are
+// compiled, the uniform flag picks one).
+template <typename R>
+struct ShPair8 {
+  R cr[8], ci[8], qa[8], qb[8];
+  int m_cur, J_cur;
+  bool b_cur;  // qb holds order J_cur (qa the one before), else the reverse
+  __device__ __forceinline__ void restart_q() {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) { qa[s] = 1; qb[s] = 0; }
+    b_cur = false;
+    J_cur = m_cur;
+  }
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) { cr[s] = 1; ci[s] = 0; }
+    m_cur = 0;
+    restart_q();
+  }
+  __device__ __forceinline__ void set_m(int m, const R *ux, const R *uy) {
+    if (m == m_cur) return;
+    if (m != m_cur + 1) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) { cr[s] = 1; ci[s] = 0; }
+      m_cur = 0;
+    }
+    for (; m_cur < m; ++m_cur) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const R tr = cr[s] * ux[s] - ci[s] * uy[s];
+        ci[s] = cr[s] * uy[s] + ci[s] * ux[s];
+        cr[s] = tr;
+      }
+    }
+    restart_q();
+  }
+  // Q_{J+1} = a z Q_J - b Q_{J-1}, from Q_m = 1 and Q_{m-1} = 0 (the first step is then
+  // (2m+1) z Q_m with the general coefficients)
+  // z / r = pz * ir (ir = 1/r, 0 at the origin, whose direction is taken as +z)
+  __device__ __forceinline__ void advance(const ShConst &c, int Jt, R pz, const R *ir) {
+    if (Jt < J_cur) restart_q();
+    while (J_cur < Jt) {
+      ++J_cur;
+      const R a = sh_a<R>(c, J_cur, m_cur), b = sh_b<R>(c, J_cur, m_cur);
+      if (b_cur) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) qa[s] = a * (ir[s] > (R)0 ? pz * ir[s] : (R)1) * qb[s] - b * qa[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) qb[s] = a * (ir[s] > (R)0 ? pz * ir[s] : (R)1) * qa[s] - b * qb[s];
+      }
+      b_cur = !b_cur;
+    }
+  }
+  template <typename Fn>
+  __device__ __forceinline__ void with_cur(Fn &&fn) const {
+    if (b_cur) fn(qb); else fn(qa);
+  }
+};
+
+// LDS ordering between the lanes of one wavefront (LDS executes a wavefront's instructions in
+// order; this keeps the compiler from moving accesses across the exchange point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// value of lane `src` (0..63) of this wavefront
+template <typename R>
+__device__ __forceinline__ cplx<R> lane_fetch(int src, cplx<R> v) {
+  const int addr = src << 2;
+  if constexpr (sizeof(R) == 4) {
+    return mk<R>(__int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v.x))),
+                 __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v.y))));
+  } else {
+    const long long xb = __double_as_longlong(v.x), yb = __double_as_longlong(v.y);
+    const int xl = __builtin_amdgcn_ds_bpermute(addr, (int)(xb & 0xffffffffLL));
+    const int xh = __builtin_amdgcn_ds_bpermute(addr, (int)(xb >> 32));
+    const int yl = __builtin_amdgcn_ds_bpermute(addr, (int)(yb & 0xffffffffLL));
+    const int yh = __builtin_amdgcn_ds_bpermute(addr, (int)(yb >> 32));
+    return mk<R>(__longlong_as_double(((long long)xh << 32) | (unsigned)xl),
+                 __longlong_as_double(((long long)yh << 32) | (unsigned)yl));
+  }
+}
+
+// One block = ROWS rows (z, y) of N cells; lane t of a row holds cells x = t + s*T.  For every
+// job, two real fields (F (u/2r)^alpha y_J^mu, or two plain input fields when PLAIN) go through
+// one complex FFT Z = FFT(a + i b) and are separated as A(k) = (Z(k) + conj Z(N-k)) / 2,
+// B(k) = (Z(k) - conj Z(N-k)) / 2i for kx < nkx.  When a row is one wavefront (T = 64) the FFT's
+// exchanges need only wavefront ordering and Z(N-k) comes from the partner lane by a cross-lane
+// permute; otherwise the rows of the block share barriers and the separation reads LDS.
+template <typename R, int N, bool PLAIN>
 __global__ void __launch_bounds__(FxShape<N>::THREADS)
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
      int njobs, int nkx, int rs, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw,
      const int *__restrict__ rowlist, const DevNorm *__restrict__ norm) {
   constexpr int T = FxShape<N>::T, ROWS = FxShape<N>::ROWS;
+  constexpr bool WAVE = (T == 64);
   constexpr int LN = N + N / 8;
   __shared__ cplx<R> lds[ROWS * LN];
   const int rl = threadIdx.x / T, t = threadIdx.x % T;
@@ -42,109 +138,160 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
     live = row < nr;
     row = live ? rowlist[row] : 0;
   }
+  if constexpr (WAVE) {
+    if (!live) return;  // a whole wavefront, and no block-wide barrier follows
+  }
   const int y = row & (N - 1), z = row / N;
   cplx<R> *my = lds + rl * LN;
   auto at = [my](int i) -> cplx<R> & { return my[i + (i >> 3)]; };
-  auto sync = []() { __syncthreads(); };
+  auto sync = []() {
+    if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
+  };
 
-  R f[8], ux[8], uy[8], uz[8], inv2r[8];
+  // per value: density and 1/r (the direction is rebuilt from the position where needed)
+  R f[8], ir[8];
   const R py = b0y + (R)y * H, pz = b0z + (R)z * H;
+  if constexpr (!PLAIN) {
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int x = t + s * T;
-    f[s] = live ? mesh[(size_t)row * N + x] : (R)0;
-    const R px = b0x + (R)x * H;
-    const R r = sqrt(px * px + py * py + pz * pz);
-    if (r > (R)0) {
-      const R ir = (R)1 / r;
-      ux[s] = px * ir; uy[s] = py * ir; uz[s] = pz * ir;
-      inv2r[s] = uhalf * ir;  // u / (2r): lengths in the unit u
-    } else {
-      ux[s] = 0; uy[s] = 0; uz[s] = 1;
-      inv2r[s] = 0;
+    for (int s = 0; s < 8; ++s) {
+      const int x = t + s * T;
+      f[s] = live ? mesh[(size_t)row * N + x] : (R)0;
+      const R px = b0x + (R)x * H;
+      const R r = sqrt(px * px + py * py + pz * pz);
+      ir[s] = (r > (R)0) ? (R)1 / r : (R)0;
     }
   }
   const size_t fstride = (size_t)N * N * rs;  // rows padded to rs (128-byte aligned)
-  // Recurrence state carried across jobs (jobs come sorted by m, then J).
-  ShRec8<R> rec;
-  rec.init();
+  ShPair8<R> rec;
+  if constexpr (!PLAIN) rec.init();
   for (int jb = 0; jb < njobs; ++jb) {
     const FieldJob J = jobs[jb];
     cplx<R> v[8];
-    if (J.kind == 2) {
-      // plain pair of real input fields of the stack at `mesh`
+    if constexpr (PLAIN) {
+      // two real input fields of the stack at `mesh` (the second may be absent)
       const R *fa = mesh + (size_t)J.Ja * N * N * N + (size_t)row * N;
       const R *fb = mesh + (size_t)(J.Jb < 0 ? 0 : J.Jb) * N * N * N + (size_t)row * N;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) v[s] = mk<R>(fa[t + s * T], J.Jb >= 0 ? fb[t + s * T] : (R)0);  // dense
+      for (int s = 0; s < 8; ++s) v[s] = mk<R>(fa[t + s * T], J.Jb >= 0 ? fb[t + s * T] : (R)0);
     } else {
-      R wa[8], wb[8];
+      // kind 0: (J, +m) and (J, -m) at one alpha: norm Q_J^m {Re, Im}(x + iy)^m;
+      // kind 1: (Ja, 0) and (Jb, 0) (Jb < 0: none), each at its own alpha.
+      // Written as one branch-free form: the second field uses ci + 1 = 1 when m = 0.
+      const bool k0 = (J.kind == 0);
+      const int Jb = (k0 || J.Jb < 0) ? J.Ja : J.Jb;
+      const R na = sh_n<R>(c_sh, J.Ja, J.m);
+      const R nb = k0 ? na : (J.Jb >= 0 ? sh_n<R>(c_sh, Jb, 0) : (R)0);
+      const R dci = k0 ? (R)0 : (R)1;
+      R wa[8];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        R p = f[s], pb = f[s];
-        for (int a = 0; a < J.alpha; ++a) p *= inv2r[s];
-        for (int a = 0; a < J.alpha_b; ++a) pb *= inv2r[s];
-        wa[s] = p;
-        wb[s] = pb;
+      for (int s = 0; s < 8; ++s) wa[s] = f[s] * na;
+      for (int a = 0; a < J.alpha; ++a) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) wa[s] *= uhalf * ir[s];  // u / (2r): lengths in the unit u
       }
-      if (J.kind == 0) {
-        rec.set_m(J.m, ux, uy);
-        rec.advance(c_sh, J.Ja, uz);
-        const R n = sh_n<R>(c_sh, J.Ja, J.m);
+      if (J.m != rec.m_cur) {
+        R ux[8], uy[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
-          v[s] = mk<R>(wa[s] * n * rec.q0[s] * rec.cr[s], wa[s] * n * rec.q0[s] * rec.ci[s]);
-      } else {
-        rec.set_m(0, ux, uy);
-        rec.advance(c_sh, J.Ja, uz);
-        const R na = sh_n<R>(c_sh, J.Ja, 0);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) v[s] = mk<R>(wa[s] * na * rec.q0[s], (R)0);
-        if (J.Jb >= 0) {
-          rec.advance(c_sh, J.Jb, uz);
-          const R nb = sh_n<R>(c_sh, J.Jb, 0);
-#pragma unroll
-          for (int s = 0; s < 8; ++s) v[s].y = wb[s] * nb * rec.q0[s];
+        for (int s = 0; s < 8; ++s) {
+          ux[s] = (b0x + (R)(t + s * T) * H) * ir[s];
+          uy[s] = py * ir[s];
         }
+        rec.set_m(J.m, ux, uy);
+      }
+      rec.advance(c_sh, J.Ja, pz, ir);
+      rec.with_cur([&](const R *q) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s].x = wa[s] * q[s] * rec.cr[s];
+      });
+      rec.advance(c_sh, Jb, pz, ir);
+      if (J.alpha_b == J.alpha) {
+        const R rb = nb / na;  // na > 0 always
+        rec.with_cur([&](const R *q) {
+#pragma unroll
+          for (int s = 0; s < 8; ++s) v[s].y = wa[s] * rb * q[s] * (rec.ci[s] + dci);
+        });
+      } else {
+        R wb[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) wb[s] = f[s] * nb;
+        for (int a = 0; a < J.alpha_b; ++a) {
+#pragma unroll
+          for (int s = 0; s < 8; ++s) wb[s] *= uhalf * ir[s];
+        }
+        rec.with_cur([&](const R *q) {
+#pragma unroll
+          for (int s = 0; s < 8; ++s) v[s].y = wb[s] * q[s] * (rec.ci[s] + dci);
+        });
       }
     }
     fft_pencil<R, N, false>(v, t, tw, at, sync);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
-    __syncthreads();
     cplx<R> *oa = out + (size_t)J.pa * fstride + (size_t)row * rs;
     cplx<R> *ob = out + (size_t)(J.pb < 0 ? 0 : J.pb) * fstride + (size_t)row * rs;
-    for (int kx = t; live && kx < rs; kx += T) {
-      if (kx >= nkx) {  // padding to the 128-byte row stride: whole-line writes
-        oa[kx] = mk<R>(0, 0);
-        if (J.pb >= 0) ob[kx] = mk<R>(0, 0);
-        continue;
+    const bool hb = J.pb >= 0;
+    if constexpr (WAVE) {
+      // lane t holds Z(t + 64 s).  Z(N - k) for k = t + 64 s, s < 4: lane (64 - t) & 63, its
+      // v[7 - s] (t > 0) or v[(8 - s) & 7] (lane 0); every lane publishes the value its
+      // partner needs.  k = 256 (s = 4) is lane 0's own v[4]; 256 < k < rs is padding.
+      const int partner = (64 - t) & 63;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const cplx<R> pub = (t == 0) ? v[(8 - s) & 7] : v[7 - s];
+        const cplx<R> b = lane_fetch<R>(partner, pub);
+        const cplx<R> a = v[s];
+        const int kx = t + 64 * s;
+        if (kx < rs) {
+          const bool keep = kx < nkx;
+          oa[kx] = keep ? mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y)) : mk<R>(0, 0);
+          if (hb) ob[kx] = keep ? mk<R>((R)0.5 * (a.y + b.y), (R)0.5 * (b.x - a.x)) : mk<R>(0, 0);
+        }
       }
-      const cplx<R> a = at(kx), b = at((N - kx) & (N - 1));
-      // A = (Z(k) + conj Z(N-k)) / 2,  B = (Z(k) - conj Z(N-k)) / (2i)
-      oa[kx] = mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y));
-      if (J.pb >= 0) ob[kx] = mk<R>((R)0.5 * (a.y + b.y), (R)0.5 * (b.x - a.x));
+      const int kx = 256 + t;
+      if (kx < rs) {
+        const bool keep = (t == 0) && kx < nkx;  // Z(256) pairs with itself
+        const cplx<R> a = v[4];
+        oa[kx] = keep ? mk<R>(a.x, (R)0) : mk<R>(0, 0);
+        if (hb) ob[kx] = keep ? mk<R>(a.y, (R)0) : mk<R>(0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
+      __syncthreads();
+      for (int kx = t; live && kx < rs; kx += T) {
+        if (kx >= nkx) {  // padding to the 128-byte row stride: whole-line writes
+          oa[kx] = mk<R>(0, 0);
+          if (hb) ob[kx] = mk<R>(0, 0);
+          continue;
+        }
+        const cplx<R> a = at(kx), b = at((N - kx) & (N - 1));
+        oa[kx] = mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y));
+        if (hb) ob[kx] = mk<R>((R)0.5 * (a.y + b.y), (R)0.5 * (b.x - a.x));
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
 template <typename R, int N>
-static void fx_launch(hipStream_t s, const void *mesh, void *out, const FieldJob *jobs, int njobs,
+static void fx_launch(hipStream_t s, bool plain, const void *mesh, void *out, const FieldJob *jobs, int njobs,
                       int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                       const int *rowlist, const DevNorm *norm) {
   constexpr int ROWS = FxShape<N>::ROWS;
   unsigned blocks = (unsigned)((size_t)N * N / ROWS);
-  hipLaunchKernelGGL((k_fx<R, N>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
-                     (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
-                     (const cplx<R> *)tw, rowlist, norm);
+  if (plain)
+    hipLaunchKernelGGL((k_fx<R, N, true>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
+                       (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
+                       (const cplx<R> *)tw, rowlist, norm);
+  else
+    hipLaunchKernelGGL((k_fx<R, N, false>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
+                       (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
+                       (const cplx<R> *)tw, rowlist, norm);
 }
 
-void launch_fx(hipStream_t s, int prec, int N, const void *mesh, void *out, const FieldJob *jobs,
+void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                const int *rowlist, const DevNorm *norm) {
-  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
-  else { PW_DISPATCH_N(fx_launch, double, s, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
+  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, plain, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
+  else { PW_DISPATCH_N(fx_launch, double, s, plain, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
 }
 
 // ------------------------------------------------------------------------------ fy / fz
