@@ -160,10 +160,12 @@ int pw_set_lanes(pw_ctx *ctx, int n_lanes);
 /* Copy an internal buffer of the context's most recent pw_estimate to host memory (for
  * per-stage checks).  what:
  *   0  painted node masses, [N][N][N] (z, y, x order; FP32 or FP64 by prec)
- *   1  bisector P_l: retained half-spectrum values of the weighted fields, [nfields][nmodes]
- *      complex (real-harmonic field index J*J + J + mu)
- *   2  bisector P_l: coordinates of those modes, [nmodes] uint32 = kx | ky << 11 | kz << 22
- *      (FFT indices; kx <= N/2); PW_EINVAL for paths that keep full spectra
+ *   1  bisector P_l: the z-pass output slots of the weighted fields, [nfields][nslots] complex
+ *      (real-harmonic field index J*J + J + mu); every retained half-spectrum mode occupies
+ *      exactly one slot
+ *   2  bisector P_l: coordinate of each slot, [nslots] uint32 = kx | ky << 11 | kz << 22 (FFT
+ *      indices; kx <= N/2), or 0xFFFFFFFF for a padding slot that holds no mode;
+ *      PW_EINVAL for paths that keep full spectra
  * *needed receives the byte count; data are copied only when dst is not NULL and
  * dst_bytes >= *needed.  Synchronises the context's stream. */
 int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed);

@@ -249,6 +249,8 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
       d.pinfo = upload(ctx, dp.get(), p.pinfo);
       d.moff = upload(ctx, dp.get(), p.moff);
       d.modecoord = upload(ctx, dp.get(), p.modecoord);
+      d.goff = upload(ctx, dp.get(), p.goff);
+      d.gsize = upload(ctx, dp.get(), p.gsize);
     };
     up_prune(h.fwd, dp->fwd);
     up_prune(h.sph, dp->sph);
@@ -424,7 +426,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const int N = h.N;
   const Prune &F = h.fwd;
   // algorithmic bytes (retained values only, no padding)
-  const double modes_real = F.full ? (double)N * F.npen_real : (double)F.nmodes;
+  const double modes_real = F.full ? (double)N * F.npen_real : (double)F.nretained;
   const double x1 = (double)h.nfields * N * N * F.nkx * csz;
   const double x2 = (double)h.nfields * N * F.npen_real * csz;
   const double x3 = (double)h.nfields * modes_real * csz;
@@ -438,13 +440,14 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
               dp->rowmask, dp->zlist, dp->norm);
   mark("fz", x2 + x3);
   if (F.npen > 0)
-    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, F.mstride, dp->tw,
+    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff, dp->fwd.gsize,
+              F.mstride, dp->tw,
               dp->planemask);
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
   const size_t nacc = (size_t)(h.nell + 2) * h.n_bins;
   if (h.path == PATH_BIS_PK) {
     // a7: contraction and FP64 binning
-    mark("contract", x3 + 4.0 * F.nmodes);
+    mark("contract", x3 + 4.0 * F.nretained);
     launch_fill(s, dp->acc, nacc, 1);
     TermTable tab;
     tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
@@ -507,7 +510,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         // forward transforms of A, pruned to the k-sphere of the bins
         const Prune &P = h.sph;
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
-                     a3 = (double)h.n_a * P.nmodes * csz;
+                     a3 = (double)h.n_a * P.nretained * csz;
         mark("afx", (double)h.n_a * ncell * rsz + a1);
         launch_fx(s, h.prec, N, true, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
                   h.unit, dp->tw, nullptr, nullptr);
@@ -517,10 +520,11 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
                     nullptr, nullptr, nullptr);
         mark("afz", a2 + a3);
         if (P.npen > 0)
-          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, P.mstride, dp->tw, nullptr);
+          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, dp->sph.goff, dp->sph.gsize,
+                    P.mstride, dp->tw, nullptr);
       }
       // a7 (midpoint): sum_nu y_l^nu(k^) Re[G_{l nu} + A_{l nu}] and FP64 k-binning
-      mark("contract", (double)(h.n0 + h.n_a) * h.sph.nmodes * csz + 4.0 * h.sph.nmodes);
+      mark("contract", (double)(h.n0 + h.n_a) * h.sph.nretained * csz + 4.0 * h.sph.nretained);
       launch_fill(s, dp->acc, nacc, 1);
       launch_contract_mid(s, h.prec, h.ell_max, A, F.rs, h.n_a > 0 ? B : nullptr, h.sph.nmodes, h.sph.mstride,
                           dp->sph.modecoord, N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->acc);
@@ -615,7 +619,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
     const double N = h.N, rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2 * rsz;
     const double fr = dn.nrows_occ / (N * N), fp = dn.nplanes_occ / N;
-    const double modes_real = h.fwd.full ? N * (double)h.fwd.npen_real : (double)h.fwd.nmodes;
+    const double modes_real = h.fwd.full ? N * (double)h.fwd.npen_real : (double)h.fwd.nretained;
     const double x1 = (double)h.nfields * N * N * h.fwd.nkx * csz;
     const double x2 = (double)h.nfields * N * h.fwd.npen_real * csz;
     const double x3 = (double)h.nfields * modes_real * csz;

@@ -108,11 +108,13 @@ void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, voi
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields,
                int nplanes, int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen,
                const void *tw, const int *rowmask, const int *zlist, const DevNorm *norm);
-// c2c along z, pruned: out[p][moff[q] + j], j < pinfo[q].kzcnt.
+// c2c along z.  Full sets (goff null): out[p][moff[q] + kz], all N kz of every pencil.
+// Sphere-pruned sets: out[p][goff[g] + slot * C + c] for pencil q = g C + c, slot as in Prune
+// (C = 128 bytes / complex size, the pencils per workgroup).  Field stride mstride.
 // planemask (may be null): empty z-planes of the input are read as zeros.
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
-               int64_t npen, const PencilInfo *pinfo, const int64_t *moff, int64_t nmodes,
-               const void *tw, const int *planemask);
+               int64_t npen, const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff,
+               const int *gsize, int64_t mstride, const void *tw, const int *planemask);
 
 // Bisector contraction + FP64 k-binning.
 struct TermTable {

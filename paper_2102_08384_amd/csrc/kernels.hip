@@ -119,8 +119,10 @@ __device__ __forceinline__ cplx<R> lane_fetch(int src, cplx<R> v) {
 // B(k) = (Z(k) - conj Z(N-k)) / 2i for kx < nkx.  When a row is one wavefront (T = 64) the FFT's
 // exchanges need only wavefront ordering and Z(N-k) comes from the partner lane by a cross-lane
 // permute; otherwise the rows of the block share barriers and the separation reads LDS.
+// FP32 at N = 512 fits three wavefronts per SIMD without spills (FP64 would spill).
 template <typename R, int N, bool PLAIN>
 __global__ void __launch_bounds__(FxShape<N>::THREADS)
+__attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && N == 512) ? 3 : 1, 8)))
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
      int njobs, int nkx, int rs, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw,
      const int *__restrict__ rowlist, const DevNorm *__restrict__ norm) {
@@ -396,14 +398,18 @@ void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *ou
   }
 }
 
-template <typename R, int N>
+// Output layouts (see Prune): full sets pencil-major, written through an LDS transpose so that
+// each pencil's run leaves as whole wavefront stores; sphere-pruned sets (goff != null) grouped
+// as [kz slot][pencil], so the C lanes of one kz write one 128-byte line straight from registers.
+template <typename R, int N, bool GROUPED>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int fpb, int64_t npen,
-     const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, int64_t mstride,
-     const cplx<R> *__restrict__ tw, const int *__restrict__ planemask) {
+     const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, const int64_t *__restrict__ goff,
+     const int *__restrict__ gsize, int64_t mstride, const cplx<R> *__restrict__ tw,
+     const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
   __shared__ cplx<R> lds[N * (C + 1)];
-  __shared__ int st[C + 1];                      // first output mode of each pencil, relative
+  __shared__ int st[C + 1];                      // full sets: first output mode of each pencil
   __shared__ int msk[N];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int64_t q0 = (int64_t)blockIdx.x * C;
@@ -414,15 +420,25 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
   FftTw<R, N> twr;
   twr.load(t, tw);
   for (int i = threadIdx.x; i < N; i += NT) msk[i] = planemask ? planemask[i] : 1;
-  const int64_t m0 = moff[q0];
-  if (threadIdx.x <= C) {
-    const int64_t qq = q0 + threadIdx.x;
-    const int64_t e = (qq < npen) ? moff[qq] : moff[npen - 1] + pinfo[npen - 1].kzcnt;
-    st[threadIdx.x] = (int)(e - m0);
+  int64_t m0;
+  int S = 0;
+  if constexpr (GROUPED) {
+    m0 = goff[blockIdx.x];
+    S = gsize[blockIdx.x];
+  } else {
+    m0 = moff[q0];
+    if (threadIdx.x <= C) {
+      const int64_t qq = q0 + threadIdx.x;
+      const int64_t e = (qq < npen) ? moff[qq] : moff[npen - 1] + pinfo[npen - 1].kzcnt;
+      st[threadIdx.x] = (int)(e - m0);
+    }
   }
   const bool has = q < npen && pinfo[q].kzcnt > 0;  // padding pencils hold no modes
   wait_vmem();
   __syncthreads();
+  if constexpr (GROUPED) {
+    if (S == 0) return;  // no pencil of the group holds a mode (uniform, after the last barrier)
+  }
   auto load = [&](int p, cplx<R> *v) {
     const cplx<R> *src = in + (size_t)p * N * npen;
 #pragma unroll
@@ -433,11 +449,17 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
   };
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
-  // output of pencil cc goes out through its own T lanes (a whole wavefront when T = 64):
-  // one contiguous run of modes per lane group, no search over the block's pencils
+  // grouped: slot of kz = t + s T, or -1 outside the group's kz extent
+  const int h = (S - 1) / 2;
+  int slot[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int kz = t + s * T;
+    slot[s] = (S == N || kz <= h) ? kz : (kz >= N - h ? kz - N + S : -1);
+  }
+  // full: pencil oc goes out through its own T lanes (a whole wavefront when T = 64)
   const int oc = threadIdx.x / T, oj = threadIdx.x % T;
-  const int obase = st[oc], ocnt = st[oc + 1] - obase;
-  const int ohalf = (ocnt - 1) / 2;
+  const int obase = GROUPED ? 0 : st[oc], ocnt = GROUPED ? 0 : st[oc + 1] - obase;
   cplx<R> nxt[8];
   load(p0, nxt);
   for (int p = p0; p < p1; ++p) {
@@ -446,39 +468,52 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
     if (p + 1 < p1) load(p + 1, nxt);
     fft_pencil<R, N, false>(v, t, twr, at, sync);
+    if constexpr (GROUPED) {
+      cplx<R> *dst = out + (size_t)p * mstride + m0 + c;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
-    __syncthreads();
-    // the block's pencils own one contiguous run of modes starting at m0; pencil oc holds the
-    // kz of its count in the order 0, 1, .., half, -(cnt-1-half), .., -1
-    cplx<R> *dst = out + (size_t)p * mstride + m0 + obase;
-    for (int j = oj; j < ocnt; j += T) {
-      const int kz = (ocnt == N) ? j : (j <= ohalf ? j : N - (ocnt - j));
-      dst[j] = lds[kz * (C + 1) + oc];
+      for (int s = 0; s < 8; ++s)
+        if (slot[s] >= 0) dst[(size_t)slot[s] * C] = v[s];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
+      __syncthreads();
+      // the block's pencils own one contiguous run of modes starting at m0, all N kz each
+      cplx<R> *dst = out + (size_t)p * mstride + m0 + obase;
+      for (int j = oj; j < ocnt; j += T) dst[j] = lds[j * (C + 1) + oc];
+      __syncthreads();  // LDS reads done before the next transform writes
     }
-    __syncthreads();  // LDS reads done before the next transform writes
   }
 }
 
 template <typename R, int N>
 static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int64_t npen,
-                      const PencilInfo *pinfo, const int64_t *moff, int64_t mstride, const void *tw,
-                      const int *planemask) {
+                      const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
+                      int64_t mstride, const void *tw, const int *planemask) {
   constexpr int C = ColShape<R, N>::C;
+  static_assert(C == 128 / (int)sizeof(cplx<R>), "z-pass groups must match 128-byte slot rows");
   const unsigned ng = (unsigned)((npen + C - 1) / C);
   const int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
   const int fpb = (nfields + G - 1) / G;
   dim3 grid(ng, (nfields + fpb - 1) / fpb);
-  hipLaunchKernelGGL((k_fz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
-                     (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, mstride, (const cplx<R> *)tw, planemask);
+  if (goff)
+    hipLaunchKernelGGL((k_fz<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
+                       (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, goff, gsize, mstride, (const cplx<R> *)tw,
+                       planemask);
+  else
+    hipLaunchKernelGGL((k_fz<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
+                       (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, goff, gsize, mstride, (const cplx<R> *)tw,
+                       planemask);
 }
 
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int64_t npen,
-               const PencilInfo *pinfo, const int64_t *moff, int64_t mstride, const void *tw,
-               const int *planemask) {
+               const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
+               int64_t mstride, const void *tw, const int *planemask) {
   if (nfields <= 0 || npen <= 0) return;
-  if (prec == 0) { PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, mstride, tw, planemask) }
-  else { PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, mstride, tw, planemask) }
+  if (prec == 0) {
+    PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask)
+  } else {
+    PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask)
+  }
 }
 
 // ------------------------------------------------------------------------------ contraction

@@ -176,8 +176,7 @@ template <typename R> struct Rec4;
 template <> struct Rec4<float> { typedef float4 T; };
 template <> struct Rec4<double> { typedef double4 T; };
 
-constexpr int kAggChunk = 65536;   // particles per workgroup of the sort kernels
-constexpr int kAggThreads = 1024;
+constexpr int kAggThreads = 1024;  // the sort kernels: one workgroup per chunk of particles
 
 template <typename RI>
 __device__ __forceinline__ bool particle_tile(const RI *__restrict__ xyzw, int64_t i, int N, double b0x,
@@ -194,14 +193,14 @@ __device__ __forceinline__ bool particle_tile(const RI *__restrict__ xyzw, int64
 // Per-workgroup LDS histogram of a chunk; one global atomic per (chunk, occupied tile).
 template <typename RI>
 __global__ void __launch_bounds__(kAggThreads)
-k_tile_count(const RI *__restrict__ xyzw, int64_t n, int N, double b0x, double b0y, double b0z, double H,
-             int assign, int ts, int ntiles, int *__restrict__ counts) {
+k_tile_count(const RI *__restrict__ xyzw, int64_t n, int64_t chunk, int N, double b0x, double b0y, double b0z,
+             double H, int assign, int ts, int ntiles, int *__restrict__ counts) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int *hist = reinterpret_cast<int *>(smem_raw);
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * kAggChunk;
-  const int64_t c1 = c0 + kAggChunk < n ? c0 + kAggChunk : n;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
     int i0[3], tile;
     double d[3];
@@ -214,6 +213,8 @@ k_tile_count(const RI *__restrict__ xyzw, int64_t n, int N, double b0x, double b
 
 // offsets = exclusive scan of counts (offsets[ntiles] = total), cursor = offsets,
 // slot[t] = rank of tile t among the occupied tiles (-1 if empty), slots[ntiles] = count.
+// Thread i owns the run [i * per, (i + 1) * per); when ntiles is a multiple of 4 * 1024 (and
+// per <= 64) the runs are read and written as 16-byte vectors.
 __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ counts, int ntiles,
                                                     int *__restrict__ offsets, int *__restrict__ cursor,
                                                     int *__restrict__ slot) {
@@ -221,10 +222,25 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ coun
   __shared__ int occ[1024];
   const int per = (ntiles + 1023) / 1024;
   const int b = threadIdx.x * per, e = min(ntiles, b + per);
+  const bool vec = (ntiles % 4096) == 0 && per <= 64;
+  int c[64];
   int s = 0, o = 0;
-  for (int i = b; i < e; ++i) {
-    s += counts[i];
-    o += counts[i] > 0;
+  if (vec) {
+#pragma unroll
+    for (int k = 0; k < 64; k += 4) {
+      if (k < per) {
+        const int4 q = *reinterpret_cast<const int4 *>(counts + b + k);
+        c[k] = q.x; c[k + 1] = q.y; c[k + 2] = q.z; c[k + 3] = q.w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 64; ++k)
+      if (k < per) { s += c[k]; o += c[k] > 0; }
+  } else {
+    for (int i = b; i < e; ++i) {
+      s += counts[i];
+      o += counts[i] > 0;
+    }
   }
   part[threadIdx.x] = s;
   occ[threadIdx.x] = o;
@@ -239,11 +255,27 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ coun
   }
   int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
   int orun = threadIdx.x > 0 ? occ[threadIdx.x - 1] : 0;
-  for (int i = b; i < e; ++i) {
-    offsets[i] = run;
-    cursor[i] = run;
-    run += counts[i];
-    slot[i] = counts[i] > 0 ? orun++ : -1;
+  if (vec) {
+#pragma unroll
+    for (int k = 0; k < 64; k += 4) {
+      if (k < per) {
+        int4 of, sl;
+        of.x = run; run += c[k]; sl.x = c[k] > 0 ? orun++ : -1;
+        of.y = run; run += c[k + 1]; sl.y = c[k + 1] > 0 ? orun++ : -1;
+        of.z = run; run += c[k + 2]; sl.z = c[k + 2] > 0 ? orun++ : -1;
+        of.w = run; run += c[k + 3]; sl.w = c[k + 3] > 0 ? orun++ : -1;
+        *reinterpret_cast<int4 *>(offsets + b + k) = of;
+        *reinterpret_cast<int4 *>(cursor + b + k) = of;
+        *reinterpret_cast<int4 *>(slot + b + k) = sl;
+      }
+    }
+  } else {
+    for (int i = b; i < e; ++i) {
+      offsets[i] = run;
+      cursor[i] = run;
+      run += counts[i];
+      slot[i] = counts[i] > 0 ? orun++ : -1;
+    }
   }
   if (threadIdx.x == 1023) {
     offsets[ntiles] = part[1023];
@@ -254,15 +286,15 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ coun
 // Reserve one run per (chunk, tile) and rank the chunk's particles inside it with LDS atomics.
 template <typename RI, typename RM>
 __global__ void __launch_bounds__(kAggThreads)
-k_tile_scatter(const RI *__restrict__ xyzw, int64_t n, int N, double b0x, double b0y, double b0z, double H,
-               int assign, int ts, int ntiles, const DevNorm *__restrict__ norm, int is_random,
+k_tile_scatter(const RI *__restrict__ xyzw, int64_t n, int64_t chunk, int N, double b0x, double b0y, double b0z,
+               double H, int assign, int ts, int ntiles, const DevNorm *__restrict__ norm, int is_random,
                int *__restrict__ cursor, typename Rec4<RM>::T *__restrict__ rec) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int *hist = reinterpret_cast<int *>(smem_raw);
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * kAggChunk;
-  const int64_t c1 = c0 + kAggChunk < n ? c0 + kAggChunk : n;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
     int i0[3], tile;
     double d[3];
@@ -290,16 +322,17 @@ k_tile_scatter(const RI *__restrict__ xyzw, int64_t n, int N, double b0x, double
 }
 
 // One workgroup per tile: the tile's nodes plus a one-node halo (local index -1 .. ts on each
-// axis, E = ts + 2) accumulated in LDS, then stored as block `slot[tile]` of the scratch.
-// Contributions are accumulated as 64-bit fixed point, round(c * fix_scale) with fix_scale a
-// power of two (integer LDS atomics run at full rate where floating-point LDS atomics are
-// serialised per lane); integer sums are exact, so the mesh does not depend on the order.
+// axis, E = ts + 2) accumulated in LDS, then stored as block `slot[tile]` of the scratch in the
+// mesh precision.  Contributions are accumulated as 64-bit fixed point, round(c * fix_scale)
+// with fix_scale a power of two (integer LDS atomics run at full rate where floating-point LDS
+// atomics are serialised per lane); integer sums are exact, so a block does not depend on the
+// order of its particles.
 template <typename RM, int ASSIGN>
 __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restrict__ offsets,
                                                     const int *__restrict__ slot,
                                                     const typename Rec4<RM>::T *__restrict__ rec,
                                                     const DevNorm *__restrict__ norm,
-                                                    unsigned long long *__restrict__ blocks) {
+                                                    RM *__restrict__ blocks) {
   const int tile = blockIdx.x;
   const int beg = offsets[tile], end = offsets[tile + 1];
   if (beg == end) return;  // uniform for the block
@@ -348,20 +381,22 @@ __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restric
     }
   }
   __syncthreads();
-  unsigned long long *dst = blocks + (size_t)slot[tile] * E3;
-  for (int c = threadIdx.x; c < E3; c += blockDim.x) dst[c] = acc[c];
+  const double inv = 1.0 / norm->fix_scale;
+  RM *dst = blocks + (size_t)slot[tile] * E3;
+  for (int c = threadIdx.x; c < E3; c += blockDim.x) dst[c] = (RM)((double)(long long)acc[c] * inv);
 }
 
 // Node (x, y, z) of tile T at local (lx, ly, lz) is covered by the block of tile T + d for
 // d in {-1, 0, 1}^3 where d_a = -1 needs l_a = 0 and d_a = +1 needs l_a = ts - 1; inside that
-// block it sits at local l - d ts, block index l - d ts + 1.  Empty tiles have no block.
+// block it sits at local l - d ts, block index l - d ts + 1.  Empty tiles have no block.  The
+// (at most eight) block values are summed in FP64 in the fixed order of d, so the mesh is the
+// same on every run.
 // One workgroup per group of GX tiles along x (GX = 2 for FP32 with at least two tiles per
 // axis, so mesh rows are written as whole 128-byte lines); the slots of the group's
 // neighbourhood are read into LDS once.  N and ts are powers of two.
 template <typename RM>
 __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx, const int *__restrict__ slot,
-                                                     const unsigned long long *__restrict__ blocks,
-                                                     const DevNorm *__restrict__ norm, RM *__restrict__ mesh,
+                                                     const RM *__restrict__ blocks, RM *__restrict__ mesh,
                                                      int *__restrict__ rowmask) {
   const int N = 1 << lgN, ts = 1 << lgts, nt = N >> lgts, E = ts + 2, GX = 1 << lggx;
   const size_t E3 = (size_t)E * E * E;
@@ -376,7 +411,6 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx
     sl[dz + 1][dy + 1][dxi] = slot[(tzz * nt + tyy) * nt + tx];
   }
   __syncthreads();
-  const double inv = 1.0 / norm->fix_scale;
   const int lgW = lggx + lgts;  // nodes per row of the group: W = GX * ts
   const int nnode = 1 << (lgW + 2 * lgts);
 #pragma unroll 4
@@ -390,19 +424,19 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx
       dlo[a] = (l[a] == 0) ? -1 : 0;
       dhi[a] = (l[a] == ts - 1) ? 1 : 0;
     }
-    unsigned long long v = 0;
+    double v = 0.0;
     for (int dz = dlo[2]; dz <= dhi[2]; ++dz)
       for (int dy = dlo[1]; dy <= dhi[1]; ++dy)
         for (int dx = dlo[0]; dx <= dhi[0]; ++dx) {
           const int s = sl[dz + 1][dy + 1][txl + dx + 1];
           if (s < 0) continue;
           const int ex = lx - dx * ts + 1, ey = ly - dy * ts + 1, ez = lz - dz * ts + 1;
-          v += blocks[(size_t)s * E3 + ((size_t)ez * E + ey) * E + ex];
+          v += (double)blocks[(size_t)s * E3 + ((size_t)ez * E + ey) * E + ex];
         }
     const int x = (tx0 << lgts) + lxg, y = (ty << lgts) + ly, z = (tz << lgts) + lz;
     const size_t g = ((size_t)z * N + y) * N + x;
-    mesh[g] = (RM)((double)(long long)v * inv);
-    if (rowmask && v != 0) rowmask[g >> lgN] = 1;  // every writer stores the same value
+    mesh[g] = (RM)v;
+    if (rowmask && v != 0.0) rowmask[g >> lgN] = 1;  // every writer stores the same value
   }
 }
 
@@ -478,19 +512,40 @@ void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, in
                      zlist, norm);
 }
 
+// Particles per workgroup of the sort kernels.  Their LDS histogram of every tile allows one
+// workgroup per CU, so a launch is sized as whole rounds of one workgroup per CU (at most 128 Ki
+// particles per chunk, at least 4096, a multiple of the workgroup size).
+static int64_t sort_chunk(int64_t n) {
+  static thread_local int ncu = 0;
+  if (ncu <= 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+    else
+      ncu = 256;
+  }
+  const int64_t per_round = (int64_t)ncu * 131072;
+  const int64_t rounds = (n + per_round - 1) / per_round;
+  int64_t c = (n + rounds * ncu - 1) / (rounds * ncu);
+  c = (c + kAggThreads - 1) / kAggThreads * kAggThreads;
+  return c < 4096 ? 4096 : c;
+}
+
 void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,
                        const double *b0, double H, int assign, int *counts) {
   if (n <= 0) return;
   const int ts = tile_size(N);
   const int nt = N / ts, ntiles = nt * nt * nt;
   const size_t lds = (size_t)ntiles * sizeof(int);
-  const unsigned chunks = (unsigned)((n + kAggChunk - 1) / kAggChunk);
+  const int64_t chunk = sort_chunk(n);
+  const unsigned chunks = (unsigned)((n + chunk - 1) / chunk);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_tile_count<float>, dim3(chunks), dim3(kAggThreads), lds, s, (const float *)xyzw, n, N,
-                       b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
+    hipLaunchKernelGGL(k_tile_count<float>, dim3(chunks), dim3(kAggThreads), lds, s, (const float *)xyzw, n, chunk,
+                       N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
   else
     hipLaunchKernelGGL(k_tile_count<double>, dim3(chunks), dim3(kAggThreads), lds, s, (const double *)xyzw, n,
-                       N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
+                       chunk, N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
 }
 
 void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot) {
@@ -504,10 +559,11 @@ void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, 
   const int ts = tile_size(N);
   const int nt = N / ts, ntiles = nt * nt * nt;
   const size_t lds = (size_t)ntiles * sizeof(int);
-  const unsigned chunks = (unsigned)((n + kAggChunk - 1) / kAggChunk);
+  const int64_t chunk = sort_chunk(n);
+  const unsigned chunks = (unsigned)((n + chunk - 1) / chunk);
 #define PW_SCAT(RI, RM)                                                                            \
   hipLaunchKernelGGL((k_tile_scatter<RI, RM>), dim3(chunks), dim3(kAggThreads), lds, s, (const RI *)xyzw, \
-                     n, N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, norm, is_random, cursor,    \
+                     n, chunk, N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, norm, is_random, cursor, \
                      (typename Rec4<RM>::T *)records)
   if (dtype == 0 && prec == 0) PW_SCAT(float, float);
   else if (dtype == 0) PW_SCAT(float, double);
@@ -529,19 +585,18 @@ void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *of
   const unsigned ntiles = (unsigned)(nt * nt * nt);
   const size_t E3 = (size_t)(ts + 2) * (ts + 2) * (ts + 2);
   const int lggx_f = nt >= 2 ? 1 : 0;  // FP32: two tiles per workgroup along x (128-byte rows)
-  unsigned long long *b = (unsigned long long *)blocks;
 #define PW_TP(RM, A)                                                                              \
   hipLaunchKernelGGL((k_tile_paint<RM, A>), dim3(ntiles), dim3(256), E3 * sizeof(unsigned long long), s, \
-                     ts, offsets, slot, (const typename Rec4<RM>::T *)records, norm, b)
+                     ts, offsets, slot, (const typename Rec4<RM>::T *)records, norm, (RM *)blocks)
   if (prec == 0) { if (assign == 2) PW_TP(float, 2); else PW_TP(float, 3); }
   else { if (assign == 2) PW_TP(double, 2); else PW_TP(double, 3); }
 #undef PW_TP
   if (prec == 0)
     hipLaunchKernelGGL(k_tile_gather<float>, dim3(ntiles >> lggx_f), dim3(256), 0, s, ilog2(N), ilog2(ts), lggx_f,
-                       slot, b, norm, (float *)mesh, rowmask);
+                       slot, (const float *)blocks, (float *)mesh, rowmask);
   else
-    hipLaunchKernelGGL(k_tile_gather<double>, dim3(ntiles), dim3(256), 0, s, ilog2(N), ilog2(ts), 0, slot, b,
-                       norm, (double *)mesh, rowmask);
+    hipLaunchKernelGGL(k_tile_gather<double>, dim3(ntiles), dim3(256), 0, s, ilog2(N), ilog2(ts), 0, slot,
+                       (const double *)blocks, (double *)mesh, rowmask);
 }
 
 }  // namespace pw

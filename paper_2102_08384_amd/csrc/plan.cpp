@@ -76,18 +76,54 @@ Prune make_prune(int N, int64_t K2, bool full, bool coords, int prec) {
       }
       p.pinfo.push_back(PencilInfo{kx, ky, cnt, 0});
       p.moff.push_back(moff);
-      if (coords && cnt > 0) {
-        const int half = (cnt - 1) / 2;
-        for (int j = 0; j < cnt; ++j) {
-          int kz = (cnt == N) ? j : (j <= half ? j : N - (cnt - j));
+      if (coords && full && cnt > 0) {
+        for (int kz = 0; kz < N; ++kz)
           p.modecoord.push_back((uint32_t)kx | ((uint32_t)ky << 11) | ((uint32_t)kz << 22));
-        }
       }
       moff += cnt;
+      p.nretained += cnt;
     }
   }
-  p.nmodes = moff;
-  p.mstride = padq(moff);
+  if (full) {
+    p.nmodes = moff;
+    p.mstride = padq(moff);
+    return p;
+  }
+  // Sphere-pruned: groups of Q adjacent pencils (the z pass transforms Q pencils per workgroup;
+  // npen is a multiple of Q), each [kz slot][pencil], so that every slot row is one 128-byte
+  // line written straight from the transform's registers.
+  p.grp = Q;
+  const int64_t ngroups = p.npen / Q;
+  p.goff.assign((size_t)ngroups + 1, 0);
+  p.gsize.assign((size_t)ngroups, 0);
+  int64_t soff = 0;
+  for (int64_t g = 0; g < ngroups; ++g) {
+    int hmax = -1;
+    bool whole = false;
+    for (int c = 0; c < Q; ++c) {
+      const int cnt = p.pinfo[(size_t)(g * Q + c)].kzcnt;
+      if (cnt == N) whole = true;
+      else if (cnt > 0) hmax = std::max(hmax, (cnt - 1) / 2);
+    }
+    const int S = whole ? N : (hmax >= 0 ? 2 * hmax + 1 : 0);
+    p.goff[(size_t)g] = soff;
+    p.gsize[(size_t)g] = S;
+    if (coords) {
+      for (int j = 0; j < S; ++j) {
+        const int kz = (S == N || j <= hmax) ? j : N - (S - j);
+        const int64_t sz = signed_idx(kz, N);
+        for (int c = 0; c < Q; ++c) {
+          const PencilInfo &pi = p.pinfo[(size_t)(g * Q + c)];
+          const bool keep = pi.kzcnt == N || (pi.kzcnt > 0 && sz * sz <= (int64_t)((pi.kzcnt - 1) / 2) * ((pi.kzcnt - 1) / 2));
+          p.modecoord.push_back(keep ? ((uint32_t)pi.kx | ((uint32_t)pi.ky << 11) | ((uint32_t)kz << 22)) : kModeNone);
+        }
+      }
+    }
+    soff += (int64_t)S * Q;
+  }
+  p.goff[(size_t)ngroups] = soff;
+  p.nmodes = soff;
+  p.mstride = padq(soff);
   return p;
 }
 

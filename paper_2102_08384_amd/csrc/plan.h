@@ -48,11 +48,23 @@ struct Prune {
   int64_t npen = 0;                 // pencils per y-pass plane, padding included
   int64_t npen_real = 0;            // retained pencils (sum of ycnt)
   std::vector<PencilInfo> pinfo;    // [npen]
-  std::vector<int64_t> moff;        // [npen]
-  int64_t nmodes = 0;               // modes per field (pencil-major), padding pencils included
+  std::vector<int64_t> moff;        // [npen] (full sets: pencil q holds modes [moff[q], +N))
+  // z-pass output.  Full sets: pencil-major, kz fastest.  Sphere-pruned sets: groups of `grp`
+  // adjacent pencils, each stored as [kz slot][pencil of the group]: slot j of group g holds
+  // kz = j for j <= h_g and kz = N - (gsize[g] - j) above (all N kz when gsize[g] == N), with
+  // h_g = (gsize[g] - 1) / 2 the largest half-count of the group's pencils.  Slots outside a
+  // pencil's own sphere (and padding pencils) carry the coordinate kModeNone.
+  int grp = 0;
+  std::vector<int64_t> goff;        // [ngroups + 1] first slot of each group
+  std::vector<int> gsize;           // [ngroups] kz slots of each group
+  int64_t nmodes = 0;               // slots per field (full: N per pencil, padding pencils included)
+  int64_t nretained = 0;            // retained modes per field (slots with a coordinate)
   int64_t mstride = 0;              // field stride of the z-pass output
-  std::vector<uint32_t> modecoord;  // kx | ky << 11 | kz << 22 (pruned sets only)
+  std::vector<uint32_t> modecoord;  // kx | ky << 11 | kz << 22 per slot (pruned sets only)
 };
+
+// coordinate of a slot that holds no retained mode: decodes to |n|^2 > 2047^2, beyond any bin
+constexpr uint32_t kModeNone = 0xFFFFFFFFu;
 
 struct HostPlan {
   int path;
@@ -101,6 +113,8 @@ struct DevPrune {
   PencilInfo *pinfo = nullptr;
   int64_t *moff = nullptr;
   uint32_t *modecoord = nullptr;
+  int64_t *goff = nullptr;   // sphere-pruned sets only
+  int *gsize = nullptr;
 };
 
 struct DevPlan {

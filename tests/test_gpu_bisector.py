@@ -61,7 +61,17 @@ def test_bisector_stages_fp64(ctx):
     mc = ctx.inspect(2)
     nf = 16
     spec = spec.reshape(nf, -1)
+    keep = mc != 0xFFFFFFFF                                  # padding slots carry no mode
+    spec, mc = spec[:, keep], mc[keep]
     kx, ky, kz = mc & 0x7FF, (mc >> 11) & 0x7FF, (mc >> 22) & 0x3FF
+    # the retained modes are distinct and are every half-spectrum mode up to the largest |n|^2
+    assert len(np.unique(mc)) == len(mc)
+    sg = lambda k: np.where(k < 16, k, k - 32)
+    s2 = sg(kx) ** 2 + sg(ky) ** 2 + sg(kz) ** 2
+    g = np.arange(32)
+    ax, ay, az = np.meshgrid(g[:17], g, g, indexing="ij")
+    full_s2 = np.where(ax == 16, 16, ax) ** 2 + sg(ay) ** 2 + sg(az) ** 2
+    assert len(mc) == np.count_nonzero(full_s2 <= s2.max())
     xn = node_positions(32, 800.0, cfg.box_origin)
     for J in range(3):
         for mu in range(-J, J + 1):
