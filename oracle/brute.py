@@ -65,8 +65,9 @@ def _dft_kernel(values, N):
     return out
 
 
-def pair_weight(kind: str, l: int, m: int, xi, xj, K: int):
-    """W^{lm}(i, j) for arrays of pair endpoints xi, xj [P, 3]."""
+def pair_weight(kind: str, l: int, m: int, xi, xj, K: int, K_lo: int = 0):
+    """W^{lm}(i, j) for arrays of pair endpoints xi, xj [P, 3]; the series kinds keep the
+    terms of order K_lo .. K in the opening angle."""
     D = xj - xi
     if kind == "mid_exact":
         return Ylm(l, m, xi + xj)
@@ -81,13 +82,13 @@ def pair_weight(kind: str, l: int, m: int, xi, xj, K: int):
         ei = Dn / (2.0 * np.linalg.norm(xi, axis=-1))
         ej = Dn / (2.0 * np.linalg.norm(xj, axis=-1))
         out = np.zeros(len(xi), dtype=np.complex128)
-        for a in range(0, K + 1, 2):
+        for a in range(K_lo + K_lo % 2, K + 1, 2):
             for (J1, J2, M), c in coeffs.Phi_table(a, l, m).items():
                 out += 0.5 * c * Ylm(J1, M, D) * (ei ** a * Ylm(J2, m - M, xi) + ej ** a * Ylm(J2, m - M, xj))
         return out
     if kind == "bis_series":
         out = np.zeros(len(xi), dtype=np.complex128)
-        for (J1, J2, M), c in coeffs.B_table(K // 2, l, m).items():
+        for (J1, J2, M), c in coeffs.B_table(K // 2, l, m, (K_lo + 1) // 2).items():
             out += c * Ylm(J1, M, xi) * Ylm(J2, m - M, xj)
         return out
     raise ValueError(kind)
@@ -111,7 +112,7 @@ def pk_pairs(gal, ran, cfg, kind: str, norm):
     out = np.zeros((len(cfg.ells), cfg.n_bins))
     for li, l in enumerate(cfg.ells):
         for m in range(-l, l + 1):
-            Wp = pair_weight(kind, l, m, pos[ii], pos[jj], cfg.order)
+            Wp = pair_weight(kind, l, m, pos[ii], pos[jj], cfg.order, cfg.order_lo)
             Ystar = np.conj(Ylm(l, m, kvec))
             for q in range(cfg.n_bins):
                 if counts[q] == 0:
@@ -121,7 +122,7 @@ def pk_pairs(gal, ran, cfg, kind: str, norm):
     with np.errstate(invalid="ignore", divide="ignore"):
         out = FOURPI / I * np.where(counts > 0, out / np.where(counts > 0, counts, 1), 0.0)
     for li, l in enumerate(cfg.ells):
-        if l == 0:
+        if l == 0 and cfg.order_lo == 0:
             out[li] -= np.where(counts > 0, S / I, 0.0)
     return out, counts
 
@@ -162,7 +163,7 @@ def xi_pairs(gal, ran, cfg, kind: str, norm):
             mui = np.sum(Du * xi_, axis=-1) / ri
             muj = np.sum(Du * xj_, axis=-1) / rj
             V = np.zeros(len(D))
-            for a in range(0, cfg.order + 1, 2):
+            for a in range(cfg.order_lo + cfg.order_lo % 2, cfg.order + 1, 2):
                 for J in range(0, l + a + 1, 2):
                     Fv = coeffs.F(a, l, J)
                     if Fv == 0.0:
@@ -173,7 +174,7 @@ def xi_pairs(gal, ran, cfg, kind: str, norm):
         else:
             V = np.zeros(len(D), dtype=np.complex128)
             for m in range(-l, l + 1):
-                V += np.conj(Ylm(l, m, D)) * pair_weight(kind, l, m, xi_, xj_, cfg.order)
+                V += np.conj(Ylm(l, m, D)) * pair_weight(kind, l, m, xi_, xj_, cfg.order, cfg.order_lo)
             V = np.real(V)
         out[li] = np.bincount(bq, weights=ww * V, minlength=cfg.n_bins)
     with np.errstate(invalid="ignore", divide="ignore"):

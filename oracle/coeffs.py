@@ -386,11 +386,12 @@ def B(beta: int, l: int, m: int, J1: int, J2: int, M: int) -> float:
     return 2.0 ** (-l) * gb * total
 
 
-def B_table(beta_max: int, l: int, m: int) -> dict:
-    """B-bar^{lm}_{J1J2M} = sum_{beta <= beta_max} B^{beta,lm}_{J1J2M} as {(J1, J2, M): value}."""
+def B_table(beta_max: int, l: int, m: int, beta_lo: int = 0) -> dict:
+    """B-bar^{lm}_{J1J2M} = sum_{beta_lo <= beta <= beta_max} B^{beta,lm}_{J1J2M} as
+    {(J1, J2, M): value} (beta_lo > 0 keeps the higher-order terms only)."""
     out: dict = {}
     Jmax = l + beta_max
-    for beta in range(0, beta_max + 1):
+    for beta in range(beta_lo, beta_max + 1):
         for J1 in range(0, Jmax + 1):
             for J2 in range(0, Jmax + 1):
                 if (l + J1 + J2) % 2:

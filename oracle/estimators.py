@@ -26,7 +26,10 @@ the bin (the angular integral); r-bins divide by v_a = N_a H^3, the bin's volume
 the grid, and exclude the zero separation.
 
 Series order K: midpoint keeps even alpha <= K; bisector keeps beta <= K // 2
-(the beta-th bisector term is O(theta^{2 beta})).
+(the beta-th bisector term is O(theta^{2 beta})).  ``Config.order_lo`` drops the terms below
+a given order: the estimate then holds the terms of order order_lo .. K only (midpoint
+alpha >= order_lo, bisector 2 beta >= order_lo), so order_lo = K gives the contribution of
+order K alone; the shot noise belongs to order 0 and is subtracted only when order_lo = 0.
 """
 from __future__ import annotations
 
@@ -56,6 +59,7 @@ class Config:
     bin_lo: float = 0.01
     bin_width: float = 0.01
     n_bins: int = 20
+    order_lo: int = 0
 
 
 @dataclass
@@ -140,7 +144,7 @@ def _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S, extra=None):
     """An empty bin has no estimate and is reported as 0 for every ell (no shot-noise term)."""
     P = FOURPI / I * sums
     for i, l in enumerate(cfg.ells):
-        if l == 0:
+        if l == 0 and cfg.order_lo == 0:
             P[i] -= np.where(counts > 0, S / I, 0.0)
     return Result(P, kmean, counts.astype(np.int64), alpha_r, I, S, extra or {})
 
@@ -148,6 +152,16 @@ def _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S, extra=None):
 # ----------------------------------------------------------------------------
 # Power spectrum
 # ----------------------------------------------------------------------------
+
+def _alphas(cfg: Config):
+    """Midpoint series orders kept: even alpha in [order_lo, order]."""
+    return [a for a in range(0, cfg.order + 1, 2) if a >= cfg.order_lo]
+
+
+def _beta_lo(cfg: Config) -> int:
+    """Lowest bisector order kept: the beta-th term is of order theta^(2 beta)."""
+    return (cfg.order_lo + 1) // 2
+
 
 def pk_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
     m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
@@ -166,7 +180,7 @@ def pk_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
     for l in cfg.ells:
         E = np.zeros_like(m, dtype=np.complex128)
         for mm in range(-l, l + 1):
-            tab = coeffs.B_table(beta_max, l, mm)
+            tab = coeffs.B_table(beta_max, l, mm, _beta_lo(cfg))
             inner = np.zeros_like(E)
             for (J1, J2, M), c in tab.items():
                 inner += c * Qneg[(J1, M)] * Qt[(J2, mm - M)]
@@ -213,7 +227,7 @@ def pk_bisector_shells(gal, ran, cfg: Config, norm=None, beta_max=None) -> Resul
     for l in cfg.ells:
         E = np.zeros(len(sel), dtype=np.complex128)
         for mm in range(-l, l + 1):
-            tab = coeffs.B_table(beta_max, l, mm)
+            tab = coeffs.B_table(beta_max, l, mm, _beta_lo(cfg))
             inner = np.zeros(len(sel), dtype=np.complex128)
             for (J1, J2, M), c in tab.items():
                 inner += c * Qs[(J1, M)][perm] * Qs[(J2, mm - M)]
@@ -254,7 +268,7 @@ def pk_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
     Dvec = separation_grid(cfg.N, cfg.L)
     Dmag = np.sqrt(np.sum(Dvec * Dvec, axis=-1))
     dtil = _fft(m, comp)
-    alphas = list(range(0, cfg.order + 1, 2))
+    alphas = _alphas(cfg)
     # Phi tables per (l, m, alpha), and the g fields they need
     tabs = {(l, mm, a): coeffs.Phi_table(a, l, mm)
             for l in cfg.ells for mm in range(-l, l + 1) for a in alphas}
@@ -336,7 +350,7 @@ def xi_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
     Dmag = np.sqrt(np.sum(Dvec * Dvec, axis=-1))
     dtil = _fft(m, comp)
     X = {l: np.zeros(m.shape, dtype=np.complex128) for l in cfg.ells}
-    for a in range(0, cfg.order + 1, 2):
+    for a in _alphas(cfg):
         Da = Dmag ** a if a > 0 else 1.0
         for J in range(0, max(cfg.ells) + a + 1, 2):
             Fs = {l: coeffs.F(a, l, J) for l in cfg.ells}
@@ -369,7 +383,7 @@ def xi_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
     for l in cfg.ells:
         X = np.zeros(m.shape, dtype=np.complex128)
         for mm in range(-l, l + 1):
-            tab = coeffs.B_table(beta_max, l, mm)
+            tab = coeffs.B_table(beta_max, l, mm, _beta_lo(cfg))
             Kprod = np.zeros(m.shape, dtype=np.complex128)
             for (J1, J2, M), c in tab.items():
                 Kprod += c * Qneg[(J1, M)] * Qt[(J2, mm - M)]

@@ -116,6 +116,48 @@ def test_midpoint_xi_equals_series_pair_sum(order):
     assert _rel(r.values, bp) < 1e-12
 
 
+# ---------------------------------------------------------------- terms of one order
+
+@pytest.mark.parametrize("los,order", [("bis", 2), ("bis", 4), ("mid", 2), ("mid", 4)])
+def test_single_order_pk_equals_series_pair_sum(los, order):
+    """order_lo = order keeps one order's terms alone (midpoint alpha = order, bisector
+    beta = order/2, Sections 3.3 and 5.2): it equals the pair sum over those terms only, its
+    monopole vanishes (no shot noise: the monopole has no term beyond zeroth order), and the
+    single-order pieces add up to the full truncated estimate."""
+    gal, ran = _tiny(seed=11 if los == "bis" else 12)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    est = pk_bisector if los == "bis" else pk_midpoint
+    kind = "bis_series" if los == "bis" else "mid_series"
+    one = _cfg_pk(order)
+    one.order_lo = order
+    r = est(gal, ran, one, norm)
+    bp, _ = brute.pk_pairs(gal, ran, one, kind, norm)
+    assert _rel(r.values, bp) < 1e-10
+    assert np.max(np.abs(r.values[0])) < 1e-12 * np.max(np.abs(r.values))
+    parts = [est(gal, ran, _cfg_pk(0), norm).values]
+    for o in range(2, order + 1, 2):
+        c = _cfg_pk(order)
+        c.order_lo, c.order = o, o
+        parts.append(est(gal, ran, c, norm).values)
+    full = est(gal, ran, _cfg_pk(order), norm).values
+    assert _rel(np.sum(parts, axis=0), full) < 1e-12
+
+
+@pytest.mark.parametrize("los", ["bis", "mid"])
+def test_single_order_xi_equals_series_pair_sum(los):
+    gal, ran = _tiny(seed=13 if los == "bis" else 14)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    est = xi_bisector if los == "bis" else xi_midpoint
+    kind = "bis_series" if los == "bis" else "mid_series"
+    cfg = _cfg_xi(4)
+    cfg.order_lo = 4
+    r = est(gal, ran, cfg, norm)
+    bp, _ = brute.xi_pairs(gal, ran, cfg, kind, norm)
+    # one order's terms are small against the products they are summed from (FP64 rounding
+    # of the cancellation), hence 1e-10 rather than 1e-12
+    assert _rel(r.values, bp) < 1e-10
+
+
 # ---------------------------------------------------------------- structural identities
 
 def _generic(seed=3, n_gal=300, n_ran=900):
