@@ -129,6 +129,22 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
                 const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
                 int64_t *counts);
 
+/* Contributions of each series order separately (the terms of order theta^(2o), o = 0 ..
+ * order/2: midpoint alpha = 2o, Sections 3.3 and 4.3; bisector beta = o, Sections 5.2 and 6),
+ * for the same configuration and catalogs as pw_estimate.
+ *   out      [n_orders][n_ell][n_bins] (host, FP64), n_orders = order/2 + 1; the slices sum to
+ *            pw_estimate's result.  The shot noise S / I belongs to slice 0 (the monopole has
+ *            no term beyond zeroth order, so its higher slices vanish).
+ *   bin_mean, counts, norm: as for pw_estimate.
+ * Bisector P_l with a generated coupling (ell_max <= 6, order <= 4) runs one pass: one set of
+ * forward transforms and a contraction that sends every order's terms to accumulators of their
+ * own.  Every other configuration runs pw_estimate at orders 0, 2, .., order and returns the
+ * differences of successive truncations.  Errors as pw_estimate; outputs written only on
+ * success. */
+int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
+                       const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
+                       int64_t *counts);
+
 /* Serving.  pw_submit validates a request, enqueues it and returns a ticket at once; a
  * worker thread of the context admits pending requests in arrival order as soon as one of the
  * context's serving lanes is free and the request's device memory fits the HBM budget (plans

@@ -72,7 +72,8 @@ struct Lane {
   size_t stage_nbar_bytes = 0;
   void *records = nullptr;  // tile-sorted particle records
   size_t records_bytes = 0;
-  double *host_res = nullptr;  // pinned: [(nell + 2) * nbins] results + DevNorm
+  double *host_res = nullptr;  // pinned: [(res_rows + 2) * nbins] results + DevNorm
+  int res_rows = 0;            // multipole rows of the result in flight (n_ell, or per order)
   size_t host_res_bytes = 0;
   hipEvent_t done = nullptr;
   DevPlan *last = nullptr;
@@ -281,8 +282,11 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
     const size_t sb = spectrum_buffer_bytes(h);
     dp->bufA = alloc_plan(ctx, dp.get(), sb);
     dp->bufB = alloc_plan(ctx, dp.get(), sb);
-    dp->acc = (double *)alloc_plan(ctx, dp.get(), (size_t)(h.nell + 2) * h.n_bins * sizeof(double));
-    dp->out = (double *)alloc_plan(ctx, dp.get(), (size_t)(h.nell + 2) * h.n_bins * sizeof(double));
+    // result rows: n_ell, or n_ell per series order for the one-pass per-order contraction
+    const size_t rows = (size_t)std::max(h.nell, h.n_orders_native * h.nell) + 2;
+    dp->acc = (double *)alloc_plan(ctx, dp.get(), rows * h.n_bins * sizeof(double));
+    dp->out = (double *)alloc_plan(ctx, dp.get(), rows * h.n_bins * sizeof(double));
+    dp->ells_orders = upload(ctx, dp.get(), h.ells_orders);
     dp->part_g = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
     dp->part_r = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
     dp->norm = (DevNorm *)alloc_plan(ctx, dp.get(), sizeof(DevNorm));
@@ -378,7 +382,7 @@ void check_request(const pw_config *cfg, const pw_catalog *gal, const pw_catalog
 // Enqueue the whole estimate on the lane's stream, ending with the copy of the results into
 // the lane's pinned buffer and the lane's completion event.  Returns the plan used.
 DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_catalog *gal,
-                         const pw_catalog *ran, const pw_norm *norm) {
+                         const pw_catalog *ran, const pw_norm *norm, bool orders = false) {
   HIPCHECK(hipSetDevice(ctx->device));
   ensure_sh(ctx->device);
   DevPlan *dp = get_plan(ctx, ln, cfg);
@@ -444,19 +448,30 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
               F.mstride, dp->tw,
               dp->planemask);
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
-  const size_t nacc = (size_t)(h.nell + 2) * h.n_bins;
+  if (orders && (h.path != PATH_BIS_PK || h.n_orders_native == 0))
+    fail(PW_EINVAL, "internal: no one-pass per-order contraction for this configuration");
+  ln.res_rows = orders ? h.n_orders_native * h.nell : h.nell;
+  const size_t nacc = (size_t)(ln.res_rows + 2) * h.n_bins;
   if (h.path == PATH_BIS_PK) {
     // a7: contraction and FP64 binning
     mark("contract", x3 + 4.0 * F.nretained);
     launch_fill(s, dp->acc, nacc, 1);
-    TermTable tab;
-    tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
-    tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
-    tab.ntargets = (int)h.t_sh.size();
-    launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, F.mstride, dp->fwd.modecoord, N,
-                        dp->bin_of_s2, n_s2, h.n_bins, h.nell, tab, h.kf, dp->winv, dp->acc);
-    mark("finalize", 0.0);
-    launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+    if (orders) {
+      // every order's terms into accumulators of their own (one pass over the spectra)
+      launch_contract_bis_generated(s, h.prec, h.ell_max, h.order / 2, A, F.nmodes, F.mstride, dp->fwd.modecoord,
+                                    N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->winv, dp->acc, 1);
+      mark("finalize", 0.0);
+      launch_finalize_pk(s, dp->acc, ln.res_rows, h.n_bins, dp->ells_orders, dp->norm, dp->out);
+    } else {
+      TermTable tab;
+      tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
+      tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
+      tab.ntargets = (int)h.t_sh.size();
+      launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, F.mstride, dp->fwd.modecoord,
+                          N, dp->bin_of_s2, n_s2, h.n_bins, h.nell, tab, h.kf, dp->winv, dp->acc);
+      mark("finalize", 0.0);
+      launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
+    }
   } else {
     // Spectra after fz: full pencil-major A[p][q * N + kz], q = ky * rs + kx.
     const double sfull = (double)N * N * F.nkx * csz;  // one full half spectrum (algorithmic)
@@ -535,7 +550,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   mark(nullptr, 0.0);
   ln.n_stages = ns - 1;
   HIPCHECK(hipGetLastError());
-  const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+  const size_t nres = (size_t)(ln.res_rows + 2) * h.n_bins;
   const size_t need = nres * sizeof(double) + sizeof(DevNorm);
   if (ln.host_res_bytes < need) {
     if (ln.host_res) (void)hipHostFree(ln.host_res);
@@ -555,17 +570,18 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
 void finish_estimate(Lane &ln, const DevPlan *dp, pw_norm *norm, double *out, double *bin_mean,
                      int64_t *counts) {
   const HostPlan &h = *dp->host;
-  const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+  const int rows = ln.res_rows;
+  const size_t nres = (size_t)(rows + 2) * h.n_bins;
   const double *res = ln.host_res;
   DevNorm dn;
   std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
   if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
   if (dn.flags & 2)
     fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
-  std::memcpy(out, res, (size_t)h.nell * h.n_bins * sizeof(double));
-  if (bin_mean) std::memcpy(bin_mean, res + (size_t)h.nell * h.n_bins, h.n_bins * sizeof(double));
+  std::memcpy(out, res, (size_t)rows * h.n_bins * sizeof(double));
+  if (bin_mean) std::memcpy(bin_mean, res + (size_t)rows * h.n_bins, h.n_bins * sizeof(double));
   if (counts)
-    for (int b = 0; b < h.n_bins; ++b) counts[b] = (int64_t)std::llround(res[(size_t)(h.nell + 1) * h.n_bins + b]);
+    for (int b = 0; b < h.n_bins; ++b) counts[b] = (int64_t)std::llround(res[(size_t)(rows + 1) * h.n_bins + b]);
   if (norm && !norm->use_given) {
     norm->alpha_r = dn.alpha_r;
     norm->I = dn.I;
@@ -600,11 +616,11 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
 }
 
 void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
-                  pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+                  pw_norm *norm, double *out, double *bin_mean, int64_t *counts, bool orders = false) {
   check_request(cfg, gal, ran, norm, out);
   make_room_main(ctx, cfg, gal, ran);
   Lane &ln = *ctx->main;
-  DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm);
+  DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm, orders);
   HIPCHECK(hipEventSynchronize(ln.done));
   for (int i = 0; i < ln.n_stages; ++i) {
     float ms = -1.0f;
@@ -614,7 +630,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   {
     // forward passes touch only the occupied rows / planes: scale their algorithmic bytes
     const HostPlan &h = *dp->host;
-    const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+    const size_t nres = (size_t)(ln.res_rows + 2) * h.n_bins;
     DevNorm dn;
     std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
     const double N = h.N, rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2 * rsz;
@@ -880,6 +896,54 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const 
   if (!ctx) return PW_EINVAL;
   try {
     run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts);
+  } catch (const Fail &f) {
+    ctx->err = f.msg;
+    return f.code;
+  } catch (const std::exception &e) {
+    ctx->err = e.what();
+    return PW_EINVAL;
+  }
+  ctx->err.clear();
+  return PW_OK;
+}
+
+int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                       pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  if (!ctx) return PW_EINVAL;
+  try {
+    if (!cfg || !out) fail(PW_EINVAL, "null configuration or output");
+    validate_config(*cfg);
+    const int nell = cfg->ell_max / 2 + 1, no = cfg->order / 2 + 1;
+    const size_t slice = (size_t)nell * cfg->n_bins;
+    if (one_pass_orders(*cfg)) {
+      run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts, true);
+    } else {
+      // each series order's terms as the difference of successive truncations K = 0, 2, ..
+      std::vector<double> prev(slice, 0.0), cur(slice);
+      pw_norm nm = norm ? *norm : pw_norm{0.0, 0.0, 0.0, 0};
+      std::vector<double> res((size_t)no * slice), bm0;
+      std::vector<int64_t> ct0;
+      pw_norm n0 = nm;
+      for (int o = 0; o < no; ++o) {
+        pw_config c = *cfg;
+        c.order = 2 * o;
+        pw_norm n1 = nm;
+        std::vector<double> bm(cfg->n_bins);
+        std::vector<int64_t> ct(cfg->n_bins);
+        run_estimate(ctx, &c, gal, ran, &n1, cur.data(), bm.data(), ct.data());
+        for (size_t i = 0; i < slice; ++i) res[(size_t)o * slice + i] = cur[i] - prev[i];
+        prev.swap(cur);
+        if (o == 0) {
+          n0 = n1;
+          bm0.swap(bm);
+          ct0.swap(ct);
+        }
+      }
+      std::memcpy(out, res.data(), res.size() * sizeof(double));
+      if (bin_mean) std::memcpy(bin_mean, bm0.data(), bm0.size() * sizeof(double));
+      if (counts) std::memcpy(counts, ct0.data(), ct0.size() * sizeof(int64_t));
+      if (norm && !norm->use_given) *norm = n0;
+    }
   } catch (const Fail &f) {
     ctx->err = f.msg;
     return f.code;

@@ -334,7 +334,7 @@ double legendre_F(int alpha, int l, int J) {
   return Gleg(0, alpha, l, J);
 }
 
-std::vector<Term> bisector_terms(int ell_max, int beta_max) {
+std::vector<Term> bisector_terms(int ell_max, int beta_max, int beta_lo) {
   RealAcc acc;
   for (int l = 0; l <= ell_max; l += 2) {
     int Jmax = l + beta_max;
@@ -345,7 +345,7 @@ std::vector<Term> bisector_terms(int ell_max, int beta_max) {
           for (int M = -J1; M <= J1; ++M) {
             if (std::abs(m - M) > J2) continue;
             double b = 0.0;
-            for (int beta = 0; beta <= beta_max; ++beta) b += Bcoef(beta, l, m, J1, J2, M);
+            for (int beta = beta_lo; beta <= beta_max; ++beta) b += Bcoef(beta, l, m, J1, J2, M);
             if (b == 0.0) continue;
             for (int nu = -l; nu <= l; ++nu) {
               cd cl = std::conj(Uval(l, m, nu));

@@ -16,9 +16,10 @@ struct Term {
 
 inline int sh_index(int J, int mu) { return J * J + J + mu; }
 
-// Bisector: S^{l nu}_{(J1mu1)(J2mu2)} with sum_{beta<=beta_max} B folded in and the pair
-// symmetrised ((J1,mu1) <= (J2,mu2) by index), for every even l <= ell_max.
-std::vector<Term> bisector_terms(int ell_max, int beta_max);
+// Bisector: S^{l nu}_{(J1mu1)(J2mu2)} with sum_{beta_lo<=beta<=beta_max} B folded in and the
+// pair symmetrised ((J1,mu1) <= (J2,mu2) by index), for every even l <= ell_max.  beta_lo =
+// beta_max gives the terms of one order, theta^(2 beta), alone.
+std::vector<Term> bisector_terms(int ell_max, int beta_max, int beta_lo = 0);
 
 // Midpoint parity-even real coupling Phi'^{alpha, l nu}_{(J1mu1)(J2mu2)} for one even alpha
 // (l even <= ell_max).  The (J2, mu2) index refers to the real field

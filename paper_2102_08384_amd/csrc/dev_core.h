@@ -149,8 +149,11 @@ __device__ __forceinline__ void fft_stage(cplx<R> v[8], int t, const Tw &tw, At 
   }
 }
 
-template <typename R, int N, bool INV, int S, int NS, typename Tw, typename At, typename Sync>
-__device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const Tw &tw, At at, Sync sync) {
+// Each LDS exchange: write, sync(), read, post().  post() is the barrier again when one LDS
+// buffer serves every exchange, or a switch to the other buffer when two alternate (the next
+// exchange's barrier then orders these reads before that buffer is written again).
+template <typename R, int N, bool INV, int S, int NS, typename Tw, typename At, typename Sync, typename Post>
+__device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const Tw &tw, At at, Sync sync, Post post) {
   constexpr int RAD = stage_radix(N, S);
   if constexpr (S == n_stages(N) - 1) {
     fft_stage<R, N, INV, S, RAD, NS, true>(v, t, tw, at);
@@ -159,8 +162,8 @@ __device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const Tw &tw, At
     sync();
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = at(t + q * (N / 8));
-    sync();
-    fft_stages<R, N, INV, S + 1, NS * RAD>(v, t, tw, at, sync);
+    post();
+    fft_stages<R, N, INV, S + 1, NS * RAD>(v, t, tw, at, sync, post);
   }
 }
 
@@ -171,7 +174,7 @@ __device__ __forceinline__ void fft_stages(cplx<R> v[8], int t, const Tw &tw, At
 template <typename R, int N, bool INV, typename At, typename Sync>
 __device__ __forceinline__ void fft_pencil(cplx<R> v[8], int t, const cplx<R> *__restrict__ tw, At at, Sync sync) {
   GlobalTw<R, N> g{tw};
-  fft_stages<R, N, INV, 0, 1>(v, t, g, at, sync);
+  fft_stages<R, N, INV, 0, 1>(v, t, g, at, sync, sync);
 }
 // The same with the lane's twiddles in registers (FftTw::load once per kernel).  Kernels that
 // prefetch the next pencil group's data across transforms use this form, with an explicit
@@ -179,7 +182,14 @@ __device__ __forceinline__ void fft_pencil(cplx<R> v[8], int t, const cplx<R> *_
 // read a twiddle.
 template <typename R, int N, bool INV, typename At, typename Sync>
 __device__ __forceinline__ void fft_pencil(cplx<R> v[8], int t, const FftTw<R, N> &tw, At at, Sync sync) {
-  fft_stages<R, N, INV, 0, 1>(v, t, tw, at, sync);
+  fft_stages<R, N, INV, 0, 1>(v, t, tw, at, sync, sync);
+}
+// Two alternating LDS buffers: `at` must address the buffer selected by the state that `flip`
+// toggles; one barrier per exchange.
+template <typename R, int N, bool INV, typename At, typename Sync, typename Flip>
+__device__ __forceinline__ void fft_pencil_db(cplx<R> v[8], int t, const FftTw<R, N> &tw, At at, Sync sync,
+                                              Flip flip) {
+  fft_stages<R, N, INV, 0, 1>(v, t, tw, at, sync, flip);
 }
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited on)
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }

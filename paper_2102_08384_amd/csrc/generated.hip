@@ -25,9 +25,11 @@ template <int L, int K, typename R> struct MidReweight {
 #include "contract_gen.inc"
 
 // Register-resident variant: the coupling for (LMAX, BMAX) is straight-line code generated at
-// build time (BisContract<L, B, R>::run), so all field values of a mode stay in VGPRs.
+// build time (BisContract<L, B, R>::run), so all field values of a mode stay in VGPRs.  With
+// ORD the terms of each order beta go to accumulators of their own (run_orders): rows
+// beta * (LMAX/2 + 1) + l/2, then the mode count and the |k| sum.
 
-template <typename R, int LMAX, int BMAX>
+template <typename R, int LMAX, int BMAX, bool ORD>
 __global__ void __launch_bounds__(256)
 k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, int64_t mstride,
                    const uint32_t *__restrict__ modecoord,
@@ -36,7 +38,7 @@ k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, int64_t mst
   using CT = BisContract<LMAX, BMAX, R>;
   constexpr int NF = CT::NF;
   constexpr int NSH = (LMAX + 1) * (LMAX + 1);
-  constexpr int NE = LMAX / 2 + 1;
+  constexpr int NE = ORD ? CT::NO * (LMAX / 2 + 1) : LMAX / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *bacc = reinterpret_cast<double *>(smem_raw);
   const int nacc = (NE + 2) * nbins;
@@ -79,7 +81,8 @@ k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, int64_t mst
     R E[NE];
 #pragma unroll
     for (int i = 0; i < NE; ++i) E[i] = 0;
-    CT::run(a, wdir, E);
+    if constexpr (ORD) CT::run_orders(a, wdir, E);
+    else CT::run(a, wdir, E);
     if (winv) {
       const R iw = winv[kx] * winv[ky] * winv[kz];
       const R iw2 = iw * iw;
@@ -101,14 +104,20 @@ template <typename R, int L, int B>
 static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, int64_t mstride,
                                 const uint32_t *modecoord,
                                 int N, const int *bin_of_s2, int64_t n_s2, int nbins, double kf,
-                                const void *winv, double *acc) {
+                                const void *winv, double *acc, int orders) {
   if constexpr (BisContract<L, B, R>::kGenerated) {
     int64_t want = (nmodes + 255) / 256;
     unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    size_t sh = (size_t)(L / 2 + 3) * nbins * sizeof(double);
-    hipLaunchKernelGGL((k_contract_bis_reg<R, L, B>), dim3(blocks), dim3(256), sh, s,
-                       (const cplx<R> *)spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf,
-                       (const R *)winv, acc);
+    const int ne = (orders ? B + 1 : 1) * (L / 2 + 1);
+    size_t sh = (size_t)(ne + 2) * nbins * sizeof(double);
+    if (orders)
+      hipLaunchKernelGGL((k_contract_bis_reg<R, L, B, true>), dim3(blocks), dim3(256), sh, s,
+                         (const cplx<R> *)spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf,
+                         (const R *)winv, acc);
+    else
+      hipLaunchKernelGGL((k_contract_bis_reg<R, L, B, false>), dim3(blocks), dim3(256), sh, s,
+                         (const cplx<R> *)spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf,
+                         (const R *)winv, acc);
     return true;
   } else {
     return false;
@@ -119,11 +128,11 @@ template <typename R>
 static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void *spec, int64_t nmodes,
                                   int64_t mstride,
                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                  int nbins, double kf, const void *winv, double *acc) {
+                                  int nbins, double kf, const void *winv, double *acc, int orders) {
 #define PW_CR(L, B)                                                                                \
   if (lmax == L && bmax == B)                                                                      \
     return contract_reg_launch<R, L, B>(s, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, \
-                                        acc);
+                                        acc, orders);
   PW_CR(0, 0) PW_CR(0, 1) PW_CR(0, 2) PW_CR(2, 0) PW_CR(2, 1) PW_CR(2, 2)
   PW_CR(4, 0) PW_CR(4, 1) PW_CR(4, 2) PW_CR(6, 0) PW_CR(6, 1) PW_CR(6, 2)
 #undef PW_CR
@@ -132,11 +141,11 @@ static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void 
 
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
                                    int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                   int nbins, double kf, const void *winv, double *acc) {
+                                   int nbins, double kf, const void *winv, double *acc, int orders) {
   return prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
-                                                  n_s2, nbins, kf, winv, acc)
+                                                  n_s2, nbins, kf, winv, acc, orders)
                    : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
-                                                   n_s2, nbins, kf, winv, acc);
+                                                   n_s2, nbins, kf, winv, acc, orders);
 }
 
 // ------------------------------------------------------------------------------ generated

@@ -133,9 +133,11 @@ void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, c
                         const DevNorm *norm, double *out);
 
 // Register-resident bisector contraction when its coupling is generated; false otherwise.
+// orders != 0: one accumulator row per (beta, l), rows beta * nell + l/2, then the mode count
+// and the |k| sum ((bmax + 1) * nell + 2 rows of nbins).
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
                                    int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                   int nbins, double kf, const void *winv, double *acc);
+                                   int nbins, double kf, const void *winv, double *acc, int orders);
 // Which (ell_max, beta_max) / (ell_max, order) have build-time generated couplings.
 bool bis_contract_generated(int lmax, int bmax);
 bool mid_reweight_generated(int lmax, int order);

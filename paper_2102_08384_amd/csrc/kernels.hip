@@ -314,7 +314,8 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
      const int *__restrict__ rowmask, const int *__restrict__ zlist, const DevNorm *__restrict__ norm) {
   constexpr int T = N / 8, C = CC, NT = CC * T;
   constexpr int Q = 128 / (int)sizeof(cplx<R>);
-  __shared__ cplx<R> lds[N * (C + 1)];
+  constexpr int LB = N * (C + 1);  // one exchange buffer; two alternate (one barrier per exchange)
+  __shared__ cplx<R> lds[2 * LB];
   __shared__ int msk[N];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   int z = blockIdx.x;
@@ -349,8 +350,10 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
       v[s] = (kx < nkx && msk[y]) ? src[(size_t)y * rs + kx] : mk<R>(0, 0);
     }
   };
-  auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
+  int lb = 0;
+  auto at = [c, &lb](int i) -> cplx<R> & { return lds[lb * LB + i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
+  auto flip = [&lb]() { lb ^= 1; };
   cplx<R> nxt[8];
   load(0, nxt);
   for (int it = 0; it < nitems; ++it) {
@@ -358,7 +361,7 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
     if (it + 1 < nitems) load(it + 1, nxt);
-    fft_pencil<R, N, INV>(v, t, twr, at, sync);
+    fft_pencil_db<R, N, INV>(v, t, twr, at, sync, flip);
     const int p = p0 + it / ncb, kx = (it % ncb) * C + c;
     cplx<R> *dst = out + ((size_t)p * nplanes + z) * npen;
 #pragma unroll
@@ -410,7 +413,8 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
      const int *__restrict__ gsize, int64_t mstride, const cplx<R> *__restrict__ tw,
      const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
-  __shared__ cplx<R> lds[N * (C + 1)];
+  constexpr int LB = N * (C + 1);  // one exchange buffer; grouped: two alternate
+  __shared__ cplx<R> lds[GROUPED ? 2 * LB : LB];
   __shared__ int st[C + 1];                      // full sets: first output mode of each pencil
   __shared__ int msk[N];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
@@ -449,8 +453,10 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
       v[s] = (has && msk[z]) ? src[(size_t)z * npen + q] : mk<R>(0, 0);
     }
   };
-  auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
+  int lb = 0;
+  auto at = [c, &lb](int i) -> cplx<R> & { return lds[lb * LB + i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
+  auto flip = [&lb]() { lb ^= 1; };
   // grouped: slot of kz = t + s T, or -1 outside the group's kz extent
   const int h = (S - 1) / 2;
   int slot[8];
@@ -469,7 +475,8 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
     if (p + 1 < p1) load(p + 1, nxt);
-    fft_pencil<R, N, false>(v, t, twr, at, sync);
+    if constexpr (GROUPED) fft_pencil_db<R, N, false>(v, t, twr, at, sync, flip);
+    else fft_pencil<R, N, false>(v, t, twr, at, sync);
     if constexpr (GROUPED) {
       cplx<R> *dst = out + (size_t)p * mstride + m0 + c;
 #pragma unroll
@@ -619,7 +626,7 @@ void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void
                          const void *winv, double *acc) {
   if (nmodes <= 0) return;
   if (launch_contract_bis_generated(s, prec, lmax, bmax, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins,
-                                    kf, winv, acc))
+                                    kf, winv, acc, 0))
     return;
   int64_t want = (nmodes + 127) / 128;
   unsigned blocks = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);

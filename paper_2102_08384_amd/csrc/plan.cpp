@@ -215,6 +215,12 @@ void validate_config(const pw_config &c) {
   }
 }
 
+bool one_pass_orders(const pw_config &c) {
+  if (path_of(c) != PATH_BIS_PK || !bis_contract_generated(c.ell_max, c.order / 2)) return false;
+  const int rows = (c.order / 2 + 1) * (c.ell_max / 2 + 1);
+  return (size_t)(rows + 2) * c.n_bins * 8 <= 65536;
+}
+
 HostPlan build_host_plan(const pw_config &c) {
   HostPlan h;
   h.path = path_of(c);
@@ -232,6 +238,9 @@ HostPlan build_host_plan(const pw_config &c) {
   }
   h.nell = c.ell_max / 2 + 1;
   for (int l = 0; l <= c.ell_max; l += 2) h.ells.push_back(l);
+  h.n_orders_native = one_pass_orders(c) ? c.order / 2 + 1 : 0;
+  for (int o = 0; o < std::max(h.n_orders_native, 1); ++o)
+    for (int l : h.ells) h.ells_orders.push_back(o == 0 ? l : -1);
   h.check_extent = (h.path == PATH_MID_PK && c.order > 0 && c.ell_max > 0) ? 1 : 0;
   h.n0 = 0; h.n_inv = 0; h.n_inplace = 0; h.nz = 0; h.ny = 0; h.n_targets = 0; h.n_a = 0;
   const int N = h.N;

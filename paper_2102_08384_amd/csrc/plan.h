@@ -98,7 +98,16 @@ struct HostPlan {
   // midpoint P: A_{l nu} fields (l >= 2) and their forward pair jobs
   int n_a;
   std::vector<FieldJob> ajobs;
+  // bisector P: series orders of the one-pass per-order contraction (0: not available) and
+  // the multipole of each of its result rows (beta * nell + l/2; -1 beyond zeroth order,
+  // where no shot noise is subtracted)
+  int n_orders_native = 0;
+  std::vector<int> ells_orders;
 };
+
+// Whether pw_estimate_orders has a one-pass path for cfg (bisector P_l with a generated
+// coupling whose per-order accumulators fit the contraction kernel's LDS).
+bool one_pass_orders(const pw_config &c);
 
 HostPlan build_host_plan(const pw_config &c);
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
@@ -124,7 +133,7 @@ struct DevPlan {
   FieldJob *jobs = nullptr, *ijobs = nullptr, *ajobs = nullptr;
   DevPrune fwd, sph;
   int *bin_of_s2 = nullptr;
-  int *ells = nullptr;
+  int *ells = nullptr, *ells_orders = nullptr;
   void *winv = nullptr;
   int *t_start = nullptr, *t_sh = nullptr, *t_ell = nullptr, *t_p1 = nullptr, *t_p2 = nullptr;
   void *t_coef = nullptr;

@@ -67,6 +67,9 @@ def _load():
     lib.pw_estimate.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                                 C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_int64)]
+    lib.pw_estimate_orders.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
+                                       C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int64)]
     lib.pw_submit.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                               C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
@@ -230,6 +233,15 @@ class Context:
 
     def estimate(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """Run one estimate.  norm = (alpha_r, I, S) to impose the normalisation."""
+        return self._run(_lib.pw_estimate, (cfg.n_ell, cfg.n_bins), cfg, gal_xyzw, ran_xyzw, ran_nbar, norm)
+
+    def estimate_orders(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
+        """Each series order's contribution: values[o] holds the terms of order theta^(2o)
+        (pw_estimate_orders); shape [order/2 + 1, n_ell, n_bins]."""
+        return self._run(_lib.pw_estimate_orders, (cfg.order // 2 + 1, cfg.n_ell, cfg.n_bins), cfg, gal_xyzw,
+                         ran_xyzw, ran_nbar, norm)
+
+    def _run(self, fn, shape, cfg, gal_xyzw, ran_xyzw, ran_nbar, norm):
         keep = []
         g = _catalog(gal_xyzw, None, keep)
         r = _catalog(ran_xyzw, ran_nbar, keep)
@@ -237,14 +249,14 @@ class Context:
         if norm is not None:
             nm.alpha_r, nm.I, nm.S = (float(v) for v in norm)
             nm.use_given = 1
-        out = np.zeros((cfg.n_ell, cfg.n_bins))
+        out = np.zeros(shape)
         bm = np.zeros(cfg.n_bins)
         cnt = np.zeros(cfg.n_bins, dtype=np.int64)
         c = cfg._c()
-        rc = _lib.pw_estimate(self._h, C.byref(c), C.byref(g), C.byref(r), C.byref(nm),
-                              out.ctypes.data_as(C.POINTER(C.c_double)),
-                              bm.ctypes.data_as(C.POINTER(C.c_double)),
-                              cnt.ctypes.data_as(C.POINTER(C.c_int64)))
+        rc = fn(self._h, C.byref(c), C.byref(g), C.byref(r), C.byref(nm),
+                out.ctypes.data_as(C.POINTER(C.c_double)),
+                bm.ctypes.data_as(C.POINTER(C.c_double)),
+                cnt.ctypes.data_as(C.POINTER(C.c_int64)))
         if rc != PW_OK:
             raise PwError(rc, self.last_error())
         return {"values": out, "bin_mean": bm, "counts": cnt, "norm": (nm.alpha_r, nm.I, nm.S)}
