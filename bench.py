@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-orders", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -203,6 +204,23 @@ def main():
                   "max_abs_diff_vs_plain": float(np.max(np.abs(s_res["values"] - res["values"])))}
         log(f"served {served['value']:.2f} catalogs/s")
 
+    orders = None
+    if not a.no_orders:
+        # each series order's terms separately (one pass for the bisector P_l)
+        for _ in range(max(1, a.warmup)):
+            ctx.estimate_orders(cfg, gx, rx, ran_nbar=rn)
+        torch.cuda.synchronize()
+        n_o = max(3, a.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(n_o):
+            o_res = ctx.estimate_orders(cfg, gx, rx, ran_nbar=rn)
+        torch.cuda.synchronize()
+        o_el = time.perf_counter() - t0
+        orders = {"value": n_o / o_el, "unit": "catalogs/s", "ms_per_catalog": o_el * 1e3 / n_o,
+                  "steps": n_o, "n_orders": int(o_res["values"].shape[0]),
+                  "max_abs_sum_minus_plain": float(np.max(np.abs(o_res["values"].sum(axis=0) - res["values"])))}
+        log(f"per-order outputs {orders['value']:.2f} catalogs/s")
+
     stages = {n: {"ms": float(np.mean(v)), "GB": stage_bytes[n] / 1e9,
                   "GBps": (stage_bytes[n] / 1e9) / (np.mean(v) / 1e3) if np.mean(v) > 0 else None}
               for n, v in stage_ms.items()}
@@ -229,6 +247,7 @@ def main():
                   "latency_ms": {"p50": float(np.percentile(p_lat, 50)),
                                  "p99": float(np.percentile(p_lat, 99))}},
         "served": served,
+        "orders": orders,
         "latency_ms": served["latency_ms"] if served else
         {"p50": float(np.percentile(p_lat, 50)), "p99": float(np.percentile(p_lat, 99))},
         "roofline": roofline,
