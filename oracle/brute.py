@@ -67,7 +67,9 @@ def _dft_kernel(values, N):
 
 def pair_weight(kind: str, l: int, m: int, xi, xj, K: int, K_lo: int = 0):
     """W^{lm}(i, j) for arrays of pair endpoints xi, xj [P, 3]; the series kinds keep the
-    terms of order K_lo .. K in the opening angle."""
+    terms of order K_lo .. K in the opening angle.  mid_series is the parity-even midpoint
+    expansion (Phi, even alpha, Section 3.3); mid_series_all the symmetrised all-parity one
+    (Section 3.1: phi, every alpha, the r2 half carrying (-1)^J1)."""
     D = xj - xi
     if kind == "mid_exact":
         return Ylm(l, m, xi + xj)
@@ -85,6 +87,16 @@ def pair_weight(kind: str, l: int, m: int, xi, xj, K: int, K_lo: int = 0):
         for a in range(K_lo + K_lo % 2, K + 1, 2):
             for (J1, J2, M), c in coeffs.Phi_table(a, l, m).items():
                 out += 0.5 * c * Ylm(J1, M, D) * (ei ** a * Ylm(J2, m - M, xi) + ej ** a * Ylm(J2, m - M, xj))
+        return out
+    if kind == "mid_series_all":
+        Dn = np.linalg.norm(D, axis=-1)
+        ei = Dn / (2.0 * np.linalg.norm(xi, axis=-1))
+        ej = Dn / (2.0 * np.linalg.norm(xj, axis=-1))
+        out = np.zeros(len(xi), dtype=np.complex128)
+        for a in range(K_lo, K + 1):
+            for (J1, J2, M), c in coeffs.phi_table(a, l, m).items():
+                out += 0.5 * c * Ylm(J1, M, D) * (ei ** a * Ylm(J2, m - M, xi)
+                                                  + (-1) ** J1 * ej ** a * Ylm(J2, m - M, xj))
         return out
     if kind == "bis_series":
         out = np.zeros(len(xi), dtype=np.complex128)
@@ -155,7 +167,8 @@ def xi_pairs(gal, ran, cfg, kind: str, norm):
     counts = np.array([((gb == q) & (g2 > 0)).sum() for q in range(cfg.n_bins)], dtype=np.float64)
     out = np.zeros((len(cfg.ells), cfg.n_bins))
     for li, l in enumerate(cfg.ells):
-        if kind == "mid_series":
+        if kind in ("mid_series", "mid_series_all"):
+            allp = kind == "mid_series_all"
             Dn = np.linalg.norm(D, axis=-1)
             Du = D / Dn[:, None]
             ri = np.linalg.norm(xi_, axis=-1)
@@ -163,13 +176,17 @@ def xi_pairs(gal, ran, cfg, kind: str, norm):
             mui = np.sum(Du * xi_, axis=-1) / ri
             muj = np.sum(Du * xj_, axis=-1) / rj
             V = np.zeros(len(D))
-            for a in range(cfg.order_lo + cfg.order_lo % 2, cfg.order + 1, 2):
-                for J in range(0, l + a + 1, 2):
-                    Fv = coeffs.F(a, l, J)
+            alphas = (range(cfg.order_lo, cfg.order + 1) if allp
+                      else range(cfg.order_lo + cfg.order_lo % 2, cfg.order + 1, 2))
+            for a in alphas:
+                for J in range(a % 2, l + a + 1, 2):
+                    Fv = coeffs.f(a, l, J) if allp else coeffs.F(a, l, J)
                     if Fv == 0.0:
                         continue
+                    # Section 4.1 symmetrised form: the r2 half carries (-1)^(l+J)
                     V += 0.5 * (2 * J + 1) / (2 * l + 1) * Fv * ((Dn / (2 * ri)) ** a * legendre(J, mui)
-                                                                  + (Dn / (2 * rj)) ** a * legendre(J, muj))
+                                                                  + (-1) ** ((l + J) % 2) * (Dn / (2 * rj)) ** a
+                                                                  * legendre(J, muj))
             V = V * (2 * l + 1) / FOURPI
         else:
             V = np.zeros(len(D), dtype=np.complex128)

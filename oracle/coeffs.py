@@ -251,6 +251,24 @@ def _psi(a0: int, a1: int, l: int, m: int):
     return {k: v for k, v in out.items() if v != 0.0}
 
 
+def phi_table(alpha: int, l: int, m: int) -> dict:
+    """All-parity midpoint coefficients phi^{alpha,lm}_{J1J2M} (Appendix B; the boxed shift
+    theorem of Section 3.1) as {(J1, J2, M): value}: J1 = alpha, alpha-2, .. >= 0 and
+    J2 = max(0, l-alpha) .. l+alpha with l + alpha + J2 even (the parity rules of Section 3.1)."""
+    out = {}
+    for J1 in range(alpha % 2, alpha + 1, 2):
+        for J2 in range(max(0, l - alpha), l + alpha + 1):
+            if (l + alpha + J2) % 2:
+                continue
+            for M in range(-J1, J1 + 1):
+                if abs(m - M) > J2:
+                    continue
+                v = phi(alpha, l, m, J1, J2, M)
+                if v != 0.0:
+                    out[(J1, J2, M)] = v
+    return out
+
+
 def Phi_table(alpha: int, l: int, m: int) -> dict:
     """Parity-even midpoint coefficients Phi^{alpha,lm}_{J1J2M} as {(J1, J2, M): value}
     (Appendix D: Phi^0 = sqrt(4pi) d d d, Phi^2 = -phi^2, Phi^4 = -phi^4 + sum phi^2 Omega^{2,2};

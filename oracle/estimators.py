@@ -11,8 +11,12 @@ grids, summing over every m and M:
   P_l(k) = (4pi/I) <Re sum_m Y_l^{m*}(k^) sum_{even alpha} sum Phi F[Y_J1^M(D^) D^alpha g^alpha_{J2,m-M}](k)> - d_l0 S/I.
 * ``pk_yamamoto``  Section 2.1 Yamamoto estimator,
   P_l(k) = (4pi/I) <Re sum_m Y_l^{m*}(k^) F[Y_l^m d](k) d*(k)> - d_l0 S/I.
+* ``pk_midpoint(parity="all")``  Section 3.2 boxed all-parity estimator: every alpha <= K
+  (odd ones too) with the shift-theorem coefficients phi of Section 3.1 in place of Phi.
 * ``xi_midpoint``  Section 4.3 boxed parity-even estimator,
   xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_{even alpha, J, M} F^{alpha,l}_J Y_J^{M*}(D^) D^alpha g^alpha_{JM}(D).
+* ``xi_midpoint(parity="all")``  Section 4.2 boxed all-parity estimator: every alpha <= K
+  with the Legendre shift coefficients f in place of F.
 * ``xi_bisector``  Section 6 boxed estimator,
   h = IFT[F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)],
   xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_m Y_l^{m*}(D^) sum B h.
@@ -60,6 +64,7 @@ class Config:
     bin_width: float = 0.01
     n_bins: int = 20
     order_lo: int = 0
+    parity: str = "even"   # midpoint series: "even" (Sections 3.3, 4.3) or "all" (3.2, 4.2)
 
 
 @dataclass
@@ -154,8 +159,17 @@ def _finish_pk(sums, kmean, counts, cfg, alpha_r, I, S, extra=None):
 # ----------------------------------------------------------------------------
 
 def _alphas(cfg: Config):
-    """Midpoint series orders kept: even alpha in [order_lo, order]."""
-    return [a for a in range(0, cfg.order + 1, 2) if a >= cfg.order_lo]
+    """Midpoint series orders kept: alpha in [order_lo, order], even ones only for the
+    parity-even form."""
+    step = 1 if cfg.parity == "all" else 2
+    return [a for a in range(0, cfg.order + 1, step) if a >= cfg.order_lo]
+
+
+def _mid_table(cfg: Config, alpha: int, l: int, m: int) -> dict:
+    """Coupling of the midpoint P_l at order alpha: phi (all-parity) or Phi (parity-even)."""
+    if cfg.parity == "all":
+        return coeffs.phi_table(alpha, l, m)
+    return coeffs.Phi_table(alpha, l, m)
 
 
 def _beta_lo(cfg: Config) -> int:
@@ -270,7 +284,7 @@ def pk_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
     dtil = _fft(m, comp)
     alphas = _alphas(cfg)
     # Phi tables per (l, m, alpha), and the g fields they need
-    tabs = {(l, mm, a): coeffs.Phi_table(a, l, mm)
+    tabs = {(l, mm, a): _mid_table(cfg, a, l, mm)
             for l in cfg.ells for mm in range(-l, l + 1) for a in alphas}
     need = {}
     for (l, mm, a), tab in tabs.items():
@@ -352,8 +366,12 @@ def xi_midpoint(gal, ran, cfg: Config, norm=None) -> Result:
     X = {l: np.zeros(m.shape, dtype=np.complex128) for l in cfg.ells}
     for a in _alphas(cfg):
         Da = Dmag ** a if a > 0 else 1.0
-        for J in range(0, max(cfg.ells) + a + 1, 2):
-            Fs = {l: coeffs.F(a, l, J) for l in cfg.ells}
+        # J has the parity of alpha (even l): f^{alpha,l}_J vanishes unless alpha + l + J is even
+        for J in range(a % 2, max(cfg.ells) + a + 1, 2):
+            if cfg.parity == "all":
+                Fs = {l: coeffs.f(a, l, J) for l in cfg.ells}
+            else:
+                Fs = {l: coeffs.F(a, l, J) for l in cfg.ells}
             if all(v == 0.0 for v in Fs.values()):
                 continue
             for M in range(-J, J + 1):

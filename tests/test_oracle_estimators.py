@@ -116,6 +116,67 @@ def test_midpoint_xi_equals_series_pair_sum(order):
     assert _rel(r.values, bp) < 1e-12
 
 
+# ---------------------------------------------------------------- all-parity midpoint
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_midpoint_allparity_pk_equals_series_pair_sum(order):
+    """Section 3.2 all-parity estimator (every alpha <= K, coefficients phi) against the pair
+    sum of the symmetrised shift-theorem series, exactly."""
+    gal, ran = _tiny(seed=15)
+    cfg = _cfg_pk(order)
+    cfg.parity = "all"
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = pk_midpoint(gal, ran, cfg, norm)
+    bp, _ = brute.pk_pairs(gal, ran, cfg, "mid_series_all", norm)
+    assert _rel(r.values, bp) < 1e-12
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_midpoint_allparity_xi_equals_series_pair_sum(order):
+    """Section 4.2 all-parity estimator (coefficients f) against the pair sum of the
+    symmetrised Legendre shift series, exactly."""
+    gal, ran = _tiny(seed=16)
+    cfg = _cfg_xi(order)
+    cfg.parity = "all"
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    r = xi_midpoint(gal, ran, cfg, norm)
+    bp, _ = brute.xi_pairs(gal, ran, cfg, "mid_series_all", norm)
+    assert _rel(r.values, bp) < 1e-12
+
+
+def test_midpoint_allparity_zeroth_order_and_monopole():
+    """At K = 0 both forms are Yamamoto (phi^0 = Phi^0, f^0 = F^0 = delta); the monopole has
+    no alpha > 0 term in either form (phi^{alpha,00} = sqrt(4pi) delta_alpha0)."""
+    gal, ran = _generic(seed=17)
+    base = dict(N=32, L=1000.0, b0=(-500, -500, 700), assign=TSC, compensate=True, bin_lo=0.01,
+                bin_width=0.02, n_bins=6)
+    e0 = pk_midpoint(gal, ran, Config(ells=(0, 2, 4), order=0, **base)).values
+    a0 = pk_midpoint(gal, ran, Config(ells=(0, 2, 4), order=0, parity="all", **base)).values
+    assert _rel(a0, e0) < 1e-13
+    for K in (1, 2, 3):
+        aK = pk_midpoint(gal, ran, Config(ells=(0,), order=K, parity="all", **base)).values[0]
+        assert _rel(aK, e0[0]) < 1e-12
+
+
+def test_midpoint_allparity_converges_to_exact_line_of_sight():
+    """The all-parity series approaches the exact midpoint pair sum as K grows (Section 3.1:
+    truncating at alpha = K leaves O(theta^{K+1})); at equal order it is at least as close as
+    the parity-even form, which needs 2 eps << 1 rather than eps << 1 (Section 3.3)."""
+    gal, ran = _tiny(seed=18)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    cfg = _cfg_pk(0, ells=(2,))
+    exact, _ = brute.pk_pairs(gal, ran, cfg, "mid_exact", norm)
+    errs = []
+    for K in range(0, 5):
+        c = _cfg_pk(K, ells=(2,))
+        c.parity = "all"
+        errs.append(np.max(np.abs(pk_midpoint(gal, ran, c, norm).values - exact)))
+    assert errs[2] < 0.5 * errs[0] and errs[4] < 0.5 * errs[2]
+    c = _cfg_pk(4, ells=(2,))
+    even4 = np.max(np.abs(pk_midpoint(gal, ran, c, norm).values - exact))
+    assert errs[4] <= 1.5 * even4
+
+
 # ---------------------------------------------------------------- terms of one order
 
 @pytest.mark.parametrize("los,order", [("bis", 2), ("bis", 4), ("mid", 2), ("mid", 4)])
