@@ -7,6 +7,8 @@
  *   - midpoint P_l(k):  Section 3.3, boxed parity-even estimator (coefficients Phi, Appendix D)
  *   - bisector P_l(k):  Section 5.2, boxed estimator (coefficients B, Appendix F)
  *   - midpoint xi_l(r): Section 4.3, boxed parity-even estimator (coefficients F, Appendix E)
+ *   - midpoint, all-parity series (midpoint_parity = 1): Section 3.2 (P_l, coefficients phi,
+ *     Appendix B) and Section 4.2 (xi_l, coefficients f, Appendix E), every alpha <= order
  *   - bisector xi_l(r): Section 6, boxed estimator (coefficients B)
  * The density field is w (n_g - alpha_r n_r) (Section 2.1); the estimators are normalised
  * by I = alpha_r sum_r w_r^2 nbar_r with alpha_r = sum w_g / sum w_r, and the shot noise
@@ -18,8 +20,8 @@
  *     box_origin + n * H, H = box_len / n_mesh, n = 0 .. n_mesh-1 per axis, periodic.
  *   - Every particle must satisfy 0 <= x_i - box_origin_i < box_len on every axis
  *     (PW_ERANGE otherwise; particles are never wrapped).
- *   - Series order K: the midpoint keeps even alpha <= K, the bisector keeps beta <= K/2
- *     (the beta-th bisector term is O(theta^(2 beta))).
+ *   - Series order K: the parity-even midpoint keeps even alpha <= K, the all-parity midpoint
+ *     every alpha <= K, the bisector beta <= K/2 (the beta-th bisector term is O(theta^(2 beta))).
  *   - Multipoles are the even ell = 0, 2, ..., ell_max; outputs are [n_ell][n_bins] row-major.
  *   - k bins: bin b holds the modes with b = floor((|k| - bin_lo) / bin_width),
  *     |k| = (2 pi / box_len) sqrt(n_x^2 + n_y^2 + n_z^2) on the signed FFT index
@@ -61,11 +63,12 @@ enum pw_stat { PW_PK = 0, PW_XI = 1 };
 enum pw_los { PW_MIDPOINT = 0, PW_BISECTOR = 1 };
 enum pw_assign { PW_CIC = 2, PW_TSC = 3 };
 enum pw_prec { PW_FP32 = 0, PW_FP64 = 1 };
+enum pw_parity { PW_PARITY_EVEN = 0, PW_PARITY_ALL = 1 };
 
 typedef struct pw_ctx pw_ctx;
 
 /* Estimator configuration (the paper's problem statement: box, mesh, ell_max, series
- * order, line of sight, bins). */
+ * order, line of sight, bins).  Zero-initialise it: later fields default to 0. */
 typedef struct {
   int stat;              /* PW_PK or PW_XI                                                */
   int los;               /* PW_MIDPOINT or PW_BISECTOR                                    */
@@ -75,11 +78,14 @@ typedef struct {
   double box_len;        /* L (same length unit as the positions, e.g. Mpc/h)             */
   double box_origin[3];  /* b0, the corner of the box                                     */
   int ell_max;           /* even, 0..8                                                    */
-  int order;             /* series order K, even, 0..8                                    */
+  int order;             /* series order K, 0..8: even, or any for the all-parity midpoint */
   int compensate;        /* 1: divide every k-space factor by the assignment window W(k)  */
   double bin_lo;         /* lower edge of bin 0 (k in 1/length, r in length)              */
   double bin_width;      /* > 0                                                           */
   int n_bins;            /* 1..4096                                                       */
+  int midpoint_parity;   /* midpoint series: 0 parity-even (Sections 3.3, 4.3: even alpha, */
+                         /* coefficients Phi, F), 1 all-parity (Sections 3.2, 4.2: every   */
+                         /* alpha <= order, coefficients phi, f); ignored for the bisector */
 } pw_config;
 
 /* A catalog: n particles as interleaved (x, y, z, w) records of dtype (PW_FP32 / PW_FP64).
@@ -129,12 +135,14 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
                 const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
                 int64_t *counts);
 
-/* Contributions of each series order separately (the terms of order theta^(2o), o = 0 ..
- * order/2: midpoint alpha = 2o, Sections 3.3 and 4.3; bisector beta = o, Sections 5.2 and 6),
- * for the same configuration and catalogs as pw_estimate.
- *   out      [n_orders][n_ell][n_bins] (host, FP64), n_orders = order/2 + 1; the slices sum to
- *            pw_estimate's result.  The shot noise S / I belongs to slice 0 (the monopole has
- *            no term beyond zeroth order, so its higher slices vanish).
+/* Contributions of each series order separately, for the same configuration and catalogs as
+ * pw_estimate: slice o holds the terms of order theta^(2o) (parity-even midpoint alpha = 2o,
+ * Sections 3.3 and 4.3; bisector beta = o, Sections 5.2 and 6), or for the all-parity midpoint
+ * the terms of alpha = o (Sections 3.2 and 4.2).
+ *   out      [n_orders][n_ell][n_bins] (host, FP64), n_orders = order/2 + 1 (all-parity
+ *            midpoint: order + 1); the slices sum to pw_estimate's result.  The shot noise
+ *            S / I belongs to slice 0 (the monopole has no term beyond zeroth order, so its
+ *            higher slices vanish).
  *   bin_mean, counts, norm: as for pw_estimate.
  * Bisector P_l with a generated coupling (ell_max <= 6, order <= 4) runs one pass: one set of
  * forward transforms and a contraction that sends every order's terms to accumulators of their
@@ -212,6 +220,10 @@ int pw_footprint(const pw_config *cfg, int64_t n_gal, int64_t n_ran, size_t *byt
  *   1  midpoint: rows (l, nu, J1, mu1, J2, mu2, value) for alpha = `alpha` (Phi, Appendix D):
  *      A_{l nu}(D) = sum Phi' y_J1^mu1(D^) |D|^alpha g_{alpha J2 mu2}(D).
  *   2  midpoint Legendre: rows (l, 0, J, 0, 0, 0, F^{alpha,l}_J) (Appendix E).
+ *   3  midpoint all-parity: rows (l, nu, J1, mu1, J2, mu2, value) for alpha = `alpha`: phi
+ *      (Appendix B) in the real basis with the (-1)^J2 of g folded in (Section 3.2):
+ *      A_{l nu}(D) = sum phi' y_J1^mu1(D^) |D|^alpha IFT[conj(d) F[(2r)^-alpha y_J2^mu2 d]].
+ *   4  midpoint all-parity Legendre: rows (l, 0, J, 0, 0, 0, f^{alpha,l}_J) (Appendix E).
  * Writes at most max_rows rows of 7 doubles to rows (may be NULL) and the row count to
  * n_rows. */
 int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,

@@ -521,7 +521,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         launch_ix(s, h.prec, N, 0, yout, B, F.rs, dp->ijobs, (int)h.ijobs.size(), nullptr, h.nell, h.nz, h.ny,
                   dp->zidx, dp->yidx, h.H, h.unit, inv_n3, nullptr, 0, 0, nullptr, dp->tw);
         mark("reweight", (double)(h.n_inv + h.n_a) * ncell * rsz);
-        launch_reweight(s, h.prec, N, h.ell_max, h.order, B, Aoff, h.H / h.unit);
+        launch_reweight(s, h.prec, N, h.ell_max, h.order, h.all_parity, B, Aoff, h.H / h.unit);
         // forward transforms of A, pruned to the k-sphere of the bins
         const Prune &P = h.sph;
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
@@ -913,12 +913,14 @@ int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
   try {
     if (!cfg || !out) fail(PW_EINVAL, "null configuration or output");
     validate_config(*cfg);
-    const int nell = cfg->ell_max / 2 + 1, no = cfg->order / 2 + 1;
+    // orders theta^(step * o): every alpha for the all-parity midpoint, even ones otherwise
+    const int step = (cfg->los == PW_MIDPOINT && cfg->midpoint_parity == PW_PARITY_ALL) ? 1 : 2;
+    const int nell = cfg->ell_max / 2 + 1, no = cfg->order / step + 1;
     const size_t slice = (size_t)nell * cfg->n_bins;
     if (one_pass_orders(*cfg)) {
       run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts, true);
     } else {
-      // each series order's terms as the difference of successive truncations K = 0, 2, ..
+      // each series order's terms as the difference of successive truncations K = 0, step, ..
       std::vector<double> prev(slice, 0.0), cur(slice);
       pw_norm nm = norm ? *norm : pw_norm{0.0, 0.0, 0.0, 0};
       std::vector<double> res((size_t)no * slice), bm0;
@@ -926,7 +928,7 @@ int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
       pw_norm n0 = nm;
       for (int o = 0; o < no; ++o) {
         pw_config c = *cfg;
-        c.order = 2 * o;
+        c.order = step * o;
         pw_norm n1 = nm;
         std::vector<double> bm(cfg->n_bins);
         std::vector<int64_t> ct(cfg->n_bins);
@@ -1083,14 +1085,21 @@ int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,
         double v[7] = {(double)t.l, (double)t.nu, (double)t.J1, (double)t.mu1, (double)t.J2, (double)t.mu2, t.c};
         r.insert(r.end(), v, v + 7);
       }
-    } else if (kind == 2) {
+    } else if (kind == 2 || kind == 4) {
+      if (alpha < 0) return PW_EINVAL;
       for (int l = 0; l <= ell_max; l += 2)
-        for (int J = 0; J <= l + alpha; J += 2) {
-          double F = legendre_F(alpha, l, J);
+        for (int J = 0; J <= l + alpha; ++J) {
+          double F = kind == 2 ? legendre_F(alpha, l, J) : legendre_f(alpha, l, J);
           if (F == 0.0) continue;
           double v[7] = {(double)l, 0.0, (double)J, 0.0, 0.0, 0.0, F};
           r.insert(r.end(), v, v + 7);
         }
+    } else if (kind == 3) {
+      if (alpha < 0) return PW_EINVAL;
+      for (const Term &t : midpoint_terms_all(ell_max, alpha)) {
+        double v[7] = {(double)t.l, (double)t.nu, (double)t.J1, (double)t.mu1, (double)t.J2, (double)t.mu2, t.c};
+        r.insert(r.end(), v, v + 7);
+      }
     } else {
       return PW_EINVAL;
     }

@@ -393,4 +393,32 @@ std::vector<Term> midpoint_terms(int ell_max, int alpha) {
   return finish(acc, false);
 }
 
+std::vector<Term> midpoint_terms_all(int ell_max, int alpha) {
+  RealAcc acc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int l = 0; l <= ell_max; l += 2)
+    for (int m = -l; m <= l; ++m)
+      for (int J1 = alpha % 2; J1 <= alpha; J1 += 2)
+        for (int J2 = std::max(0, l - alpha); J2 <= l + alpha; ++J2) {
+          if ((l + alpha + J2) % 2) continue;
+          for (int M = -J1; M <= J1; ++M) {
+            if (std::abs(m - M) > J2) continue;
+            const double c = omega(alpha, l, m, 0, J1, J2, M) * parity_sign(J2);
+            if (c == 0.0) continue;
+            for (int nu = -l; nu <= l; ++nu) {
+              cd cl = std::conj(Uval(l, m, nu));
+              if (cl == cd(0.0, 0.0)) continue;
+              int n1[2], n2[2], c1, c2; cd v1[2], v2[2];
+              Urow(J1, M, n1, v1, &c1);
+              Urow(J2, m - M, n2, v2, &c2);
+              for (int a = 0; a < c1; ++a)
+                for (int bb = 0; bb < c2; ++bb)
+                  acc[std::make_tuple(l, nu, sh_index(J1, n1[a]), sh_index(J2, n2[bb]))] +=
+                      cl * c * v1[a] * v2[bb];
+            }
+          }
+        }
+  return finish(acc, false);
+}
+
 }  // namespace pw

@@ -26,6 +26,12 @@ std::vector<Term> bisector_terms(int ell_max, int beta_max, int beta_lo = 0);
 // (2r)^-alpha y_J2^mu2(x^) d of series order alpha.
 std::vector<Term> midpoint_terms(int ell_max, int alpha);
 
+// Midpoint all-parity real coupling for one alpha >= 0 (Section 3.2): the shift-theorem
+// coefficients phi^{alpha, lm}_{J1J2M} (Appendix B) in the real basis, with the sign
+// (-1)^J2 of g^alpha_{J2 M} folded in, so that
+//   A_{l nu}(D) = sum phi' y_J1^mu1(D^) |D|^alpha IFT[conj(d) F[(2r)^-alpha y_J2^mu2 d]](D).
+std::vector<Term> midpoint_terms_all(int ell_max, int alpha);
+
 // Parity-even Legendre coefficients F^{alpha,l}_J (Appendix E).
 double legendre_F(int alpha, int l, int J);
 

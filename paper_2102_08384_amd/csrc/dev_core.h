@@ -339,8 +339,8 @@ struct ShRec8 {
 };
 
 // All y_l^nu for even l <= LMAX (index sh_index(l, nu) - compact even-l layout given by
-// the caller through out[l*l + l + nu] with odd l left untouched).
-template <typename R, int LMAX>
+// the caller through out[l*l + l + nu] with odd l left untouched); with ODD every l <= LMAX.
+template <typename R, int LMAX, bool ODD = false>
 __device__ __forceinline__ void real_sh_even(const ShConst &c, R x, R y, R z, R *out) {
 #pragma unroll
   for (int m = 0; m <= LMAX; ++m) {
@@ -353,7 +353,7 @@ __device__ __forceinline__ void real_sh_even(const ShConst &c, R x, R y, R z, R 
       else if (l == m + 1) q = (R)(2 * m + 1) * z;
       else q = sh_a<R>(c, l, m) * z * q1 - sh_b<R>(c, l, m) * q2;
       if (l > m) { q2 = q1; q1 = q; }
-      if ((l & 1) == 0) {
+      if (ODD || (l & 1) == 0) {
         R n = sh_n<R>(c, l, m) * q;
         out[l * l + l + m] = n * cr;
         if (m > 0) out[l * l + l - m] = n * ci;

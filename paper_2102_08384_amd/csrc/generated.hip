@@ -22,6 +22,9 @@ template <int L, int B, typename R> struct BisContract {
 template <int L, int K, typename R> struct MidReweight {
   static constexpr bool kGenerated = false;
 };
+template <int L, int K, typename R> struct MidReweightAll {
+  static constexpr bool kGenerated = false;
+};
 #include "contract_gen.inc"
 
 // Register-resident variant: the coupling for (LMAX, BMAX) is straight-line code generated at
@@ -157,18 +160,18 @@ bool bis_contract_generated(int lmax, int bmax) {
   return false;
 }
 
-int mid_reweight_nfields(int lmax, int order) {
-#define PW_MN(L, K) if (lmax == L && order == K) return MidReweight<L, K, float>::kGenerated ? MidReweight<L, K, float>::NG : -1;
+int mid_reweight_nfields(int lmax, int order, int all_parity) {
+#define PW_MN(L, K) if (!all_parity && lmax == L && order == K) return MidReweight<L, K, float>::kGenerated ? MidReweight<L, K, float>::NG : -1;
   PW_MN(2, 2) PW_MN(2, 4) PW_MN(2, 6) PW_MN(4, 2) PW_MN(4, 4) PW_MN(4, 6) PW_MN(6, 2) PW_MN(6, 4)
 #undef PW_MN
+#define PW_MNA(L, K) if (all_parity && lmax == L && order == K) return MidReweightAll<L, K, float>::kGenerated ? MidReweightAll<L, K, float>::NG : -1;
+  PW_MNA(2, 1) PW_MNA(2, 2) PW_MNA(2, 3) PW_MNA(2, 4) PW_MNA(4, 1) PW_MNA(4, 2) PW_MNA(4, 3) PW_MNA(4, 4)
+#undef PW_MNA
   return -1;
 }
 
-bool mid_reweight_generated(int lmax, int order) {
-#define PW_MG(L, K) if (lmax == L && order == K) return MidReweight<L, K, float>::kGenerated;
-  PW_MG(2, 2) PW_MG(2, 4) PW_MG(2, 6) PW_MG(4, 2) PW_MG(4, 4) PW_MG(4, 6) PW_MG(6, 2) PW_MG(6, 4)
-#undef PW_MG
-  return false;
+bool mid_reweight_generated(int lmax, int order, int all_parity) {
+  return mid_reweight_nfields(lmax, order, all_parity) >= 0;
 }
 
 // Bisector xi targets over the full pencil-major spectra: one thread per mode.
@@ -230,12 +233,14 @@ void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const vo
 }
 
 // Midpoint real-space re-weighting: one thread per cell of the separation grid
-// (D = H * signed index, minimum image), g[i][cell] -> A[j][cell].
-template <typename R, int L, int K>
+// (D = H * signed index, minimum image), g[i][cell] -> A[j][cell].  Parity-even (ALLP false):
+// even alpha and J1, Dp[i] = |D|^(2i); all-parity: every alpha and J1, Dp[i] = |D|^i.
+template <typename R, int L, int K, bool ALLP>
 __global__ void __launch_bounds__(256)
 k_reweight(const R *__restrict__ g, R *__restrict__ A, int N, R Hu) {
-  using MR = MidReweight<L, K, R>;
+  using MR = typename std::conditional<ALLP, MidReweightAll<L, K, R>, MidReweight<L, K, R>>::type;
   constexpr int NSH = (K + 1) * (K + 1);
+  constexpr int NDP = ALLP ? K + 1 : K / 2 + 1;
   const size_t ncell = (size_t)N * N * N;
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(c % N), y = (int)((c / N) % N), z = (int)(c / ((size_t)N * N));
@@ -245,15 +250,17 @@ k_reweight(const R *__restrict__ g, R *__restrict__ A, int N, R Hu) {
     R yD[NSH];
 #pragma unroll
     for (int i = 0; i < NSH; ++i) yD[i] = 0;
-    R Dp[K / 2 + 1];
+    R Dp[NDP];
     Dp[0] = 1;
+    const R dstep = ALLP ? sqrt(d2) : d2;
 #pragma unroll
-    for (int i = 1; i <= K / 2; ++i) Dp[i] = Dp[i - 1] * d2;
+    for (int i = 1; i < NDP; ++i) Dp[i] = Dp[i - 1] * dstep;
     if (d2 > (R)0) {
       const R ir = (R)1 / sqrt(d2);
-      real_sh_even<R, K>(c_sh_gen, dx * ir, dy * ir, dz * ir, yD);
+      real_sh_even<R, K, ALLP>(c_sh_gen, dx * ir, dy * ir, dz * ir, yD);
     } else {
-      real_sh_even<R, K>(c_sh_gen, (R)0, (R)0, (R)1, yD);
+      // D = 0: |D|^alpha = 0 for every alpha > 0, so the direction is immaterial
+      real_sh_even<R, K, ALLP>(c_sh_gen, (R)0, (R)0, (R)1, yD);
     }
     R gv[MR::NG];
 #pragma unroll
@@ -265,24 +272,30 @@ k_reweight(const R *__restrict__ g, R *__restrict__ A, int N, R Hu) {
   }
 }
 
-template <typename R, int L, int K>
+template <typename R, int L, int K, bool ALLP>
 static void reweight_launch(hipStream_t s, int N, const void *g, void *A, double Hu) {
-  if constexpr (MidReweight<L, K, R>::kGenerated) {
+  using MR = typename std::conditional<ALLP, MidReweightAll<L, K, R>, MidReweight<L, K, R>>::type;
+  if constexpr (MR::kGenerated) {
     const size_t ncell = (size_t)N * N * N;
     size_t want = (ncell + 255) / 256;
     unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
-    hipLaunchKernelGGL((k_reweight<R, L, K>), dim3(blocks), dim3(256), 0, s, (const R *)g, (R *)A, N, (R)Hu);
+    hipLaunchKernelGGL((k_reweight<R, L, K, ALLP>), dim3(blocks), dim3(256), 0, s, (const R *)g, (R *)A, N,
+                       (R)Hu);
   }
 }
 
-void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, const void *g, void *A, double Hu) {
-#define PW_RW(L, K)                                                                               \
-  if (lmax == L && order == K) {                                                                  \
-    if (prec == 0) reweight_launch<float, L, K>(s, N, g, A, Hu);                                   \
-    else reweight_launch<double, L, K>(s, N, g, A, Hu);                                            \
+void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, int all_parity, const void *g, void *A,
+                     double Hu) {
+#define PW_RW(L, K, AP)                                                                           \
+  if (lmax == L && order == K && all_parity == AP) {                                              \
+    if (prec == 0) reweight_launch<float, L, K, AP>(s, N, g, A, Hu);                               \
+    else reweight_launch<double, L, K, AP>(s, N, g, A, Hu);                                        \
     return;                                                                                       \
   }
-  PW_RW(2, 2) PW_RW(2, 4) PW_RW(2, 6) PW_RW(4, 2) PW_RW(4, 4) PW_RW(4, 6) PW_RW(6, 2) PW_RW(6, 4)
+  PW_RW(2, 2, 0) PW_RW(2, 4, 0) PW_RW(2, 6, 0) PW_RW(4, 2, 0) PW_RW(4, 4, 0) PW_RW(4, 6, 0) PW_RW(6, 2, 0)
+  PW_RW(6, 4, 0)
+  PW_RW(2, 1, 1) PW_RW(2, 2, 1) PW_RW(2, 3, 1) PW_RW(2, 4, 1) PW_RW(4, 1, 1) PW_RW(4, 2, 1) PW_RW(4, 3, 1)
+  PW_RW(4, 4, 1)
 #undef PW_RW
 }
 

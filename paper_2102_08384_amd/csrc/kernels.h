@@ -140,9 +140,9 @@ bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, 
                                    int nbins, double kf, const void *winv, double *acc, int orders);
 // Which (ell_max, beta_max) / (ell_max, order) have build-time generated couplings.
 bool bis_contract_generated(int lmax, int bmax);
-bool mid_reweight_generated(int lmax, int order);
+bool mid_reweight_generated(int lmax, int order, int all_parity);
 // Number of g fields the generated re-weighting reads (-1: not generated).
-int mid_reweight_nfields(int lmax, int order);
+int mid_reweight_nfields(int lmax, int order, int all_parity);
 
 // ---- inverse path (inverse.hip) ----
 // Inverse z pass over full pencil-major spectra in[p][q * N + kz] (q = ky * nkx + kx):
@@ -165,7 +165,8 @@ void launch_ix(hipStream_t s, int prec, int N, int mode, const void *in, void *o
                int64_t n_s2, int nbins, double *acc, const void *tw);
 // Midpoint real-space re-weighting: A_{l nu}(D) from the alpha > 0 g fields (generated),
 // with |D| in the length unit of the forward weights (Hu = H / unit).
-void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, const void *g, void *A, double Hu);
+void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, int all_parity, const void *g, void *A,
+                     double Hu);
 // Bisector xi targets: T[t][i] = sum S Re(conj(R_p1) R_p2) / W(k)^2 over the full
 // pencil-major spectra (i = q * N + kz, q = ky * rs + kx), written as real values (generated).
 void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const void *spec, int64_t nmodes,

@@ -165,7 +165,7 @@ void sort_jobs(std::vector<FieldJob> &jobs) {
 PlanKey make_key(const pw_config &c) {
   return PlanKey(c.stat, c.los, c.assign, c.prec, c.n_mesh, c.box_len, c.box_origin[0],
                  c.box_origin[1], c.box_origin[2], c.ell_max, c.order, c.compensate, c.bin_lo,
-                 c.bin_width, c.n_bins);
+                 c.bin_width, c.n_bins, c.los == PW_MIDPOINT ? c.midpoint_parity : 0);
 }
 
 void validate_config(const pw_config &c) {
@@ -179,7 +179,11 @@ void validate_config(const pw_config &c) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(c.box_origin[a])) plan_fail(PW_EINVAL, "box_origin must be finite");
   if (c.ell_max < 0 || c.ell_max > 8 || (c.ell_max & 1)) plan_fail(PW_EINVAL, "ell_max must be even, 0..8");
-  if (c.order < 0 || c.order > 8 || (c.order & 1)) plan_fail(PW_EINVAL, "order must be even, 0..8");
+  if (c.midpoint_parity != PW_PARITY_EVEN && c.midpoint_parity != PW_PARITY_ALL)
+    plan_fail(PW_EINVAL, "midpoint_parity must be PW_PARITY_EVEN or PW_PARITY_ALL");
+  const bool allp = c.los == PW_MIDPOINT && c.midpoint_parity == PW_PARITY_ALL;
+  if (c.order < 0 || c.order > 8 || (!allp && (c.order & 1)))
+    plan_fail(PW_EINVAL, "order must be in 0..8 (even except for the all-parity midpoint)");
   if (!(c.bin_width > 0) || !std::isfinite(c.bin_lo) || !std::isfinite(c.bin_width))
     plan_fail(PW_EINVAL, "bins must have a finite bin_lo and bin_width > 0");
   if (c.n_bins < 1 || c.n_bins > 4096) plan_fail(PW_EINVAL, "n_bins must be in 1..4096");
@@ -194,10 +198,11 @@ void validate_config(const pw_config &c) {
     if (lds > 65536)
       plan_fail(PW_EINVAL, "ell_max + order/2 (or n_bins) too large for the contraction kernel's LDS");
   } else if (path == PATH_MID_PK) {
-    if (c.ell_max >= 2 && c.order >= 2 && !mid_reweight_generated(c.ell_max, c.order))
-      plan_fail(PW_EINVAL,
-                "midpoint P_l: (ell_max, order) has no re-weighting kernel (built: ell_max 2..6 with "
-                "order 2..4, and order 6 for ell_max <= 4)");
+    if (c.ell_max >= 2 && c.order >= (allp ? 1 : 2) && !mid_reweight_generated(c.ell_max, c.order, allp))
+      plan_fail(PW_EINVAL, allp ? "midpoint P_l, all-parity: (ell_max, order) has no re-weighting kernel "
+                                  "(built: ell_max 2..4 with order 1..4)"
+                                : "midpoint P_l: (ell_max, order) has no re-weighting kernel (built: "
+                                  "ell_max 2..6 with order 2..4, and order 6 for ell_max <= 4)");
     if ((size_t)(nell + 2) * c.n_bins * 8 > 65536) plan_fail(PW_EINVAL, "n_bins too large");
   } else {
     const double r_hi = c.bin_lo + c.n_bins * c.bin_width;
@@ -242,6 +247,7 @@ HostPlan build_host_plan(const pw_config &c) {
   for (int o = 0; o < std::max(h.n_orders_native, 1); ++o)
     for (int l : h.ells) h.ells_orders.push_back(o == 0 ? l : -1);
   h.check_extent = (h.path == PATH_MID_PK && c.order > 0 && c.ell_max > 0) ? 1 : 0;
+  h.all_parity = (c.los == PW_MIDPOINT && c.midpoint_parity == PW_PARITY_ALL) ? 1 : 0;
   h.n0 = 0; h.n_inv = 0; h.n_inplace = 0; h.nz = 0; h.ny = 0; h.n_targets = 0; h.n_a = 0;
   const int N = h.N;
   const bool is_pk = c.stat == PW_PK;
@@ -291,16 +297,17 @@ HostPlan build_host_plan(const pw_config &c) {
       }
   } else {
     // alpha = 0: y_J^mu d, J = 0, 2, .., ell_max (index even_index(J, mu));
-    // alpha = 2, 4, .., order (only when ell_max >= 2: the monopole has no alpha > 0 term):
-    //   (2r)^-alpha y_J^mu d, J even <= ell_max + alpha, in (alpha, J, mu) order after them.
+    // alpha > 0 (only when ell_max >= 2: the monopole has no alpha > 0 term):
+    //   (2r)^-alpha y_J^mu d, J <= ell_max + alpha with the parity of alpha, in (alpha, J, mu)
+    //   order after them; alpha = 2, 4, .., order (parity-even) or 1, 2, .., order (all-parity).
     std::map<std::tuple<int, int, int>, int> f0, fa;
     int p = 0;
     for (int J = 0; J <= c.ell_max; J += 2)
       for (int mu = -J; mu <= J; ++mu) f0[std::make_tuple(0, J, mu)] = p++;
     h.n0 = p;
     if (c.ell_max >= 2)
-      for (int alpha = 2; alpha <= c.order; alpha += 2)
-        for (int J = 0; J <= c.ell_max + alpha; J += 2)
+      for (int alpha = h.all_parity ? 1 : 2; alpha <= c.order; alpha += h.all_parity ? 1 : 2)
+        for (int J = alpha % 2; J <= c.ell_max + alpha; J += 2)
           for (int mu = -J; mu <= J; ++mu) fa[std::make_tuple(alpha, J, mu)] = p++;
     h.nfields = p;
     add_jobs(f0, h.jobs);
@@ -363,7 +370,9 @@ HostPlan build_host_plan(const pw_config &c) {
   }
   sort_jobs(h.ijobs);
   // xi: per-field multipole coefficients of every inverse job, [job][side][l]
-  //   midpoint: F^{alpha,l}_J (Appendix E); bisector: the target's own l.
+  //   midpoint: F^{alpha,l}_J, or (-1)^J f^{alpha,l}_J all-parity (Appendix E; the sign is
+  //   that of g^alpha_J, trivial for the even J of the parity-even form); bisector: the
+  //   target's own l.
   if (h.path == PATH_MID_XI || h.path == PATH_BIS_XI) {
     for (const FieldJob &j : h.ijobs) {
       const int Jb = j.kind == 0 ? j.Ja : j.Jb;
@@ -371,8 +380,11 @@ HostPlan build_host_plan(const pw_config &c) {
         for (int l : h.ells) {
           double F = 0.0;
           if (h.path == PATH_MID_XI) {
-            if (side == 0) F = legendre_F(j.alpha, l, j.Ja);
-            else if (j.pb >= 0) F = legendre_F(j.alpha_b, l, Jb);
+            auto coef = [&](int alpha, int J) {
+              return h.all_parity ? ((J & 1) ? -1.0 : 1.0) * legendre_f(alpha, l, J) : legendre_F(alpha, l, J);
+            };
+            if (side == 0) F = coef(j.alpha, j.Ja);
+            else if (j.pb >= 0) F = coef(j.alpha_b, Jb);
           } else {
             F = side == 0 ? (l == j.Ja ? 1.0 : 0.0) : (j.pb >= 0 && l == Jb ? 1.0 : 0.0);
           }
@@ -391,7 +403,7 @@ HostPlan build_host_plan(const pw_config &c) {
       if (!ok) plan_fail(PW_EINVAL, "midpoint alpha = 0 coupling is not the identity");
     }
     if (h.n_inv > 0) {
-      if (mid_reweight_nfields(c.ell_max, c.order) != h.n_inv)
+      if (mid_reweight_nfields(c.ell_max, c.order, h.all_parity) != h.n_inv)
         plan_fail(PW_EINVAL, "internal: midpoint field set differs from the re-weighting kernel's");
       for (int l = 2; l <= c.ell_max; l += 2) h.n_a += 2 * l + 1;
       for (int i = 0; i < h.n_a; i += 2)

@@ -26,7 +26,7 @@ namespace pw {
 [[noreturn]] void plan_fail(int code, const char *msg);
 
 typedef std::tuple<int, int, int, int, int, double, double, double, double, int, int, int, double,
-                   double, int>
+                   double, int, int>
     PlanKey;
 
 PlanKey make_key(const pw_config &c);
@@ -72,6 +72,7 @@ struct HostPlan {
   double L, H, kf;
   double unit;               // length unit of the radial weights (about twice the box-centre distance)
   int check_extent;
+  int all_parity;            // midpoint: 1 = all-parity series (every alpha), 0 = parity-even
   std::vector<int> ells;
   // forward fields and the pair jobs of the x pass
   int nfields;

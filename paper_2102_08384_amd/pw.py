@@ -22,6 +22,7 @@ PW_PK, PW_XI = 0, 1
 PW_MIDPOINT, PW_BISECTOR = 0, 1
 PW_CIC, PW_TSC = 2, 3
 PW_FP32, PW_FP64 = 0, 1
+PW_PARITY_EVEN, PW_PARITY_ALL = 0, 1
 
 _ERRNAMES = {PW_EINVAL: "PW_EINVAL", PW_ERANGE: "PW_ERANGE", PW_ENOMEM: "PW_ENOMEM",
              PW_EDEVICE: "PW_EDEVICE", PW_EBUSY: "PW_EBUSY", PW_EAGAIN: "PW_EAGAIN",
@@ -38,7 +39,8 @@ class _Config(C.Structure):
     _fields_ = [("stat", C.c_int), ("los", C.c_int), ("assign", C.c_int), ("prec", C.c_int),
                 ("n_mesh", C.c_int), ("box_len", C.c_double), ("box_origin", C.c_double * 3),
                 ("ell_max", C.c_int), ("order", C.c_int), ("compensate", C.c_int),
-                ("bin_lo", C.c_double), ("bin_width", C.c_double), ("n_bins", C.c_int)]
+                ("bin_lo", C.c_double), ("bin_width", C.c_double), ("n_bins", C.c_int),
+                ("midpoint_parity", C.c_int)]
 
 
 class _Catalog(C.Structure):
@@ -114,6 +116,7 @@ class Config:
     bin_lo: float = 0.01
     bin_width: float = 0.01
     n_bins: int = 20
+    midpoint_parity: int = PW_PARITY_EVEN
 
     def _c(self):
         c = _Config()
@@ -124,6 +127,7 @@ class Config:
             c.box_origin[i] = float(self.box_origin[i])
         c.ell_max, c.order, c.compensate = self.ell_max, self.order, int(self.compensate)
         c.bin_lo, c.bin_width, c.n_bins = float(self.bin_lo), float(self.bin_width), self.n_bins
+        c.midpoint_parity = int(self.midpoint_parity)
         return c
 
     @property
@@ -238,8 +242,9 @@ class Context:
     def estimate_orders(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """Each series order's contribution: values[o] holds the terms of order theta^(2o)
         (pw_estimate_orders); shape [order/2 + 1, n_ell, n_bins]."""
-        return self._run(_lib.pw_estimate_orders, (cfg.order // 2 + 1, cfg.n_ell, cfg.n_bins), cfg, gal_xyzw,
-                         ran_xyzw, ran_nbar, norm)
+        step = 1 if (cfg.los == PW_MIDPOINT and cfg.midpoint_parity == PW_PARITY_ALL) else 2
+        return self._run(_lib.pw_estimate_orders, (cfg.order // step + 1, cfg.n_ell, cfg.n_bins), cfg,
+                         gal_xyzw, ran_xyzw, ran_nbar, norm)
 
     def _run(self, fn, shape, cfg, gal_xyzw, ran_xyzw, ran_nbar, norm):
         keep = []

@@ -134,6 +134,52 @@ def test_legendre_F_table_matches_oracle():
                     assert got[(l, J)] == pytest.approx(v, rel=1e-11)
 
 
+@pytest.mark.parametrize("alpha", [1, 2, 3])
+def test_midpoint_allparity_table_matches_oracle(alpha):
+    """Real-basis all-parity coupling: the oracle's phi (Appendix B) with the (-1)^J2 of
+    g^alpha_J2 (Section 3.2) folded in."""
+    ell_max = 4
+    exp = {}
+    for l in range(0, ell_max + 1, 2):
+        Ul = _U(l)
+        for m in range(-l, l + 1):
+            for (J1, J2, M), c in coeffs.phi_table(alpha, l, m).items():
+                c = c * (-1) ** J2
+                U1 = _U(J1)[M + J1]
+                U2 = _U(J2)[m - M + J2]
+                for nu in range(-l, l + 1):
+                    cl = np.conj(Ul[m + l, nu + l])
+                    if cl == 0:
+                        continue
+                    for n1 in range(-J1, J1 + 1):
+                        for n2 in range(-J2, J2 + 1):
+                            val = cl * c * U1[n1 + J1] * U2[n2 + J2]
+                            if val == 0:
+                                continue
+                            k = (l, nu, _idx(J1, n1), _idx(J2, n2))
+                            exp[k] = exp.get(k, 0) + val
+    exp = {k: v for k, v in exp.items() if abs(v) > 1e-12}
+    assert max(abs(v.imag) for v in exp.values()) < 1e-11
+    got = _rows_to_dict(pw.coupling_table(3, ell_max, 4, alpha), False)
+    assert set(got) == set(exp)
+    for k in exp:
+        assert got[k] == pytest.approx(exp[k].real, rel=1e-10, abs=1e-11)
+
+
+def test_legendre_f_table_matches_oracle():
+    for alpha in (0, 1, 2, 3, 4):
+        rows = pw.coupling_table(4, 4, 4, alpha)
+        got = {(int(r[0]), int(r[2])): r[6] for r in rows}
+        n = 0
+        for l in (0, 2, 4):
+            for J in range(0, l + alpha + 1):
+                v = coeffs.f(alpha, l, J)
+                if abs(v) > 1e-12:
+                    assert got[(l, J)] == pytest.approx(v, rel=1e-11)
+                    n += 1
+        assert n == len(got)
+
+
 def test_footprint_and_validation_need_no_device():
     cfg = pw.Config(n_mesh=64, los=pw.PW_BISECTOR, stat=pw.PW_PK, ell_max=4, order=4,
                     bin_lo=0.01, bin_width=0.01, n_bins=20)
