@@ -86,6 +86,9 @@ typedef struct {
   int midpoint_parity;   /* midpoint series: 0 parity-even (Sections 3.3, 4.3: even alpha, */
                          /* coefficients Phi, F), 1 all-parity (Sections 3.2, 4.2: every   */
                          /* alpha <= order, coefficients phi, f); ignored for the bisector */
+  int memory_lean;       /* bisector P_l: 1 = forward transforms in small groups of fields  */
+                         /* through group-sized work buffers (about a quarter of the device */
+                         /* memory at 512^3, same results bit for bit); ignored elsewhere   */
 } pw_config;
 
 /* A catalog: n particles as interleaved (x, y, z, w) records of dtype (PW_FP32 / PW_FP64).

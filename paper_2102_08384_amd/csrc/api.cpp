@@ -281,7 +281,15 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
     dp->mesh = alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * h.N * rsz);
     const size_t sb = spectrum_buffer_bytes(h);
     dp->bufA = alloc_plan(ctx, dp.get(), sb);
-    dp->bufB = alloc_plan(ctx, dp.get(), sb);
+    if (h.lean) {
+      // memory-lean bisector: the k-sphere of every field (A) and one group's x / y passes
+      dp->bufB = alloc_plan(ctx, dp.get(), lean_x_bytes(h));
+      dp->bufC = alloc_plan(ctx, dp.get(), lean_y_bytes(h));
+      dp->lean_jobs = upload(ctx, dp.get(), h.lean_jobs);
+      dp->lean_fmap = upload(ctx, dp.get(), h.lean_fmap);
+    } else {
+      dp->bufB = alloc_plan(ctx, dp.get(), sb);
+    }
     // result rows: n_ell, or n_ell per series order for the one-pass per-order contraction
     const size_t rows = (size_t)std::max(h.nell, h.n_orders_native * h.nell) + 2;
     dp->acc = (double *)alloc_plan(ctx, dp.get(), rows * h.n_bins * sizeof(double));
@@ -435,18 +443,34 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const double x2 = (double)h.nfields * N * F.npen_real * csz;
   const double x3 = (double)h.nfields * modes_real * csz;
   char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
-  mark("fx", ncell * rsz + x1);
-  launch_fx(s, h.prec, N, false, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
-            h.unit, dp->tw, dp->rowlist, dp->norm);
-  mark("fy", x1 + x2);
-  if (F.npen > 0)
-    launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
-              dp->rowmask, dp->zlist, dp->norm);
-  mark("fz", x2 + x3);
-  if (F.npen > 0)
-    launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff, dp->fwd.gsize,
-              F.mstride, dp->tw,
-              dp->planemask);
+  if (h.lean) {
+    // groups of fields through the x, y and z passes; the z pass writes each field's k-sphere
+    // into A at its own index (fmap), so the contraction below sees the usual layout
+    mark("forward", ncell * rsz + 2.0 * x1 + 2.0 * x2 + x3);
+    const int ng = F.npen > 0 ? (int)h.lean_jstart.size() - 1 : 0;
+    for (int g = 0; g < ng; ++g) {
+      const int j0 = h.lean_jstart[g], nj = h.lean_jstart[g + 1] - j0;
+      const int f0 = h.lean_fstart[g], nf = h.lean_fstart[g + 1] - f0;
+      launch_fx(s, h.prec, N, false, dp->mesh, B, dp->lean_jobs + j0, nj, F.nkx, F.rs, cfg->box_origin, h.H,
+                h.unit, dp->tw, dp->rowlist, dp->norm);
+      launch_fy(s, h.prec, N, 0, B, dp->bufC, nf, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
+                dp->rowmask, dp->zlist, dp->norm);
+      launch_fz(s, h.prec, N, dp->bufC, A, nf, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff, dp->fwd.gsize,
+                F.mstride, dp->tw, dp->planemask, dp->lean_fmap + f0);
+    }
+  } else {
+    mark("fx", ncell * rsz + x1);
+    launch_fx(s, h.prec, N, false, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
+              h.unit, dp->tw, dp->rowlist, dp->norm);
+    mark("fy", x1 + x2);
+    if (F.npen > 0)
+      launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
+                dp->rowmask, dp->zlist, dp->norm);
+    mark("fz", x2 + x3);
+    if (F.npen > 0)
+      launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff, dp->fwd.gsize,
+                F.mstride, dp->tw, dp->planemask);
+  }
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
   if (orders && (h.path != PATH_BIS_PK || h.n_orders_native == 0))
     fail(PW_EINVAL, "internal: no one-pass per-order contraction for this configuration");
@@ -644,6 +668,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
       if (nm == "fx") ln.st_bytes[i] = fr * (N * N * N * rsz + x1);
       else if (nm == "fy") ln.st_bytes[i] = fr * x1 + fp * x2;
       else if (nm == "fz") ln.st_bytes[i] = fp * x2 + x3;
+      else if (nm == "forward") ln.st_bytes[i] = fr * (N * N * N * rsz + 2 * x1) + 2 * fp * x2 + x3;
     }
     ln.occ_rows = dn.nrows_occ;
     ln.occ_planes = dn.nplanes_occ;

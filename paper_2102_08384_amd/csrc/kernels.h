@@ -112,9 +112,11 @@ void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *ou
 // Sphere-pruned sets: out[p][goff[g] + slot * C + c] for pencil q = g C + c, slot as in Prune
 // (C = 128 bytes / complex size, the pencils per workgroup).  Field stride mstride.
 // planemask (may be null): empty z-planes of the input are read as zeros.
+// fmap (may be null): the output field index of each input field p (sphere-pruned sets only)
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
                int64_t npen, const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff,
-               const int *gsize, int64_t mstride, const void *tw, const int *planemask);
+               const int *gsize, int64_t mstride, const void *tw, const int *planemask,
+               const int *fmap = nullptr);
 
 // Bisector contraction + FP64 k-binning.
 struct TermTable {
@@ -125,6 +127,15 @@ struct TermTable {
   const void *coef;      // float or double
   int ntargets;
 };
+// Threads per block of the table-driven bisector contraction: every field value of a block's
+// modes is staged in LDS (nfields * threads complex values) beside the FP64 bins, within 64 KiB;
+// 0 when not even the smallest block fits.
+inline int contract_bis_threads(int prec, int nfields, int nell, int nbins) {
+  const size_t csz = prec == 0 ? 8 : 16, bins = (size_t)(nell + 2) * nbins * 8;
+  for (int nth = prec == 0 ? 128 : 64; nth >= 16; nth /= 2)
+    if ((size_t)nfields * nth * csz + bins <= 65536) return nth;
+  return 0;
+}
 void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
                          int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,

@@ -411,7 +411,7 @@ __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int fpb, int64_t npen,
      const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, const int64_t *__restrict__ goff,
      const int *__restrict__ gsize, int64_t mstride, const cplx<R> *__restrict__ tw,
-     const int *__restrict__ planemask) {
+     const int *__restrict__ planemask, const int *__restrict__ fmap) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
   constexpr int LB = N * (C + 1);  // one exchange buffer; grouped: two alternate
   __shared__ cplx<R> lds[GROUPED ? 2 * LB : LB];
@@ -478,7 +478,8 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
     if constexpr (GROUPED) fft_pencil_db<R, N, false>(v, t, twr, at, sync, flip);
     else fft_pencil<R, N, false>(v, t, twr, at, sync);
     if constexpr (GROUPED) {
-      cplx<R> *dst = out + (size_t)p * mstride + m0 + c;
+      // fmap: output field of input field p (a group of fields transformed at a time)
+      cplx<R> *dst = out + (size_t)(fmap ? fmap[p] : p) * mstride + m0 + c;
 #pragma unroll
       for (int s = 0; s < 8; ++s)
         if (slot[s] >= 0) dst[(size_t)slot[s] * C] = v[s];
@@ -497,7 +498,7 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 template <typename R, int N>
 static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int64_t npen,
                       const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
-                      int64_t mstride, const void *tw, const int *planemask) {
+                      int64_t mstride, const void *tw, const int *planemask, const int *fmap) {
   constexpr int C = ColShape<R, N>::C;
   static_assert(C == 128 / (int)sizeof(cplx<R>), "z-pass groups must match 128-byte slot rows");
   const unsigned ng = (unsigned)((npen + C - 1) / C);
@@ -507,21 +508,23 @@ static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int
   if (goff)
     hipLaunchKernelGGL((k_fz<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
                        (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, goff, gsize, mstride, (const cplx<R> *)tw,
-                       planemask);
+                       planemask, fmap);
   else
     hipLaunchKernelGGL((k_fz<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
                        (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, goff, gsize, mstride, (const cplx<R> *)tw,
-                       planemask);
+                       planemask, (const int *)nullptr);
 }
 
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int64_t npen,
                const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
-               int64_t mstride, const void *tw, const int *planemask) {
+               int64_t mstride, const void *tw, const int *planemask, const int *fmap) {
   if (nfields <= 0 || npen <= 0) return;
   if (prec == 0) {
-    PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask)
+    PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask,
+                  fmap)
   } else {
-    PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask)
+    PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask,
+                  fmap)
   }
 }
 
@@ -628,32 +631,35 @@ void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void
   if (launch_contract_bis_generated(s, prec, lmax, bmax, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins,
                                     kf, winv, acc, 0))
     return;
-  int64_t want = (nmodes + 127) / 128;
-  unsigned blocks = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+  const int nth = contract_bis_threads(prec, nfields, nell, nbins);  // validated by the planner
+  int64_t want = (nmodes + nth - 1) / nth;
+  unsigned blocks = (unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192);
 #define PW_CONTRACT(R, L, NTH)                                                                     \
-  {                                                                                                \
+  if (nth == NTH) {                                                                                \
     size_t sh = (size_t)nfields * NTH * sizeof(cplx<R>) + (size_t)(nell + 2) * nbins * sizeof(double); \
     hipLaunchKernelGGL((k_contract_bis<R, L, NTH>), dim3(blocks), dim3(NTH), sh, s,                \
                        (const cplx<R> *)spec, nfields, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, \
                        nbins, nell, tab, kf, (const R *)winv, acc);                                \
   }
+#define PW_CONTRACT_L(R, L) PW_CONTRACT(R, L, 128) PW_CONTRACT(R, L, 64) PW_CONTRACT(R, L, 32) PW_CONTRACT(R, L, 16)
   if (prec == 0) {
     switch (lmax) {
-      case 0: PW_CONTRACT(float, 0, 128) break;
-      case 2: PW_CONTRACT(float, 2, 128) break;
-      case 4: PW_CONTRACT(float, 4, 128) break;
-      case 6: PW_CONTRACT(float, 6, 128) break;
-      default: PW_CONTRACT(float, 8, 128) break;
+      case 0: PW_CONTRACT_L(float, 0) break;
+      case 2: PW_CONTRACT_L(float, 2) break;
+      case 4: PW_CONTRACT_L(float, 4) break;
+      case 6: PW_CONTRACT_L(float, 6) break;
+      default: PW_CONTRACT_L(float, 8) break;
     }
   } else {
     switch (lmax) {
-      case 0: PW_CONTRACT(double, 0, 64) break;
-      case 2: PW_CONTRACT(double, 2, 64) break;
-      case 4: PW_CONTRACT(double, 4, 64) break;
-      case 6: PW_CONTRACT(double, 6, 64) break;
-      default: PW_CONTRACT(double, 8, 64) break;
+      case 0: PW_CONTRACT_L(double, 0) break;
+      case 2: PW_CONTRACT_L(double, 2) break;
+      case 4: PW_CONTRACT_L(double, 4) break;
+      case 6: PW_CONTRACT_L(double, 6) break;
+      default: PW_CONTRACT_L(double, 8) break;
     }
   }
+#undef PW_CONTRACT_L
 #undef PW_CONTRACT
 }
 

@@ -165,7 +165,8 @@ void sort_jobs(std::vector<FieldJob> &jobs) {
 PlanKey make_key(const pw_config &c) {
   return PlanKey(c.stat, c.los, c.assign, c.prec, c.n_mesh, c.box_len, c.box_origin[0],
                  c.box_origin[1], c.box_origin[2], c.ell_max, c.order, c.compensate, c.bin_lo,
-                 c.bin_width, c.n_bins, c.los == PW_MIDPOINT ? c.midpoint_parity : 0);
+                 c.bin_width, c.n_bins, c.los == PW_MIDPOINT ? c.midpoint_parity : 0,
+                 (c.los == PW_BISECTOR && c.stat == PW_PK) ? c.memory_lean : 0);
 }
 
 void validate_config(const pw_config &c) {
@@ -179,6 +180,7 @@ void validate_config(const pw_config &c) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(c.box_origin[a])) plan_fail(PW_EINVAL, "box_origin must be finite");
   if (c.ell_max < 0 || c.ell_max > 8 || (c.ell_max & 1)) plan_fail(PW_EINVAL, "ell_max must be even, 0..8");
+  if (c.memory_lean != 0 && c.memory_lean != 1) plan_fail(PW_EINVAL, "memory_lean must be 0 or 1");
   if (c.midpoint_parity != PW_PARITY_EVEN && c.midpoint_parity != PW_PARITY_ALL)
     plan_fail(PW_EINVAL, "midpoint_parity must be PW_PARITY_EVEN or PW_PARITY_ALL");
   const bool allp = c.los == PW_MIDPOINT && c.midpoint_parity == PW_PARITY_ALL;
@@ -193,10 +195,9 @@ void validate_config(const pw_config &c) {
     int Jmax = c.ell_max + c.order / 2;
     int nf = (Jmax + 1) * (Jmax + 1);
     bool gen = bis_contract_generated(c.ell_max, c.order / 2);
-    size_t lds = gen ? (size_t)(nell + 2) * c.n_bins * 8
-                     : (size_t)nf * (c.prec == PW_FP32 ? 128 * 8 : 64 * 16) + (size_t)(nell + 2) * c.n_bins * 8;
-    if (lds > 65536)
-      plan_fail(PW_EINVAL, "ell_max + order/2 (or n_bins) too large for the contraction kernel's LDS");
+    const bool fits = gen ? (size_t)(nell + 2) * c.n_bins * 8 <= 65536
+                          : contract_bis_threads(c.prec == PW_FP32 ? 0 : 1, nf, nell, c.n_bins) > 0;
+    if (!fits) plan_fail(PW_EINVAL, "ell_max + order/2 (or n_bins) too large for the contraction kernel's LDS");
   } else if (path == PATH_MID_PK) {
     if (c.ell_max >= 2 && c.order >= (allp ? 1 : 2) && !mid_reweight_generated(c.ell_max, c.order, allp))
       plan_fail(PW_EINVAL, allp ? "midpoint P_l, all-parity: (ell_max, order) has no re-weighting kernel "
@@ -318,6 +319,33 @@ HostPlan build_host_plan(const pw_config &c) {
     h.n_inplace = (h.path == PATH_MID_PK) ? h.n0 : 0;
   }
   sort_jobs(h.jobs);
+  h.lean = (h.path == PATH_BIS_PK && c.memory_lean) ? 1 : 0;
+  if (h.lean) {
+    // consecutive sorted jobs (the x pass's harmonic recurrence runs along them) in groups of
+    // about kLeanFields fields, each field at a slot local to its group
+    h.lean_jstart.push_back(0);
+    h.lean_fstart.push_back(0);
+    int nf = 0;
+    for (size_t i = 0; i < h.jobs.size(); ++i) {
+      FieldJob j = h.jobs[i];
+      const int base = (int)h.lean_fmap.size() - h.lean_fstart.back();
+      h.lean_fmap.push_back(j.pa);
+      j.pa = base;
+      nf = base + 1;
+      if (j.pb >= 0) {
+        h.lean_fmap.push_back(j.pb);
+        j.pb = base + 1;
+        nf = base + 2;
+      }
+      h.lean_jobs.push_back(j);
+      if (nf >= kLeanFields || i + 1 == h.jobs.size()) {
+        h.lean_maxf = std::max(h.lean_maxf, nf);
+        h.lean_jstart.push_back((int)h.lean_jobs.size());
+        h.lean_fstart.push_back((int)h.lean_fmap.size());
+        nf = 0;
+      }
+    }
+  }
 
   // ------------------------------------------------------------------ retention
   h.fwd = make_prune(N, h.K2, h.path != PATH_BIS_PK, h.path == PATH_BIS_PK, c.prec);
@@ -442,6 +470,7 @@ HostPlan build_host_plan(const pw_config &c) {
 
 size_t spectrum_buffer_bytes(const HostPlan &h) {
   const size_t csz = h.prec == PW_FP32 ? 8 : 16;
+  if (h.lean) return std::max<size_t>((size_t)h.nfields * h.fwd.mstride * csz, 16);  // the k-sphere
   const size_t x1 = (size_t)h.nfields * h.N * h.N * h.fwd.rs * csz;
   const size_t x2 = (size_t)h.nfields * h.N * h.fwd.npen * csz;
   const size_t x3 = (size_t)h.nfields * h.fwd.mstride * csz;
@@ -453,6 +482,7 @@ size_t plan_bytes(const pw_config &c) {
   const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
   const int ts = tile_size(h.N), nt = h.N / ts;
   size_t b = (size_t)h.N * h.N * h.N * rsz + 2 * spectrum_buffer_bytes(h);
+  if (h.lean) b = (size_t)h.N * h.N * h.N * rsz + spectrum_buffer_bytes(h) + lean_x_bytes(h) + lean_y_bytes(h);
   b += h.fwd.modecoord.size() * 4 + h.sph.modecoord.size() * 4 + h.bin_of_s2.size() * 4 +
        (h.fwd.pinfo.size() + h.sph.pinfo.size()) * 24;
   b += (size_t)nt * nt * nt * ((ts + 2) * (ts + 2) * (ts + 2) * 8 + 16);
@@ -467,6 +497,16 @@ size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
 
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
   return plan_bytes(c) + catalog_bytes(c, n_gal, n_ran);
+}
+
+size_t lean_x_bytes(const HostPlan &h) {
+  const size_t csz = h.prec == PW_FP32 ? 8 : 16;
+  return (size_t)h.lean_maxf * h.N * h.N * h.fwd.rs * csz;
+}
+
+size_t lean_y_bytes(const HostPlan &h) {
+  const size_t csz = h.prec == PW_FP32 ? 8 : 16;
+  return (size_t)h.lean_maxf * h.N * h.fwd.npen * csz;
 }
 
 }  // namespace pw

@@ -26,7 +26,7 @@ namespace pw {
 [[noreturn]] void plan_fail(int code, const char *msg);
 
 typedef std::tuple<int, int, int, int, int, double, double, double, double, int, int, int, double,
-                   double, int, int>
+                   double, int, int, int>
     PlanKey;
 
 PlanKey make_key(const pw_config &c);
@@ -104,7 +104,16 @@ struct HostPlan {
   // where no shot noise is subtracted)
   int n_orders_native = 0;
   std::vector<int> ells_orders;
+  // bisector P, memory-lean: the sorted jobs in groups of about kLeanFields fields; group g has
+  // jobs [lean_jstart[g], lean_jstart[g+1]) of lean_jobs (field slots local to the group) and
+  // fields [lean_fstart[g], lean_fstart[g+1]) of lean_fmap (local slot -> field index)
+  int lean = 0;
+  int lean_maxf = 0;
+  std::vector<FieldJob> lean_jobs;
+  std::vector<int> lean_jstart, lean_fstart, lean_fmap;
 };
+
+constexpr int kLeanFields = 8;
 
 // Whether pw_estimate_orders has a one-pass path for cfg (bisector P_l with a generated
 // coupling whose per-order accumulators fit the contraction kernel's LDS).
@@ -114,8 +123,11 @@ HostPlan build_host_plan(const pw_config &c);
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
 size_t plan_bytes(const pw_config &c);       // device bytes of one plan (tables + work buffers)
 size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);  // records + staging
-// bytes of each of the two spectrum buffers
+// bytes of each of the two spectrum buffers (memory-lean: of the k-sphere buffer)
 size_t spectrum_buffer_bytes(const HostPlan &h);
+// memory-lean bisector: x-pass and y-pass work buffers of one field group
+size_t lean_x_bytes(const HostPlan &h);
+size_t lean_y_bytes(const HostPlan &h);
 
 struct DevPrune {
   int *ycnt = nullptr;
@@ -131,7 +143,9 @@ struct DevPlan {
   std::unique_ptr<HostPlan> host;
   std::vector<std::pair<void *, size_t>> allocs;
   void *tw = nullptr;
-  FieldJob *jobs = nullptr, *ijobs = nullptr, *ajobs = nullptr;
+  FieldJob *jobs = nullptr, *ijobs = nullptr, *ajobs = nullptr, *lean_jobs = nullptr;
+  int *lean_fmap = nullptr;
+  void *bufC = nullptr;  // memory-lean: y-pass output of one field group
   DevPrune fwd, sph;
   int *bin_of_s2 = nullptr;
   int *ells = nullptr, *ells_orders = nullptr;

@@ -40,7 +40,7 @@ class _Config(C.Structure):
                 ("n_mesh", C.c_int), ("box_len", C.c_double), ("box_origin", C.c_double * 3),
                 ("ell_max", C.c_int), ("order", C.c_int), ("compensate", C.c_int),
                 ("bin_lo", C.c_double), ("bin_width", C.c_double), ("n_bins", C.c_int),
-                ("midpoint_parity", C.c_int)]
+                ("midpoint_parity", C.c_int), ("memory_lean", C.c_int)]
 
 
 class _Catalog(C.Structure):
@@ -117,6 +117,7 @@ class Config:
     bin_width: float = 0.01
     n_bins: int = 20
     midpoint_parity: int = PW_PARITY_EVEN
+    memory_lean: int = 0
 
     def _c(self):
         c = _Config()
@@ -128,6 +129,7 @@ class Config:
         c.ell_max, c.order, c.compensate = self.ell_max, self.order, int(self.compensate)
         c.bin_lo, c.bin_width, c.n_bins = float(self.bin_lo), float(self.bin_width), self.n_bins
         c.midpoint_parity = int(self.midpoint_parity)
+        c.memory_lean = int(self.memory_lean)
         return c
 
     @property

@@ -180,6 +180,21 @@ def test_legendre_f_table_matches_oracle():
         assert n == len(got)
 
 
+def test_memory_lean_footprint():
+    """The memory-lean bisector keeps the k-sphere of every field plus one field group's x- and
+    y-pass buffers: at the 512^3 headline configuration about a third of the default."""
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, n_mesh=512, box_len=2700.0,
+                    box_origin=(-1350.0, -1350.0, -200.0), ell_max=4, order=4, bin_lo=0.005,
+                    bin_width=0.005, n_bins=79)
+    full = pw.footprint(cfg, 4_000_000, 20_000_000)
+    cfg.memory_lean = 1
+    lean = pw.footprint(cfg, 4_000_000, 20_000_000)
+    assert lean < 0.4 * full
+    cfg.memory_lean = 2
+    with pytest.raises(pw.PwError):
+        pw.footprint(cfg, 1000, 1000)
+
+
 def test_footprint_and_validation_need_no_device():
     cfg = pw.Config(n_mesh=64, los=pw.PW_BISECTOR, stat=pw.PW_PK, ell_max=4, order=4,
                     bin_lo=0.01, bin_width=0.01, n_bins=20)

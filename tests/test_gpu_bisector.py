@@ -128,6 +128,24 @@ def test_bisector_orders(ctx, ell_max, order):
     assert np.all(err < 1e-4)
 
 
+@pytest.mark.parametrize("ell_max,order,prec", [(4, 6, pw.PW_FP32), (4, 8, pw.PW_FP64), (6, 6, pw.PW_FP64),
+                                                (8, 8, pw.PW_FP32), (8, 8, pw.PW_FP64)])
+def test_bisector_high_orders(ctx, ell_max, order, prec):
+    """beta_max up to 4 and ell_max up to 8 (up to 169 real fields): the table-driven
+    contraction with smaller blocks so that every field value of a block fits in LDS."""
+    dtype = np.float64 if prec == pw.PW_FP64 else np.float32
+    say("bisector P", "fp64" if prec == pw.PW_FP64 else "fp32", "N=32 ell_max", ell_max, "order", order)
+    gal, ran = uniform_catalog(51, 2000, 6000, (0, 0, 1100), 400)
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=prec, n_mesh=32,
+                    box_len=800.0, box_origin=(-400.0, -400.0, 700.0), ell_max=ell_max, order=order,
+                    compensate=1, bin_lo=0.004, bin_width=0.012, n_bins=8)
+    res, ref = _run(ctx, cfg, gal, ran, dtype)
+    assert np.array_equal(res["counts"], ref.counts)
+    err = max_err_per_ell(res["values"], ref.values)
+    say("err", err)
+    assert np.all(err < (1e-10 if prec == pw.PW_FP64 else 1e-4))
+
+
 def test_bisector_lognormal_cone_n128(ctx):
     say("bisector P fp32 N=128 lognormal cone (C3 geometry, 2e5 galaxies)")
     gal, ran = make_workload_catalog("C3", index=7, n_gal=200_000)
