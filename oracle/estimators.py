@@ -17,6 +17,8 @@ grids, summing over every m and M:
   xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_{even alpha, J, M} F^{alpha,l}_J Y_J^{M*}(D^) D^alpha g^alpha_{JM}(D).
 * ``xi_midpoint(parity="all")``  Section 4.2 boxed all-parity estimator: every alpha <= K
   with the Legendre shift coefficients f in place of F.
+* ``xi_normalized``  optional, not in the paper (which divides xi_l by I and the bin volume and
+  leaves the survey window): the random-pair normalisation and window correction below.
 * ``xi_bisector``  Section 6 boxed estimator,
   h = IFT[F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)],
   xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_m Y_l^{m*}(D^) sum B h.
@@ -410,3 +412,72 @@ def xi_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
         X_list.append(X)
     sums, rmean, counts = _bin_r(X_list, cfg)
     return _finish_xi(sums, rmean, counts, cfg, alpha_r, I, S)
+
+
+# ----------------------------------------------------------------------------
+# Correlation function: random-pair normalisation and window (edge) correction
+# ----------------------------------------------------------------------------
+# The paper normalises xi_l by I and the bin volume and leaves the survey window alone.  The
+# optional normalisation below divides by the random-pair count of the bin instead (as
+# Landy-Szalay pair counts do) and removes the window's mixing of multipoles:
+#   N_l(a)  = sum over separations in bin a of the estimator's pair sum (the same quantity
+#             xi_l holds before its 1/(I v_a)), i.e. xi_l(a) * I * v_a;
+#   R_L(a)  = the same pair sum for the randoms alone, w alpha_r n_r (L = 0 is the weighted
+#             random-pair count RR of the bin), i.e. xi_L^R(a) * I * v_a;
+#   writing RR(mu) = sum_L R_L L_L(mu) and xi(mu) = sum_l' xi_l' L_l'(mu), the data pair sum
+#   N_l = (2l+1) < L_l RR xi > gives
+#     N_l / R_0 = sum_l' M_{l l'} xi_l',  M_{l l'} = (2l+1) sum_L (l L l'; 0 0 0)^2 f_L,
+#   with f_L = R_L / R_0 (f_0 = 1); the window-corrected multipoles solve this system in
+#   every bin, and N_l / R_0 alone is the random-pair normalised estimate.
+
+def _empty(gal):
+    return {k: np.zeros((0,) + np.asarray(v).shape[1:]) for k, v in gal.items()}
+
+
+def xi_window(gal, ran, cfg: Config, estimator, norm=None, L_max=None) -> Result:
+    """Random-pair multipoles xi_L^R (L = 0, 2, .., L_max; default 2 ell_max): `estimator`
+    (xi_midpoint or xi_bisector) on the randoms alone, alpha_r w n_r, with the data's
+    alpha_r, I, S, so that the results share the data's 1 / (I v_a)."""
+    if norm is None:
+        norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    if L_max is None:
+        L_max = 2 * max(cfg.ells)
+    wcfg = Config(**{**cfg.__dict__, "ells": tuple(range(0, L_max + 1, 2))})
+    return estimator(_empty(gal), ran, wcfg, norm)
+
+
+def xi_window_matrix(ells, f):
+    """M_{l l'} = (2l+1) sum_L (l L l'; 0 0 0)^2 f_L for one bin; f maps even L to f_L."""
+    M = np.zeros((len(ells), len(ells)))
+    for i, l in enumerate(ells):
+        for j, lp in enumerate(ells):
+            tot = 0.0
+            for L, fL in f.items():
+                w = coeffs.wigner3j(l, L, lp, 0, 0, 0)
+                tot += w * w * fL
+            M[i, j] = (2 * l + 1) * tot
+    return M
+
+
+def xi_normalized(gal, ran, cfg: Config, estimator, norm=None, L_max=None):
+    """(xi_RR, xi_edge, f): xi_RR[l][a] = N_l / R_0, xi_edge[l][a] the window-corrected
+    multipoles (M^-1 N / R_0, windows f_L up to L_max), f[L][a] = R_L / R_0.  Bins without
+    random pairs are 0."""
+    if norm is None:
+        norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    data = estimator(gal, ran, cfg, norm).values
+    win = xi_window(gal, ran, cfg, estimator, norm, L_max).values
+    Ls = list(range(0, win.shape[0] * 2, 2))
+    nb = data.shape[1]
+    xr = np.zeros_like(data)
+    xe = np.zeros_like(data)
+    f = np.zeros_like(win)
+    for a in range(nb):
+        R0 = win[0, a]
+        if R0 == 0.0:
+            continue
+        xr[:, a] = data[:, a] / R0
+        f[:, a] = win[:, a] / R0
+        M = xi_window_matrix(list(cfg.ells), {L: f[i, a] for i, L in enumerate(Ls)})
+        xe[:, a] = np.linalg.solve(M, xr[:, a])
+    return xr, xe, f

@@ -326,3 +326,69 @@ def test_bisector_shell_path_equals_full_grid_path():
     assert np.allclose(a.bin_mean, b.bin_mean, rtol=1e-14, atol=0)
     scale = np.max(np.abs(a.values[0]))
     assert np.max(np.abs(a.values - b.values)) < 1e-12 * scale
+
+
+# ---------------------------------------------------------------- random-pair normalisation
+
+def test_xi_window_equals_random_pair_sum():
+    """The randoms-only multipoles R_L / (I v_a) equal the brute-force pair sum over the randoms
+    alone, with the data's normalisation (node-placed tiny catalog, both lines of sight)."""
+    from oracle.estimators import xi_window
+    gal, ran = _tiny(seed=19)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    cfg = _cfg_xi(2)
+    for est, kind in ((xi_midpoint, "mid_series"), (xi_bisector, "bis_series")):
+        w = xi_window(gal, ran, cfg, est, norm, L_max=4)
+        empty = {k: np.zeros((0,) + np.asarray(v).shape[1:]) for k, v in gal.items()}
+        bp, _ = brute.xi_pairs(empty, ran, cfg, kind, norm)
+        assert _rel(w.values, bp) < 1e-12
+
+
+def test_xi_window_matrix_against_quadrature():
+    """M_{l l'} = (2l+1) sum_L (l L l'; 000)^2 f_L is the Legendre-product integral
+    (2l+1) int dmu/2 L_l(mu) L_l'(mu) sum_L f_L L_L(mu), computed here by Gauss-Legendre
+    quadrature (no 3j symbols); f_0 = 1 alone gives the identity."""
+    from numpy.polynomial import legendre as npl
+    from oracle.estimators import xi_window_matrix
+    ells = [0, 2, 4]
+    assert np.allclose(xi_window_matrix(ells, {0: 1.0}), np.eye(3), atol=1e-14)
+    f = {0: 1.0, 2: -0.31, 4: 0.12, 6: -0.05, 8: 0.02}
+    x, wq = npl.leggauss(40)
+    P = {n: npl.legval(x, [0] * n + [1]) for n in range(9)}
+    RR = sum(v * P[L] for L, v in f.items())
+    ref = np.array([[(2 * l + 1) * np.sum(wq * P[l] * P[lp] * RR) / 2 for lp in ells] for l in ells])
+    assert np.allclose(xi_window_matrix(ells, f), ref, atol=1e-13)
+
+
+def test_xi_window_correction_recovers_multipoles():
+    """With pair counts that follow RR(mu) xi(mu) exactly, N_l / R_0 mixes the multipoles through
+    the window and the correction recovers them: build N_l / R_0 by quadrature from a chosen
+    xi_l' and window f_L, then solve."""
+    from numpy.polynomial import legendre as npl
+    from oracle.estimators import xi_window_matrix
+    ells = [0, 2, 4]
+    f = {0: 1.0, 2: 0.4, 4: -0.2, 6: 0.1, 8: -0.03}
+    xi_true = np.array([2.0, -0.7, 0.3])
+    x, wq = npl.leggauss(40)
+    P = {n: npl.legval(x, [0] * n + [1]) for n in range(9)}
+    RR = sum(v * P[L] for L, v in f.items())
+    xi_mu = sum(v * P[l] for l, v in zip(ells, xi_true))
+    NR = np.array([(2 * l + 1) * np.sum(wq * P[l] * RR * xi_mu) / 2 for l in ells])
+    assert not np.allclose(NR, xi_true)
+    assert np.allclose(np.linalg.solve(xi_window_matrix(ells, f), NR), xi_true, rtol=1e-12)
+
+
+def test_xi_normalized_is_ratio_of_estimates():
+    """xi_RR = N_l / R_0 bin by bin (the data estimate over the randoms-only monopole, both with
+    the data's 1 / (I v_a)), f_0 = 1, and a survey window has non-zero higher multipoles."""
+    from oracle.estimators import xi_normalized, xi_window
+    gal, ran = _generic(seed=20, n_gal=600, n_ran=3000)
+    cfg = Config(N=32, L=1000.0, b0=(-500, -500, 700), assign=TSC, ells=(0, 2, 4), order=2,
+                 compensate=True, bin_lo=20.0, bin_width=60.0, n_bins=6)
+    norm = scalars(gal["w"], ran["w"], ran["nbar"])
+    xr, xe, f = xi_normalized(gal, ran, cfg, xi_midpoint, norm)
+    data = xi_midpoint(gal, ran, cfg, norm).values
+    win = xi_window(gal, ran, cfg, xi_midpoint, norm).values
+    assert np.allclose(xr, data / win[0][None, :], rtol=1e-12)
+    assert np.allclose(f[0], 1.0)
+    assert f.shape[0] == 5 and np.max(np.abs(f[1:])) > 1e-3
