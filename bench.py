@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--no-orders", action="store_true")
     ap.add_argument("--midpoint-parity", choices=["even", "all"], default="even",
                     help="midpoint series form (the headline workload is the bisector)")
+    ap.add_argument("--memory-lean", action="store_true",
+                    help="bisector P_l: forward transforms in groups of fields (less device memory)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -194,6 +196,7 @@ def main():
     rx = torch.from_numpy(to_xyzw(ran, np.float32)).to(dev)
     rn = torch.from_numpy(ran["nbar"].astype(np.float32)).to(dev)
     cfg = workload_config(pw, a.workload, 1 if a.midpoint_parity == "all" else 0)
+    cfg.memory_lean = 1 if a.memory_lean else 0
     knames = KERNEL_NAMES if wl.los == "bisector" else KERNEL_NAMES_MID
     stream = torch.cuda.current_stream(dev)
     if a.copy_calibration:
@@ -258,6 +261,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": describe(wl, a.workload, cfg),
                    "mode": "served" if served else "plain",
+                   "memory_lean": bool(a.memory_lean),
                    "inputs": "resident in HBM (device pointers)"},
         "plain": {"value": plain_value, "ms_per_catalog": p_el * 1e3 / a.steps,
                   "latency_ms": {"p50": float(np.percentile(p_lat, 50)),

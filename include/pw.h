@@ -156,6 +156,24 @@ int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
                        const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
                        int64_t *counts);
 
+/* Correlation-function multipoles normalised by random pairs and corrected for the survey
+ * window.  The paper divides xi_l by I and the bin volume and leaves the window alone; this
+ * call adds the Landy-Szalay-style normalisation on top of the same estimator (cfg->stat must
+ * be PW_XI, either line of sight and series form).  Per r-bin a:
+ *   N_l(a)   the estimate's pair sum (pw_estimate's xi_l times I v_a);
+ *   R_L(a)   the same sum for the randoms alone (w alpha_r n_r, with the data's normalisation;
+ *            R_0 is the bin's weighted random-pair count), L = 0, 2, .., L_max;
+ *   xi_rr    [n_ell][n_bins]  N_l / R_0;
+ *   xi_edge  [n_ell][n_bins]  the solution of N_l / R_0 = sum_l' M_ll' xi_l',
+ *            M_ll' = (2l+1) sum_L (l L l'; 0 0 0)^2 f_L (may be NULL);
+ *   window   [L_max/2 + 1][n_bins]  f_L = R_L / R_0 (may be NULL).
+ * L_max = 2 ell_max, capped at 8 (midpoint) or 6 (bisector, whose built couplings stop there);
+ * *n_window receives L_max/2 + 1.  Bins without random pairs are 0.  Costs two estimates.
+ * Errors as pw_estimate; outputs written only on success. */
+int pw_estimate_xi_normalized(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
+                              const pw_catalog *ran, pw_norm *norm, double *xi_rr, double *xi_edge,
+                              double *window, int *n_window, double *bin_mean, int64_t *counts);
+
 /* Serving.  pw_submit validates a request, enqueues it and returns a ticket at once; a
  * worker thread of the context admits pending requests in arrival order as soon as one of the
  * context's serving lanes is free and the request's device memory fits the HBM budget (plans

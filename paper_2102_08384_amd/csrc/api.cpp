@@ -982,6 +982,94 @@ int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
   return PW_OK;
 }
 
+// Solve the n x n system A x = b in place by Gaussian elimination with partial pivoting
+// (n <= 5: the multipoles of one r-bin).
+static void solve_small(int n, double *A, double *b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[i * n + k]) > std::fabs(A[piv * n + k])) piv = i;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[piv * n + j]);
+      std::swap(b[k], b[piv]);
+    }
+    if (A[k * n + k] == 0.0) fail(PW_EINVAL, "window matrix is singular in a bin");
+    for (int i = k + 1; i < n; ++i) {
+      const double f = A[i * n + k] / A[k * n + k];
+      for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * b[j];
+    b[k] = s / A[k * n + k];
+  }
+}
+
+int pw_estimate_xi_normalized(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                              pw_norm *norm, double *xi_rr, double *xi_edge, double *window, int *n_window,
+                              double *bin_mean, int64_t *counts) {
+  if (!ctx) return PW_EINVAL;
+  try {
+    if (!cfg || !xi_rr || !gal) fail(PW_EINVAL, "null configuration, catalog or output");
+    if (cfg->stat != PW_XI) fail(PW_EINVAL, "pw_estimate_xi_normalized needs stat = PW_XI");
+    validate_config(*cfg);
+    const int nell = cfg->ell_max / 2 + 1, nb = cfg->n_bins;
+    std::vector<double> data((size_t)nell * nb), bm(nb);
+    std::vector<int64_t> ct(nb);
+    pw_norm nm = norm ? *norm : pw_norm{0.0, 0.0, 0.0, 0};
+    run_estimate(ctx, cfg, gal, ran, &nm, data.data(), bm.data(), ct.data());
+    // the randoms alone, alpha_r w n_r, with the data's normalisation
+    pw_config wc = *cfg;
+    wc.ell_max = std::min(2 * cfg->ell_max, cfg->los == PW_BISECTOR ? 6 : 8);
+    const int nL = wc.ell_max / 2 + 1;
+    pw_catalog none = *gal;
+    none.n = 0;
+    pw_norm given = nm;
+    given.use_given = 1;
+    std::vector<double> win((size_t)nL * nb);
+    run_estimate(ctx, &wc, &none, ran, &given, win.data(), nullptr, nullptr);
+    std::vector<double> rr((size_t)nell * nb, 0.0), edge((size_t)nell * nb, 0.0), f((size_t)nL * nb, 0.0);
+    for (int a = 0; a < nb; ++a) {
+      const double R0 = win[a];
+      if (R0 == 0.0) continue;
+      for (int i = 0; i < nL; ++i) f[(size_t)i * nb + a] = win[(size_t)i * nb + a] / R0;
+      double M[25], x[5];
+      for (int i = 0; i < nell; ++i) {
+        const int l = 2 * i;
+        rr[(size_t)i * nb + a] = x[i] = data[(size_t)i * nb + a] / R0;
+        for (int j = 0; j < nell; ++j) {
+          const int lp = 2 * j;
+          double t = 0.0;
+          for (int k = 0; k < nL; ++k) {
+            const double w = wigner3j(l, 2 * k, lp, 0, 0, 0);
+            t += w * w * f[(size_t)k * nb + a];
+          }
+          M[i * nell + j] = (2 * l + 1) * t;
+        }
+      }
+      solve_small(nell, M, x);
+      for (int i = 0; i < nell; ++i) edge[(size_t)i * nb + a] = x[i];
+    }
+    std::memcpy(xi_rr, rr.data(), rr.size() * sizeof(double));
+    if (xi_edge) std::memcpy(xi_edge, edge.data(), edge.size() * sizeof(double));
+    if (window) std::memcpy(window, f.data(), f.size() * sizeof(double));
+    if (n_window) *n_window = nL;
+    if (bin_mean) std::memcpy(bin_mean, bm.data(), bm.size() * sizeof(double));
+    if (counts) std::memcpy(counts, ct.data(), ct.size() * sizeof(int64_t));
+    if (norm && !norm->use_given) *norm = nm;
+  } catch (const Fail &e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::exception &e) {
+    ctx->err = e.what();
+    return PW_EINVAL;
+  }
+  ctx->err.clear();
+  return PW_OK;
+}
+
 int pw_set_lanes(pw_ctx *ctx, int n_lanes) {
   if (!ctx) return PW_EINVAL;
   if (n_lanes < 1 || n_lanes > kMaxLanes) {

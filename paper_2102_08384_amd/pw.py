@@ -72,6 +72,10 @@ def _load():
     lib.pw_estimate_orders.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                                        C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]
+    lib.pw_estimate_xi_normalized.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
+                                              C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                              C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                              C.POINTER(C.c_int64)]
     lib.pw_submit.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                               C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
@@ -247,6 +251,33 @@ class Context:
         step = 1 if (cfg.los == PW_MIDPOINT and cfg.midpoint_parity == PW_PARITY_ALL) else 2
         return self._run(_lib.pw_estimate_orders, (cfg.order // step + 1, cfg.n_ell, cfg.n_bins), cfg,
                          gal_xyzw, ran_xyzw, ran_nbar, norm)
+
+    def estimate_xi_normalized(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
+        """xi_l over the bins' random-pair counts (xi_rr), window-corrected (xi_edge), and the
+        window multipoles f_L = R_L / R_0 (pw_estimate_xi_normalized)."""
+        keep = []
+        g = _catalog(gal_xyzw, None, keep)
+        r = _catalog(ran_xyzw, ran_nbar, keep)
+        nm = _Norm()
+        if norm is not None:
+            nm.alpha_r, nm.I, nm.S = (float(v) for v in norm)
+            nm.use_given = 1
+        rr = np.zeros((cfg.n_ell, cfg.n_bins))
+        edge = np.zeros((cfg.n_ell, cfg.n_bins))
+        win = np.zeros((5, cfg.n_bins))
+        nw = C.c_int(0)
+        bm = np.zeros(cfg.n_bins)
+        cnt = np.zeros(cfg.n_bins, dtype=np.int64)
+        c = cfg._c()
+        dp = C.POINTER(C.c_double)
+        rc = _lib.pw_estimate_xi_normalized(self._h, C.byref(c), C.byref(g), C.byref(r), C.byref(nm),
+                                            rr.ctypes.data_as(dp), edge.ctypes.data_as(dp), win.ctypes.data_as(dp),
+                                            C.byref(nw), bm.ctypes.data_as(dp),
+                                            cnt.ctypes.data_as(C.POINTER(C.c_int64)))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        return {"xi_rr": rr, "xi_edge": edge, "window": win[:nw.value], "bin_mean": bm, "counts": cnt,
+                "norm": (nm.alpha_r, nm.I, nm.S)}
 
     def _run(self, fn, shape, cfg, gal_xyzw, ran_xyzw, ran_nbar, norm):
         keep = []
