@@ -1,5 +1,7 @@
 """Serving loop (pw_submit / pw_poll / pw_wait / pw_cancel): every request's result in a mixed,
 concurrent stream equals its result alone (pw_estimate), and the stream matches the oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -25,12 +27,19 @@ def _requests():
         (pw.PW_PK, pw.PW_BISECTOR, 32, pw.PW_FP64, 3000, 105, (0.005, 0.02, 9)),
         (pw.PW_PK, pw.PW_BISECTOR, 64, pw.PW_FP32, 15000, 106, (0.005, 0.02, 9)),
         (pw.PW_PK, pw.PW_MIDPOINT, 32, pw.PW_FP32, 5000, 107, (0.005, 0.02, 9)),
+        # all-parity midpoint at an odd order, and the memory-lean bisector plan
+        (pw.PW_PK, pw.PW_MIDPOINT, 32, pw.PW_FP32, 6000, 108, (0.005, 0.02, 9),
+         dict(midpoint_parity=pw.PW_PARITY_ALL, order=3)),
+        (pw.PW_PK, pw.PW_BISECTOR, 64, pw.PW_FP32, 11000, 109, (0.005, 0.02, 9), dict(memory_lean=1)),
     ]
-    for i, (stat, los, N, prec, ng, seed, (lo, w, nb)) in enumerate(specs):
+    for i, spec in enumerate(specs):
+        stat, los, N, prec, ng, seed, (lo, w, nb) = spec[:7]
+        extra = spec[7] if len(spec) > 7 else {}
         gal, ran = uniform_catalog(seed, ng, 3 * ng, (0, 0, 1000), 440)
         cfg = pw.Config(stat=stat, los=los, assign=pw.PW_TSC, prec=prec, n_mesh=N, box_len=1000.0,
                         box_origin=(-500.0, -500.0, 600.0), ell_max=4, order=4 if los == pw.PW_MIDPOINT else 2,
                         compensate=1, bin_lo=lo, bin_width=w, n_bins=nb)
+        cfg = dataclasses.replace(cfg, **extra)
         dt = np.float64 if prec == pw.PW_FP64 else np.float32
         gx, g64 = rounded(gal, dt)
         rx, r64 = rounded(ran, dt)
@@ -45,13 +54,15 @@ def _requests():
 
 def _oracle(cfg, g64, r64):
     oc = oracle_cfg(cfg)
+    if cfg.midpoint_parity == pw.PW_PARITY_ALL:
+        oc = dataclasses.replace(oc, parity="all")
     if cfg.stat == pw.PW_PK:
         return (pk_bisector if cfg.los == pw.PW_BISECTOR else pk_midpoint)(g64, r64, oc)
     return (xi_bisector if cfg.los == pw.PW_BISECTOR else xi_midpoint)(g64, r64, oc)
 
 
 def test_mixed_stream_equals_alone_and_oracle():
-    say("serving: 7 mixed requests on 3 lanes vs alone vs oracle")
+    say("serving: 9 mixed requests on 3 lanes vs alone vs oracle")
     reqs = _requests()
     with pw.Context(0) as ctx:
         ctx.set_lanes(3)
