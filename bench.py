@@ -161,6 +161,112 @@ def served_run(ctx, cfg, gx, rx, rn, steps, warmup, torch):
     return elapsed, lat, res
 
 
+def stream_requests(pw, torch, n_req, seed=5):
+    """A mixed stream of P_l requests in the shape of the serving workload: galaxy counts
+    uniform in [1e5, 4e6] with 5x randoms, meshes 128/256/512, midpoint or bisector by a fair
+    coin, l <= 4, order 4.  Catalogs are seeded subsamples of one lognormal cone per geometry
+    (bisector: r in [400, 2000], L = 2700; midpoint: r in [500, 1500], box doubled, L = 4000),
+    resident on the device.  Returns (label, cfg, gal, ran, nbar) tuples."""
+    from synthetic import WORKLOADS, make_workload_catalog, to_xyzw
+    rng = np.random.default_rng(seed)
+    pools = {}
+    for los, name in ((pw.PW_BISECTOR, "C3"), (pw.PW_MIDPOINT, "C2")):
+        g, r = make_workload_catalog(name, index=1, n_gal=4_000_000)
+        # shuffled once, so that any window of consecutive records is a uniform subsample
+        gx = to_xyzw(g, np.float32)[rng.permutation(len(g["pos"]))]
+        rx = to_xyzw(r, np.float32)[rng.permutation(len(r["pos"]))]
+        pools[los] = (gx, rx, float(r["nbar"][0]), WORKLOADS[name])
+    out = []
+    for i in range(n_req):
+        los = pw.PW_BISECTOR if rng.random() < 0.5 else pw.PW_MIDPOINT
+        N = int(rng.choice([128, 256, 512]))
+        gx, rx, nbar, wl = pools[los]
+        ng = int(rng.uniform(1e5, 4e6))
+        g0 = int(rng.integers(0, len(gx) - ng + 1))
+        r0 = int(rng.integers(0, len(rx) - 5 * ng + 1))
+        # nbar scales with the subsampled count (the weights stay those of the pool)
+        nb = nbar * ng / len(gx)
+        kny = np.pi * N / wl.L
+        nbins = int((min(0.40, kny) - 0.005) / 0.005)
+        cfg = pw.Config(stat=pw.PW_PK, los=los, assign=pw.PW_TSC, prec=pw.PW_FP32, n_mesh=N, box_len=wl.L,
+                        box_origin=wl.b0, ell_max=4, order=4, compensate=1, bin_lo=0.005, bin_width=0.005,
+                        n_bins=nbins)
+        g = torch.from_numpy(gx[g0:g0 + ng]).cuda()
+        r = torch.from_numpy(rx[r0:r0 + 5 * ng]).cuda()
+        n = torch.full((5 * ng,), nb, dtype=torch.float32, device="cuda")
+        out.append((f"{'bis' if los == pw.PW_BISECTOR else 'mid'}{N} ng={ng}", cfg, g, r, n))
+    return out
+
+
+def stream_bench(a):
+    """Serving under Poisson arrivals: capacity from one plain pass over the stream, then the
+    same requests submitted at exponential inter-arrival times at 0.7x and 1.5x that rate;
+    latency runs from pw_submit to the result on the host (inputs device-resident)."""
+    import torch
+    from paper_2102_08384_amd import pw
+    log("building a stream of", a.stream, "requests")
+    reqs = stream_requests(pw, torch, a.stream)
+    torch.cuda.synchronize()
+    ctx = pw.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.set_lanes(a.lanes)
+    # warm every configuration once (plans built, kernels loaded)
+    seen = set()
+    for lab, cfg, g, r, n in reqs:
+        key = (cfg.los, cfg.n_mesh)
+        if key not in seen:
+            seen.add(key)
+            ctx.estimate(cfg, g, r, ran_nbar=n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_lat = []
+    for lab, cfg, g, r, n in reqs:
+        t1 = time.perf_counter()
+        ctx.estimate(cfg, g, r, ran_nbar=n)
+        plain_lat.append((time.perf_counter() - t1) * 1e3)
+    plain_el = time.perf_counter() - t0
+    cap = len(reqs) / plain_el
+    log(f"plain pass: {cap:.2f} requests/s")
+    out = {"metric": "serving stream (mixed P_l requests) requests/s and latency", "unit": "requests/s",
+           "n_gpus": 1, "requests": len(reqs), "lanes": a.lanes,
+           "mix": "N_g ~ U[1e5, 4e6] + 5 N_g randoms; mesh 128/256/512; midpoint (L = 4000) or bisector "
+                  "(L = 2700) by a fair coin; l <= 4, order 4; FP32; catalogs device-resident",
+           "plain": {"value": cap, "latency_ms": {"p50": float(np.percentile(plain_lat, 50)),
+                                                  "p99": float(np.percentile(plain_lat, 99))}}}
+    rng = np.random.default_rng(11)
+    for load in (0.7, 1.5):
+        gaps = rng.exponential(1.0 / (load * cap), len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets, sub = [], []
+        for i, (lab, cfg, g, r, n) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[i]:
+                time.sleep(5e-5)
+            sub.append(time.perf_counter())
+            tickets.append(ctx.submit(cfg, g, r, ran_nbar=n))
+        done = [None] * len(reqs)
+        failed = []
+        while any(d is None for d in done):
+            for i, t in enumerate(tickets):
+                if done[i] is None:
+                    try:
+                        if t.poll() is None:
+                            continue
+                    except pw.PwError as e:
+                        failed.append(f"{reqs[i][0]}: {e}")
+                    done[i] = time.perf_counter()
+            time.sleep(1e-4)
+        el = max(done) - t0
+        lat = [(d - s_) * 1e3 for s_, d in zip(sub, done)]
+        out[f"served_at_{load}x"] = {"offered": load * cap, "value": (len(reqs) - len(failed)) / el,
+                                     "failed": failed,
+                                     "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                    "p99": float(np.percentile(lat, 99))}}
+        log(f"served at {load}x: {len(reqs) / el:.2f} requests/s, p50 {np.percentile(lat, 50):.1f} ms")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,11 +282,17 @@ def main():
                     help="midpoint series form (the headline workload is the bisector)")
     ap.add_argument("--memory-lean", action="store_true",
                     help="bisector P_l: forward transforms in groups of fields (less device memory)")
+    ap.add_argument("--stream", type=int, default=0,
+                    help="instead of the headline: a mixed stream of this many requests under Poisson "
+                         "arrivals (serving throughput and latency)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
+    if a.stream > 0:
+        stream_bench(a)
+        return
 
     import torch
     from paper_2102_08384_amd import pw

@@ -125,6 +125,25 @@ struct pw_ctx {
   std::thread worker;
   bool worker_started = false;
   bool stop = false;
+  // lane 0 in use by a pw_estimate / pw_inspect call: the admission of served requests may
+  // evict lane 0's cached plans only while this is false
+  bool main_busy = false;
+};
+
+// Marks lane 0 busy for the scope (guarded by ctx->mu); wakes the serving worker when done.
+struct MainBusy {
+  pw_ctx *ctx;
+  explicit MainBusy(pw_ctx *c) : ctx(c) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->main_busy = true;
+  }
+  ~MainBusy() {
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->main_busy = false;
+    }
+    ctx->cv.notify_all();
+  }
 };
 
 namespace {
@@ -642,6 +661,7 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
 void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
                   pw_norm *norm, double *out, double *bin_mean, int64_t *counts, bool orders = false) {
   check_request(cfg, gal, ran, norm, out);
+  MainBusy busy(ctx);
   make_room_main(ctx, cfg, gal, ran);
   Lane &ln = *ctx->main;
   DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm, orders);
@@ -737,7 +757,8 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
       if (e < best_extra) { best = lp.get(); best_extra = e; }
     }
     if (!best) return {nullptr, nullptr};  // every lane busy
-    // make room: evict idle lanes' plans, least recently used first
+    // make room: evict idle lanes' plans (lane 0's too while no pw_estimate runs), least
+    // recently used first
     while (mem_used(ctx) + best_extra > ctx->budget) {
       Lane *vl = nullptr;
       const PlanKey *vk = nullptr;
@@ -749,6 +770,9 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
           if (kv.second < oldest) { oldest = kv.second; vl = lp.get(); vk = &kv.first; }
         }
       }
+      if (!ctx->main_busy)
+        for (auto &kv : ctx->main->plan_stamp)
+          if (kv.second < oldest) { oldest = kv.second; vl = ctx->main.get(); vk = &kv.first; }
       if (!vl) break;
       PlanKey k = *vk;
       evict_plan(ctx, *vl, k);
@@ -758,7 +782,7 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
       ctx->pending.erase(it);
       return {r, best};
     }
-    bool running = false;
+    bool running = ctx->main_busy;  // lane 0 may still release memory
     for (auto &lp : ctx->lanes) running = running || lp->cur != nullptr;
     if (!running) {
       // can never fit: fail it and look at the next one
@@ -831,7 +855,7 @@ void worker_loop(pw_ctx *ctx) {
       }
     }
     if (ctx->stop && ctx->pending.empty() && !any_running) break;
-    if (any_running) {
+    if (any_running || (ctx->main_busy && !ctx->pending.empty())) {
       ctx->cv.wait_for(lk, std::chrono::microseconds(100));
     } else {
       ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->pending.empty(); });
@@ -1242,6 +1266,7 @@ int pw_stage_info(pw_ctx *ctx, int stage, const char **name, double *ms, double 
 int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *needed) {
   if (!ctx || !needed) return PW_EINVAL;
   try {
+    MainBusy busy(ctx);  // keeps the serving admission from evicting lane 0's last plan
     DevPlan *dp = ctx->main->last;
     if (!dp) fail(PW_EINVAL, "pw_inspect: no estimate has run on this context");
     const HostPlan &h = *dp->host;

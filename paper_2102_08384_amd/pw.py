@@ -340,6 +340,16 @@ class Ticket:
         self.bin_mean = np.zeros(cfg.n_bins)
         self.counts = np.zeros(cfg.n_bins, dtype=np.int64)
 
+    def __del__(self):
+        # The worker writes a request's outputs into this ticket's arrays and reads its inputs
+        # until the request is final: a ticket dropped while pending (an exception, interpreter
+        # shutdown) waits for that before its buffers go.  After pw_destroy nothing is written.
+        try:
+            if self.status == PW_EAGAIN and self.id and self._ctx._h:
+                _lib.pw_wait(self._ctx._h, self.id)
+        except Exception:
+            pass
+
     def _final(self, rc):
         self.status = rc
         if rc == PW_OK:

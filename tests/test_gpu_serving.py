@@ -123,3 +123,39 @@ def test_cancel_errors_and_never_fitting():
         with pytest.raises(pw.PwError) as ei:
             small.submit(reqs[0]["cfg"], reqs[0]["gx"], reqs[0]["rx"], ran_nbar=reqs[0]["nbar"])
         assert ei.value.code == pw.PW_ENOMEM
+
+
+def test_served_request_evicts_idle_estimate_plans():
+    """Plans cached by pw_estimate (lane 0) give way to a served request when the budget is
+    tight: with room for one plan, an estimate followed by a request of another
+    configuration must still complete (it used to fail with PW_ENOMEM)."""
+    say("serving: a served request evicts lane 0's cached plan")
+    reqs = _requests()
+    a, b = reqs[0], reqs[5]            # two bisector P_l at 64^3, different catalogs and sizes
+    b = dict(b, cfg=dataclasses.replace(b["cfg"], order=4))   # a different configuration
+    need = max(pw.footprint(r["cfg"], len(r["gx"]), len(r["rx"])) for r in (a, b))
+    with pw.Context(0, hbm_budget=int(need * 1.4)) as ctx:
+        ctx.set_lanes(1)
+        ctx.estimate(a["cfg"], a["gx"], a["rx"], ran_nbar=a["nbar"])
+        got = ctx.submit(b["cfg"], b["gx"], b["rx"], ran_nbar=b["nbar"]).wait()
+        again = ctx.estimate(a["cfg"], a["gx"], a["rx"], ran_nbar=a["nbar"])
+    ref = _oracle(b["cfg"], b["g64"], b["r64"])
+    assert np.all(max_err_per_ell(got["values"], ref.values) < 1e-4)
+    assert np.all(np.isfinite(again["values"]))
+
+
+def test_dropped_tickets_wait_for_their_requests():
+    """A ticket dropped while its request is pending or running waits for it before its
+    output arrays and inputs are released; the context stays usable afterwards."""
+    import gc
+    say("serving: tickets dropped while pending")
+    reqs = _requests()[:5]
+    with pw.Context(0) as ctx:
+        ctx.set_lanes(2)
+        for r in reqs:
+            ctx.submit(r["cfg"], r["gx"], r["rx"], ran_nbar=r["nbar"])   # ticket dropped at once
+        gc.collect()
+        r = reqs[0]
+        alone = ctx.estimate(r["cfg"], r["gx"], r["rx"], ran_nbar=r["nbar"])
+        served = ctx.submit(r["cfg"], r["gx"], r["rx"], ran_nbar=r["nbar"]).wait()
+    assert np.all(max_err_per_ell(served["values"], alone["values"]) < 1e-10)
