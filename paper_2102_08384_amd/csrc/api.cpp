@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -72,6 +73,9 @@ struct Lane {
   size_t stage_nbar_bytes = 0;
   void *records = nullptr;  // tile-sorted particle records
   size_t records_bytes = 0;
+  void *work = nullptr;  // the workspace all plans of the lane run in (see WorkLayout)
+  size_t work_bytes = 0;
+  uint64_t used_stamp = 0;  // last estimate launched on the lane (LRU eviction of `work`)
   double *host_res = nullptr;  // pinned: [(res_rows + 2) * nbins] results + DevNorm
   int res_rows = 0;            // multipole rows of the result in flight (n_ell, or per order)
   size_t host_res_bytes = 0;
@@ -96,7 +100,7 @@ struct Req {
   pw_norm *norm_out = nullptr;
   double *out = nullptr, *bin_mean = nullptr;
   int64_t *counts = nullptr;
-  size_t need = 0;     // device bytes of a plan for cfg plus catalog staging (admission)
+  size_t need_tables = 0, need_work = 0;  // device bytes of cfg's plan tables and workspace
   int status = PW_EAGAIN;
   std::string err;
   DevPlan *dp = nullptr;
@@ -111,7 +115,7 @@ struct pw_ctx {
   std::mutex mem_mu;  // guards `used`
   std::string err;
   size_t lds_per_block = 65536;
-  uint64_t stamp = 0;
+  std::atomic<uint64_t> stamp{0};
   std::unique_ptr<Lane> main;                 // lane 0: pw_estimate
   std::vector<std::unique_ptr<Lane>> lanes;   // serving lanes
   int n_lanes = 2;
@@ -121,7 +125,11 @@ struct pw_ctx {
   std::deque<Req *> pending;
   std::map<uint64_t, std::unique_ptr<Req>> reqs;
   uint64_t next_ticket = 1;
-  std::map<PlanKey, size_t> plan_bytes_cache;  // plan footprint per configuration
+  // host plans by configuration, shared by the lanes' device plans (guarded by hp_mu); beyond
+  // kHostPlans entries, the least recently used one that no device plan holds is dropped
+  std::mutex hp_mu;
+  std::map<PlanKey, std::pair<std::shared_ptr<const HostPlan>, uint64_t>> hplans;
+  uint64_t hp_stamp = 0;
   std::thread worker;
   bool worker_started = false;
   bool stop = false;
@@ -241,11 +249,42 @@ void ensure_sh(int device) {
   g_sh_uploaded.push_back(device);
 }
 
+constexpr size_t kHostPlans = 16;
+
+// The host plan of cfg: from the context's cache, else built (outside every lock: building
+// takes from milliseconds to a second) and cached.
+std::shared_ptr<const HostPlan> host_plan(pw_ctx *ctx, const pw_config &cfg) {
+  const PlanKey key = make_key(cfg);
+  {
+    std::lock_guard<std::mutex> lk(ctx->hp_mu);
+    auto it = ctx->hplans.find(key);
+    if (it != ctx->hplans.end()) {
+      it->second.second = ++ctx->hp_stamp;
+      return it->second.first;
+    }
+  }
+  std::shared_ptr<const HostPlan> built = std::make_shared<const HostPlan>(build_host_plan(cfg));
+  std::lock_guard<std::mutex> lk(ctx->hp_mu);
+  auto ins = ctx->hplans.emplace(key, std::make_pair(built, (uint64_t)0)).first;  // or another thread's
+  ins->second.second = ++ctx->hp_stamp;
+  std::shared_ptr<const HostPlan> hp = ins->second.first;
+  while (ctx->hplans.size() > kHostPlans) {
+    auto victim = ctx->hplans.end();
+    for (auto e = ctx->hplans.begin(); e != ctx->hplans.end(); ++e)
+      if (e != ins && e->second.first.use_count() == 1 &&
+          (victim == ctx->hplans.end() || e->second.second < victim->second.second))
+        victim = e;
+    if (victim == ctx->hplans.end()) break;
+    ctx->hplans.erase(victim);
+  }
+  return hp;
+}
+
 std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
-  std::unique_ptr<HostPlan> hp(new HostPlan(build_host_plan(*cfg)));
   std::unique_ptr<DevPlan> dp(new DevPlan());
-  dp->host = std::move(hp);
-  HostPlan &h = *dp->host;
+  dp->host = host_plan(ctx, *cfg);
+  const HostPlan &h = *dp->host;
+  dp->work = work_layout(h);
   try {
     // twiddles exp(-2 pi i e / N)
     std::vector<double> tw(2 * h.N);
@@ -296,18 +335,11 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
     dp->t_p1 = upload(ctx, dp.get(), h.t_p1);
     dp->t_p2 = upload(ctx, dp.get(), h.t_p2);
     dp->t_coef = up_real(h.t_coef);
-    size_t rsz = h.prec == PW_FP32 ? 4 : 8;
-    dp->mesh = alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * h.N * rsz);
-    const size_t sb = spectrum_buffer_bytes(h);
-    dp->bufA = alloc_plan(ctx, dp.get(), sb);
+    // the mesh, spectrum buffers and paint tiles live in the lane's workspace (bind_work);
+    // memory-lean: A holds the k-sphere of every field, B and C one group's x / y passes
     if (h.lean) {
-      // memory-lean bisector: the k-sphere of every field (A) and one group's x / y passes
-      dp->bufB = alloc_plan(ctx, dp.get(), lean_x_bytes(h));
-      dp->bufC = alloc_plan(ctx, dp.get(), lean_y_bytes(h));
       dp->lean_jobs = upload(ctx, dp.get(), h.lean_jobs);
       dp->lean_fmap = upload(ctx, dp.get(), h.lean_fmap);
-    } else {
-      dp->bufB = alloc_plan(ctx, dp.get(), sb);
     }
     // result rows: n_ell, or n_ell per series order for the one-pass per-order contraction
     const size_t rows = (size_t)std::max(h.nell, h.n_orders_native * h.nell) + 2;
@@ -324,7 +356,6 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
       dp->tile_offsets = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
       dp->tile_cursor = (int *)alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * sizeof(int));
       dp->tile_slot = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
-      dp->tile_blocks = alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * (ts + 2) * (ts + 2) * (ts + 2) * 8);
       dp->rowmask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
       dp->rowlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
       dp->planemask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
@@ -355,8 +386,30 @@ DevPlan *get_plan(pw_ctx *ctx, Lane &ln, const pw_config *cfg) {
     ln.plan_bytes[key] = plan_alloc_bytes(dp.get());
     it = ln.plans.emplace(key, std::move(dp)).first;
   }
-  ln.plan_stamp[key] = ++ctx->stamp;
+  ln.plan_stamp[key] = ln.used_stamp = ++ctx->stamp;
   return it->second.get();
+}
+
+// Points the plan's work buffers into the lane's workspace, growing the workspace first when
+// the plan needs more.  The lane has nothing in flight (one estimate at a time per lane).
+void bind_work(pw_ctx *ctx, Lane &ln, DevPlan *dp) {
+  if (ln.work_bytes < dp->work.total) {
+    ln.last = nullptr;  // its buffers go with the old workspace
+    ensure_buffer(ctx, &ln.work, &ln.work_bytes, dp->work.total);
+  }
+  char *w = (char *)ln.work;
+  dp->mesh = w + dp->work.mesh;
+  dp->bufA = w + dp->work.bufA;
+  dp->bufB = w + dp->work.bufB;
+  dp->bufC = dp->host->lean ? w + dp->work.bufC : nullptr;
+  dp->tile_blocks = w + dp->work.tiles;
+}
+
+void evict_work(pw_ctx *ctx, Lane &ln) {
+  ln.last = nullptr;
+  dev_free(ctx, ln.work, ln.work_bytes);
+  ln.work = nullptr;
+  ln.work_bytes = 0;
 }
 
 void evict_plan(pw_ctx *ctx, Lane &ln, const PlanKey &key) {
@@ -413,7 +466,8 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   HIPCHECK(hipSetDevice(ctx->device));
   ensure_sh(ctx->device);
   DevPlan *dp = get_plan(ctx, ln, cfg);
-  HostPlan &h = *dp->host;
+  bind_work(ctx, ln, dp);
+  const HostPlan &h = *dp->host;
   hipStream_t s = ln.stream;
   ln.last = dp;
   const void *gnb = nullptr, *rnb = nullptr;
@@ -632,22 +686,34 @@ void finish_estimate(Lane &ln, const DevPlan *dp, pw_norm *norm, double *out, do
   }
 }
 
-// Make room for a plan on lane 0 by evicting cached plans (lane 0's other plans, then idle
-// serving lanes'), least recently used first.
+// Make room on lane 0 for cfg's plan tables, workspace and catalogs by evicting idle serving
+// lanes' workspaces, then cached plans (lane 0's other ones, idle serving lanes'), least
+// recently used first.
 void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran) {
   Lane &ln = *ctx->main;
   const PlanKey key = make_key(*cfg);
-  if (ln.plans.count(key)) return;
+  std::shared_ptr<const HostPlan> hp = host_plan(ctx, *cfg);
+  const size_t tables = table_bytes(*hp), work = work_layout(*hp).total;
   std::lock_guard<std::mutex> lk(ctx->mu);
-  auto it = ctx->plan_bytes_cache.find(key);
-  if (it == ctx->plan_bytes_cache.end()) it = ctx->plan_bytes_cache.emplace(key, plan_bytes(*cfg)).first;
-  const size_t need = it->second + catalog_bytes(*cfg, gal->n, ran->n);
-  while (mem_used(ctx) + need > ctx->budget) {
+  auto need = [&]() -> size_t {
+    size_t n = ln.plans.count(key) ? 0 : tables;
+    return n + (work > ln.work_bytes ? work - ln.work_bytes : 0);
+  };
+  if (need() == 0) return;
+  const size_t cat = catalog_bytes(*cfg, gal->n, ran->n);
+  while (mem_used(ctx) + need() + cat > ctx->budget) {
+    Lane *wl = nullptr;
+    uint64_t oldest = (uint64_t)-1;
+    for (auto &lp : ctx->lanes)
+      if (!lp->cur && lp->work && lp->used_stamp < oldest) { oldest = lp->used_stamp; wl = lp.get(); }
+    if (wl) {
+      evict_work(ctx, *wl);
+      continue;
+    }
     Lane *vl = nullptr;
     PlanKey vk;
-    uint64_t oldest = (uint64_t)-1;
     for (auto &kv : ln.plan_stamp)
-      if (kv.second < oldest) { oldest = kv.second; vl = &ln; vk = kv.first; }
+      if (kv.first != key && kv.second < oldest) { oldest = kv.second; vl = &ln; vk = kv.first; }
     for (auto &lp : ctx->lanes) {
       if (lp->cur) continue;
       for (auto &kv : lp->plan_stamp)
@@ -719,6 +785,7 @@ void destroy_lane(pw_ctx *ctx, Lane *ln) {
   for (int i = 0; i < 2; ++i) dev_free(ctx, ln->stage[i], ln->stage_bytes[i]);
   dev_free(ctx, ln->stage_nbar, ln->stage_nbar_bytes);
   dev_free(ctx, ln->records, ln->records_bytes);
+  evict_work(ctx, *ln);
   if (ln->host_res) (void)hipHostFree(ln->host_res);
   for (int i = 0; i <= kMaxStages; ++i)
     if (ln->ev[i]) (void)hipEventDestroy(ln->ev[i]);
@@ -730,7 +797,8 @@ void destroy_lane(pw_ctx *ctx, Lane *ln) {
 // Bytes a lane still has to allocate to run `r` (0 when its plan and buffers are resident).
 size_t lane_extra_bytes(const Lane &ln, const Req &r) {
   size_t extra = 0;
-  if (ln.plans.find(make_key(r.cfg)) == ln.plans.end()) extra += r.need;
+  if (ln.plans.find(make_key(r.cfg)) == ln.plans.end()) extra += r.need_tables;
+  if (ln.work_bytes < r.need_work) extra += r.need_work - ln.work_bytes;
   const size_t rs = r.cfg.prec == PW_FP32 ? 4 : 8;
   const size_t rec = (size_t)(r.gal.n + r.ran.n) * 4 * rs;
   if (ln.records_bytes < rec) extra += rec;
@@ -757,12 +825,25 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
       if (e < best_extra) { best = lp.get(); best_extra = e; }
     }
     if (!best) return {nullptr, nullptr};  // every lane busy
-    // make room: evict idle lanes' plans (lane 0's too while no pw_estimate runs), least
-    // recently used first
+    // make room: evict the workspaces of idle lanes other than `best` (lane 0's too while no
+    // pw_estimate runs), then idle lanes' cached plans, least recently used first
+    const bool main_idle = !ctx->main_busy;
     while (mem_used(ctx) + best_extra > ctx->budget) {
+      Lane *wl = nullptr;
+      uint64_t oldest = (uint64_t)-1;
+      for (auto &lp : ctx->lanes)
+        if (!lp->cur && lp.get() != best && lp->work && lp->used_stamp < oldest) {
+          oldest = lp->used_stamp;
+          wl = lp.get();
+        }
+      if (main_idle && ctx->main->work && ctx->main->used_stamp < oldest) wl = ctx->main.get();
+      if (wl) {
+        evict_work(ctx, *wl);
+        best_extra = lane_extra_bytes(*best, *r);
+        continue;
+      }
       Lane *vl = nullptr;
       const PlanKey *vk = nullptr;
-      uint64_t oldest = (uint64_t)-1;
       for (auto &lp : ctx->lanes) {
         if (lp->cur) continue;
         for (auto &kv : lp->plan_stamp) {
@@ -770,7 +851,7 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
           if (kv.second < oldest) { oldest = kv.second; vl = lp.get(); vk = &kv.first; }
         }
       }
-      if (!ctx->main_busy)
+      if (main_idle)
         for (auto &kv : ctx->main->plan_stamp)
           if (kv.second < oldest) { oldest = kv.second; vl = ctx->main.get(); vk = &kv.first; }
       if (!vl) break;
@@ -1123,20 +1204,12 @@ int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw
     r->out = out;
     r->bin_mean = bin_mean;
     r->counts = counts;
-    const PlanKey key = make_key(*cfg);
-    size_t pb = 0;
     {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      auto it = ctx->plan_bytes_cache.find(key);
-      if (it != ctx->plan_bytes_cache.end()) pb = it->second;
+      std::shared_ptr<const HostPlan> hp = host_plan(ctx, *cfg);
+      r->need_tables = table_bytes(*hp);
+      r->need_work = work_layout(*hp).total;
     }
-    if (!pb) {
-      pb = plan_bytes(*cfg);
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->plan_bytes_cache[key] = pb;
-    }
-    r->need = pb;
-    size_t whole = pb + catalog_bytes(*cfg, gal->n, ran->n);
+    size_t whole = r->need_tables + r->need_work + catalog_bytes(*cfg, gal->n, ran->n);
     if (whole > ctx->budget) fail(PW_ENOMEM, "request needs %zu bytes, budget is %zu", whole, ctx->budget);
     std::lock_guard<std::mutex> lk(ctx->mu);
     start_worker(ctx);

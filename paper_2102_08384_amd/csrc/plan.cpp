@@ -477,16 +477,44 @@ size_t spectrum_buffer_bytes(const HostPlan &h) {
   return std::max<size_t>(std::max(x1, std::max(x2, x3)), 16);
 }
 
+WorkLayout work_layout(const HostPlan &h) {
+  const size_t rsz = h.prec == PW_FP32 ? 4 : 8;
+  const int ts = tile_size(h.N), nt = h.N / ts;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  WorkLayout w;
+  size_t off = 0;
+  w.mesh = off;
+  off += up((size_t)h.N * h.N * h.N * rsz);
+  w.bufA = off;
+  off += up(spectrum_buffer_bytes(h));
+  w.bufB = off;
+  off += up(h.lean ? lean_x_bytes(h) : spectrum_buffer_bytes(h));
+  w.bufC = off;
+  if (h.lean) off += up(lean_y_bytes(h));
+  w.tiles = off;
+  off += up((size_t)nt * nt * nt * (ts + 2) * (ts + 2) * (ts + 2) * 8);
+  w.total = off;
+  return w;
+}
+
+size_t table_bytes(const HostPlan &h) {
+  const size_t rsz = h.prec == PW_FP32 ? 4 : 8;
+  const int ts = tile_size(h.N), nt = h.N / ts;
+  size_t b = (h.fwd.modecoord.size() + h.sph.modecoord.size() + h.bin_of_s2.size()) * 4 +
+             (h.fwd.pinfo.size() + h.sph.pinfo.size()) * sizeof(PencilInfo) +
+             (h.fwd.moff.size() + h.sph.moff.size() + h.fwd.goff.size() + h.sph.goff.size() + h.fwd.yoff.size() +
+              h.sph.yoff.size() + h.iyoff.size()) * 8 +
+             (h.fwd.ycnt.size() + h.sph.ycnt.size() + h.fwd.gsize.size() + h.sph.gsize.size() + h.zrank.size() +
+              h.zidx.size() + h.yidx.size() + h.iycnt.size()) * 4;
+  b += (h.t_start.size() + h.t_sh.size() + h.t_ell.size() + h.t_p1.size() + h.t_p2.size()) * 4 +
+       (h.t_coef.size() + h.winv.size() + h.icoef.size()) * rsz;
+  b += (size_t)nt * nt * nt * 16 + (size_t)h.N * h.N * 8 + (size_t)h.N * 8;  // tile sort, occupancy
+  return b + ((size_t)1 << 20);  // job lists, twiddles, result rows and scalars
+}
+
 size_t plan_bytes(const pw_config &c) {
   HostPlan h = build_host_plan(c);
-  const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
-  const int ts = tile_size(h.N), nt = h.N / ts;
-  size_t b = (size_t)h.N * h.N * h.N * rsz + 2 * spectrum_buffer_bytes(h);
-  if (h.lean) b = (size_t)h.N * h.N * h.N * rsz + spectrum_buffer_bytes(h) + lean_x_bytes(h) + lean_y_bytes(h);
-  b += h.fwd.modecoord.size() * 4 + h.sph.modecoord.size() * 4 + h.bin_of_s2.size() * 4 +
-       (h.fwd.pinfo.size() + h.sph.pinfo.size()) * 24;
-  b += (size_t)nt * nt * nt * ((ts + 2) * (ts + 2) * (ts + 2) * 8 + 16);
-  return b;
+  return table_bytes(h) + work_layout(h).total;
 }
 
 size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {

@@ -122,6 +122,17 @@ bool one_pass_orders(const pw_config &c);
 HostPlan build_host_plan(const pw_config &c);
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
 size_t plan_bytes(const pw_config &c);       // device bytes of one plan (tables + work buffers)
+
+// The work buffers of one estimate (the mesh, the spectrum buffers, the paint tiles) as byte
+// offsets into one workspace.  A lane runs one estimate at a time, so all plans cached on a
+// lane share one workspace of the largest size any of them needs.
+struct WorkLayout {
+  size_t mesh = 0, bufA = 0, bufB = 0, bufC = 0, tiles = 0;  // offsets (bufC: memory-lean only)
+  size_t total = 0;
+};
+WorkLayout work_layout(const HostPlan &h);
+// device bytes of a plan's own tables (everything but the workspace), an upper bound
+size_t table_bytes(const HostPlan &h);
 size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);  // records + staging
 // bytes of each of the two spectrum buffers (memory-lean: of the k-sphere buffer)
 size_t spectrum_buffer_bytes(const HostPlan &h);
@@ -140,7 +151,8 @@ struct DevPrune {
 };
 
 struct DevPlan {
-  std::unique_ptr<HostPlan> host;
+  std::shared_ptr<const HostPlan> host;  // shared with the context's host-plan cache
+  WorkLayout work;
   std::vector<std::pair<void *, size_t>> allocs;
   void *tw = nullptr;
   FieldJob *jobs = nullptr, *ijobs = nullptr, *ajobs = nullptr, *lean_jobs = nullptr;
