@@ -35,7 +35,7 @@ COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
 KERNEL_NAMES = {"fx": "k_fx", "fy": "k_fy", "fz": "k_fz", "contract": "k_contract_bis_reg"}
 # midpoint P_l: forward passes, product + inverse z pass, inverse y/x passes, re-weighting, the
 # forward passes of the A fields and the k-space contraction
-KERNEL_NAMES_MID = {"fx": "k_fx", "fy": "k_fy", "fz": "k_fz", "iz": "k_iz", "iy": "k_fy", "ix": "k_ix",
+KERNEL_NAMES_MID = {"fx": "k_fx", "fy": "k_fy", "fziz": "k_fziz", "iy": "k_fy", "ix": "k_ix", "ix_bin": "k_ix",
                     "reweight": "k_reweight", "afx": "k_fx", "afy": "k_fy", "afz": "k_fz",
                     "contract": "k_contract_mid"}
 
@@ -246,14 +246,11 @@ def stream_bench(a):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tickets, sub = [], []
-        for i, (lab, cfg, g, r, n) in enumerate(reqs):
-            while time.perf_counter() - t0 < arrivals[i]:
-                time.sleep(5e-5)
-            sub.append(time.perf_counter())
-            tickets.append(ctx.submit(cfg, g, r, ran_nbar=n))
         done = [None] * len(reqs)
         failed = []
-        while any(d is None for d in done):
+
+        def poll_all():
+            # completion times are taken while the later requests are still being submitted
             for i, t in enumerate(tickets):
                 if done[i] is None:
                     try:
@@ -262,6 +259,15 @@ def stream_bench(a):
                     except pw.PwError as e:
                         failed.append(f"{reqs[i][0]}: {e}")
                     done[i] = time.perf_counter()
+
+        for i, (lab, cfg, g, r, n) in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[i]:
+                poll_all()
+                time.sleep(5e-5)
+            sub.append(time.perf_counter())
+            tickets.append(ctx.submit(cfg, g, r, ran_nbar=n))
+        while any(d is None for d in done):
+            poll_all()
             time.sleep(1e-4)
         el = max(done) - t0
         lat = [(d - s_) * 1e3 for s_, d in zip(sub, done)]

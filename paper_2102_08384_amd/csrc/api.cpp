@@ -516,6 +516,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const double x2 = (double)h.nfields * N * F.npen_real * csz;
   const double x3 = (double)h.nfields * modes_real * csz;
   char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
+  const bool mid = h.path == PATH_MID_PK || h.path == PATH_MID_XI;
   if (h.lean) {
     // groups of fields through the x, y and z passes; the z pass writes each field's k-sphere
     // into A at its own index (fmap), so the contraction below sees the usual layout
@@ -539,10 +540,13 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     if (F.npen > 0)
       launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
                 dp->rowmask, dp->zlist, dp->norm);
-    mark("fz", x2 + x3);
-    if (F.npen > 0)
-      launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff, dp->fwd.gsize,
-                F.mstride, dp->tw, dp->planemask);
+    // (midpoint: the z pass is fused with the product and the inverse z pass below)
+    if (!mid) {
+      mark("fz", x2 + x3);
+      if (F.npen > 0)
+        launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff,
+                  dp->fwd.gsize, F.mstride, dp->tw, dp->planemask);
+    }
   }
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
   if (orders && (h.path != PATH_BIS_PK || h.n_orders_native == 0))
@@ -570,7 +574,8 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
       launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
     }
   } else {
-    // Spectra after fz: full pencil-major A[p][q * N + kz], q = ky * rs + kx.
+    // Full sets: pencil q = ky * rs + kx, N values each (bisector xi: the z-pass spectra in A,
+    // pencil-major [p][q * N + kz]; midpoint: the y-pass output in B, [p][z][q]).
     const double sfull = (double)N * N * F.nkx * csz;  // one full half spectrum (algorithmic)
     const size_t sfull_b = (size_t)N * F.npen * (size_t)csz;  // one full pencil-major spectrum
     const double inv_n3 = 1.0 / ncell;
@@ -579,27 +584,28 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     const double ypart = (double)h.n_inv * npl * h.ny * F.nkx * csz;
     const bool xi = h.path != PATH_MID_PK;
     if (xi) launch_fill(s, dp->acc, nacc, 1);
-    void *zin = A, *zout = B;
-    int real_in = 0;
+    void *zout;
+    const double sqrt4pi = std::sqrt(4.0 * 3.14159265358979323846);
     if (h.path == PATH_BIS_XI) {
-      // a8 (bisector): T_{l nu}(k) = sum S Re(conj R_p1 R_p2) / W^2 on every mode
+      // a8 (bisector): T_{l nu}(k) = sum S Re(conj R_p1 R_p2) / W^2 on every mode, then the
+      // inverse z pass of the real targets
       mark("targets", x3 + (double)h.n_targets * modes_real * rsz);
       launch_targets(s, h.prec, N, h.ell_max, h.order / 2, A, F.nmodes, F.rs, dp->winv, B);
-      zin = B;
       zout = A;
-      real_in = 1;
+      mark("iz", (double)h.n_targets * modes_real * rsz + zpart);
+      launch_iz(s, h.prec, N, B, zout, h.n_targets, 0, 1, F.npen, F.nkx, F.rs, nullptr, sqrt4pi, nullptr,
+                dp->zrank, npl, dp->tw);
+    } else {
+      // a4 z pass + a5: conj(D) Q / W^2 (D = sqrt(4 pi) Q_{0,0,0}) + inverse z pass, one kernel
+      // from the y-pass output (B): the alpha = 0 products of P_l stay in k-space at the front
+      // of A, the retained z planes of the others follow them
+      zout = A + (size_t)h.n_inplace * sfull_b;
+      mark("fziz", x2 + (double)h.n_inplace * sfull + zpart);
+      launch_fziz(s, h.prec, N, B, A, zout, h.nfields, h.n_inplace, F.npen, F.rs, sqrt4pi, dp->winv, dp->zrank,
+                  npl, dp->tw, dp->planemask);
     }
-    // a5: conj(D) Q / W^2 (midpoint) and the inverse z pass; D = sqrt(4 pi) Q_{0,0,0}
-    const int nzf = h.path == PATH_BIS_XI ? h.n_targets : h.nfields;
-    // bytes: the input spectra (+ D once), the in-place products and the retained z planes
-    mark("iz", (real_in ? (double)nzf * modes_real * rsz : (double)(nzf + 1) * sfull) +
-                   (double)h.n_inplace * sfull + zpart);
-    const double sqrt4pi = std::sqrt(4.0 * 3.14159265358979323846);
-    launch_iz(s, h.prec, N, zin, zout, nzf, h.n_inplace, real_in, F.npen, F.nkx, F.rs,
-              h.path == PATH_BIS_XI ? nullptr : A, sqrt4pi, h.path == PATH_BIS_XI ? nullptr : dp->winv,
-              dp->zrank, npl, dp->tw);
-    // inverse y pass into the other buffer (midpoint P: behind the alpha = 0 products)
-    void *yout = (zout == B) ? (void *)(A + (size_t)h.n_inplace * sfull_b) : (void *)B;
+    // inverse y pass of the retained z planes into B
+    void *yout = B;
     mark("iy", (double)h.n_inv * npl * N * F.nkx * csz + ypart);
     launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, F.rs, dp->iycnt, dp->iyoff,
               (int64_t)h.ny * F.rs, dp->tw, nullptr, nullptr, nullptr);
@@ -613,32 +619,32 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     } else {
       void *Aoff = A + (size_t)h.n_inplace * sfull_b;  // behind the alpha = 0 products
       if (h.n_inv > 0) {
-        // g fields in real space (B), then a6: A_{l nu} = sum Phi' y(D^) |D|^alpha g (into Aoff)
+        // g fields in real space (Aoff), then a6: A_{l nu} = sum Phi' y(D^) |D|^alpha g (into B)
         mark("ix", ypart + (double)h.n_inv * ncell * rsz);
-        launch_ix(s, h.prec, N, 0, yout, B, F.rs, dp->ijobs, (int)h.ijobs.size(), nullptr, h.nell, h.nz, h.ny,
+        launch_ix(s, h.prec, N, 0, yout, Aoff, F.rs, dp->ijobs, (int)h.ijobs.size(), nullptr, h.nell, h.nz, h.ny,
                   dp->zidx, dp->yidx, h.H, h.unit, inv_n3, nullptr, 0, 0, nullptr, dp->tw);
         mark("reweight", (double)(h.n_inv + h.n_a) * ncell * rsz);
-        launch_reweight(s, h.prec, N, h.ell_max, h.order, h.all_parity, B, Aoff, h.H / h.unit);
-        // forward transforms of A, pruned to the k-sphere of the bins
+        launch_reweight(s, h.prec, N, h.ell_max, h.order, h.all_parity, Aoff, B, h.H / h.unit);
+        // forward transforms of A, pruned to the k-sphere of the bins (ending in Aoff)
         const Prune &P = h.sph;
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
                      a3 = (double)h.n_a * P.nretained * csz;
         mark("afx", (double)h.n_a * ncell * rsz + a1);
-        launch_fx(s, h.prec, N, true, Aoff, B, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
+        launch_fx(s, h.prec, N, true, B, Aoff, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
                   h.unit, dp->tw, nullptr, nullptr);
         mark("afy", a1 + a2);
         if (P.npen > 0)
-          launch_fy(s, h.prec, N, 0, B, Aoff, h.n_a, N, P.nkx, P.rs, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw,
+          launch_fy(s, h.prec, N, 0, Aoff, B, h.n_a, N, P.nkx, P.rs, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw,
                     nullptr, nullptr, nullptr);
         mark("afz", a2 + a3);
         if (P.npen > 0)
-          launch_fz(s, h.prec, N, Aoff, B, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, dp->sph.goff, dp->sph.gsize,
+          launch_fz(s, h.prec, N, B, Aoff, h.n_a, P.npen, dp->sph.pinfo, dp->sph.moff, dp->sph.goff, dp->sph.gsize,
                     P.mstride, dp->tw, nullptr);
       }
       // a7 (midpoint): sum_nu y_l^nu(k^) Re[G_{l nu} + A_{l nu}] and FP64 k-binning
       mark("contract", (double)(h.n0 + h.n_a) * h.sph.nretained * csz + 4.0 * h.sph.nretained);
       launch_fill(s, dp->acc, nacc, 1);
-      launch_contract_mid(s, h.prec, h.ell_max, A, F.rs, h.n_a > 0 ? B : nullptr, h.sph.nmodes, h.sph.mstride,
+      launch_contract_mid(s, h.prec, h.ell_max, A, F.rs, h.n_a > 0 ? Aoff : nullptr, h.sph.nmodes, h.sph.mstride,
                           dp->sph.modecoord, N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->acc);
       mark("finalize", 0.0);
       launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
@@ -754,6 +760,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
       if (nm == "fx") ln.st_bytes[i] = fr * (N * N * N * rsz + x1);
       else if (nm == "fy") ln.st_bytes[i] = fr * x1 + fp * x2;
       else if (nm == "fz") ln.st_bytes[i] = fp * x2 + x3;
+      else if (nm == "fziz") ln.st_bytes[i] -= (1.0 - fp) * x2;  // reads the occupied planes only
       else if (nm == "forward") ln.st_bytes[i] = fr * (N * N * N * rsz + 2 * x1) + 2 * fp * x2 + x3;
     }
     ln.occ_rows = dn.nrows_occ;

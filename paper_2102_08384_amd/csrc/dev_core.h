@@ -194,6 +194,13 @@ __device__ __forceinline__ void fft_pencil_db(cplx<R> v[8], int t, const FftTw<R
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited on)
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Groups of fields per block (grid.y) for column passes, so that a launch has about 4096
+// blocks when the pencil dimension alone gives fewer.
+inline int field_groups(int nfields, int nblocks_other) {
+  int g = (8 * 512 + nblocks_other - 1) / (nblocks_other > 0 ? nblocks_other : 1);
+  return g < 1 ? 1 : (g > nfields ? nfields : g);
+}
+
 // Row-mode pencils (x passes): ROWS rows of N elements per block, T = N/8 lanes per row.
 template <int N> struct FxShape {
   static constexpr int T = N / 8;                          // lanes per pencil

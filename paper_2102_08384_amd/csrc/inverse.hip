@@ -1,8 +1,9 @@
 // HIP kernels of the inverse-transform paths (gfx950, wave64).
 //
-//   iz             inverse FFT along z of full pencil-major spectra, with the midpoint product
-//                  conj(D) Q / W^2 (Section 3.2, g fields) fused in front; output pruned to the
-//                  retained z planes
+//   iz             inverse FFT along z of full pencil-major spectra (bisector xi_l targets);
+//                  output pruned to the retained z planes
+//   fziz           midpoint g fields: forward FFT along z, the product conj(D) Q / W^2
+//                  (Section 3.2) and the inverse FFT along z in one pass over each pencil
 //   ix             complex-to-real inverse FFT along x of field pairs; either stores the real
 //                  fields or, for xi_l, weights them by |D|^alpha y_J^mu(D^) times the per-field
 //                  multipole coefficient and bins the sums into r-shells in FP64
@@ -138,6 +139,144 @@ void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields,
   } else {
     PW_DISPATCH_N(iz_launch, double, s, in, out, nfields, n_inplace, real_in, npen, nkx, rs, D, d_scale, winv,
                   zrank, nz, tw)
+  }
+}
+
+// ------------------------------------------------------------------------------ fziz
+// Midpoint g fields (Section 3.2): the forward z pass, the product conj(D) Q / W^2 and the
+// inverse z pass all act along one pencil (kx, ky), so one kernel does the three and the full
+// spectra never go through HBM.  Input: the y-pass output of full sets, [field][z][pencil q]
+// (q = ky * rs + kx, every pencil N long; pencils kx >= nkx are zero padding).  Field 0 is
+// Q_{0,0,0}; D = d_scale * its transform.  Fields p < n_inplace keep the product in k-space,
+// pencil-major at prod[p][q * N + kz]; the others go back to z and leave the retained planes
+// at out[p - n_inplace][zrank[z]][q].  A block owns C adjacent pencils and one group of fields
+// [p0, p1); it transforms field 0 first (every group does) and prefetches the next field's
+// loads across each transform.  conj(D) / W^2 waits in LDS (each lane its own 8 values), which
+// keeps the N = 512 FP32 form within 128 VGPRs.
+template <typename R, int N>
+__global__ void __launch_bounds__((ColShape<R, N>::THREADS))
+k_fziz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ prod, cplx<R> *__restrict__ out, int nfields,
+       int n_inplace, int fpb, int64_t npen, int rs, R d_scale, const R *__restrict__ winv,
+       const int *__restrict__ zrank, int nz, const cplx<R> *__restrict__ tw, const int *__restrict__ planemask) {
+  constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
+  constexpr int LOGN = log2i(N);
+  __shared__ cplx<R> lds[N * (C + 1)];
+  __shared__ cplx<R> dls[8 * NT];
+  __shared__ int msk[N];
+  __shared__ int zrk[N];
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t q0 = (int64_t)blockIdx.x * C;
+  const int64_t q = q0 + c;
+  const int p0 = blockIdx.y * fpb;
+  const int p1 = min(nfields, p0 + fpb);
+  if (p0 >= p1) return;  // uniform
+  FftTw<R, N> twr;
+  twr.load(t, tw);
+  for (int i = threadIdx.x; i < N; i += NT) {
+    msk[i] = planemask ? planemask[i] : 1;
+    zrk[i] = zrank ? zrank[i] : -1;
+  }
+  const bool has = q < npen;
+  R iwxy = (R)1;
+  if (winv && has) {
+    const int qky = (int)(q / rs), qkx = (int)(q - (int64_t)qky * rs);
+    iwxy = winv[qkx] * winv[qky];
+  }
+  wait_vmem();
+  __syncthreads();
+  auto load = [&](int p, cplx<R> *v) {
+    const cplx<R> *src = in + (size_t)p * N * npen;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int z = t + s * T;
+      v[s] = (has && msk[z]) ? src[(size_t)z * npen + q] : mk<R>(0, 0);
+    }
+  };
+  auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
+  auto sync = []() { __syncthreads(); };
+  cplx<R> nxt[8];
+  const int pf = p0 > 0 ? p0 : 1;  // first field after D's own
+  // field p's product (in v, kz = t + s T): stored in k-space, or transformed back to z
+  auto finish = [&](int p, cplx<R> *v) {
+    if (p < n_inplace) {
+      // stays in k-space: pencil-major, coalesced through LDS
+#pragma unroll
+      for (int s = 0; s < 8; ++s) at(t + s * T) = v[s];
+      __syncthreads();
+      cplx<R> *dst = prod + (size_t)p * npen * N + (size_t)q0 * N;
+      const int nval = (int)(((npen - q0) < C ? (npen - q0) : C) * N);
+      for (int e = threadIdx.x; e < nval; e += NT) {
+        const int cc = e >> LOGN, kz = e & (N - 1);
+        dst[e] = lds[kz * (C + 1) + cc];
+      }
+      __syncthreads();
+    } else {
+      fft_pencil<R, N, true>(v, t, twr, at, sync);
+      if (has) {
+        cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * npen;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int zr = zrk[t + s * T];
+          if (zr >= 0) dst[(size_t)zr * npen + q] = v[s];
+        }
+      }
+    }
+  };
+  // conj(D) / W^2 on every mode, D = d_scale Q_000~; field 0's own product is then
+  // d_scale |Q_000~|^2 / W^2
+  {
+    cplx<R> d[8], v[8];
+    load(0, d);
+    if (pf < p1) load(pf, nxt);
+    fft_pencil<R, N, false>(d, t, twr, at, sync);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const R iw = iwxy * (winv ? winv[t + s * T] : (R)1);
+      const R f = d_scale * iw * iw;
+      v[s] = mk<R>(f * (d[s].x * d[s].x + d[s].y * d[s].y), (R)0);
+      dls[s * NT + threadIdx.x] = mk<R>(d[s].x * f, -d[s].y * f);
+    }
+    if (p0 == 0) finish(0, v);
+  }
+  for (int p = pf; p < p1; ++p) {
+    cplx<R> v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = nxt[s];
+    if (p + 1 < p1) load(p + 1, nxt);
+    fft_pencil<R, N, false>(v, t, twr, at, sync);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = cmul(dls[s * NT + threadIdx.x], v[s]);
+    finish(p, v);
+  }
+}
+
+template <typename R, int N>
+static void fziz_launch(hipStream_t s, const void *in, void *prod, void *out, int nfields, int n_inplace,
+                        int64_t npen, int rs, double d_scale, const void *winv, const int *zrank, int nz,
+                        const void *tw, const int *planemask) {
+  constexpr int C = ColShape<R, N>::C;
+  const unsigned ng = (unsigned)((npen + C - 1) / C);
+  // field groups fill the chip on small meshes; each group transforms D again, so keep >= 8
+  // fields per group
+  int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
+  G = std::max(1, std::min(G, nfields / 8));
+  const int fpb = (nfields + G - 1) / G;
+  dim3 grid(ng, (nfields + fpb - 1) / fpb);
+  hipLaunchKernelGGL((k_fziz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
+                     (cplx<R> *)prod, (cplx<R> *)out, nfields, n_inplace, fpb, npen, rs, (R)d_scale,
+                     (const R *)winv, zrank, nz, (const cplx<R> *)tw, planemask);
+}
+
+void launch_fziz(hipStream_t s, int prec, int N, const void *in, void *prod, void *out, int nfields, int n_inplace,
+                 int64_t npen, int rs, double d_scale, const void *winv, const int *zrank, int nz, const void *tw,
+                 const int *planemask) {
+  if (nfields <= 0 || npen <= 0) return;
+  if (prec == 0) {
+    PW_DISPATCH_N(fziz_launch, float, s, in, prod, out, nfields, n_inplace, npen, rs, d_scale, winv, zrank, nz,
+                  tw, planemask)
+  } else {
+    PW_DISPATCH_N(fziz_launch, double, s, in, prod, out, nfields, n_inplace, npen, rs, d_scale, winv, zrank, nz,
+                  tw, planemask)
   }
 }
 

@@ -165,6 +165,13 @@ int mid_reweight_nfields(int lmax, int order, int all_parity);
 void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields, int n_inplace,
                int real_in, int64_t npen, int nkx, int rs, const void *D, double d_scale,
                const void *winv, const int *zrank, int nz, const void *tw);
+// Midpoint g fields: forward z pass of the y-pass output in[p][z][q] (full sets), the product
+// conj(D) Q / W^2 with D = d_scale * (field 0's transform), then either the product stays
+// pencil-major in prod[p][q * N + kz] (p < n_inplace) or the inverse z pass writes the
+// retained planes out[p - n_inplace][zrank[z]][q].  planemask: z planes with data (others zero).
+void launch_fziz(hipStream_t s, int prec, int N, const void *in, void *prod, void *out, int nfields, int n_inplace,
+                 int64_t npen, int rs, double d_scale, const void *winv, const int *zrank, int nz, const void *tw,
+                 const int *planemask);
 // Inverse x pass (complex-to-real) of pair jobs on the rows (zr, yr) of in[p][zr][yr * rs + kx],
 // kx <= N/2, scaled by `scale`.
 //   mode 0: out[p][z][y][x] real fields (nz = ny = N).

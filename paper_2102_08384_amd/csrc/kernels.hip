@@ -301,10 +301,6 @@ void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, voi
 // C pencils (z pass) and loops over a group of fields, issuing the global loads of the next
 // field before transforming the current one (barriers do not wait for global loads), so memory
 // latency hides behind the FFT.  Occupancy masks live in LDS, loaded once per block.
-inline int field_groups(int nfields, int nblocks_other) {
-  int g = (8 * 512 + nblocks_other - 1) / (nblocks_other > 0 ? nblocks_other : 1);
-  return g < 1 ? 1 : (g > nfields ? nfields : g);
-}
 
 // y pass: CC adjacent kx columns per block (CC * N/8 threads)
 template <typename R, int N, bool INV, int CC>

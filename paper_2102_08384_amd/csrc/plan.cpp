@@ -459,10 +459,14 @@ HostPlan build_host_plan(const pw_config &c) {
   }
   const size_t rsz = h.prec == PW_FP32 ? 4 : 8, csz = 2 * rsz;
   if (h.path == PATH_MID_PK && h.n_a > 0) {
-    const size_t sfull = (size_t)N * h.fwd.npen * csz;
-    if ((size_t)h.n_a * N * N * N * rsz > (size_t)h.n_inv * sfull ||
-        (size_t)h.n_a * N * N * h.sph.rs * csz > spectrum_buffer_bytes(h) ||
-        (size_t)h.n_a * h.sph.mstride * csz > spectrum_buffer_bytes(h))
+    // buffer A: the alpha = 0 products, then a region (avail) that holds in turn the retained z
+    // planes, the real g fields and the A fields' x-pass and z-pass outputs; B holds the y-pass
+    // outputs and the re-weighted A fields in real space
+    const size_t sfull = (size_t)N * h.fwd.npen * csz, sb = spectrum_buffer_bytes(h);
+    const size_t front = (size_t)h.n_inplace * sfull, avail = sb > front ? sb - front : 0;
+    if ((size_t)h.n_inv * h.nz * h.fwd.npen * csz > avail || (size_t)h.n_inv * N * N * N * rsz > avail ||
+        (size_t)h.n_a * N * N * N * rsz > sb || (size_t)h.n_a * N * N * h.sph.rs * csz > avail ||
+        (size_t)h.n_a * h.sph.mstride * csz > avail)
       plan_fail(PW_EINVAL, "internal: A fields do not fit the spectrum buffer");
   }
   return h;

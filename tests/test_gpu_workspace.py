@@ -28,12 +28,18 @@ def _case(N, los, seed, prec=pw.PW_FP64):
     return cfg, gx, rx, ran["nbar"].astype(dt)
 
 
+def _buffer(ctx, cfg):
+    """What the estimate left in the workspace: the k-sphere spectra (bisector P_l) or the mesh."""
+    what = 1 if cfg.los == pw.PW_BISECTOR else 0
+    return ctx.inspect(what, np.float64 if cfg.prec == pw.PW_FP64 else np.float32).copy()
+
+
 def _fresh(case):
     cfg, gx, rx, nb = case
     with pw.Context(0) as c:
         res = c.estimate(cfg, gx, rx, ran_nbar=nb)
-        sph = c.inspect(1, np.float64 if cfg.prec == pw.PW_FP64 else np.float32).copy()
-    return res, sph
+        buf = _buffer(c, cfg)
+    return res, buf
 
 
 def test_workspace_grows_under_cached_plans():
@@ -47,11 +53,10 @@ def test_workspace_grows_under_cached_plans():
         for case in (small, large, small, large, small):
             cfg, gx, rx, nb = case
             res = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
-            want, sph = ref[id(case)]
+            want, buf = ref[id(case)]
             assert _close(res["values"], want["values"])
             assert np.array_equal(res["counts"], want["counts"])
-            # the k-sphere spectra this estimate left in the workspace
-            assert np.array_equal(ctx.inspect(1, np.float64), sph)
+            assert np.array_equal(_buffer(ctx, cfg), buf)
 
 
 def test_workspace_budget_holds_tables_of_both():
