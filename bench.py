@@ -91,11 +91,13 @@ def cpu_baseline(name, frac=0.25, n_mesh=96):
 
 
 def source_digest():
-    """Digest of the kernel sources; counter-based traffic is reported only for this digest."""
+    """Digest of the sources of every kernel the bisector P_l workload runs and of their launch
+    code (all of csrc/ but inverse.hip, which holds only the inverse-transform and midpoint
+    kernels); counter-based traffic is reported only for this digest."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2102_08384_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
+        if f.endswith((".hip", ".h", ".cpp")) and f != "inverse.hip":
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
