@@ -101,6 +101,7 @@ struct Req {
   double *out = nullptr, *bin_mean = nullptr;
   int64_t *counts = nullptr;
   size_t need_tables = 0, need_work = 0;  // device bytes of cfg's plan tables and workspace
+  size_t reserved = 0;  // bytes promised to this request's launch (pw_ctx::reserved)
   int status = PW_EAGAIN;
   std::string err;
   DevPlan *dp = nullptr;
@@ -136,6 +137,29 @@ struct pw_ctx {
   // lane 0 in use by a pw_estimate / pw_inspect call: the admission of served requests may
   // evict lane 0's cached plans only while this is false
   bool main_busy = false;
+  // device bytes promised to launches that allocate outside `mu` (lane 0's, or a serving
+  // lane's just admitted), so that two launches do not count the same free bytes
+  size_t reserved = 0;
+};
+
+// A promise of device bytes to one launch (pw_ctx::reserved), kept until its allocations are
+// made or it fails.
+struct Reservation {
+  pw_ctx *ctx;
+  size_t bytes = 0;
+  explicit Reservation(pw_ctx *c) : ctx(c) {}
+  Reservation(const Reservation &) = delete;
+  Reservation &operator=(const Reservation &) = delete;
+  ~Reservation() { release(); }
+  void release() {
+    if (!bytes) return;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->reserved -= bytes;
+      bytes = 0;
+    }
+    ctx->cv.notify_all();
+  }
 };
 
 // Marks lane 0 busy for the scope (guarded by ctx->mu); wakes the serving worker when done.
@@ -695,7 +719,8 @@ void finish_estimate(Lane &ln, const DevPlan *dp, pw_norm *norm, double *out, do
 // Make room on lane 0 for cfg's plan tables, workspace and catalogs by evicting idle serving
 // lanes' workspaces, then cached plans (lane 0's other ones, idle serving lanes'), least
 // recently used first.
-void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran) {
+void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                    Reservation &res) {
   Lane &ln = *ctx->main;
   const PlanKey key = make_key(*cfg);
   std::shared_ptr<const HostPlan> hp = host_plan(ctx, *cfg);
@@ -707,7 +732,7 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
   };
   if (need() == 0) return;
   const size_t cat = catalog_bytes(*cfg, gal->n, ran->n);
-  while (mem_used(ctx) + need() + cat > ctx->budget) {
+  while (mem_used(ctx) + ctx->reserved + need() + cat > ctx->budget) {
     Lane *wl = nullptr;
     uint64_t oldest = (uint64_t)-1;
     for (auto &lp : ctx->lanes)
@@ -728,15 +753,19 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
     if (!vl) break;
     evict_plan(ctx, *vl, vk);
   }
+  res.bytes = need() + cat;  // (if it does not fit, the allocation fails with PW_ENOMEM)
+  ctx->reserved += res.bytes;
 }
 
 void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
                   pw_norm *norm, double *out, double *bin_mean, int64_t *counts, bool orders = false) {
   check_request(cfg, gal, ran, norm, out);
   MainBusy busy(ctx);
-  make_room_main(ctx, cfg, gal, ran);
+  Reservation res(ctx);
+  make_room_main(ctx, cfg, gal, ran, res);
   Lane &ln = *ctx->main;
   DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm, orders);
+  res.release();
   HIPCHECK(hipEventSynchronize(ln.done));
   for (int i = 0; i < ln.n_stages; ++i) {
     float ms = -1.0f;
@@ -835,7 +864,7 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
     // make room: evict the workspaces of idle lanes other than `best` (lane 0's too while no
     // pw_estimate runs), then idle lanes' cached plans, least recently used first
     const bool main_idle = !ctx->main_busy;
-    while (mem_used(ctx) + best_extra > ctx->budget) {
+    while (mem_used(ctx) + ctx->reserved + best_extra > ctx->budget) {
       Lane *wl = nullptr;
       uint64_t oldest = (uint64_t)-1;
       for (auto &lp : ctx->lanes)
@@ -866,8 +895,10 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
       evict_plan(ctx, *vl, k);
       best_extra = lane_extra_bytes(*best, *r);
     }
-    if (mem_used(ctx) + best_extra <= ctx->budget) {
+    if (mem_used(ctx) + ctx->reserved + best_extra <= ctx->budget) {
       ctx->pending.erase(it);
+      r->reserved = best_extra;  // released once the launch has made its allocations
+      ctx->reserved += best_extra;
       return {r, best};
     }
     bool running = ctx->main_busy;  // lane 0 may still release memory
@@ -933,6 +964,8 @@ void worker_loop(pw_ctx *ctx) {
         msg = e.what();
       }
       lk.lock();
+      ctx->reserved -= r->reserved;
+      r->reserved = 0;
       if (code != PW_OK) {
         r->status = code;
         r->err = msg;
