@@ -176,9 +176,11 @@ int pw_estimate_xi_normalized(pw_ctx *ctx, const pw_config *cfg, const pw_catalo
 
 /* Serving.  pw_submit validates a request, enqueues it and returns a ticket at once; a
  * worker thread of the context admits pending requests in arrival order as soon as one of the
- * context's serving lanes is free and the request's device memory fits the HBM budget (plans
- * and work buffers of idle lanes are evicted, least recently used first, to make room; a
- * plan stays resident on its lane for later requests of the same configuration).  Each lane
+ * context's serving lanes is free and the request's device memory fits the HBM budget (the
+ * workspaces, then the cached plans of idle lanes are evicted, least recently used first, to
+ * make room).  A plan (tables only) stays resident on its lane for later requests of the same
+ * configuration; all plans of a lane share one workspace (mesh and spectrum buffers) that
+ * grows to the largest of them.  Host-side plans are cached per context.  Each lane
  * has its own HIP stream, so admitted requests of any size, mesh and estimator run
  * concurrently on the device.  The inputs and output buffers must stay valid until the ticket
  * completes or is cancelled; outputs are written when the request finishes.
