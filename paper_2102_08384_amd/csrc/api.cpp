@@ -66,7 +66,6 @@ struct Lane {
   bool own_stream = false;
   std::map<PlanKey, std::unique_ptr<DevPlan>> plans;
   std::map<PlanKey, uint64_t> plan_stamp;  // last use (LRU eviction)
-  std::map<PlanKey, size_t> plan_bytes;
   void *stage[2] = {nullptr, nullptr};
   size_t stage_bytes[2] = {0, 0};
   void *stage_nbar = nullptr;
@@ -396,19 +395,11 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
   return dp;
 }
 
-size_t plan_alloc_bytes(const DevPlan *dp) {
-  size_t b = 0;
-  for (auto &a : dp->allocs) b += a.second;
-  return b;
-}
-
 DevPlan *get_plan(pw_ctx *ctx, Lane &ln, const pw_config *cfg) {
   PlanKey key = make_key(*cfg);
   auto it = ln.plans.find(key);
   if (it == ln.plans.end()) {
-    std::unique_ptr<DevPlan> dp = build_dev_plan(ctx, cfg);
-    ln.plan_bytes[key] = plan_alloc_bytes(dp.get());
-    it = ln.plans.emplace(key, std::move(dp)).first;
+    it = ln.plans.emplace(key, build_dev_plan(ctx, cfg)).first;
   }
   ln.plan_stamp[key] = ln.used_stamp = ++ctx->stamp;
   return it->second.get();
@@ -443,7 +434,6 @@ void evict_plan(pw_ctx *ctx, Lane &ln, const PlanKey &key) {
   free_plan(ctx, it->second.get());
   ln.plans.erase(it);
   ln.plan_stamp.erase(key);
-  ln.plan_bytes.erase(key);
 }
 
 const void *stage_catalog(pw_ctx *ctx, Lane &ln, const pw_catalog *c, int slot, const void **nbar_out) {
