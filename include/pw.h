@@ -174,7 +174,9 @@ int pw_estimate_xi_normalized(pw_ctx *ctx, const pw_config *cfg, const pw_catalo
                               const pw_catalog *ran, pw_norm *norm, double *xi_rr, double *xi_edge,
                               double *window, int *n_window, double *bin_mean, int64_t *counts);
 
-/* Serving.  pw_submit validates a request, enqueues it and returns a ticket at once; a
+/* Serving.  pw_submit validates a request, enqueues it and returns a ticket at once (the
+ * first request of a configuration on a context also builds its host plan on the calling
+ * thread: tens of ms, about 0.3 s for a midpoint plan at 512^3); a
  * worker thread of the context admits pending requests in arrival order as soon as one of the
  * context's serving lanes is free and the request's device memory fits the HBM budget (the
  * workspaces, then the cached plans of idle lanes are evicted, least recently used first, to
