@@ -400,6 +400,8 @@ def main():
         "roofline": roofline,
         "stages": stages,
         "monopole_first_bins": res["values"][0][:3].tolist(),
+        # launch shapes the autotuner picked during the warm-up (candidate 0 = default shape)
+        "autotune": pw.tune_entries(),
     }
     ctx.close()
     if a.workload != "C3":

@@ -227,6 +227,21 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
 int pw_set_timing(pw_ctx *ctx, int on);
 int pw_stage_info(pw_ctx *ctx, int stage, const char **name, double *ms, double *bytes);
 
+/* Autotuning of the column passes (the forward y and z passes, the midpoint's fused z pass,
+ * the inverse y pass).  Each has a few launch shapes (fields per workgroup, columns per
+ * workgroup) that compute the same values at different speeds; candidate 0 is the default.
+ * mode 1 (the default): the first launch of each shape key in the process times every
+ * candidate twice on the estimate's own data (the estimate synchronises its stream once for
+ * this) and keeps the fastest for the rest of the process; the environment variable
+ * PW_TUNE=0 turns the timing off, and PW_TUNE_CACHE=<file> stores and reloads the choices.
+ * mode 0: default shapes; mode 2 + i: candidate i wherever it exists (default elsewhere), for
+ * tests and benchmarks.  PW_EINVAL for other modes. */
+int pw_set_tuning(pw_ctx *ctx, int mode);
+/* Entry `index` (0, 1, ..) of the process's tuning table: the shape key (NUL-terminated,
+ * truncated to key_len), the chosen candidate, its time and the default's in milliseconds (-1
+ * when loaded from PW_TUNE_CACHE).  Any output pointer may be NULL.  PW_EINVAL past the end. */
+int pw_tune_entry(int index, char *key, size_t key_len, int *choice, double *ms_best, double *ms_default);
+
 /* Message of the last error on this context (thread-unsafe, valid until the next call). */
 const char *pw_last_error(const pw_ctx *ctx);
 

@@ -15,9 +15,12 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdarg>
+#include <cfloat>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -79,6 +82,7 @@ struct Lane {
   int res_rows = 0;            // multipole rows of the result in flight (n_ell, or per order)
   size_t host_res_bytes = 0;
   hipEvent_t done = nullptr;
+  hipEvent_t tev[2] = {nullptr, nullptr};  // autotuning: around one candidate launch
   DevPlan *last = nullptr;
   // stage timing (lane 0)
   bool timing = false;
@@ -136,6 +140,8 @@ struct pw_ctx {
   // lane 0 in use by a pw_estimate / pw_inspect call: the admission of served requests may
   // evict lane 0's cached plans only while this is false
   bool main_busy = false;
+  // launch shapes of the column passes: 1 = autotuned, 0 = defaults, 2 + i = candidate i
+  int tune_mode = 1;
   // device bytes promised to launches that allocate outside `mu` (lane 0's, or a serving
   // lane's just admitted), so that two launches do not count the same free bytes
   size_t reserved = 0;
@@ -473,6 +479,123 @@ void check_request(const pw_config *cfg, const pw_catalog *gal, const pw_catalog
     fail(PW_EINVAL, "random catalog needs nbar when the normalisation is not given");
 }
 
+// ------------------------------------------------------------------------------ autotuner
+// Launch shapes (ColTune) of the column passes are picked per shape key, once per process: on
+// the first launch of a key, every candidate runs twice on the lane's stream, on the estimate's
+// own data, timed with events, and the fastest is kept.  Each candidate reads one buffer and
+// writes another, so a repeat recomputes the same output and the estimate goes on from there.
+// Candidate 0 is the default shape.  PW_TUNE=0 in the environment turns the timing off (the
+// defaults are used); PW_TUNE_CACHE names a file of "key choice" lines read at first use and
+// appended to with each new choice.
+struct TuneEntry {
+  std::string key;
+  int choice;
+  double ms_best, ms_default;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;          // in the order the keys were settled
+std::map<std::string, size_t> g_tune_at;  // key -> index into g_tune
+bool g_tune_loaded = false;
+
+bool tune_env_on() {
+  const char *e = std::getenv("PW_TUNE");
+  return !(e && e[0] == '0' && e[1] == 0);
+}
+
+// Called with g_tune_mu held.
+void tune_load_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = std::getenv("PW_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  std::string key;
+  int choice;
+  while (f >> key >> choice) {
+    if (choice < 0 || g_tune_at.count(key)) continue;
+    g_tune_at[key] = g_tune.size();
+    g_tune.push_back(TuneEntry{key, choice, -1.0, -1.0});
+  }
+}
+
+int tune_lookup(const std::string &key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_cache();
+  auto it = g_tune_at.find(key);
+  return it == g_tune_at.end() ? -1 : g_tune[it->second].choice;
+}
+
+void tune_store(const std::string &key, int choice, double ms_best, double ms_default) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune_at.count(key)) return;  // another lane settled it first
+  g_tune_at[key] = g_tune.size();
+  g_tune.push_back(TuneEntry{key, choice, ms_best, ms_default});
+  const char *path = std::getenv("PW_TUNE_CACHE");
+  if (path && *path) {
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << choice << "\n";
+  }
+}
+
+template <typename Run>
+void tuned_launch(pw_ctx *ctx, Lane &ln, const std::string &key, const std::vector<ColTune> &cands, Run run) {
+  const int mode = ctx->tune_mode;
+  if (mode == 0 || cands.size() < 2) return run(cands[0]);
+  if (mode >= 2) return run(cands[(size_t)(mode - 2) < cands.size() ? (size_t)(mode - 2) : 0]);
+  const int known = tune_lookup(key);
+  if (known >= 0 && known < (int)cands.size()) return run(cands[(size_t)known]);
+  if (!tune_env_on()) return run(cands[0]);
+  std::vector<float> ms(cands.size(), FLT_MAX);
+  for (int rep = 0; rep < 2; ++rep)
+    for (size_t i = 0; i < cands.size(); ++i) {
+      HIPCHECK(hipEventRecord(ln.tev[0], ln.stream));
+      run(cands[i]);
+      HIPCHECK(hipEventRecord(ln.tev[1], ln.stream));
+      HIPCHECK(hipEventSynchronize(ln.tev[1]));
+      float t = 0.0f;
+      HIPCHECK(hipEventElapsedTime(&t, ln.tev[0], ln.tev[1]));
+      ms[i] = std::min(ms[i], t);
+    }
+  const size_t best = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+  tune_store(key, (int)best, ms[best], ms[0]);
+}
+
+std::string tune_key(const char *pass, const HostPlan &h, int nfields, int64_t a, int64_t b) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s:p%d:N%d:f%d:a%lld:b%lld", pass, h.prec, h.N, nfields, (long long)a,
+                (long long)b);
+  return buf;
+}
+
+// Candidates: the default, then other field groupings (and half-segment columns for the y pass
+// in FP32).
+std::vector<ColTune> fy_candidates(int prec, int nfields) {
+  std::vector<ColTune> c(1);
+  for (int f : {1, 4}) {
+    if (f >= nfields) continue;
+    ColTune t;
+    t.fpb = f;
+    c.push_back(t);
+  }
+  if (prec == PW_FP32) {
+    ColTune t;
+    t.cols = 8;
+    c.push_back(t);
+  }
+  return c;
+}
+
+std::vector<ColTune> fz_candidates(int nfields) {
+  std::vector<ColTune> c(1);
+  for (int f : {nfields, (nfields + 1) / 2, (nfields + 3) / 4}) {
+    if (f < 1 || (c.size() > 1 && c.back().fpb == f)) continue;
+    ColTune t;
+    t.fpb = f;
+    c.push_back(t);
+  }
+  return c;
+}
+
 // Enqueue the whole estimate on the lane's stream, ending with the copy of the results into
 // the lane's pinned buffer and the lane's completion event.  Returns the plan used.
 DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_catalog *gal,
@@ -552,14 +675,20 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
               h.unit, dp->tw, dp->rowlist, dp->norm);
     mark("fy", x1 + x2);
     if (F.npen > 0)
-      launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
-                dp->rowmask, dp->zlist, dp->norm);
+      tuned_launch(ctx, ln, tune_key("fy", h, h.nfields, F.nkx, F.npen), fy_candidates(h.prec, h.nfields),
+                   [&](ColTune t) {
+                     launch_fy(s, h.prec, N, 0, A, B, h.nfields, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff,
+                               F.npen, dp->tw, dp->rowmask, dp->zlist, dp->norm, t);
+                   });
     // (midpoint: the z pass is fused with the product and the inverse z pass below)
     if (!mid) {
       mark("fz", x2 + x3);
       if (F.npen > 0)
-        launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff,
-                  dp->fwd.gsize, F.mstride, dp->tw, dp->planemask);
+        tuned_launch(ctx, ln, tune_key("fz", h, h.nfields, F.npen, F.goff.empty() ? 0 : 1),
+                     fz_candidates(h.nfields), [&](ColTune t) {
+                       launch_fz(s, h.prec, N, B, A, h.nfields, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff,
+                                 dp->fwd.gsize, F.mstride, dp->tw, dp->planemask, nullptr, t);
+                     });
     }
   }
   const int64_t n_s2 = (int64_t)h.bin_of_s2.size();
@@ -615,14 +744,19 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
       // of A, the retained z planes of the others follow them
       zout = A + (size_t)h.n_inplace * sfull_b;
       mark("fziz", x2 + (double)h.n_inplace * sfull + zpart);
-      launch_fziz(s, h.prec, N, B, A, zout, h.nfields, h.n_inplace, F.npen, F.rs, sqrt4pi, dp->winv, dp->zrank,
-                  npl, dp->tw, dp->planemask);
+      tuned_launch(ctx, ln, tune_key("fziz", h, h.nfields, h.n_inplace, npl), fz_candidates(h.nfields),
+                   [&](ColTune t) {
+                     launch_fziz(s, h.prec, N, B, A, zout, h.nfields, h.n_inplace, F.npen, F.rs, sqrt4pi, dp->winv,
+                                 dp->zrank, npl, dp->tw, dp->planemask, t);
+                   });
     }
     // inverse y pass of the retained z planes into B
     void *yout = B;
     mark("iy", (double)h.n_inv * npl * N * F.nkx * csz + ypart);
-    launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, F.rs, dp->iycnt, dp->iyoff,
-              (int64_t)h.ny * F.rs, dp->tw, nullptr, nullptr, nullptr);
+    tuned_launch(ctx, ln, tune_key("iy", h, h.n_inv, npl, h.ny), fy_candidates(h.prec, h.n_inv), [&](ColTune t) {
+      launch_fy(s, h.prec, N, 1, zout, yout, h.n_inv, npl, F.nkx, F.rs, dp->iycnt, dp->iyoff,
+                (int64_t)h.ny * F.rs, dp->tw, nullptr, nullptr, nullptr, t);
+    });
     if (xi) {
       // a8: c2r along x fused with the |D|^alpha y(D^) weighting and FP64 r-binning
       mark("ix_bin", ypart);
@@ -798,6 +932,7 @@ Lane *make_lane(int id, hipStream_t user_stream) {
     ln->own_stream = true;
   }
   HIPCHECK(hipEventCreateWithFlags(&ln->done, hipEventDisableTiming));
+  for (int i = 0; i < 2; ++i) HIPCHECK(hipEventCreate(&ln->tev[i]));
   if (id == 0)
     for (int i = 0; i <= kMaxStages; ++i) HIPCHECK(hipEventCreate(&ln->ev[i]));
   return ln.release();
@@ -816,6 +951,8 @@ void destroy_lane(pw_ctx *ctx, Lane *ln) {
   for (int i = 0; i <= kMaxStages; ++i)
     if (ln->ev[i]) (void)hipEventDestroy(ln->ev[i]);
   if (ln->done) (void)hipEventDestroy(ln->done);
+  for (int i = 0; i < 2; ++i)
+    if (ln->tev[i]) (void)hipEventDestroy(ln->tev[i]);
   if (ln->own_stream && ln->stream) (void)hipStreamDestroy(ln->stream);
 }
 
@@ -1355,6 +1492,28 @@ int pw_coupling_table(int kind, int ell_max, int order, int alpha, double *rows,
 int pw_set_timing(pw_ctx *ctx, int on) {
   if (!ctx) return PW_EINVAL;
   ctx->main->timing = on != 0;
+  return PW_OK;
+}
+
+int pw_set_tuning(pw_ctx *ctx, int mode) {
+  if (!ctx || mode < 0) return PW_EINVAL;
+  ctx->tune_mode = mode;
+  return PW_OK;
+}
+
+int pw_tune_entry(int index, char *key, size_t key_len, int *choice, double *ms_best, double *ms_default) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_cache();
+  if (index < 0 || (size_t)index >= g_tune.size()) return PW_EINVAL;
+  const TuneEntry &e = g_tune[(size_t)index];
+  if (key && key_len > 0) {
+    const size_t n = std::min(key_len - 1, e.key.size());
+    std::memcpy(key, e.key.data(), n);
+    key[n] = 0;
+  }
+  if (choice) *choice = e.choice;
+  if (ms_best) *ms_best = e.ms_best;
+  if (ms_default) *ms_default = e.ms_default;
   return PW_OK;
 }
 

@@ -253,14 +253,18 @@ k_fziz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ prod, cplx<R> *__re
 template <typename R, int N>
 static void fziz_launch(hipStream_t s, const void *in, void *prod, void *out, int nfields, int n_inplace,
                         int64_t npen, int rs, double d_scale, const void *winv, const int *zrank, int nz,
-                        const void *tw, const int *planemask) {
+                        const void *tw, const int *planemask, ColTune tune) {
   constexpr int C = ColShape<R, N>::C;
   const unsigned ng = (unsigned)((npen + C - 1) / C);
-  // field groups fill the chip on small meshes; each group transforms D again, so keep >= 8
-  // fields per group
-  int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
-  G = std::max(1, std::min(G, nfields / 8));
-  const int fpb = (nfields + G - 1) / G;
+  int fpb = tune.fpb;
+  if (fpb <= 0) {
+    // field groups fill the chip on small meshes; each group transforms D again, so keep >= 8
+    // fields per group
+    int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
+    G = std::max(1, std::min(G, nfields / 8));
+    fpb = (nfields + G - 1) / G;
+  }
+  fpb = std::min(fpb, nfields);
   dim3 grid(ng, (nfields + fpb - 1) / fpb);
   hipLaunchKernelGGL((k_fziz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
                      (cplx<R> *)prod, (cplx<R> *)out, nfields, n_inplace, fpb, npen, rs, (R)d_scale,
@@ -269,14 +273,14 @@ static void fziz_launch(hipStream_t s, const void *in, void *prod, void *out, in
 
 void launch_fziz(hipStream_t s, int prec, int N, const void *in, void *prod, void *out, int nfields, int n_inplace,
                  int64_t npen, int rs, double d_scale, const void *winv, const int *zrank, int nz, const void *tw,
-                 const int *planemask) {
+                 const int *planemask, ColTune tune) {
   if (nfields <= 0 || npen <= 0) return;
   if (prec == 0) {
     PW_DISPATCH_N(fziz_launch, float, s, in, prod, out, nfields, n_inplace, npen, rs, d_scale, winv, zrank, nz,
-                  tw, planemask)
+                  tw, planemask, tune)
   } else {
     PW_DISPATCH_N(fziz_launch, double, s, in, prod, out, nfields, n_inplace, npen, rs, d_scale, winv, zrank, nz,
-                  tw, planemask)
+                  tw, planemask, tune)
   }
 }
 

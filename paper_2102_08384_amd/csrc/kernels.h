@@ -99,6 +99,15 @@ inline int row_stride(int nkx, int prec) {
 void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                const int *rowlist, const DevNorm *norm);
+// Launch shape of a column pass, as picked by the autotuner: fields per workgroup (fpb; 0 = the
+// default, which aims at about 4096 workgroups per launch) and, for the y pass, adjacent
+// columns per workgroup (cols: 0 = one 128-byte row segment, 8 = half of one in FP32).  Every
+// shape computes the same values; only the speed differs.
+struct ColTune {
+  int fpb = 0;
+  int cols = 0;
+};
+
 // c2c along y (forward, or inverse when inv), on nplanes planes per field:
 // in[p][plane][y * rs + kx] -> out[p][plane][yoff[y'] + kx] for kx < ycnt[y'] (y' the output
 // index, npen values per output plane).
@@ -107,7 +116,8 @@ void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, voi
 // input rows are read as zeros.
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields,
                int nplanes, int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen,
-               const void *tw, const int *rowmask, const int *zlist, const DevNorm *norm);
+               const void *tw, const int *rowmask, const int *zlist, const DevNorm *norm,
+               ColTune tune = ColTune());
 // c2c along z.  Full sets (goff null): out[p][moff[q] + kz], all N kz of every pencil.
 // Sphere-pruned sets: out[p][goff[g] + slot * C + c] for pencil q = g C + c, slot as in Prune
 // (C = 128 bytes / complex size, the pencils per workgroup).  Field stride mstride.
@@ -116,7 +126,7 @@ void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *ou
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
                int64_t npen, const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff,
                const int *gsize, int64_t mstride, const void *tw, const int *planemask,
-               const int *fmap = nullptr);
+               const int *fmap = nullptr, ColTune tune = ColTune());
 
 // Bisector contraction + FP64 k-binning.
 struct TermTable {
@@ -171,7 +181,7 @@ void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields,
 // retained planes out[p - n_inplace][zrank[z]][q].  planemask: z planes with data (others zero).
 void launch_fziz(hipStream_t s, int prec, int N, const void *in, void *prod, void *out, int nfields, int n_inplace,
                  int64_t npen, int rs, double d_scale, const void *winv, const int *zrank, int nz, const void *tw,
-                 const int *planemask);
+                 const int *planemask, ColTune tune = ColTune());
 // Inverse x pass (complex-to-real) of pair jobs on the rows (zr, yr) of in[p][zr][yr * rs + kx],
 // kx <= N/2, scaled by `scale`.
 //   mode 0: out[p][z][y][x] real fields (nz = ny = N).

@@ -371,31 +371,47 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 template <typename R, int N>
 static void fy_launch(hipStream_t s, int inv, const void *in, void *out, int nfields, int nplanes, int nkx,
                       int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
-                      const int *rowmask, const int *zlist, const DevNorm *norm) {
-  constexpr int CY = ColShape<R, N>::C;  // 128-byte row segments (8 columns measured 30% slower)
-  const int G = field_groups(nfields, nplanes);
-  const int fpb = (nfields + G - 1) / G;
+                      const int *rowmask, const int *zlist, const DevNorm *norm, ColTune tune) {
+  constexpr int CY = ColShape<R, N>::C;  // 128-byte row segments
+  int fpb = tune.fpb;
+  if (fpb <= 0) {
+    const int G = field_groups(nfields, nplanes);
+    fpb = (nfields + G - 1) / G;
+  }
+  fpb = std::min(fpb, nfields);
   dim3 grid(nplanes, (nfields + fpb - 1) / fpb);
-  if (inv)
-    hipLaunchKernelGGL((k_fy<R, N, true, CY>), grid, dim3(CY * (N / 8)), 0, s, (const cplx<R> *)in,
-                       (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw,
-                       rowmask, zlist, norm);
-  else
-    hipLaunchKernelGGL((k_fy<R, N, false, CY>), grid, dim3(CY * (N / 8)), 0, s, (const cplx<R> *)in,
-                       (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen, (const cplx<R> *)tw,
-                       rowmask, zlist, norm);
+#define PW_FY(CC)                                                                                  \
+  do {                                                                                             \
+    if (inv)                                                                                       \
+      hipLaunchKernelGGL((k_fy<R, N, true, CC>), grid, dim3((CC) * (N / 8)), 0, s, (const cplx<R> *)in, \
+                         (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen,          \
+                         (const cplx<R> *)tw, rowmask, zlist, norm);                                \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_fy<R, N, false, CC>), grid, dim3((CC) * (N / 8)), 0, s, (const cplx<R> *)in, \
+                         (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen,          \
+                         (const cplx<R> *)tw, rowmask, zlist, norm);                                \
+  } while (0)
+  // half-segment columns (8 per workgroup) only where a full segment holds 16 (FP32)
+  if constexpr (CY == 16) {
+    if (tune.cols == 8) {
+      PW_FY(8);
+      return;
+    }
+  }
+  PW_FY(CY);
+#undef PW_FY
 }
 
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields, int nplanes,
                int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
-               const int *rowmask, const int *zlist, const DevNorm *norm) {
+               const int *rowmask, const int *zlist, const DevNorm *norm, ColTune tune) {
   if (nfields <= 0 || nplanes <= 0) return;
   if (prec == 0) {
     PW_DISPATCH_N(fy_launch, float, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
-                  zlist, norm)
+                  zlist, norm, tune)
   } else {
     PW_DISPATCH_N(fy_launch, double, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
-                  zlist, norm)
+                  zlist, norm, tune)
   }
 }
 
@@ -494,12 +510,17 @@ k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 template <typename R, int N>
 static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int64_t npen,
                       const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
-                      int64_t mstride, const void *tw, const int *planemask, const int *fmap) {
+                      int64_t mstride, const void *tw, const int *planemask, const int *fmap,
+                      ColTune tune) {
   constexpr int C = ColShape<R, N>::C;
   static_assert(C == 128 / (int)sizeof(cplx<R>), "z-pass groups must match 128-byte slot rows");
   const unsigned ng = (unsigned)((npen + C - 1) / C);
-  const int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
-  const int fpb = (nfields + G - 1) / G;
+  int fpb = tune.fpb;
+  if (fpb <= 0) {
+    const int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
+    fpb = (nfields + G - 1) / G;
+  }
+  fpb = std::min(fpb, nfields);
   dim3 grid(ng, (nfields + fpb - 1) / fpb);
   if (goff)
     hipLaunchKernelGGL((k_fz<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
@@ -513,14 +534,14 @@ static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int
 
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int64_t npen,
                const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
-               int64_t mstride, const void *tw, const int *planemask, const int *fmap) {
+               int64_t mstride, const void *tw, const int *planemask, const int *fmap, ColTune tune) {
   if (nfields <= 0 || npen <= 0) return;
   if (prec == 0) {
     PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask,
-                  fmap)
+                  fmap, tune)
   } else {
     PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask,
-                  fmap)
+                  fmap, tune)
   }
 }
 

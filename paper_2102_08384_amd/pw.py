@@ -85,6 +85,9 @@ def _load():
     lib.pw_set_lanes.argtypes = [P, C.c_int]
     lib.pw_inspect.argtypes = [P, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.pw_set_timing.argtypes = [P, C.c_int]
+    lib.pw_set_tuning.argtypes = [P, C.c_int]
+    lib.pw_tune_entry.argtypes = [C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
     lib.pw_stage_info.argtypes = [P, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]
     lib.pw_last_error.argtypes = [P]
@@ -214,6 +217,12 @@ class Context:
 
     def set_timing(self, on: bool):
         _lib.pw_set_timing(self._h, 1 if on else 0)
+
+    def set_tuning(self, mode: int):
+        """Launch shapes of the column passes: 1 autotuned (default), 0 defaults, 2 + i candidate i."""
+        rc = _lib.pw_set_tuning(self._h, int(mode))
+        if rc != PW_OK:
+            raise PwError(rc, "pw_set_tuning: mode must be >= 0")
 
     def stages(self):
         """[(name, ms, algorithmic_bytes)] of the most recent estimate."""
@@ -376,6 +385,18 @@ class Ticket:
         rc = _lib.pw_cancel(self._ctx._h, self.id)
         if rc not in (PW_OK,):
             raise PwError(rc, self._ctx.last_error())
+
+
+def tune_entries():
+    """The process's autotuning table: [{key, choice, ms_best, ms_default}] (pw_tune_entry)."""
+    out = []
+    buf = C.create_string_buffer(256)
+    ch, mb, md = C.c_int(), C.c_double(), C.c_double()
+    i = 0
+    while _lib.pw_tune_entry(i, buf, len(buf), C.byref(ch), C.byref(mb), C.byref(md)) == PW_OK:
+        out.append({"key": buf.value.decode(), "choice": ch.value, "ms_best": mb.value, "ms_default": md.value})
+        i += 1
+    return out
 
 
 def footprint(cfg: Config, n_gal: int, n_ran: int) -> int:

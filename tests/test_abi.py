@@ -210,3 +210,23 @@ def test_footprint_and_validation_need_no_device():
     bad = pw.Config(bin_width=0.0)
     with pytest.raises(pw.PwError):
         pw.footprint(bad, 1, 1)
+
+
+def test_tune_cache_file_is_loaded(tmp_path):
+    """PW_TUNE_CACHE: the launch-shape choices a file holds make up the tuning table, without a
+    device; malformed choices are skipped."""
+    import ast
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    f = tmp_path / "tune.txt"
+    f.write_text("fy:p0:N512:f28:a173:b93216 3\nfz:p0:N512:f28:a93216:b1 1\nbad -1\n")
+    code = "from paper_2102_08384_amd import pw; print(pw.tune_entries())"
+    env = dict(os.environ, PW_TUNE_CACHE=str(f))
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                         check=True).stdout
+    entries = ast.literal_eval(out.strip().splitlines()[-1])
+    assert [(e["key"], e["choice"]) for e in entries] == [("fy:p0:N512:f28:a173:b93216", 3),
+                                                          ("fz:p0:N512:f28:a93216:b1", 1)]
+    assert all(e["ms_best"] == -1.0 and e["ms_default"] == -1.0 for e in entries)

@@ -1,0 +1,88 @@
+"""Autotuned launch shapes of the column passes (pw_set_tuning, pw_tune_entry): every candidate
+shape computes the same values as the default one, bit for bit on the transforms, and the
+autotuner's first launch (which times every candidate on the estimate's own data) leaves a
+correct estimate and a table entry per pass."""
+import numpy as np
+import pytest
+
+from oracle.estimators import pk_bisector, pk_midpoint, xi_midpoint
+
+from gpu_common import say, rounded, oracle_cfg, max_err_per_ell, uniform_catalog
+
+pytestmark = pytest.mark.gpu
+
+pw = pytest.importorskip("paper_2102_08384_amd.pw")
+
+
+def _close(a, b, tol=1e-12):
+    """Same arithmetic, FP64 shell sums in another order."""
+    return np.max(np.abs(a - b)) <= tol * np.max(np.abs(b))
+
+
+def _cfg(stat, los, prec, n_mesh):
+    bins = (dict(bin_lo=0.004, bin_width=0.012, n_bins=8) if stat == pw.PW_PK
+            else dict(bin_lo=20.0, bin_width=40.0, n_bins=8))
+    return pw.Config(stat=stat, los=los, assign=pw.PW_TSC, prec=prec, n_mesh=n_mesh, box_len=800.0,
+                     box_origin=(-400.0, -400.0, 700.0), ell_max=4, order=4 if los == pw.PW_MIDPOINT else 2,
+                     compensate=1, **bins)
+
+
+@pytest.mark.parametrize("prec", [pw.PW_FP32, pw.PW_FP64])
+def test_bisector_every_shape_same_spectra(prec):
+    """Bisector P_l: the forward y and z passes under every candidate shape give the default's
+    k-sphere spectra bit for bit."""
+    dt = np.float32 if prec == pw.PW_FP32 else np.float64
+    say("tune: bisector P N=64 every shape", "fp32" if prec == pw.PW_FP32 else "fp64")
+    gal, ran = uniform_catalog(401, 6000, 18000, (0, 0, 1100), 400)
+    gx, g64 = rounded(gal, dt)
+    rx, r64 = rounded(ran, dt)
+    nb = ran["nbar"].astype(dt)
+    cfg = _cfg(pw.PW_PK, pw.PW_BISECTOR, prec, 64)
+    with pw.Context(0) as ctx:
+        ctx.set_tuning(0)
+        base = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
+        sph = ctx.inspect(1, dt).copy()
+        for mode in range(2, 7):   # candidates 0..4 (past the last one: the default)
+            ctx.set_tuning(mode)
+            res = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
+            assert np.array_equal(ctx.inspect(1, dt), sph), mode
+            assert _close(res["values"], base["values"]), mode
+        ctx.set_tuning(1)
+        tuned = ctx.estimate(cfg, gx, rx, ran_nbar=nb)   # first launch: times the candidates
+        assert np.array_equal(ctx.inspect(1, dt), sph)
+        again = ctx.estimate(cfg, gx, rx, ran_nbar=nb)   # the cached choice
+        assert np.array_equal(ctx.inspect(1, dt), sph)
+    assert _close(tuned["values"], base["values"]) and _close(again["values"], base["values"])
+    ref = pk_bisector(g64, r64, oracle_cfg(cfg))
+    assert np.all(max_err_per_ell(base["values"], ref.values) < (1e-4 if prec == pw.PW_FP32 else 1e-10))
+    entries = {e["key"].split(":")[0]: e for e in pw.tune_entries()}
+    say("tuning table", pw.tune_entries())
+    for k in ("fy", "fz"):
+        assert k in entries
+        assert entries[k]["choice"] >= 0
+
+
+@pytest.mark.parametrize("stat", [pw.PW_PK, pw.PW_XI])
+def test_midpoint_every_shape_same_values(stat):
+    """Midpoint: the forward y pass, the fused z pass and the inverse y pass under every
+    candidate shape give the default's multipoles, and the oracle's."""
+    say("tune: midpoint N=32 fp64 every shape", "pk" if stat == pw.PW_PK else "xi")
+    gal, ran = uniform_catalog(411 + stat, 3000, 9000, (0, 0, 1100), 400)
+    gx, g64 = rounded(gal, np.float64)
+    rx, r64 = rounded(ran, np.float64)
+    cfg = _cfg(stat, pw.PW_MIDPOINT, pw.PW_FP64, 32)
+    with pw.Context(0) as ctx:
+        ctx.set_tuning(0)
+        base = ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"])
+        for mode in (2, 3, 4, 5, 1):
+            ctx.set_tuning(mode)
+            res = ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"])
+            assert _close(res["values"], base["values"]), mode
+    ref = (pk_midpoint if stat == pw.PW_PK else xi_midpoint)(g64, r64, oracle_cfg(cfg))
+    assert np.all(max_err_per_ell(base["values"], ref.values) < 1e-10)
+
+
+def test_tuning_mode_validation():
+    with pw.Context(0) as ctx:
+        with pytest.raises(pw.PwError):
+            ctx.set_tuning(-1)
