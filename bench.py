@@ -90,6 +90,28 @@ def cpu_baseline(name, frac=0.25, n_mesh=96):
                       f"single-threaded FFTs (one catalog per value^-1 seconds)"}
 
 
+def oracle_check(workload, midpoint_parity, cfg, values):
+    """Per-multipole error of the measured estimate against the FP64 oracle's values for the
+    same catalog (catalog 0 of the workload, FP32-rounded inputs) and configuration, stored by
+    tests/golden/make_full_size.py; in units of the oracle's monopole scale.  None when no
+    stored values match the configuration."""
+    case = {"C3": "c3_bisector_pk", "C2": "c2_midpoint_pk", "C4": "c4_midpoint_xi"}.get(workload)
+    path = os.path.join(ROOT, "tests", "golden", f"full_{case}.json")
+    if case is None or midpoint_parity != "even" or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        gold = json.load(fh)
+    same = (gold["n_mesh"] == cfg.n_mesh and gold["n_bins"] == cfg.n_bins and gold["order"] == cfg.order
+            and max(gold["ells"]) == cfg.ell_max and abs(gold["bin_lo"] - cfg.bin_lo) < 1e-12
+            and abs(gold["bin_width"] - cfg.bin_width) < 1e-12 and gold["assign"] == cfg.assign)
+    if not same:
+        return None
+    ref = np.asarray(gold["values"])
+    err = np.max(np.abs(np.asarray(values) - ref), axis=1) / np.max(np.abs(ref[0]))
+    return {"max_err_per_ell": err.tolist(), "ells": gold["ells"], "tolerance": 1e-4,
+            "reference": f"FP64 oracle on the same catalog, stored in tests/golden/full_{case}.json"}
+
+
 def source_digest():
     """Digest of the sources of every kernel the bisector P_l workload runs and of their launch
     code (all of csrc/ but inverse.hip, which holds only the inverse-transform and midpoint
@@ -402,6 +424,8 @@ def main():
         "monopole_first_bins": res["values"][0][:3].tolist(),
         # launch shapes the autotuner picked during the warm-up (candidate 0 = default shape)
         "autotune": pw.tune_entries(),
+        # error of the measured estimate against the FP64 oracle, per multipole
+        "oracle_check": oracle_check(a.workload, a.midpoint_parity, cfg, res["values"]),
     }
     ctx.close()
     if a.workload != "C3":
