@@ -543,7 +543,7 @@ void tuned_launch(pw_ctx *ctx, Lane &ln, const std::string &key, const std::vect
   if (mode == 0 || cands.size() < 2) return run(cands[0]);
   if (mode >= 2) return run(cands[(size_t)(mode - 2) < cands.size() ? (size_t)(mode - 2) : 0]);
   const int known = tune_lookup(key);
-  if (known >= 0 && known < (int)cands.size()) return run(cands[(size_t)known]);
+  if (known >= 0) return run(cands[known < (int)cands.size() ? (size_t)known : 0]);  // (a stale file: default)
   if (!tune_env_on()) return run(cands[0]);
   std::vector<float> ms(cands.size(), FLT_MAX);
   for (int rep = 0; rep < 2; ++rep)

@@ -86,3 +86,45 @@ def test_tuning_mode_validation():
     with pw.Context(0) as ctx:
         with pytest.raises(pw.PwError):
             ctx.set_tuning(-1)
+
+
+def test_stale_cache_choice_falls_back_to_default(tmp_path):
+    """A PW_TUNE_CACHE entry whose choice no longer exists selects the default shape, once,
+    without re-timing the candidates on every launch (run in a process of its own, since the
+    cache file is read at first use)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("tune: stale cache entry")
+    code = r'''
+import numpy as np
+from paper_2102_08384_amd import pw
+from gpu_common import rounded, uniform_catalog
+gal, ran = uniform_catalog(431, 3000, 9000, (0, 0, 1100), 400)
+gx, _ = rounded(gal, np.float32); rx, _ = rounded(ran, np.float32)
+cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=pw.PW_FP32, n_mesh=32, box_len=800.0,
+                box_origin=(-400.0, -400.0, 700.0), ell_max=4, order=2, compensate=1, bin_lo=0.004,
+                bin_width=0.012, n_bins=8)
+with pw.Context(0) as ctx:
+    a = ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"].astype(np.float32))
+    b = ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"].astype(np.float32))
+    ctx.set_tuning(0)
+    c = ctx.estimate(cfg, gx, rx, ran_nbar=ran["nbar"].astype(np.float32))
+assert np.max(np.abs(a["values"] - c["values"])) <= 1e-5 * np.max(np.abs(c["values"]))
+assert np.max(np.abs(b["values"] - c["values"])) <= 1e-5 * np.max(np.abs(c["values"]))
+print(pw.tune_entries())
+'''
+    f = tmp_path / "tune.txt"
+    env = dict(os.environ, PW_TUNE_CACHE=str(f), PYTHONPATH=os.pathsep.join([root, os.path.join(root, "tests")]))
+    f.write_text("")
+    first = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                           timeout=240)
+    assert first.returncode == 0, first.stderr[-2000:]
+    keys = [line.split()[0] for line in f.read_text().splitlines() if line.strip()]
+    assert keys
+    f.write_text("".join(f"{k} 99\n" for k in keys))   # choices that do not exist
+    second = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                            timeout=240)
+    assert second.returncode == 0, second.stderr[-2000:]
+    assert f.read_text().count("\n") == len(keys)       # nothing re-tuned, nothing appended
