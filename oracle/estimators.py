@@ -21,7 +21,9 @@ grids, summing over every m and M:
   leaves the survey window): the random-pair normalisation and window correction below.
 * ``xi_bisector``  Section 6 boxed estimator,
   h = IFT[F[Y_J1^M d](-k) F[Y_J2^{m-M} d](k)],
-  xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_m Y_l^{m*}(D^) sum B h.
+  xi_l(r_a) = (4pi/I) (1/v_a) sum_{D in a} Re sum_m Y_l^{m*}(D^) sum B h
+  (``xi_bisector_streamed``: the same, with the transforms held on disk and the k-space sums
+  formed slab by slab, for meshes whose transforms do not fit in host memory together).
 
 Normalisation (reading of Section 2.1): the substitution d -> w (n_g - alpha_r n_r) / I^{1/2}
 makes the 1/V of the definition inconsistent, so every estimator is divided by
@@ -412,6 +414,101 @@ def xi_bisector(gal, ran, cfg: Config, norm=None, beta_max=None) -> Result:
         X_list.append(X)
     sums, rmean, counts = _bin_r(X_list, cfg)
     return _finish_xi(sums, rmean, counts, cfg, alpha_r, I, S)
+
+
+def xi_bisector_streamed(gal, ran, cfg: Config, workdir: str, norm=None, beta_max=None,
+                         slab: int = 16) -> Result:
+    """xi_bisector for meshes whose transforms do not fit in host memory together (Section 6
+    boxed estimator, the same steps).
+
+    * Each transform F[Y_J^M d] with M >= 0 is computed once and written to a disk-backed array
+      (np.memmap under `workdir`).  Those with M < 0 follow from Y_J^{-M} = (-1)^M conj(Y_J^M)
+      and the reality of the density: F[Y_J^{-M} d](k) = (-1)^M conj(F[Y_J^M d](-k)).
+    * The k-space sums K_lm = sum_{beta J1 J2 M} B Q(-k) Q(k) are formed for one slab of the
+      first k index at a time (rows k and, for Q(-k), the mirrored rows (-n) mod N).
+    * The inverse DFT is separable: each slab is transformed over the last two axes, the
+      separations |D| > r_max (beyond the last bin) are dropped on those axes, and the first
+      axis is transformed once every slab is in.  The 1/N^3 factor is split 1/N^2, 1/N.
+    * Binning is the full-grid rule (r_bin_index) restricted to the kept separations, which
+      hold every binned one."""
+    import os
+    m, alpha_r, I, S = _prepare(gal, ran, cfg, norm)
+    if beta_max is None:
+        beta_max = cfg.order // 2
+    N = cfg.N
+    H = cfg.L / N
+    comp = _compensation(cfg)
+    Jmax = max(cfg.ells) + beta_max
+    xn = node_positions(N, cfg.L, cfg.b0)
+    files = {}
+    for J in range(Jmax + 1):
+        for M in range(0, J + 1):
+            path = os.path.join(workdir, f"spectrum_J{J}_M{M}.c128")
+            arr = np.memmap(path, dtype=np.complex128, mode="w+", shape=(N, N, N))
+            arr[...] = _fft(m * Ylm(J, M, xn), comp)
+            arr.flush()
+            del arr
+            files[(J, M)] = path
+    del xn, m
+    spec = {key: np.memmap(p, dtype=np.complex128, mode="r", shape=(N, N, N)) for key, p in files.items()}
+
+    # separations kept on each axis: signed index s with |s| H < r_max
+    r_max = cfg.bin_lo + cfg.n_bins * cfg.bin_width
+    w = min(int(math.ceil(r_max / H)), N // 2 - 1)
+    keep_s = np.arange(-w, w + 1)
+    keep = keep_s % N
+    targets = [(l, mm) for l in cfg.ells for mm in range(-l, l + 1)]
+    tabs = {(l, mm): coeffs.B_table(beta_max, l, mm, _beta_lo(cfg)) for (l, mm) in targets}
+    acc = {t: np.zeros((N, len(keep), len(keep)), dtype=np.complex128) for t in targets}
+
+    def neg_yz(X):
+        # X at index (-n) mod N on the last two axes
+        return np.roll(X[:, ::-1, ::-1], 1, axis=(1, 2))
+
+    for a in range(0, N, slab):
+        rows = np.arange(a, min(a + slab, N))
+        mirror = (-rows) % N
+        Qk, Qmk = {}, {}
+        for (J, M), arr in spec.items():
+            at_k = np.array(arr[rows])                 # F[Y_J^M d](k), k in the slab
+            at_mk = neg_yz(np.array(arr[mirror]))      # F[Y_J^M d](-k)
+            Qk[(J, M)], Qmk[(J, M)] = at_k, at_mk
+            if M > 0:
+                sgn = -1.0 if M % 2 else 1.0
+                Qk[(J, -M)] = sgn * np.conj(at_mk)
+                Qmk[(J, -M)] = sgn * np.conj(at_k)
+        for t in targets:
+            Kp = np.zeros((len(rows), N, N), dtype=np.complex128)
+            for (J1, J2, M), c in tabs[t].items():
+                Kp += c * Qmk[(J1, M)] * Qk[(J2, t[1] - M)]
+            h = scipy.fft.ifft2(Kp, axes=(1, 2), workers=-1)
+            acc[t][rows] = h[:, keep][:, :, keep]
+        del Qk, Qmk
+    del spec
+    for p in files.values():
+        os.remove(p)
+
+    s1 = keep_s * H
+    D = np.stack(np.meshgrid(s1, s1, s1, indexing="ij"), axis=-1)
+    b_full, r_full = r_bin_index(N, cfg.L, cfg.bin_lo, cfg.bin_width, cfg.n_bins)
+    b = b_full[np.ix_(keep, keep, keep)]
+    rmag = r_full[np.ix_(keep, keep, keep)]
+    counts = np.bincount(b[b >= 0], minlength=cfg.n_bins).astype(np.float64)
+    assert np.array_equal(counts, np.bincount(b_full[b_full >= 0], minlength=cfg.n_bins)), \
+        "kept separations must hold every binned one"
+    del b_full, r_full
+    sel = b >= 0
+    X_vals = []
+    for l in cfg.ells:
+        X = np.zeros(b.shape, dtype=np.complex128)
+        for mm in range(-l, l + 1):
+            Hlm = scipy.fft.ifft(acc[(l, mm)], axis=0, workers=-1)[keep]
+            X += np.conj(Ylm(l, mm, D)) * Hlm
+        X_vals.append(np.bincount(b[sel], weights=np.real(X)[sel], minlength=cfg.n_bins))
+    rsum = np.bincount(b[sel], weights=rmag[sel], minlength=cfg.n_bins)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rmean = np.where(counts > 0, rsum / np.where(counts > 0, counts, 1), 0.0)
+    return _finish_xi(np.array(X_vals), rmean, counts, cfg, alpha_r, I, S)
 
 
 # ----------------------------------------------------------------------------

@@ -2,7 +2,7 @@
 
 * Nodes sit at x_n = b0 + n H, H = L / N, n = 0..N-1 on each axis; the observer
   is at the origin of the coordinate system the positions are given in.
-* Painting (mass assignment, the nbodykit step of Section 6.2): node masses
+* Painting (mass assignment, the nbodykit step of Section 7.2): node masses
   m_n = sum_p w_p W(u_p - n), u = (x - b0)/H, periodic node indices.
   CIC: i0 = floor(u), weights (1-d, d) at (i0, i0+1), d = u - i0.
   TSC: i0 = floor(u + 1/2), d = u - i0, weights (1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2)

@@ -1,6 +1,6 @@
 """Synthetic catalogs standing in for the paper's MultiDark-Patchy BOSS DR12 mocks.
 
-The mocks of Section 6.2 are not available; these seeded generators produce
+The mocks of Section 7.2 are not available; these seeded generators produce
 catalogs with the shapes, sizes, weights and clustering statistics of the
 workloads the estimator is measured on.  Recipe (all host numpy, FP64, PCG64):
 

@@ -1,6 +1,7 @@
 """Write the full-size expected values of the parity tests with the FP64 oracle.
 
-    python tests/golden/make_full_size.py {c3_bisector_pk,c2_midpoint_pk,c4_midpoint_xi,c4_bisector_xi_256}
+    python tests/golden/make_full_size.py {c3_bisector_pk,c2_midpoint_pk,c4_midpoint_xi,c4_bisector_xi,
+                                           c4_bisector_xi_256}
 
 Each case takes the seeded synthetic catalog of its workload (catalog index 0), rounds the
 positions, weights and nbar to FP32 exactly as the GPU receives them, runs the oracle
@@ -13,8 +14,10 @@ tests/golden/full_<case>.json.  Nothing here calls the library.
                        19 k-bins 0.01-0.20
   c4_midpoint_xi       midpoint xi_l (Section 4.3), 512^3 CIC, 4e6 + 2e7, l <= 4, order 4,
                        25 r-bins 0-200
-  c4_bisector_xi_256   bisector xi_l (Section 6) on the same catalog at 256^3 (the 512^3
-                       oracle needs every full transform at once, ~100 GB)
+  c4_bisector_xi       bisector xi_l (Section 6), 512^3 CIC, 4e6 + 2e7, l <= 4, order 4,
+                       25 r-bins 0-200 (streamed oracle: the 28 transforms with M >= 0, ~60 GB,
+                       are held on disk under $PW_ORACLE_SCRATCH, default <repo>/_oracle_scratch)
+  c4_bisector_xi_256   bisector xi_l (Section 6) on the same catalog at 256^3 (full-grid oracle)
 """
 from __future__ import annotations
 
@@ -30,13 +33,23 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle.estimators import (Config, pk_bisector_shells, pk_midpoint, xi_midpoint,  # noqa: E402
-                               xi_bisector)
+                               xi_bisector, xi_bisector_streamed)
 from synthetic import WORKLOADS, make_workload_catalog, to_xyzw  # noqa: E402
+
+
+
+def xi_bisector_on_disk(g, r, cfg):
+    """xi_bisector_streamed with its transforms in the scratch folder."""
+    scratch = os.environ.get("PW_ORACLE_SCRATCH", os.path.join(ROOT, "_oracle_scratch"))
+    os.makedirs(scratch, exist_ok=True)
+    return xi_bisector_streamed(g, r, cfg, scratch, slab=32)
+
 
 CASES = {
     "c3_bisector_pk": ("C3", None, pk_bisector_shells),
     "c2_midpoint_pk": ("C2", None, pk_midpoint),
     "c4_midpoint_xi": ("C4", None, xi_midpoint),
+    "c4_bisector_xi": ("C4", None, xi_bisector_on_disk),
     "c4_bisector_xi_256": ("C4", 256, xi_bisector),
 }
 
