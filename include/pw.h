@@ -36,7 +36,8 @@
  *
  * Errors: every call returns PW_OK (0) or a negative code; pw_last_error() gives a message.
  * No exception crosses this ABI.  Outputs are written only on success.
- * A pw_ctx is not thread-safe: use it from one thread at a time.
+ * Threads: a pw_ctx takes pw_estimate-family calls from one thread at a time and submission
+ * calls from one thread at a time; the two may be different threads (see pw_submit).
  */
 #ifndef PW_H
 #define PW_H
@@ -54,7 +55,7 @@ enum {
   PW_ERANGE = -2,    /* a particle lies outside the box                           */
   PW_ENOMEM = -3,    /* the request does not fit the context's HBM budget         */
   PW_EDEVICE = -4,   /* a HIP runtime call failed                                 */
-  PW_EBUSY = -5,     /* the submission queue is full                              */
+  PW_EBUSY = -5,     /* the submission queue is full (pw_set_queue_limit)         */
   PW_EAGAIN = -6,    /* ticket still pending (pw_poll)                            */
   PW_ECANCELED = -7  /* ticket was cancelled                                      */
 };
@@ -96,7 +97,12 @@ typedef struct {
  * particle; it is read for the randoms only, to form I.  Pointers are host memory when
  * on_device == 0 and device memory of the context's GPU when on_device == 1.  The caller
  * owns the memory; the library never frees or retains it past the call (pw_estimate) or
- * past the ticket's completion (pw_submit). */
+ * past the ticket's completion (pw_submit).
+ * Device memory must hold its final values when the call is made: the library reads it on
+ * its own streams (and on the context's stream for pw_estimate) without waiting for work the
+ * caller has queued on other streams, so synchronise the producing stream first.  Host
+ * memory is copied to the device on the lane's stream; pinned host memory (hipHostMalloc)
+ * is read in place and asynchronously. */
 typedef struct {
   const void *xyzw;
   const void *nbar;
@@ -185,9 +191,14 @@ int pw_estimate_xi_normalized(pw_ctx *ctx, const pw_config *cfg, const pw_catalo
  * grows to the largest of them.  Host-side plans are cached per context.  Each lane
  * has its own HIP stream, so admitted requests of any size, mesh and estimator run
  * concurrently on the device.  The inputs and output buffers must stay valid until the ticket
- * completes or is cancelled; outputs are written when the request finishes.
+ * completes or is cancelled; outputs are written when the request finishes.  Pageable host
+ * catalogs are copied into pinned buffers the context owns (a pool of at most 8 GiB, reused
+ * across requests) on the submitting thread, so that the lane's copy to the device runs
+ * asynchronously beside other lanes' kernels; without room in the pool the request reads the
+ * caller's memory when it is launched.
  *   pw_submit   PW_OK and *ticket, or an error for a malformed request / one that can never
- *               fit the budget (PW_ENOMEM); nothing is enqueued then.
+ *               fit the budget (PW_ENOMEM), or PW_EBUSY while the context already holds its
+ *               queue limit of requests pending or running; nothing is enqueued then.
  *   pw_poll     PW_EAGAIN while pending or running; otherwise the request's final status
  *               (PW_OK, PW_ECANCELED or the error of pw_estimate), after which the ticket is
  *               released (a later call on it returns PW_EINVAL).
@@ -205,6 +216,10 @@ int pw_cancel(pw_ctx *ctx, uint64_t ticket);
 /* Number of serving lanes (1..8, default 2); only before the first pw_submit (PW_EBUSY
  * after). */
 int pw_set_lanes(pw_ctx *ctx, int n_lanes);
+/* Backpressure: pw_submit returns PW_EBUSY while max_in_flight requests of the context are
+ * pending or running (1..2^30, default 1024; PW_EINVAL otherwise).  A lower limit applies to
+ * later submissions only; requests already queued stay queued. */
+int pw_set_queue_limit(pw_ctx *ctx, int64_t max_in_flight);
 
 /* Copy an internal buffer of the context's most recent pw_estimate to host memory (for
  * per-stage checks).  what:
@@ -242,11 +257,14 @@ int pw_set_tuning(pw_ctx *ctx, int mode);
  * when loaded from PW_TUNE_CACHE).  Any output pointer may be NULL.  PW_EINVAL past the end. */
 int pw_tune_entry(int index, char *key, size_t key_len, int *choice, double *ms_best, double *ms_default);
 
-/* Message of the last error on this context (thread-unsafe, valid until the next call). */
+/* Message of the last error on this context ("" after a successful call), from any thread.
+ * The returned string belongs to the calling thread and stays valid until that thread's next
+ * pw_last_error call. */
 const char *pw_last_error(const pw_ctx *ctx);
 
-/* Device-memory footprint (bytes) pw_estimate needs for cfg with the given catalog sizes;
- * host-only, needs no device. */
+/* Device-memory footprint (bytes) pw_estimate needs for cfg with the given catalog sizes,
+ * for host catalogs in the mesh precision with the randoms' nbar (device-resident catalogs
+ * need less: no staging); host-only, needs no device. */
 int pw_footprint(const pw_config *cfg, int64_t n_gal, int64_t n_ran, size_t *bytes);
 
 /* Coupling tables used by the kernels, in the real spherical-harmonic basis

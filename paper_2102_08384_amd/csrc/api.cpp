@@ -108,6 +108,8 @@ struct Req {
   int status = PW_EAGAIN;
   std::string err;
   DevPlan *dp = nullptr;
+  void *pin = nullptr;  // context-owned pinned copy of the host catalogs (pw_submit), or NULL
+  size_t pin_bytes = 0;
 };
 
 }  // namespace
@@ -117,6 +119,7 @@ struct pw_ctx {
   size_t budget = 0;
   size_t used = 0;
   std::mutex mem_mu;  // guards `used`
+  mutable std::mutex err_mu;  // guards `err` (written by the caller's and the worker's threads)
   std::string err;
   size_t lds_per_block = 65536;
   std::atomic<uint64_t> stamp{0};
@@ -145,6 +148,14 @@ struct pw_ctx {
   // device bytes promised to launches that allocate outside `mu` (lane 0's, or a serving
   // lane's just admitted), so that two launches do not count the same free bytes
   size_t reserved = 0;
+  // pw_submit refuses a request (PW_EBUSY) while this many are pending or running
+  size_t queue_limit = 1024;
+  // pinned host buffers holding copies of pageable host catalogs of submitted requests
+  // (guarded by pin_mu): the free ones, and the bytes held in all (free and in use)
+  std::mutex pin_mu;
+  std::vector<std::pair<void *, size_t>> pin_free;
+  size_t pin_held = 0;
+  size_t pin_cap = (size_t)8 << 30;
 };
 
 // A promise of device bytes to one launch (pw_ctx::reserved), kept until its allocations are
@@ -184,6 +195,64 @@ struct MainBusy {
 };
 
 namespace {
+
+void set_err(pw_ctx *ctx, const std::string &msg) {
+  std::lock_guard<std::mutex> lk(ctx->err_mu);
+  ctx->err = msg;
+}
+
+// Pinned staging of pageable host catalogs (pw_submit): a buffer of at least `bytes` from the
+// context's pool, or NULL when holding it would exceed the pool's cap (the request then reads
+// the caller's memory at launch, as pw_estimate does).
+void *pin_acquire(pw_ctx *ctx, size_t bytes, size_t *got) {
+  std::lock_guard<std::mutex> lk(ctx->pin_mu);
+  size_t best = ctx->pin_free.size();
+  for (size_t i = 0; i < ctx->pin_free.size(); ++i)
+    if (ctx->pin_free[i].second >= bytes && (best == ctx->pin_free.size() ||
+                                             ctx->pin_free[i].second < ctx->pin_free[best].second))
+      best = i;
+  if (best < ctx->pin_free.size()) {
+    void *p = ctx->pin_free[best].first;
+    *got = ctx->pin_free[best].second;
+    ctx->pin_free.erase(ctx->pin_free.begin() + (long)best);
+    return p;
+  }
+  // drop free buffers that are too small while the cap is in the way
+  while (ctx->pin_held + bytes > ctx->pin_cap && !ctx->pin_free.empty()) {
+    (void)hipHostFree(ctx->pin_free.back().first);
+    ctx->pin_held -= ctx->pin_free.back().second;
+    ctx->pin_free.pop_back();
+  }
+  if (ctx->pin_held + bytes > ctx->pin_cap) return nullptr;
+  void *p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  ctx->pin_held += bytes;
+  *got = bytes;
+  return p;
+}
+
+void pin_release(pw_ctx *ctx, Req *r) {
+  if (!r->pin) return;
+  std::lock_guard<std::mutex> lk(ctx->pin_mu);
+  ctx->pin_free.push_back({r->pin, r->pin_bytes});
+  r->pin = nullptr;
+  r->pin_bytes = 0;
+}
+
+// True when `p` is host memory the device can read directly (pinned or registered).
+bool host_pinned(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory the runtime does not know: not an error here
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
 
 void *dev_alloc(pw_ctx *ctx, size_t bytes) {
   if (bytes == 0) return nullptr;
@@ -855,7 +924,7 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
     return n + (work > ln.work_bytes ? work - ln.work_bytes : 0);
   };
   if (need() == 0) return;
-  const size_t cat = catalog_bytes(*cfg, gal->n, ran->n);
+  const size_t cat = catalog_bytes(*cfg, *gal, *ran);
   while (mem_used(ctx) + ctx->reserved + need() + cat > ctx->budget) {
     Lane *wl = nullptr;
     uint64_t oldest = (uint64_t)-1;
@@ -922,6 +991,41 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   finish_estimate(ln, dp, norm, out, bin_mean, counts);
 }
 
+// pw_submit: copy the request's pageable host catalogs (and the randoms' nbar) into one pinned
+// buffer of the context's pool, on the caller's thread, so that the lane's copies to the device
+// run asynchronously beside other lanes' kernels.  Host memory that is already pinned is read
+// in place.  Without room in the pool the request keeps the caller's pointers.
+void stage_pinned(pw_ctx *ctx, Req *r) {
+  struct Piece {
+    const void **ptr;
+    size_t bytes;
+  };
+  std::vector<Piece> pieces;
+  auto add = [&](pw_catalog &c, bool with_nbar) {
+    if (c.on_device || c.n <= 0) return;
+    const size_t isz = c.dtype == PW_FP32 ? 4 : 8;
+    if (!host_pinned(c.xyzw)) pieces.push_back({&c.xyzw, (size_t)c.n * 4 * isz});
+    if (with_nbar && c.nbar && !host_pinned(c.nbar)) pieces.push_back({&c.nbar, (size_t)c.n * isz});
+  };
+  add(r->gal, false);
+  add(r->ran, true);
+  if (pieces.empty()) return;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t need = 0;
+  for (auto &p : pieces) need += up(p.bytes);
+  size_t got = 0;
+  void *buf = pin_acquire(ctx, need, &got);
+  if (!buf) return;
+  r->pin = buf;
+  r->pin_bytes = got;
+  char *dst = (char *)buf;
+  for (auto &p : pieces) {
+    std::memcpy(dst, *p.ptr, p.bytes);
+    *p.ptr = dst;
+    dst += up(p.bytes);
+  }
+}
+
 Lane *make_lane(int id, hipStream_t user_stream) {
   std::unique_ptr<Lane> ln(new Lane());
   ln->id = id;
@@ -971,6 +1075,10 @@ size_t lane_extra_bytes(const Lane &ln, const Req &r) {
     return have >= b ? 0 : b;
   };
   extra += stg(r.gal, ln.stage_bytes[0]) + stg(r.ran, ln.stage_bytes[1]);
+  if (!r.ran.on_device && r.ran.nbar) {
+    const size_t nb = (size_t)r.ran.n * (r.ran.dtype == PW_FP32 ? 4 : 8);
+    if (ln.stage_nbar_bytes < nb) extra += nb;
+  }
   return extra;
 }
 
@@ -1034,6 +1142,7 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
       // can never fit: fail it and look at the next one
       r->status = PW_ENOMEM;
       r->err = "request does not fit the context's HBM budget";
+      pin_release(ctx, r);
       ctx->pending.erase(it);
       ctx->cv.notify_all();
       return pick_admission(ctx);
@@ -1068,6 +1177,7 @@ void worker_loop(pw_ctx *ctx) {
           r->err = f.msg;
         }
       }
+      pin_release(ctx, r);  // the lane's copies out of it are complete
       ln.cur = nullptr;
       ctx->cv.notify_all();
     }
@@ -1089,6 +1199,10 @@ void worker_loop(pw_ctx *ctx) {
       } catch (const std::exception &e) {
         code = PW_EINVAL;
         msg = e.what();
+      }
+      if (code != PW_OK && r->pin) {
+        (void)hipStreamSynchronize(ln.stream);  // staging copies enqueued before the failure
+        pin_release(ctx, r);
       }
       lk.lock();
       ctx->reserved -= r->reserved;
@@ -1123,7 +1237,7 @@ int req_final(pw_ctx *ctx, uint64_t ticket, bool erase) {
   if (it == ctx->reqs.end()) return PW_EINVAL;
   int st = it->second->status;
   if (st != PW_EAGAIN) {
-    ctx->err = it->second->err;
+    set_err(ctx, it->second->err);
     if (erase) ctx->reqs.erase(it);
   }
   return st;
@@ -1171,6 +1285,7 @@ int pw_destroy(pw_ctx *ctx) {
       for (Req *r : ctx->pending) {
         r->status = PW_ECANCELED;
         r->err = "context destroyed";
+        pin_release(ctx, r);
       }
       ctx->pending.clear();
       ctx->stop = true;
@@ -1184,6 +1299,8 @@ int pw_destroy(pw_ctx *ctx) {
   ctx->lanes.clear();
   if (ctx->main) destroy_lane(ctx, ctx->main.get());
   ctx->main.reset();
+  for (auto &b : ctx->pin_free) (void)hipHostFree(b.first);
+  ctx->pin_free.clear();
   delete ctx;
   return PW_OK;
 }
@@ -1194,13 +1311,13 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const 
   try {
     run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts);
   } catch (const Fail &f) {
-    ctx->err = f.msg;
+    set_err(ctx, f.msg);
     return f.code;
   } catch (const std::exception &e) {
-    ctx->err = e.what();
+    set_err(ctx, e.what());
     return PW_EINVAL;
   }
-  ctx->err.clear();
+  set_err(ctx, std::string());
   return PW_OK;
 }
 
@@ -1244,13 +1361,13 @@ int pw_estimate_orders(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
       if (norm && !norm->use_given) *norm = n0;
     }
   } catch (const Fail &f) {
-    ctx->err = f.msg;
+    set_err(ctx, f.msg);
     return f.code;
   } catch (const std::exception &e) {
-    ctx->err = e.what();
+    set_err(ctx, e.what());
     return PW_EINVAL;
   }
-  ctx->err.clear();
+  set_err(ctx, std::string());
   return PW_OK;
 }
 
@@ -1332,24 +1449,24 @@ int pw_estimate_xi_normalized(pw_ctx *ctx, const pw_config *cfg, const pw_catalo
     if (counts) std::memcpy(counts, ct.data(), ct.size() * sizeof(int64_t));
     if (norm && !norm->use_given) *norm = nm;
   } catch (const Fail &e) {
-    ctx->err = e.msg;
+    set_err(ctx, e.msg);
     return e.code;
   } catch (const std::exception &e) {
-    ctx->err = e.what();
+    set_err(ctx, e.what());
     return PW_EINVAL;
   }
-  ctx->err.clear();
+  set_err(ctx, std::string());
   return PW_OK;
 }
 
 int pw_set_lanes(pw_ctx *ctx, int n_lanes) {
   if (!ctx) return PW_EINVAL;
   if (n_lanes < 1 || n_lanes > kMaxLanes) {
-    ctx->err = "n_lanes must be in 1..8";
+    set_err(ctx, "n_lanes must be in 1..8");
     return PW_EINVAL;
   }
   if (ctx->worker_started) {
-    ctx->err = "pw_set_lanes: the serving loop has already started";
+    set_err(ctx, "pw_set_lanes: the serving loop has already started");
     return PW_EBUSY;
   }
   ctx->n_lanes = n_lanes;
@@ -1376,8 +1493,21 @@ int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw
       r->need_tables = table_bytes(*hp);
       r->need_work = work_layout(*hp).total;
     }
-    size_t whole = r->need_tables + r->need_work + catalog_bytes(*cfg, gal->n, ran->n);
+    size_t whole = r->need_tables + r->need_work + catalog_bytes(*cfg, *gal, *ran);
     if (whole > ctx->budget) fail(PW_ENOMEM, "request needs %zu bytes, budget is %zu", whole, ctx->budget);
+    auto in_flight = [&]() {
+      size_t n = ctx->pending.size();
+      for (auto &lp : ctx->lanes) n += lp->cur ? 1 : 0;
+      return n;
+    };
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      if (in_flight() >= ctx->queue_limit)
+        fail(PW_EBUSY, "the submission queue is full: %zu requests pending or running (limit %zu)", in_flight(),
+             ctx->queue_limit);
+    }
+    // (one submitting thread: the count can only fall until the request is queued below)
+    stage_pinned(ctx, r.get());
     std::lock_guard<std::mutex> lk(ctx->mu);
     start_worker(ctx);
     r->ticket = ctx->next_ticket++;
@@ -1385,13 +1515,26 @@ int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw
     ctx->pending.push_back(r.get());
     ctx->reqs[r->ticket] = std::move(r);
   } catch (const Fail &f) {
-    ctx->err = f.msg;
+    pin_release(ctx, r.get());
+    set_err(ctx, f.msg);
     return f.code;
   } catch (const std::exception &e) {
-    ctx->err = e.what();
+    pin_release(ctx, r.get());
+    set_err(ctx, e.what());
     return PW_EINVAL;
   }
   ctx->cv.notify_all();
+  return PW_OK;
+}
+
+int pw_set_queue_limit(pw_ctx *ctx, int64_t max_in_flight) {
+  if (!ctx) return PW_EINVAL;
+  if (max_in_flight < 1 || max_in_flight > ((int64_t)1 << 30)) {
+    set_err(ctx, "pw_set_queue_limit: max_in_flight must be in 1..2^30");
+    return PW_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->queue_limit = (size_t)max_in_flight;
   return PW_OK;
 }
 
@@ -1420,7 +1563,7 @@ int pw_cancel(pw_ctx *ctx, uint64_t ticket) {
   auto pit = std::find(ctx->pending.begin(), ctx->pending.end(), r);
   if (pit == ctx->pending.end()) {
     if (r->status == PW_EAGAIN) {
-      ctx->err = "pw_cancel: the request is already running";
+      set_err(ctx, "pw_cancel: the request is already running");
       return PW_EBUSY;
     }
     return PW_OK;  // already finished; the ticket keeps its status
@@ -1428,11 +1571,18 @@ int pw_cancel(pw_ctx *ctx, uint64_t ticket) {
   ctx->pending.erase(pit);
   r->status = PW_ECANCELED;
   r->err = "cancelled";
+  pin_release(ctx, r);
   ctx->cv.notify_all();
   return PW_OK;
 }
 
-const char *pw_last_error(const pw_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *pw_last_error(const pw_ctx *ctx) {
+  if (!ctx) return "null context";
+  thread_local std::string copy;  // stays valid until this thread's next pw_last_error
+  std::lock_guard<std::mutex> lk(ctx->err_mu);
+  copy = ctx->err;
+  return copy.c_str();
+}
 int pw_footprint(const pw_config *cfg, int64_t n_gal, int64_t n_ran, size_t *bytes) {
   if (!cfg || !bytes) return PW_EINVAL;
   try {
@@ -1558,7 +1708,7 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
       }
     }
   } catch (const Fail &f) {
-    ctx->err = f.msg;
+    set_err(ctx, f.msg);
     return f.code;
   }
   return PW_OK;

@@ -527,6 +527,15 @@ size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
   return (size_t)(n_gal + n_ran) * 4 * rsz * 2 + (size_t)n_ran * rsz;
 }
 
+size_t catalog_bytes(const pw_config &c, const pw_catalog &gal, const pw_catalog &ran) {
+  const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
+  auto isz = [](const pw_catalog &k) -> size_t { return k.dtype == PW_FP32 ? 4 : 8; };
+  size_t b = (size_t)(gal.n + ran.n) * 4 * rsz;  // tile-sorted records
+  if (!gal.on_device) b += (size_t)gal.n * 4 * isz(gal);
+  if (!ran.on_device) b += (size_t)ran.n * 4 * isz(ran) + (ran.nbar ? (size_t)ran.n * isz(ran) : 0);
+  return b;
+}
+
 size_t footprint_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
   return plan_bytes(c) + catalog_bytes(c, n_gal, n_ran);
 }

@@ -133,7 +133,11 @@ struct WorkLayout {
 WorkLayout work_layout(const HostPlan &h);
 // device bytes of a plan's own tables (everything but the workspace), an upper bound
 size_t table_bytes(const HostPlan &h);
-size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);  // records + staging
+// device bytes of an estimate's particle buffers: the tile-sorted records (mesh precision) and
+// the staging of host catalogs (their own dtype) with the randoms' nbar; the count form assumes
+// host catalogs of the mesh precision with nbar (pw_footprint)
+size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
+size_t catalog_bytes(const pw_config &c, const pw_catalog &gal, const pw_catalog &ran);
 // bytes of each of the two spectrum buffers (memory-lean: of the k-sphere buffer)
 size_t spectrum_buffer_bytes(const HostPlan &h);
 // memory-lean bisector: x-pass and y-pass work buffers of one field group

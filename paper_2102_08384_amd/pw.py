@@ -14,7 +14,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpw.so")
+# PW_LIB names another build of the library (the host-only sanitized one, for CPU checks)
+LIB_PATH = os.environ.get("PW_LIB") or os.path.join(HERE, "libpw.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pw.h")
 
 PW_OK, PW_EINVAL, PW_ERANGE, PW_ENOMEM, PW_EDEVICE, PW_EBUSY, PW_EAGAIN, PW_ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -83,6 +84,7 @@ def _load():
     lib.pw_wait.argtypes = [P, C.c_uint64]
     lib.pw_cancel.argtypes = [P, C.c_uint64]
     lib.pw_set_lanes.argtypes = [P, C.c_int]
+    lib.pw_set_queue_limit.argtypes = [P, C.c_int64]
     lib.pw_inspect.argtypes = [P, C.c_int, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.pw_set_timing.argtypes = [P, C.c_int]
     lib.pw_set_tuning.argtypes = [P, C.c_int]
@@ -148,7 +150,7 @@ def _catalog(xyzw, nbar, keep):
     """Describe a catalog; keep references alive in `keep`."""
     cat = _Catalog()
     try:
-        import torch  # noqa: F401
+        import torch
         is_torch = hasattr(xyzw, "data_ptr") and hasattr(xyzw, "is_cuda")
     except ImportError:
         is_torch = False
@@ -167,6 +169,10 @@ def _catalog(xyzw, nbar, keep):
             nb = nbar.to(dtype=t.dtype, device=t.device).contiguous()
             keep.append(nb)
             cat.nbar = nb.data_ptr()
+        if t.is_cuda:
+            # the library reads device inputs on its own streams: the copies and casts above
+            # (and whatever produced the tensors) must be complete first
+            torch.cuda.current_stream(t.device).synchronize()
         return cat
     a = np.ascontiguousarray(xyzw)
     if a.ndim != 2 or a.shape[1] != 4:
@@ -312,6 +318,12 @@ class Context:
     # ---------------------------------------------------------------- serving
     def set_lanes(self, n: int):
         rc = _lib.pw_set_lanes(self._h, n)
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+
+    def set_queue_limit(self, n: int):
+        """pw_submit raises PwError(PW_EBUSY) while n requests are pending or running."""
+        rc = _lib.pw_set_queue_limit(self._h, int(n))
         if rc != PW_OK:
             raise PwError(rc, self.last_error())
 
