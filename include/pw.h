@@ -144,6 +144,25 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
                 const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
                 int64_t *counts);
 
+/* pw_estimate for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  It allocates no device memory and no
+ * pinned host memory: every device buffer of the estimate (plan tables, mesh, spectrum buffers,
+ * paint tiles, particle records) is carved from one static device array of 256 MiB that each
+ * GPU the library runs on holds until the process ends; the results come back through a
+ * pageable host buffer of the context.  Arguments, outputs and results are those of
+ * pw_estimate, with two limits:
+ *   - catalogs must be device-resident (on_device = 1): PW_EINVAL otherwise;
+ *   - the estimate must fit the 256 MiB scratch (every estimator at 32^3, bisector P_l at
+ *     64^3 with a few million particles): PW_ENOMEM with the bytes needed otherwise, before
+ *     anything is written to the device.
+ * Every call on a GPU uses that GPU's one scratch array, which keeps the last call's contents
+ * (each call clears what it accumulates): calls that overlap on one GPU, from different
+ * contexts or threads, race.  Plan tables are uploaded on every call (nothing is cached in the
+ * scratch). */
+int pw_estimate_noalloc(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
+                        const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
+                        int64_t *counts);
+
 /* Contributions of each series order separately, for the same configuration and catalogs as
  * pw_estimate: slice o holds the terms of order theta^(2o) (parity-even midpoint alpha = 2o,
  * Sections 3.3 and 4.3; bisector beta = o, Sections 5.2 and 6), or for the all-parity midpoint

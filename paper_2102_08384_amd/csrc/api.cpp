@@ -93,6 +93,7 @@ struct Lane {
   double st_bytes[kMaxStages] = {};
   struct Req *cur = nullptr;  // serving lanes: the request in flight
   int occ_rows = 0, occ_planes = 0;  // occupancy of the most recent estimate (lane 0)
+  std::vector<double> noalloc_res;   // lane 0: pageable results of pw_estimate_noalloc
 };
 
 struct Req {
@@ -157,6 +158,46 @@ struct pw_ctx {
   size_t pin_held = 0;
   size_t pin_cap = (size_t)8 << 30;
 };
+
+// ------------------------------------------------------------------------------ static scratch
+// pw_estimate_noalloc runs in this fixed device array: one estimate's plan tables, workspace
+// (mesh, spectrum buffers, paint tiles) and particle records, carved in that order.  Each
+// device the library runs on holds its own copy until the process ends.  Host code reaches it
+// only through the address hipGetSymbolAddress gives for that device (scratch_of), never
+// through the array's name.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_at;         // device -> address of that device's `scratch`
+std::map<int, std::string> g_scratch_err;  // device -> why its address could not be resolved
+
+// Once per device, with the device current (pw_create): resolve and keep its scratch address.
+// A failure is kept for pw_estimate_noalloc to report; the other entry points do not need it.
+void resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_at.count(device)) return;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) {
+    g_scratch_at[device] = (char *)p;
+    return;
+  }
+  (void)hipGetLastError();
+  g_scratch_err[device] = std::string("hipGetSymbolAddress(scratch) failed: ") +
+                          (e == hipSuccess ? "null address" : hipGetErrorString(e));
+}
+
+char *scratch_of(int device, std::string *why) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_at.find(device);
+  if (it != g_scratch_at.end()) return it->second;
+  auto er = g_scratch_err.find(device);
+  *why = er == g_scratch_err.end() ? std::string("not resolved") : er->second;
+  return nullptr;
+}
+}  // namespace
 
 // A promise of device bytes to one launch (pw_ctx::reserved), kept until its allocations are
 // made or it fails.
@@ -294,19 +335,35 @@ void ensure_buffer(pw_ctx *ctx, void **p, size_t *have, size_t need) {
   *have = need;
 }
 
+// Where a plan's device memory comes from: the context's allocations (counted against its
+// budget, freed with the plan), or consecutive 256-byte-aligned pieces of a fixed region that
+// nothing allocates (pw_estimate_noalloc's static scratch).
+struct PlanMem {
+  pw_ctx *ctx;
+  DevPlan *dp;
+  char *region = nullptr;  // fixed region, or NULL for allocations
+  size_t cap = 0, off = 0;
+  void *get(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    if (region) {
+      const size_t o = (off + 255) & ~(size_t)255;
+      if (o > cap || bytes > cap - o)
+        fail(PW_ENOMEM, "the static scratch (%zu bytes) is too small for this estimate", cap);
+      off = o + bytes;
+      return region + o;
+    }
+    void *p = dev_alloc(ctx, bytes);
+    dp->allocs.push_back({p, bytes});
+    return p;
+  }
+};
+
 template <typename T>
-T *upload(pw_ctx *ctx, DevPlan *dp, const std::vector<T> &v) {
+T *upload(PlanMem &m, const std::vector<T> &v) {
   if (v.empty()) return nullptr;
   size_t bytes = v.size() * sizeof(T);
-  T *p = (T *)dev_alloc(ctx, bytes);
-  dp->allocs.push_back({p, bytes});
+  T *p = (T *)m.get(bytes);
   HIPCHECK(hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice));
-  return p;
-}
-
-void *alloc_plan(pw_ctx *ctx, DevPlan *dp, size_t bytes) {
-  void *p = dev_alloc(ctx, bytes);
-  dp->allocs.push_back({p, bytes});
   return p;
 }
 
@@ -378,8 +435,13 @@ std::shared_ptr<const HostPlan> host_plan(pw_ctx *ctx, const pw_config &cfg) {
   return hp;
 }
 
-std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
+// A device plan of cfg: its tables uploaded, its workspace layout computed (bind_work points it
+// into a workspace).  With `region`, every table is carved from that fixed region (and *used
+// receives the bytes taken) instead of being allocated.
+std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg, char *region = nullptr,
+                                        size_t cap = 0, size_t *used = nullptr) {
   std::unique_ptr<DevPlan> dp(new DevPlan());
+  PlanMem M{ctx, dp.get(), region, cap, 0};
   dp->host = host_plan(ctx, *cfg);
   const HostPlan &h = *dp->host;
   dp->work = work_layout(h);
@@ -393,72 +455,72 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
     }
     if (h.prec == PW_FP32) {
       std::vector<float> twf(tw.begin(), tw.end());
-      dp->tw = upload(ctx, dp.get(), twf);
+      dp->tw = upload(M, twf);
     } else {
-      dp->tw = upload(ctx, dp.get(), tw);
+      dp->tw = upload(M, tw);
     }
-    dp->jobs = upload(ctx, dp.get(), h.jobs);
-    dp->ijobs = upload(ctx, dp.get(), h.ijobs);
-    dp->ajobs = upload(ctx, dp.get(), h.ajobs);
+    dp->jobs = upload(M, h.jobs);
+    dp->ijobs = upload(M, h.ijobs);
+    dp->ajobs = upload(M, h.ajobs);
     auto up_prune = [&](const Prune &p, DevPrune &d) {
-      d.ycnt = upload(ctx, dp.get(), p.ycnt);
-      d.yoff = upload(ctx, dp.get(), p.yoff);
-      d.pinfo = upload(ctx, dp.get(), p.pinfo);
-      d.moff = upload(ctx, dp.get(), p.moff);
-      d.modecoord = upload(ctx, dp.get(), p.modecoord);
-      d.goff = upload(ctx, dp.get(), p.goff);
-      d.gsize = upload(ctx, dp.get(), p.gsize);
+      d.ycnt = upload(M, p.ycnt);
+      d.yoff = upload(M, p.yoff);
+      d.pinfo = upload(M, p.pinfo);
+      d.moff = upload(M, p.moff);
+      d.modecoord = upload(M, p.modecoord);
+      d.goff = upload(M, p.goff);
+      d.gsize = upload(M, p.gsize);
     };
     up_prune(h.fwd, dp->fwd);
     up_prune(h.sph, dp->sph);
-    dp->bin_of_s2 = upload(ctx, dp.get(), h.bin_of_s2);
-    dp->ells = upload(ctx, dp.get(), h.ells);
-    dp->zrank = upload(ctx, dp.get(), h.zrank);
-    dp->zidx = upload(ctx, dp.get(), h.zidx);
-    dp->yidx = upload(ctx, dp.get(), h.yidx);
-    dp->iycnt = upload(ctx, dp.get(), h.iycnt);
-    dp->iyoff = upload(ctx, dp.get(), h.iyoff);
+    dp->bin_of_s2 = upload(M, h.bin_of_s2);
+    dp->ells = upload(M, h.ells);
+    dp->zrank = upload(M, h.zrank);
+    dp->zidx = upload(M, h.zidx);
+    dp->yidx = upload(M, h.yidx);
+    dp->iycnt = upload(M, h.iycnt);
+    dp->iyoff = upload(M, h.iyoff);
     auto up_real = [&](const std::vector<double> &v) -> void * {
       if (h.prec == PW_FP32) {
         std::vector<float> f(v.begin(), v.end());
-        return upload(ctx, dp.get(), f);
+        return upload(M, f);
       }
-      return upload(ctx, dp.get(), v);
+      return upload(M, v);
     };
     dp->winv = up_real(h.winv);
     dp->icoef = up_real(h.icoef);
-    dp->t_start = upload(ctx, dp.get(), h.t_start);
-    dp->t_sh = upload(ctx, dp.get(), h.t_sh);
-    dp->t_ell = upload(ctx, dp.get(), h.t_ell);
-    dp->t_p1 = upload(ctx, dp.get(), h.t_p1);
-    dp->t_p2 = upload(ctx, dp.get(), h.t_p2);
+    dp->t_start = upload(M, h.t_start);
+    dp->t_sh = upload(M, h.t_sh);
+    dp->t_ell = upload(M, h.t_ell);
+    dp->t_p1 = upload(M, h.t_p1);
+    dp->t_p2 = upload(M, h.t_p2);
     dp->t_coef = up_real(h.t_coef);
     // the mesh, spectrum buffers and paint tiles live in the lane's workspace (bind_work);
     // memory-lean: A holds the k-sphere of every field, B and C one group's x / y passes
     if (h.lean) {
-      dp->lean_jobs = upload(ctx, dp.get(), h.lean_jobs);
-      dp->lean_fmap = upload(ctx, dp.get(), h.lean_fmap);
+      dp->lean_jobs = upload(M, h.lean_jobs);
+      dp->lean_fmap = upload(M, h.lean_fmap);
     }
     // result rows: n_ell, or n_ell per series order for the one-pass per-order contraction
     const size_t rows = (size_t)std::max(h.nell, h.n_orders_native * h.nell) + 2;
-    dp->acc = (double *)alloc_plan(ctx, dp.get(), rows * h.n_bins * sizeof(double));
-    dp->out = (double *)alloc_plan(ctx, dp.get(), rows * h.n_bins * sizeof(double));
-    dp->ells_orders = upload(ctx, dp.get(), h.ells_orders);
-    dp->part_g = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
-    dp->part_r = (double *)alloc_plan(ctx, dp.get(), kScalarBlocks * kScalarCols * sizeof(double));
-    dp->norm = (DevNorm *)alloc_plan(ctx, dp.get(), sizeof(DevNorm));
+    dp->acc = (double *)M.get(rows * h.n_bins * sizeof(double));
+    dp->out = (double *)M.get(rows * h.n_bins * sizeof(double));
+    dp->ells_orders = upload(M, h.ells_orders);
+    dp->part_g = (double *)M.get(kScalarBlocks * kScalarCols * sizeof(double));
+    dp->part_r = (double *)M.get(kScalarBlocks * kScalarCols * sizeof(double));
+    dp->norm = (DevNorm *)M.get(sizeof(DevNorm));
     {
       const int ts = tile_size(h.N), nt = h.N / ts;
       dp->ntiles = nt * nt * nt;
-      dp->tile_counts = (int *)alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * sizeof(int));
-      dp->tile_offsets = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
-      dp->tile_cursor = (int *)alloc_plan(ctx, dp.get(), (size_t)dp->ntiles * sizeof(int));
-      dp->tile_slot = (int *)alloc_plan(ctx, dp.get(), (size_t)(dp->ntiles + 1) * sizeof(int));
-      dp->rowmask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
-      dp->rowlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * h.N * sizeof(int));
-      dp->planemask = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
-      dp->zlist = (int *)alloc_plan(ctx, dp.get(), (size_t)h.N * sizeof(int));
-      dp->occ_blockcnt = (int *)alloc_plan(ctx, dp.get(), (size_t)occupancy_blocks(h.N) * sizeof(int));
+      dp->tile_counts = (int *)M.get((size_t)dp->ntiles * sizeof(int));
+      dp->tile_offsets = (int *)M.get((size_t)(dp->ntiles + 1) * sizeof(int));
+      dp->tile_cursor = (int *)M.get((size_t)dp->ntiles * sizeof(int));
+      dp->tile_slot = (int *)M.get((size_t)(dp->ntiles + 1) * sizeof(int));
+      dp->rowmask = (int *)M.get((size_t)h.N * h.N * sizeof(int));
+      dp->rowlist = (int *)M.get((size_t)h.N * h.N * sizeof(int));
+      dp->planemask = (int *)M.get((size_t)h.N * sizeof(int));
+      dp->zlist = (int *)M.get((size_t)h.N * sizeof(int));
+      dp->occ_blockcnt = (int *)M.get((size_t)occupancy_blocks(h.N) * sizeof(int));
       if ((size_t)dp->ntiles * sizeof(int) > ctx->lds_per_block)
         fail(PW_EINVAL, "n_mesh too large for the tile sort on this device (%zu bytes of LDS per block)",
              ctx->lds_per_block);
@@ -467,6 +529,7 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg) {
     free_plan(ctx, dp.get());
     throw;
   }
+  if (used) *used = M.off;
   return dp;
 }
 
@@ -665,17 +728,27 @@ std::vector<ColTune> fz_candidates(int nfields) {
   return c;
 }
 
+// An estimate whose device memory is all in place (pw_estimate_noalloc): the plan with its
+// tables and workspace, the particle records, and a host buffer for the results.
+struct Placed {
+  DevPlan *dp;
+  void *records;
+  double *host_res;  // (rows + 2) * n_bins doubles + DevNorm, pageable
+};
+
 // Enqueue the whole estimate on the lane's stream, ending with the copy of the results into
-// the lane's pinned buffer and the lane's completion event.  Returns the plan used.
+// the lane's pinned buffer (or `placed`'s) and the lane's completion event.  Returns the plan
+// used.
 DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_catalog *gal,
-                         const pw_catalog *ran, const pw_norm *norm, bool orders = false) {
+                         const pw_catalog *ran, const pw_norm *norm, bool orders = false,
+                         const Placed *placed = nullptr) {
   HIPCHECK(hipSetDevice(ctx->device));
   ensure_sh(ctx->device);
-  DevPlan *dp = get_plan(ctx, ln, cfg);
-  bind_work(ctx, ln, dp);
+  DevPlan *dp = placed ? placed->dp : get_plan(ctx, ln, cfg);
+  if (!placed) bind_work(ctx, ln, dp);
   const HostPlan &h = *dp->host;
   hipStream_t s = ln.stream;
-  ln.last = dp;
+  ln.last = placed ? nullptr : dp;
   const void *gnb = nullptr, *rnb = nullptr;
   const void *gx = stage_catalog(ctx, ln, gal, 0, &gnb);
   const void *rx = stage_catalog(ctx, ln, ran, 1, &rnb);
@@ -700,17 +773,18 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
                        use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
   // a2: paint (particles read once, mesh written once)
   mark("paint", 4.0 * isz_g * gal->n + 4.0 * isz_r * ran->n + ncell * rsz);
-  ensure_buffer(ctx, &ln.records, &ln.records_bytes, (size_t)(gal->n + ran->n) * 4 * (size_t)rsz);
+  if (!placed) ensure_buffer(ctx, &ln.records, &ln.records_bytes, (size_t)(gal->n + ran->n) * 4 * (size_t)rsz);
+  void *records = placed ? placed->records : ln.records;
   launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
   launch_fill(s, dp->rowmask, (size_t)h.N * h.N, 0);
   launch_tile_count(s, gx, gal->n, gal->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
   launch_tile_count(s, rx, ran->n, ran->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
   launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
   launch_tile_scatter(s, gx, gal->n, gal->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0,
-                      dp->tile_cursor, ln.records);
+                      dp->tile_cursor, records);
   launch_tile_scatter(s, rx, ran->n, ran->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1,
-                      dp->tile_cursor, ln.records);
-  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, ln.records,
+                      dp->tile_cursor, records);
+  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records,
                     dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
   launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->occ_blockcnt, dp->norm);
   // a3 + a4: weighted fields and the forward transforms
@@ -872,29 +946,30 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   HIPCHECK(hipGetLastError());
   const size_t nres = (size_t)(ln.res_rows + 2) * h.n_bins;
   const size_t need = nres * sizeof(double) + sizeof(DevNorm);
-  if (ln.host_res_bytes < need) {
+  if (!placed && ln.host_res_bytes < need) {
     if (ln.host_res) (void)hipHostFree(ln.host_res);
     ln.host_res = nullptr;
     ln.host_res_bytes = 0;
     HIPCHECK(hipHostMalloc((void **)&ln.host_res, need, hipHostMallocDefault));
     ln.host_res_bytes = need;
   }
-  HIPCHECK(hipMemcpyAsync(ln.host_res, dp->out, nres * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipMemcpyAsync((char *)ln.host_res + nres * sizeof(double), dp->norm, sizeof(DevNorm),
+  double *res_host = placed ? placed->host_res : ln.host_res;
+  HIPCHECK(hipMemcpyAsync(res_host, dp->out, nres * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync((char *)res_host + nres * sizeof(double), dp->norm, sizeof(DevNorm),
                           hipMemcpyDeviceToHost, s));
   HIPCHECK(hipEventRecord(ln.done, s));
   return dp;
 }
 
-// After the lane's completion event: check the flags and write the caller's outputs.
-void finish_estimate(Lane &ln, const DevPlan *dp, pw_norm *norm, double *out, double *bin_mean,
-                     int64_t *counts) {
+// After the lane's completion event: check the flags and write the caller's outputs from the
+// copied results `res`.
+void finish_estimate(Lane &ln, const DevPlan *dp, const double *res, pw_norm *norm, double *out,
+                     double *bin_mean, int64_t *counts) {
   const HostPlan &h = *dp->host;
   const int rows = ln.res_rows;
   const size_t nres = (size_t)(rows + 2) * h.n_bins;
-  const double *res = ln.host_res;
   DevNorm dn;
-  std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
+  std::memcpy(&dn, (const char *)res + nres * sizeof(double), sizeof(DevNorm));
   if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
   if (dn.flags & 2)
     fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
@@ -950,6 +1025,9 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
   ctx->reserved += res.bytes;
 }
 
+void complete_main(Lane &ln, const DevPlan *dp, const double *res_host, pw_norm *norm, double *out,
+                   double *bin_mean, int64_t *counts);
+
 void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
                   pw_norm *norm, double *out, double *bin_mean, int64_t *counts, bool orders = false) {
   check_request(cfg, gal, ran, norm, out);
@@ -959,6 +1037,13 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   Lane &ln = *ctx->main;
   DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm, orders);
   res.release();
+  complete_main(ln, dp, ln.host_res, norm, out, bin_mean, counts);
+}
+
+// Lane 0 after launch_estimate: wait, read the stage times, scale the forward passes'
+// algorithmic bytes by the measured occupancy, and write the outputs.
+void complete_main(Lane &ln, const DevPlan *dp, const double *res_host, pw_norm *norm, double *out,
+                   double *bin_mean, int64_t *counts) {
   HIPCHECK(hipEventSynchronize(ln.done));
   for (int i = 0; i < ln.n_stages; ++i) {
     float ms = -1.0f;
@@ -970,7 +1055,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     const HostPlan &h = *dp->host;
     const size_t nres = (size_t)(ln.res_rows + 2) * h.n_bins;
     DevNorm dn;
-    std::memcpy(&dn, (const char *)ln.host_res + nres * sizeof(double), sizeof(DevNorm));
+    std::memcpy(&dn, (const char *)res_host + nres * sizeof(double), sizeof(DevNorm));
     const double N = h.N, rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2 * rsz;
     const double fr = dn.nrows_occ / (N * N), fp = dn.nplanes_occ / N;
     const double modes_real = h.fwd.full ? N * (double)h.fwd.npen_real : (double)h.fwd.nretained;
@@ -988,7 +1073,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
     ln.occ_rows = dn.nrows_occ;
     ln.occ_planes = dn.nplanes_occ;
   }
-  finish_estimate(ln, dp, norm, out, bin_mean, counts);
+  finish_estimate(ln, dp, res_host, norm, out, bin_mean, counts);
 }
 
 // pw_submit: copy the request's pageable host catalogs (and the randoms' nbar) into one pinned
@@ -1024,6 +1109,44 @@ void stage_pinned(pw_ctx *ctx, Req *r) {
     *p.ptr = dst;
     dst += up(p.bytes);
   }
+}
+
+// pw_estimate_noalloc: pw_estimate with every device buffer in the static scratch (nothing is
+// allocated on the device or pinned on the host); device-resident catalogs only.
+void run_estimate_noalloc(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                          pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  check_request(cfg, gal, ran, norm, out);
+  if ((gal->n > 0 && !gal->on_device) || (ran->n > 0 && !ran->on_device))
+    fail(PW_EINVAL, "pw_estimate_noalloc reads device-resident catalogs only (on_device = 1)");
+  std::string why;
+  char *region = scratch_of(ctx->device, &why);
+  if (!region) fail(PW_EDEVICE, "the static scratch of device %d: %s", ctx->device, why.c_str());
+  std::shared_ptr<const HostPlan> hp = host_plan(ctx, *cfg);
+  const size_t rsz = hp->prec == PW_FP32 ? 4 : 8;
+  const size_t rec = (size_t)(gal->n + ran->n) * 4 * rsz;
+  const size_t need = table_bytes(*hp) + work_layout(*hp).total + rec + 2 * 256;
+  if (need > kScratchBytes)
+    fail(PW_ENOMEM,
+         "pw_estimate_noalloc: this estimate needs about %zu bytes of device scratch, the static scratch holds "
+         "%zu (%zu MiB); use pw_estimate",
+         need, kScratchBytes, kScratchBytes >> 20);
+  MainBusy busy(ctx);
+  Lane &ln = *ctx->main;
+  size_t used = 0;
+  std::unique_ptr<DevPlan> dp = build_dev_plan(ctx, cfg, region, kScratchBytes, &used);
+  PlanMem M{ctx, dp.get(), region, kScratchBytes, used};
+  char *w = (char *)M.get(dp->work.total);
+  dp->mesh = w + dp->work.mesh;
+  dp->bufA = w + dp->work.bufA;
+  dp->bufB = w + dp->work.bufB;
+  dp->bufC = hp->lean ? w + dp->work.bufC : nullptr;
+  dp->tile_blocks = w + dp->work.tiles;
+  void *records = M.get(rec);
+  const size_t words = (size_t)(hp->nell + 2) * hp->n_bins + (sizeof(DevNorm) + 7) / 8;
+  if (ln.noalloc_res.size() < words) ln.noalloc_res.resize(words);
+  Placed pl{dp.get(), records, ln.noalloc_res.data()};
+  launch_estimate(ctx, ln, cfg, gal, ran, norm, false, &pl);
+  complete_main(ln, dp.get(), pl.host_res, norm, out, bin_mean, counts);
 }
 
 Lane *make_lane(int id, hipStream_t user_stream) {
@@ -1170,7 +1293,7 @@ void worker_loop(pw_ctx *ctx) {
         r->err = std::string("device error: ") + hipGetErrorString(q);
       } else {
         try {
-          finish_estimate(ln, r->dp, r->norm_out, r->out, r->bin_mean, r->counts);
+          finish_estimate(ln, r->dp, ln.host_res, r->norm_out, r->out, r->bin_mean, r->counts);
           r->status = PW_OK;
         } catch (const Fail &f) {
           r->status = f.code;
@@ -1261,6 +1384,7 @@ int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_strea
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     ensure_sh(device);
+    resolve_scratch(device);
     {
       int lds = 0;
       HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
@@ -1310,6 +1434,22 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const 
   if (!ctx) return PW_EINVAL;
   try {
     run_estimate(ctx, cfg, gal, ran, norm, out, bin_mean, counts);
+  } catch (const Fail &f) {
+    set_err(ctx, f.msg);
+    return f.code;
+  } catch (const std::exception &e) {
+    set_err(ctx, e.what());
+    return PW_EINVAL;
+  }
+  set_err(ctx, std::string());
+  return PW_OK;
+}
+
+int pw_estimate_noalloc(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
+                        pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  if (!ctx) return PW_EINVAL;
+  try {
+    run_estimate_noalloc(ctx, cfg, gal, ran, norm, out, bin_mean, counts);
   } catch (const Fail &f) {
     set_err(ctx, f.msg);
     return f.code;

@@ -70,6 +70,9 @@ def _load():
     lib.pw_estimate.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                                 C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_int64)]
+    lib.pw_estimate_noalloc.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
+                                        C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_int64)]
     lib.pw_estimate_orders.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                                        C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]
@@ -259,6 +262,12 @@ class Context:
     def estimate(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """Run one estimate.  norm = (alpha_r, I, S) to impose the normalisation."""
         return self._run(_lib.pw_estimate, (cfg.n_ell, cfg.n_bins), cfg, gal_xyzw, ran_xyzw, ran_nbar, norm)
+
+    def estimate_noalloc(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
+        """pw_estimate_noalloc: the estimate in the library's static device scratch (device
+        tensors only; small configurations)."""
+        return self._run(_lib.pw_estimate_noalloc, (cfg.n_ell, cfg.n_bins), cfg, gal_xyzw, ran_xyzw,
+                         ran_nbar, norm)
 
     def estimate_orders(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """Each series order's contribution: values[o] holds the terms of order theta^(2o)
