@@ -1,17 +1,25 @@
-"""Benchmark: bisector P_l on the 512^3 headline workload (catalogs/s, served vs plain).
+"""Benchmark: bisector P_l on the 512^3 headline workload (catalogs/s, served vs plain), and the
+serving stream (p50/p99 latency under Poisson arrivals).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--lanes 2] [--workload C3]
-                [--no-cpu-baseline] [--no-served] [--copy-calibration]
+                [--no-cpu-baseline] [--no-served] [--no-serving] [--serving-requests 256]
+                [--copy-calibration] [--stream N] [--figures]
 
 A step is one pass of the whole hot path (FP64 scalars, paint, weighted fields, pruned forward
 FFTs, contraction and FP64 binning) over one synthetic catalog already resident in HBM,
 through the C ABI.
-  plain   one synchronous pw_estimate per catalog on one stream
-  served  K catalogs submitted at once to the serving loop (pw_submit), which runs them on
-          `--lanes` concurrent lanes; latency = submit -> result on the host
-`value` is the served throughput; the plain one is reported beside it.  The roofline entry is
-for the dominant kernel of the plain run (HIP events on its stream).  --copy-calibration also
-runs one device-to-device copy of known size, the reference for the HBM traffic counters.
+  plain    one synchronous pw_estimate per catalog on one stream, stage timing off
+  stages   a separate pass with stage timing on (HIP events on the library's stream): the
+           per-stage times and the roofline of the dominant kernel
+  served   K catalogs submitted at once to the serving loop (pw_submit), which runs them on
+           `--lanes` concurrent lanes: saturated throughput
+  serving  the serving workload: a stream of mixed requests (galaxies ~ U[1e5, 4e6] with 5x
+           randoms, meshes 128/256/512, midpoint or bisector) whose catalogs sit in pinned host
+           memory; capacity from a plain pass, then Poisson arrivals at 0.7x and 1.5x of it;
+           latency = pw_submit -> result on the host (includes the copy to the device)
+`value` is the served throughput of the headline workload; `latency_ms` is the serving
+stream's at 0.7x load.  --stream N prints only a serving stream of N requests.  --figures
+writes the per-order and convergence analogues of the paper's figures to figures/.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -38,6 +46,10 @@ KERNEL_NAMES = {"fx": "k_fx", "fy": "k_fy", "fz": "k_fz", "contract": "k_contrac
 KERNEL_NAMES_MID = {"fx": "k_fx", "fy": "k_fy", "fziz": "k_fziz", "iy": "k_fy", "ix": "k_ix", "ix_bin": "k_ix",
                     "reweight": "k_reweight", "afx": "k_fx", "afy": "k_fy", "afz": "k_fz",
                     "contract": "k_contract_mid"}
+# bisector xi_l: forward passes, per-mode targets, inverse z / y passes, c2r x pass with r-binning
+KERNEL_NAMES_BXI = {"fx": "k_fx", "fy": "k_fy", "fz": "k_fz", "targets": "k_targets", "iz": "k_iz",
+                    "iy": "k_fy", "ix_bin": "k_ix"}
+GOLDEN_CASE = {"C3": "c3_bisector_pk", "C2": "c2_midpoint_pk", "C4": "c4_midpoint_xi", "C4B": "c4_bisector_xi"}
 
 
 def log(*a):
@@ -67,7 +79,8 @@ def describe(wl, name, cfg):
 
 def cpu_baseline(name, frac=0.25, n_mesh=96):
     """The oracle as it stands, on a bounded sample of the workload: the same catalog
-    subsampled to `frac` of its particles, on an n_mesh^3 mesh with the same bins/orders."""
+    subsampled to `frac` of its particles, on an n_mesh^3 mesh with the same bins/orders; plus
+    the oracle's recorded time on the full workload (tests/golden)."""
     from oracle.estimators import Config as OConfig, pk_bisector
     from synthetic import WORKLOADS, make_workload_catalog
     wl = WORKLOADS[name]
@@ -82,12 +95,23 @@ def cpu_baseline(name, frac=0.25, n_mesh=96):
     t0 = time.perf_counter()
     pk_bisector(g, r, cfg)
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "catalogs/s", "cores": 1, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"{name} catalog subsampled to {frac:g} of its particles "
-                      f"({len(g['pos'])} galaxies + {len(r['pos'])} randoms) on a {n_mesh}^3 mesh "
-                      f"(full workload: {wl.N}^3), same l<=4, order {wl.order}, bins; numpy FP64, "
-                      f"single-threaded FFTs (one catalog per value^-1 seconds)"}
+    cores = len(os.sched_getaffinity(0))
+    out = {"value": 1.0 / dt, "unit": "catalogs/s", "cores": cores, "kind": "oracle",
+           "seconds": dt, "fft_threads": os.cpu_count(),
+           "sample": f"{name} catalog subsampled to {frac:g} of its particles "
+                     f"({len(g['pos'])} galaxies + {len(r['pos'])} randoms) on a {n_mesh}^3 mesh "
+                     f"(full workload: {wl.N}^3), same l<=4, order {wl.order}, bins; numpy/scipy FP64, "
+                     f"FFTs on os.cpu_count() threads over the {cores} cores this process may use"}
+    gold = os.path.join(ROOT, "tests", "golden", f"full_{GOLDEN_CASE.get(name, '')}.json")
+    if os.path.exists(gold):
+        with open(gold) as fh:
+            gd = json.load(fh)
+        if "seconds" in gd:
+            out["full_size"] = {"value": 1.0 / gd["seconds"], "seconds": gd["seconds"], "oracle": gd["oracle"],
+                                "where": gd.get("host", "the build container (8 cores, no GPU), when the "
+                                                        "expected values were written"),
+                                "cores": gd.get("host_cores", 8)}
+    return out
 
 
 def oracle_check(workload, midpoint_parity, cfg, values):
@@ -95,7 +119,7 @@ def oracle_check(workload, midpoint_parity, cfg, values):
     same catalog (catalog 0 of the workload, FP32-rounded inputs) and configuration, stored by
     tests/golden/make_full_size.py; in units of the oracle's monopole scale.  None when no
     stored values match the configuration."""
-    case = {"C3": "c3_bisector_pk", "C2": "c2_midpoint_pk", "C4": "c4_midpoint_xi"}.get(workload)
+    case = GOLDEN_CASE.get(workload)
     path = os.path.join(ROOT, "tests", "golden", f"full_{case}.json")
     if case is None or midpoint_parity != "even" or not os.path.exists(path):
         return None
@@ -125,39 +149,70 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+def _profile_text(name):
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None, path
+    return open(path).read(), path
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
     summary is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "bisector_pk_512_traffic.txt")
-    if not os.path.exists(path):
+    txt, path = _profile_text("bisector_pk_512_traffic.txt")
+    if txt is None:
         return None, None
-    txt = open(path).read()
     m = re.search(r"^source_digest\s*=\s*(\S+)", txt, re.M)
     if not m or m.group(1) != source_digest():
         return None, "counters taken on other kernel sources"
     m = re.search(rf"^{re.escape(kernel)}\s+traffic_bytes_per_launch\s*=\s*(\S+)", txt, re.M)
     if not m:
         return None, None
-    return float(m.group(1)), path
+    return float(m.group(1)), os.path.relpath(path, ROOT)
+
+
+def rocprof_avg_us(kernel):
+    """Average duration of `kernel` from the committed kernel-trace summary, when it was taken
+    on these kernel sources; else None."""
+    txt, path = _profile_text("bisector_pk_512_kernels.md")
+    if txt is None:
+        return None, None
+    m = re.search(r"source_digest\s*=\s*(\S+)", txt)
+    if not m or m.group(1) != source_digest():
+        return None, "kernel trace taken on other kernel sources"
+    m = re.search(rf"^\|\s*pw::{re.escape(kernel)}<[^|]*\|\s*\d+\s*\|\s*([0-9.]+)\s*\|", txt, re.M)
+    if not m:
+        return None, None
+    return float(m.group(1)), os.path.relpath(path, ROOT)
 
 
 def plain_run(ctx, cfg, gx, rx, rn, steps, warmup, torch):
     for _ in range(warmup):
         ctx.estimate(cfg, gx, rx, ran_nbar=rn)
     torch.cuda.synchronize()
-    lat, stage_ms, stage_bytes = [], {}, {}
+    lat = []
     t0 = time.perf_counter()
     res = None
     for _ in range(steps):
         t1 = time.perf_counter()
         res = ctx.estimate(cfg, gx, rx, ran_nbar=rn)
         lat.append((time.perf_counter() - t1) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, lat, res
+
+
+def stage_run(ctx, cfg, gx, rx, rn, steps):
+    """Per-stage GPU times from HIP events on the library's stream (timing on for this pass only)."""
+    ctx.set_timing(True)
+    stage_ms, stage_bytes = {}, {}
+    for _ in range(steps):
+        ctx.estimate(cfg, gx, rx, ran_nbar=rn)
         for name, ms, by in ctx.stages():
             stage_ms.setdefault(name, []).append(ms)
             stage_bytes[name] = by
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    return elapsed, lat, stage_ms, stage_bytes, res
+    ctx.set_timing(False)
+    return stage_ms, stage_bytes
 
 
 def served_run(ctx, cfg, gx, rx, rn, steps, warmup, torch):
@@ -185,86 +240,93 @@ def served_run(ctx, cfg, gx, rx, rn, steps, warmup, torch):
     return elapsed, lat, res
 
 
+# ------------------------------------------------------------------------------ serving stream
+
 def stream_requests(pw, torch, n_req, seed=5):
-    """A mixed stream of P_l requests in the shape of the serving workload: galaxy counts
-    uniform in [1e5, 4e6] with 5x randoms, meshes 128/256/512, midpoint or bisector by a fair
-    coin, l <= 4, order 4.  Catalogs are seeded subsamples of one lognormal cone per geometry
-    (bisector: r in [400, 2000], L = 2700; midpoint: r in [500, 1500], box doubled, L = 4000),
-    resident on the device.  Returns (label, cfg, gal, ran, nbar) tuples."""
+    """The serving workload: P_l requests with galaxy counts uniform in [1e5, 4e6] and 5x
+    randoms, a mesh of 128, 256 or 512, the midpoint or the bisector by a fair coin, l <= 4,
+    order 4, k-bins 0.005 .. min(0.40, k_Nyq) by 0.005.  Catalogs are windows of one shuffled
+    lognormal cone per geometry (bisector: r in [400, 2000], L = 2700; midpoint: r in
+    [500, 1500], box doubled, L = 4000) held in pinned host memory, so any window is a uniform
+    subsample; nbar scales with the subsampled count (one pinned array holds every request's).
+    Returns (label, cfg, gal, ran, nbar) tuples of pinned host tensors."""
     from synthetic import WORKLOADS, make_workload_catalog, to_xyzw
     rng = np.random.default_rng(seed)
     pools = {}
     for los, name in ((pw.PW_BISECTOR, "C3"), (pw.PW_MIDPOINT, "C2")):
         g, r = make_workload_catalog(name, index=1, n_gal=4_000_000)
-        # shuffled once, so that any window of consecutive records is a uniform subsample
-        gx = to_xyzw(g, np.float32)[rng.permutation(len(g["pos"]))]
-        rx = to_xyzw(r, np.float32)[rng.permutation(len(r["pos"]))]
+        gx = torch.from_numpy(to_xyzw(g, np.float32)[rng.permutation(len(g["pos"]))]).pin_memory()
+        rx = torch.from_numpy(to_xyzw(r, np.float32)[rng.permutation(len(r["pos"]))]).pin_memory()
         pools[los] = (gx, rx, float(r["nbar"][0]), WORKLOADS[name])
-    out = []
+    spec = []
     for i in range(n_req):
         los = pw.PW_BISECTOR if rng.random() < 0.5 else pw.PW_MIDPOINT
         N = int(rng.choice([128, 256, 512]))
-        gx, rx, nbar, wl = pools[los]
         ng = int(rng.uniform(1e5, 4e6))
+        gx = pools[los][0]
+        rx = pools[los][1]
         g0 = int(rng.integers(0, len(gx) - ng + 1))
         r0 = int(rng.integers(0, len(rx) - 5 * ng + 1))
-        # nbar scales with the subsampled count (the weights stay those of the pool)
-        nb = nbar * ng / len(gx)
+        spec.append((los, N, ng, g0, r0))
+    nbar_all = torch.empty(sum(5 * s[2] for s in spec), dtype=torch.float32).pin_memory()
+    out, off = [], 0
+    for los, N, ng, g0, r0 in spec:
+        gx, rx, nbar, wl = pools[los]
+        nbar_all[off:off + 5 * ng] = nbar * ng / len(gx)
         kny = np.pi * N / wl.L
         nbins = int((min(0.40, kny) - 0.005) / 0.005)
         cfg = pw.Config(stat=pw.PW_PK, los=los, assign=pw.PW_TSC, prec=pw.PW_FP32, n_mesh=N, box_len=wl.L,
                         box_origin=wl.b0, ell_max=4, order=4, compensate=1, bin_lo=0.005, bin_width=0.005,
                         n_bins=nbins)
-        g = torch.from_numpy(gx[g0:g0 + ng]).cuda()
-        r = torch.from_numpy(rx[r0:r0 + 5 * ng]).cuda()
-        n = torch.full((5 * ng,), nb, dtype=torch.float32, device="cuda")
-        out.append((f"{'bis' if los == pw.PW_BISECTOR else 'mid'}{N} ng={ng}", cfg, g, r, n))
+        out.append((f"{'bis' if los == pw.PW_BISECTOR else 'mid'}{N} ng={ng}", cfg, gx[g0:g0 + ng],
+                    rx[r0:r0 + 5 * ng], nbar_all[off:off + 5 * ng]))
+        off += 5 * ng
     return out
 
 
-def stream_bench(a):
-    """Serving under Poisson arrivals: capacity from one plain pass over the stream, then (after
-    one untimed served pass that warms the lanes) the same requests submitted at exponential
-    inter-arrival times at 0.7x and 1.5x that rate; latency runs from pw_submit to the result
-    on the host (inputs device-resident)."""
-    import torch
-    from paper_2102_08384_amd import pw
-    log("building a stream of", a.stream, "requests")
-    reqs = stream_requests(pw, torch, a.stream)
-    torch.cuda.synchronize()
-    ctx = pw.Context(0, stream=torch.cuda.current_stream().cuda_stream)
-    ctx.set_lanes(a.lanes)
-    # warm every configuration once (plans built, kernels loaded)
+def _pct(v):
+    return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99))} if len(v) else None
+
+
+def serving_stream(pw, torch, n_req, lanes, loads=(0.7, 1.5)):
+    """Capacity from one plain pass over the stream (one pw_estimate after another), then, after
+    one untimed served pass that warms the lanes, the same requests at exponential
+    inter-arrival times at each load x capacity; latency from pw_submit to the result on the
+    host.  Failed requests are counted, not retried."""
+    log("building a serving stream of", n_req, "requests (catalogs in pinned host memory)")
+    t0 = time.perf_counter()
+    reqs = stream_requests(pw, torch, n_req)
+    log(f"stream ready in {time.perf_counter() - t0:.1f}s")
+    ctx = pw.Context(0)
+    ctx.set_lanes(lanes)
     seen = set()
-    for lab, cfg, g, r, n in reqs:
+    for lab, cfg, g, r, n in reqs:         # every configuration once: plans built, kernels loaded
         key = (cfg.los, cfg.n_mesh)
         if key not in seen:
             seen.add(key)
             ctx.estimate(cfg, g, r, ran_nbar=n)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain_lat = []
     for lab, cfg, g, r, n in reqs:
         t1 = time.perf_counter()
         ctx.estimate(cfg, g, r, ran_nbar=n)
         plain_lat.append((time.perf_counter() - t1) * 1e3)
-    plain_el = time.perf_counter() - t0
-    cap = len(reqs) / plain_el
-    log(f"plain pass: {cap:.2f} requests/s")
-    out = {"metric": "serving stream (mixed P_l requests) requests/s and latency", "unit": "requests/s",
-           "n_gpus": 1, "requests": len(reqs), "lanes": a.lanes,
+    cap = len(reqs) / (time.perf_counter() - t0)
+    log(f"serving: plain pass {cap:.2f} requests/s")
+    mix = {}
+    for lab, *_ in reqs:
+        k = lab.split()[0]
+        mix[k] = mix.get(k, 0) + 1
+    out = {"requests": len(reqs), "lanes": lanes, "mix_counts": mix,
            "mix": "N_g ~ U[1e5, 4e6] + 5 N_g randoms; mesh 128/256/512; midpoint (L = 4000) or bisector "
-                  "(L = 2700) by a fair coin; l <= 4, order 4; FP32; catalogs device-resident",
-           "plain": {"value": cap, "latency_ms": {"p50": float(np.percentile(plain_lat, 50)),
-                                                  "p99": float(np.percentile(plain_lat, 99))}}}
-    # warm the serving lanes: every request once, submitted at once (plans and workspaces)
-    t0 = time.perf_counter()
+                  "(L = 2700) by a fair coin; l <= 4, order 4; FP32; catalogs in pinned host memory "
+                  "(copied to the device inside each request)",
+           "plain": {"value": cap, "unit": "requests/s", "latency_ms": _pct(plain_lat)}}
     warm = [ctx.submit(cfg, g, r, ran_nbar=n) for lab, cfg, g, r, n in reqs]
     for t in warm:
         t.wait()
-    log(f"served warm-up pass (saturated, cold lanes): {len(reqs) / (time.perf_counter() - t0):.2f} requests/s")
     rng = np.random.default_rng(11)
-    for load in (0.7, 1.5):
+    for load in loads:
         gaps = rng.exponential(1.0 / (load * cap), len(reqs))
         arrivals = np.cumsum(gaps) - gaps[0]
         torch.cuda.synchronize()
@@ -274,7 +336,7 @@ def stream_bench(a):
         failed = []
 
         def poll_all():
-            # completion times are taken while the later requests are still being submitted
+            # completion times are taken while later requests are still being submitted
             for i, t in enumerate(tickets):
                 if done[i] is None:
                     try:
@@ -289,20 +351,33 @@ def stream_bench(a):
                 poll_all()
                 time.sleep(5e-5)
             sub.append(time.perf_counter())
-            tickets.append(ctx.submit(cfg, g, r, ran_nbar=n))
+            try:
+                tickets.append(ctx.submit(cfg, g, r, ran_nbar=n))
+            except pw.PwError as e:        # refused at submission (queue full)
+                failed.append(f"{lab}: {e}")
+                tickets.append(None)
+                done[i] = time.perf_counter()
         while any(d is None for d in done):
             poll_all()
             time.sleep(1e-4)
         el = max(done) - t0
-        lat = [(d - s_) * 1e3 for s_, d in zip(sub, done)]
-        out[f"served_at_{load}x"] = {"offered": load * cap, "value": (len(reqs) - len(failed)) / el,
-                                     "failed": failed,
-                                     "latency_ms": {"p50": float(np.percentile(lat, 50)),
-                                                    "p99": float(np.percentile(lat, 99))}}
-        log(f"served at {load}x: {len(reqs) / el:.2f} requests/s, p50 {np.percentile(lat, 50):.1f} ms")
+        lat = [(d - s_) * 1e3 for s_, d, t in zip(sub, done, tickets) if t is not None]
+        out[f"at_{load}x"] = {"offered": load * cap, "value": (len(reqs) - len(failed)) / el,
+                              "unit": "requests/s", "failed": len(failed), "failures": failed[:5],
+                              "latency_ms": _pct(lat)}
+        log(f"serving at {load}x: {(len(reqs) - len(failed)) / el:.2f} requests/s, p50 {np.percentile(lat, 50):.1f} "
+            f"ms, p99 {np.percentile(lat, 99):.1f} ms, {len(failed)} failed")
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
+
+# ------------------------------------------------------------------------------ figures
+
+def figures_leg(pw, torch):
+    raise NotImplementedError
+
+
+# ------------------------------------------------------------------------------ main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -313,6 +388,8 @@ def main():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-orders", action="store_true")
     ap.add_argument("--midpoint-parity", choices=["even", "all"], default="even",
@@ -320,19 +397,25 @@ def main():
     ap.add_argument("--memory-lean", action="store_true",
                     help="bisector P_l: forward transforms in groups of fields (less device memory)")
     ap.add_argument("--stream", type=int, default=0,
-                    help="instead of the headline: a mixed stream of this many requests under Poisson "
-                         "arrivals (serving throughput and latency)")
+                    help="only a serving stream of this many requests (throughput and latency)")
+    ap.add_argument("--figures", action="store_true",
+                    help="write the analogues of the paper's per-order and convergence figures")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
-    if a.stream > 0:
-        stream_bench(a)
-        return
-
     import torch
     from paper_2102_08384_amd import pw
+    if a.figures:
+        print(json.dumps(figures_leg(pw, torch)), flush=True)
+        return
+    if a.stream > 0:
+        out = {"metric": "serving stream (mixed P_l requests) requests/s and latency", "n_gpus": 1}
+        out.update(serving_stream(pw, torch, a.stream, a.lanes))
+        print(json.dumps(out), flush=True)
+        return
+
     from synthetic import WORKLOADS, make_workload_catalog, to_xyzw
 
     wl = WORKLOADS[a.workload]
@@ -346,7 +429,7 @@ def main():
     rn = torch.from_numpy(ran["nbar"].astype(np.float32)).to(dev)
     cfg = workload_config(pw, a.workload, 1 if a.midpoint_parity == "all" else 0)
     cfg.memory_lean = 1 if a.memory_lean else 0
-    knames = KERNEL_NAMES if wl.los == "bisector" else KERNEL_NAMES_MID
+    knames = (KERNEL_NAMES if wl.stat == "pk" else KERNEL_NAMES_BXI) if wl.los == "bisector" else KERNEL_NAMES_MID
     stream = torch.cuda.current_stream(dev)
     if a.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -357,26 +440,26 @@ def main():
         log(f"calibration copy of {COPY_BYTES} bytes done")
         del src, dst
     ctx = pw.Context(0, stream=stream.cuda_stream)
-    ctx.set_timing(True)
     ctx.set_lanes(a.lanes)
 
-    log("plain: warmup", a.warmup, "then", a.steps, "steps")
-    p_el, p_lat, stage_ms, stage_bytes, res = plain_run(ctx, cfg, gx, rx, rn, a.steps, a.warmup, torch)
+    log("plain: warmup", a.warmup, "then", a.steps, "steps (stage timing off)")
+    p_el, p_lat, res = plain_run(ctx, cfg, gx, rx, rn, a.steps, a.warmup, torch)
     plain_value = a.steps / p_el
     log(f"plain {plain_value:.2f} catalogs/s")
+    n_stage = max(3, a.steps // 4)
+    stage_ms, stage_bytes = stage_run(ctx, cfg, gx, rx, rn, n_stage)
     served = None
     if not a.no_served:
         log("served:", a.lanes, "lanes, warmup", a.warmup, "then", a.steps, "catalogs")
         s_el, s_lat, s_res = served_run(ctx, cfg, gx, rx, rn, a.steps, a.warmup, torch)
         served = {"value": a.steps / s_el, "ms_per_catalog": s_el * 1e3 / a.steps, "lanes": a.lanes,
-                  "latency_ms": {"p50": float(np.percentile(s_lat, 50)),
-                                 "p99": float(np.percentile(s_lat, 99))},
-                  "arrivals": f"{a.steps} catalogs submitted at once (saturated queue)",
+                  "latency_ms_saturated": _pct(s_lat),
+                  "arrivals": f"{a.steps} catalogs submitted at once (saturated queue: the latency is queue depth)",
                   "max_abs_diff_vs_plain": float(np.max(np.abs(s_res["values"] - res["values"])))}
         log(f"served {served['value']:.2f} catalogs/s")
 
     orders = None
-    if not a.no_orders:
+    if not a.no_orders and wl.stat == "pk":
         # each series order's terms separately (one pass for the bisector P_l)
         for _ in range(max(1, a.warmup)):
             ctx.estimate_orders(cfg, gx, rx, ran_nbar=rn)
@@ -397,13 +480,26 @@ def main():
               for n, v in stage_ms.items()}
     dom = max((n for n in stages if n in knames), key=lambda n: stages[n]["ms"])
     ach = stages[dom]["GBps"]
-    traffic, tsrc = counter_traffic(knames[dom]) if a.workload == "C3" else (None, None)
+    headline = a.workload == "C3" and not a.memory_lean
+    traffic, tsrc = counter_traffic(knames[dom]) if headline else (None, None)
+    rp_us, rp_src = rocprof_avg_us(knames[dom]) if headline else (None, None)
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": knames[dom], "algorithmic_bytes_per_launch": stage_bytes[dom],
-                "avg_ms": stages[dom]["ms"], "traffic_source": tsrc}
+                "avg_ms": stages[dom]["ms"], "timing": f"HIP events on the library's stream, {n_stage} estimates",
+                "traffic_source": tsrc}
+    if rp_us:
+        roofline["rocprof"] = {"avg_ms": rp_us / 1e3, "frac": stage_bytes[dom] / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                               "source": rp_src}
+    serving = None
+    if not a.no_serving and a.workload == "C3":
+        ctx.close()
+        del gx, rx, rn
+        torch.cuda.empty_cache()
+        serving = serving_stream(pw, torch, a.serving_requests, a.lanes)
     value = served["value"] if served else plain_value
     elapsed = (a.steps / value)
+    latency = (serving["at_0.7x"]["latency_ms"] if serving else _pct(p_lat))
     out = {
         "metric": METRIC, "value": value, "unit": "catalogs/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": elapsed * 1e3 / a.steps, "higher_is_better": True,
@@ -412,13 +508,13 @@ def main():
                    "mode": "served" if served else "plain",
                    "memory_lean": bool(a.memory_lean),
                    "inputs": "resident in HBM (device pointers)"},
-        "plain": {"value": plain_value, "ms_per_catalog": p_el * 1e3 / a.steps,
-                  "latency_ms": {"p50": float(np.percentile(p_lat, 50)),
-                                 "p99": float(np.percentile(p_lat, 99))}},
+        "plain": {"value": plain_value, "ms_per_catalog": p_el * 1e3 / a.steps, "latency_ms": _pct(p_lat)},
         "served": served,
+        "serving": serving,
+        "latency_ms": latency,
+        "latency_source": ("serving stream at 0.7x of its plain capacity (Poisson arrivals, pinned host inputs)"
+                           if serving else "plain pw_estimate calls"),
         "orders": orders,
-        "latency_ms": served["latency_ms"] if served else
-        {"p50": float(np.percentile(p_lat, 50)), "p99": float(np.percentile(p_lat, 99))},
         "roofline": roofline,
         "stages": stages,
         "monopole_first_bins": res["values"][0][:3].tolist(),
@@ -427,7 +523,8 @@ def main():
         # error of the measured estimate against the FP64 oracle, per multipole
         "oracle_check": oracle_check(a.workload, a.midpoint_parity, cfg, res["values"]),
     }
-    ctx.close()
+    if serving is None:
+        ctx.close()
     if a.workload != "C3":
         out["metric"] = f"{a.workload} catalogs/s (secondary workload; the headline metric is C3's)"
     if not a.no_cpu_baseline and a.workload == "C3":

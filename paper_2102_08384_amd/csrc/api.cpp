@@ -521,7 +521,8 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg, char 
       dp->planemask = (int *)M.get((size_t)h.N * sizeof(int));
       dp->zlist = (int *)M.get((size_t)h.N * sizeof(int));
       dp->occ_blockcnt = (int *)M.get((size_t)occupancy_blocks(h.N) * sizeof(int));
-      if ((size_t)dp->ntiles * sizeof(int) > ctx->lds_per_block)
+      // the sort kernels hold one counter per tile (and the count kernel its FP64 reduction rows)
+      if ((size_t)dp->ntiles * sizeof(int) + kSortLdsExtra > ctx->lds_per_block)
         fail(PW_EINVAL, "n_mesh too large for the tile sort on this device (%zu bytes of LDS per block)",
              ctx->lds_per_block);
     }
@@ -763,27 +764,25 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const double rsz = h.prec == PW_FP32 ? 4.0 : 8.0, csz = 2.0 * rsz;
   const double isz_g = gal->dtype == PW_FP32 ? 4.0 : 8.0, isz_r = ran->dtype == PW_FP32 ? 4.0 : 8.0;
   const double ncell = (double)h.N * h.N * h.N;
-  // a1: FP64 scalars
-  mark("scalars", 4.0 * isz_g * gal->n + 5.0 * isz_r * ran->n);
-  launch_scalars(s, gx, nullptr, gal->n, gal->dtype, dp->part_g);
-  launch_scalars(s, rx, rnb, ran->n, ran->dtype, dp->part_r);
-  const bool use_given = norm && norm->use_given;
-  launch_finalize_norm(s, dp->part_g, dp->part_r, dp->norm, cfg->box_origin, cfg->box_len,
-                       h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
-                       use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
-  // a2: paint (particles read once, mesh written once)
-  mark("paint", 4.0 * isz_g * gal->n + 4.0 * isz_r * ran->n + ncell * rsz);
-  if (!placed) ensure_buffer(ctx, &ln.records, &ln.records_bytes, (size_t)(gal->n + ran->n) * 4 * (size_t)rsz);
+  // a1 + a2: FP64 scalars and the tile sort (two passes over the particles), paint, gather and
+  // occupancy; algorithmic bytes: particles (and the randoms' nbar) read once, mesh written once
+  mark("paint", 4.0 * isz_g * gal->n + 5.0 * isz_r * ran->n + ncell * rsz);
+  const SortLayout SL = sort_layout(h.N, gal->n, ran->n);
+  const size_t rec_pad = records_bytes(h.prec, gal->n, ran->n);
+  if (!placed) ensure_buffer(ctx, &ln.records, &ln.records_bytes, rec_pad + SL.hist_bytes);
   void *records = placed ? placed->records : ln.records;
+  int *chunk_hist = (int *)((char *)records + rec_pad);
   launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
   launch_fill(s, dp->rowmask, (size_t)h.N * h.N, 0);
-  launch_tile_count(s, gx, gal->n, gal->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
-  launch_tile_count(s, rx, ran->n, ran->dtype, h.N, cfg->box_origin, h.H, cfg->assign, dp->tile_counts);
+  launch_sort_count(s, SL, gx, gal->dtype, rx, ran->dtype, rnb, gal->n, ran->n, h.N, cfg->box_origin, h.H,
+                    cfg->assign, chunk_hist, dp->tile_counts, dp->part_g, dp->part_r);
+  const bool use_given = norm && norm->use_given;
+  launch_finalize_norm(s, dp->part_g, SL.nblk_g, dp->part_r, SL.nblk_r, dp->norm, cfg->box_origin, cfg->box_len,
+                       h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
+                       use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
   launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
-  launch_tile_scatter(s, gx, gal->n, gal->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 0,
-                      dp->tile_cursor, records);
-  launch_tile_scatter(s, rx, ran->n, ran->dtype, h.prec, h.N, cfg->box_origin, h.H, cfg->assign, dp->norm, 1,
-                      dp->tile_cursor, records);
+  launch_sort_scatter(s, SL, gx, gal->dtype, rx, ran->dtype, gal->n, ran->n, h.prec, h.N, cfg->box_origin, h.H,
+                      cfg->assign, dp->norm, chunk_hist, dp->tile_cursor, records);
   launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records,
                     dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
   launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->occ_blockcnt, dp->norm);
@@ -1122,8 +1121,7 @@ void run_estimate_noalloc(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *g
   char *region = scratch_of(ctx->device, &why);
   if (!region) fail(PW_EDEVICE, "the static scratch of device %d: %s", ctx->device, why.c_str());
   std::shared_ptr<const HostPlan> hp = host_plan(ctx, *cfg);
-  const size_t rsz = hp->prec == PW_FP32 ? 4 : 8;
-  const size_t rec = (size_t)(gal->n + ran->n) * 4 * rsz;
+  const size_t rec = records_bytes(hp->prec, gal->n, ran->n) + sort_layout(hp->N, gal->n, ran->n).hist_bytes;
   const size_t need = table_bytes(*hp) + work_layout(*hp).total + rec + 2 * 256;
   if (need > kScratchBytes)
     fail(PW_ENOMEM,
@@ -1189,8 +1187,8 @@ size_t lane_extra_bytes(const Lane &ln, const Req &r) {
   size_t extra = 0;
   if (ln.plans.find(make_key(r.cfg)) == ln.plans.end()) extra += r.need_tables;
   if (ln.work_bytes < r.need_work) extra += r.need_work - ln.work_bytes;
-  const size_t rs = r.cfg.prec == PW_FP32 ? 4 : 8;
-  const size_t rec = (size_t)(r.gal.n + r.ran.n) * 4 * rs;
+  const size_t rec = records_bytes(r.cfg.prec, r.gal.n, r.ran.n) +
+                    sort_layout(r.cfg.n_mesh, r.gal.n, r.ran.n).hist_bytes;
   if (ln.records_bytes < rec) extra += rec;
   auto stg = [&](const pw_catalog &c, size_t have) -> size_t {
     if (c.on_device) return 0;

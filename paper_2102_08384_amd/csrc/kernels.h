@@ -13,7 +13,7 @@ struct ShConst;
 // [0] sum w, [1] sum w^2, [2] sum w^2 nbar, [3..5] min x,y,z, [6..8] max x,y,z, [9] count,
 // [10] sum |w|
 constexpr int kScalarCols = 11;
-constexpr int kScalarBlocks = 512;
+constexpr int kScalarBlocks = 4096;  // at most this many partial rows (sort chunks) per catalog
 
 // Device-resident normalisation, filled by the finalize kernel.
 struct DevNorm {
@@ -46,10 +46,10 @@ void upload_sh_const(const ShConst &c);
 void upload_sh_const_inverse(const ShConst &c);
 void upload_sh_const_generated(const ShConst &c);
 
-void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n, int dtype,
-                    double *partial);
-void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
-                          const double *b0, double L, int check_extent, int use_given,
+// alpha_r, I, S, the range / extent flags and the painting scale from the partial rows of the
+// two catalogs (nblk_g, nblk_r rows of kScalarCols written by launch_sort_count).
+void launch_finalize_norm(hipStream_t s, const double *pg, int nblk_g, const double *pr, int nblk_r,
+                          DevNorm *norm, const double *b0, double L, int check_extent, int use_given,
                           double ga, double gI, double gS);
 // Zero n_elems values: prec 0 float, 1 double, 2 int.
 void launch_fill(hipStream_t s, void *p, size_t n_elems, int prec);
@@ -62,12 +62,27 @@ void launch_fill(hipStream_t s, void *p, size_t n_elems, int prec);
 // kernels keep one LDS counter per tile (ntiles * 4 bytes per workgroup).
 constexpr int kTile = 16;
 inline int tile_size(int N) { return N < kTile ? N : kTile; }
-void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,
-                       const double *b0, double H, int assign, int *counts);
+// The sort reads the particles twice.  Both catalogs are cut into chunks of `chunk` particles,
+// one workgroup each (galaxy chunks first), a layout fixed by the mesh and the catalog sizes.
+constexpr int kSortNominalCUs = 256;
+constexpr size_t kSortLdsExtra = 16 * 11 * sizeof(double);  // k_sort_count: per-wave reduction rows
+struct SortLayout {
+  int64_t chunk = 0;
+  int nblk_g = 0, nblk_r = 0, ntiles = 0;
+  size_t hist_bytes = 0;  // chunk_hist: one row of ntiles counts per chunk
+};
+SortLayout sort_layout(int N, int64_t n_gal, int64_t n_ran);
+// Pass 1: FP64 scalar partial rows (part_g / part_r), each chunk's tile histogram into
+// chunk_hist and the tile totals added to counts (zeroed by the caller).  rnbar: the randoms'
+// nbar (or NULL).
+void launch_sort_count(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx, int rdtype,
+                       const void *rnbar, int64_t ng, int64_t nr, int N, const double *b0, double H, int assign,
+                       int *chunk_hist, int *counts, double *part_g, double *part_r);
 void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot);
-void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, int N,
-                         const double *b0, double H, int assign, const DevNorm *norm,
-                         int is_random, int *cursor, void *records);
+// Pass 2: tile-sorted records in the mesh precision (prec), randoms weighted by -alpha_r.
+void launch_sort_scatter(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx,
+                         int rdtype, int64_t ng, int64_t nr, int prec, int N, const double *b0, double H,
+                         int assign, const DevNorm *norm, const int *chunk_hist, int *cursor, void *records);
 // blocks: scratch of ntiles * (TS+2)^3 int64 values; slot: [ntiles + 1] from the scan.
 // rowmask (N*N ints, zeroed by the caller; may be null) receives 1 for every x-row (z, y)
 // holding a non-zero node.

@@ -1,11 +1,15 @@
 // Catalog reductions, normalisation and mass assignment (gfx950).
 //
-//   scalars       FP64 reductions over a catalog (sum w, sum w^2, sum w^2 nbar, bounding box)
+//   sort_count    first pass over the particles (galaxies and randoms in one launch): FP64
+//                 reductions per workgroup (sum w, sum w^2, sum w^2 nbar, sum |w|, bounding
+//                 box, count) and the workgroup's LDS histogram of anchor tiles, stored per
+//                 chunk and added to the tile totals
 //   norm          alpha_r = sum w_g / sum w_r, I = alpha_r sum_r w_r^2 nbar_r,
 //                 S = sum_g w_g^2 + alpha_r^2 sum_r w_r^2 (Section 2.1), range / extent flags
-//   tile_count    per-workgroup LDS histogram of the tile of every particle's anchor node
 //   tile_scan     exclusive scan of the tile counts, compact slots of the occupied tiles
-//   tile_scatter  particles -> tile-sorted records (node offset inside the tile, signed weight)
+//   sort_scatter  second (last) pass over the particles: each chunk reserves its runs from its
+//                 stored histogram and writes tile-sorted records (node offset inside the
+//                 tile, signed weight)
 //   tile_paint    CIC / TSC taps of one tile's particles accumulated in LDS (tile + halo),
 //                 written as a block to the tile's scratch slot
 //   tile_gather   every mesh node = sum of the (at most eight) blocks that cover it
@@ -14,51 +18,6 @@
 
 namespace pw {
 
-// ------------------------------------------------------------------------------ scalars
-template <typename R>
-__global__ void __launch_bounds__(256) k_scalars(const R *__restrict__ xyzw, const R *__restrict__ nbar,
-                                                 int64_t n, double *__restrict__ partial) {
-  double sw = 0, sw2 = 0, swn = 0, swa = 0;
-  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-  double cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double x = xyzw[4 * i], y = xyzw[4 * i + 1], z = xyzw[4 * i + 2], w = xyzw[4 * i + 3];
-    sw += w;
-    sw2 += w * w;
-    swa += fabs(w);
-    if (nbar) swn += w * w * (double)nbar[i];
-    mn[0] = fmin(mn[0], x); mn[1] = fmin(mn[1], y); mn[2] = fmin(mn[2], z);
-    mx[0] = fmax(mx[0], x); mx[1] = fmax(mx[1], y); mx[2] = fmax(mx[2], z);
-    cnt += 1;
-  }
-  __shared__ double red[256];
-  double vals[kScalarCols] = {sw, sw2, swn, mn[0], mn[1], mn[2], mx[0], mx[1], mx[2], cnt, swa};
-  for (int c = 0; c < kScalarCols; ++c) {
-    red[threadIdx.x] = vals[c];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        double a = red[threadIdx.x], b = red[threadIdx.x + off];
-        red[threadIdx.x] = (c >= 3 && c < 6) ? fmin(a, b) : (c >= 6 && c < 9) ? fmax(a, b) : a + b;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x * kScalarCols + c] = red[0];
-    __syncthreads();
-  }
-}
-
-void launch_scalars(hipStream_t s, const void *xyzw, const void *nbar, int64_t n, int dtype,
-                    double *partial) {
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_scalars<float>, dim3(kScalarBlocks), dim3(256), 0, s,
-                       (const float *)xyzw, (const float *)nbar, n, partial);
-  else
-    hipLaunchKernelGGL(k_scalars<double>, dim3(kScalarBlocks), dim3(256), 0, s,
-                       (const double *)xyzw, (const double *)nbar, n, partial);
-}
-
 
 constexpr int kNormThreads = 256;
 __device__ __forceinline__ double combine(int c, double a, double b) {
@@ -66,16 +25,17 @@ __device__ __forceinline__ double combine(int c, double a, double b) {
 }
 
 __global__ void __launch_bounds__(kNormThreads)
-k_finalize_norm(const double *pg, const double *pr, DevNorm *norm, double b0x, double b0y, double b0z, double L,
-                int check_extent, int use_given, double ga, double gI, double gS) {
-  // fixed-order (deterministic) reduction of the per-block partial rows: thread t folds rows
+k_finalize_norm(const double *pg, int nblk_g, const double *pr, int nblk_r, DevNorm *norm, double b0x, double b0y,
+                double b0z, double L, int check_extent, int use_given, double ga, double gI, double gS) {
+  // fixed-order (deterministic) reduction of the per-workgroup partial rows: thread t folds rows
   // t, t + 256, ..., then a tree in LDS
   __shared__ double red[2 * kScalarCols][kNormThreads];
   for (int k = 0; k < 2; ++k) {
     const double *p = k ? pr : pg;
+    const int nb = k ? nblk_r : nblk_g;
     for (int c = 0; c < kScalarCols; ++c) {
       double v = (c >= 3 && c < 6) ? 1e300 : (c >= 6 && c < 9) ? -1e300 : 0.0;
-      for (int b = threadIdx.x; b < kScalarBlocks; b += kNormThreads) v = combine(c, v, p[b * kScalarCols + c]);
+      for (int b = threadIdx.x; b < nb; b += kNormThreads) v = combine(c, v, p[b * kScalarCols + c]);
       red[k * kScalarCols + c][threadIdx.x] = v;
     }
   }
@@ -134,11 +94,11 @@ k_finalize_norm(const double *pg, const double *pr, DevNorm *norm, double b0x, d
   *norm = n;
 }
 
-void launch_finalize_norm(hipStream_t s, const double *pg, const double *pr, DevNorm *norm,
-                          const double *b0, double L, int check_extent, int use_given,
+void launch_finalize_norm(hipStream_t s, const double *pg, int nblk_g, const double *pr, int nblk_r,
+                          DevNorm *norm, const double *b0, double L, int check_extent, int use_given,
                           double ga, double gI, double gS) {
-  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kNormThreads), 0, s, pg, pr, norm, b0[0], b0[1], b0[2],
-                     L, check_extent, use_given, ga, gI, gS);
+  hipLaunchKernelGGL(k_finalize_norm, dim3(1), dim3(kNormThreads), 0, s, pg, nblk_g, pr, nblk_r, norm, b0[0],
+                     b0[1], b0[2], L, check_extent, use_given, ga, gI, gS);
 }
 
 // ------------------------------------------------------------------------------ fill
@@ -178,37 +138,107 @@ template <> struct Rec4<double> { typedef double4 T; };
 
 constexpr int kAggThreads = 1024;  // the sort kernels: one workgroup per chunk of particles
 
+// One catalog record (x, y, z, w) in FP64; `vec`: the array is 16-byte aligned, so a record is
+// one 16-byte load (FP32) or two (FP64).
 template <typename RI>
-__device__ __forceinline__ bool particle_tile(const RI *__restrict__ xyzw, int64_t i, int N, double b0x,
-                                              double b0y, double b0z, double H, int assign, int ts,
-                                              int i0[3], double d[3], int *tile) {
-  const double u[3] = {((double)xyzw[4 * i] - b0x) / H, ((double)xyzw[4 * i + 1] - b0y) / H,
-                       ((double)xyzw[4 * i + 2] - b0z) / H};
+__device__ __forceinline__ void load_record(const RI *__restrict__ p, int64_t i, bool vec, double v[4]) {
+  if constexpr (sizeof(RI) == 4) {
+    if (vec) {
+      const float4 q = reinterpret_cast<const float4 *>(p)[i];
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      return;
+    }
+  } else {
+    if (vec) {
+      const double2 a = reinterpret_cast<const double2 *>(p)[2 * i];
+      const double2 b = reinterpret_cast<const double2 *>(p)[2 * i + 1];
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+      return;
+    }
+  }
+  v[0] = (double)p[4 * i]; v[1] = (double)p[4 * i + 1]; v[2] = (double)p[4 * i + 2]; v[3] = (double)p[4 * i + 3];
+}
+
+// Anchor node, offsets and tile of a particle at (x, y, z); false outside the box.
+__device__ __forceinline__ bool particle_tile(const double v[4], int N, double b0x, double b0y, double b0z,
+                                              double H, int assign, int ts, int i0[3], double d[3], int *tile) {
+  const double u[3] = {(v[0] - b0x) / H, (v[1] - b0y) / H, (v[2] - b0z) / H};
   if (!anchor3(u, assign, N, i0, d)) return false;
   const int nt = N / ts;
   *tile = ((i0[2] / ts) * nt + i0[1] / ts) * nt + i0[0] / ts;
   return true;
 }
 
-// Per-workgroup LDS histogram of a chunk; one global atomic per (chunk, occupied tile).
-template <typename RI>
+constexpr int kSortWaves = kAggThreads / 64;
+
+__device__ __forceinline__ double wave_combine(int c, double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = combine(c, v, __shfl_xor(v, off));
+  return v;
+}
+
+// First pass.  Workgroup b < nblk_g takes galaxy chunk b, the others random chunk
+// b - nblk_g (chunks of `chunk` particles).  It folds the FP64 scalars of its particles into
+// one partial row (part_g / part_r, a fixed-order reduction: wavefront butterflies, then the
+// waves in order) and histograms the anchor tiles in LDS; the histogram is stored as row b of
+// chunk_hist and added to the tile totals (one global atomic per occupied tile).
+template <typename RG, typename RR>
 __global__ void __launch_bounds__(kAggThreads)
-k_tile_count(const RI *__restrict__ xyzw, int64_t n, int64_t chunk, int N, double b0x, double b0y, double b0z,
-             double H, int assign, int ts, int ntiles, int *__restrict__ counts) {
+k_sort_count(const RG *__restrict__ gx, const RR *__restrict__ rx, const RR *__restrict__ rnbar, int64_t ng,
+             int64_t nr, int64_t chunk, int nblk_g, int vec_g, int vec_r, int N, double b0x, double b0y,
+             double b0z, double H, int assign, int ts, int ntiles, int *__restrict__ chunk_hist,
+             int *__restrict__ counts, double *__restrict__ part_g, double *__restrict__ part_r) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  int *hist = reinterpret_cast<int *>(smem_raw);
+  double *red = reinterpret_cast<double *>(smem_raw);  // [kSortWaves][kScalarCols]
+  int *hist = reinterpret_cast<int *>(red + kSortWaves * kScalarCols);
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
   __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const bool ran = (int)blockIdx.x >= nblk_g;
+  const int b = ran ? (int)blockIdx.x - nblk_g : (int)blockIdx.x;
+  const int64_t n = ran ? nr : ng;
+  const int64_t c0 = (int64_t)b * chunk;
   const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+  double sw = 0, sw2 = 0, swn = 0, swa = 0, cnt = 0;
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
   for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    double v[4];
+    if (ran) load_record(rx, i, vec_r != 0, v);
+    else load_record(gx, i, vec_g != 0, v);
+    const double w = v[3];
+    sw += w;
+    sw2 += w * w;
+    swa += fabs(w);
+    if (ran && rnbar) swn += w * w * (double)rnbar[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = fmin(mn[a], v[a]);
+      mx[a] = fmax(mx[a], v[a]);
+    }
+    cnt += 1;
     int i0[3], tile;
     double d[3];
-    if (particle_tile(xyzw, i, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
+    if (particle_tile(v, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
+  }
+  double vals[kScalarCols] = {sw, sw2, swn, mn[0], mn[1], mn[2], mx[0], mx[1], mx[2], cnt, swa};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < kScalarCols; ++c) {
+    const double r = wave_combine(c, vals[c]);
+    if (lane == 0) red[wv * kScalarCols + c] = r;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
-    if (hist[t]) atomicAdd(&counts[t], hist[t]);
+  if ((int)threadIdx.x < kScalarCols) {
+    const int c = threadIdx.x;
+    double acc = red[c];
+    for (int w = 1; w < kSortWaves; ++w) acc = combine(c, acc, red[w * kScalarCols + c]);
+    (ran ? part_r : part_g)[(size_t)b * kScalarCols + c] = acc;
+  }
+  int *row = chunk_hist + (size_t)blockIdx.x * ntiles;
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const int c = hist[t];
+    row[t] = c;
+    if (c) atomicAdd(&counts[t], c);
+  }
 }
 
 // offsets = exclusive scan of counts (offsets[ntiles] = total), cursor = offsets,
@@ -283,40 +313,42 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ coun
   }
 }
 
-// Reserve one run per (chunk, tile) and rank the chunk's particles inside it with LDS atomics.
-template <typename RI, typename RM>
+// Second pass, same chunks as k_sort_count: reserve one run per (chunk, tile) from the stored
+// histogram (one global atomic per occupied tile), then rank the chunk's particles inside their
+// runs with LDS atomics and write their records (randoms carry -alpha_r w).
+template <typename RG, typename RR, typename RM>
 __global__ void __launch_bounds__(kAggThreads)
-k_tile_scatter(const RI *__restrict__ xyzw, int64_t n, int64_t chunk, int N, double b0x, double b0y, double b0z,
-               double H, int assign, int ts, int ntiles, const DevNorm *__restrict__ norm, int is_random,
+k_sort_scatter(const RG *__restrict__ gx, const RR *__restrict__ rx, int64_t ng, int64_t nr, int64_t chunk,
+               int nblk_g, int vec_g, int vec_r, int N, double b0x, double b0y, double b0z, double H, int assign,
+               int ts, int ntiles, const DevNorm *__restrict__ norm, const int *__restrict__ chunk_hist,
                int *__restrict__ cursor, typename Rec4<RM>::T *__restrict__ rec) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int *hist = reinterpret_cast<int *>(smem_raw);
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) hist[t] = 0;
-  __syncthreads();
-  const int64_t c0 = (int64_t)blockIdx.x * chunk;
-  const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
-  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-    int i0[3], tile;
-    double d[3];
-    if (particle_tile(xyzw, i, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
-  }
-  __syncthreads();
+  const int *row = chunk_hist + (size_t)blockIdx.x * ntiles;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    const int c = hist[t];
+    const int c = row[t];
     hist[t] = c ? atomicAdd(&cursor[t], c) : 0;  // base of this chunk's run in tile t
   }
   __syncthreads();
-  const double wmul = is_random ? -norm->alpha_r : 1.0;
+  const bool ran = (int)blockIdx.x >= nblk_g;
+  const int b = ran ? (int)blockIdx.x - nblk_g : (int)blockIdx.x;
+  const int64_t n = ran ? nr : ng;
+  const int64_t c0 = (int64_t)b * chunk;
+  const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+  const double wmul = ran ? -norm->alpha_r : 1.0;
   for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    double v[4];
+    if (ran) load_record(rx, i, vec_r != 0, v);
+    else load_record(gx, i, vec_g != 0, v);
     int i0[3], tile;
     double d[3];
-    if (!particle_tile(xyzw, i, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) continue;
+    if (!particle_tile(v, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) continue;
     const int pos = atomicAdd(&hist[tile], 1);
     typename Rec4<RM>::T r;
     r.x = (RM)((double)(i0[0] % ts) + d[0]);
     r.y = (RM)((double)(i0[1] % ts) + d[1]);
     r.z = (RM)((double)(i0[2] % ts) + d[2]);
-    r.w = (RM)((double)xyzw[4 * i + 3] * wmul);
+    r.w = (RM)(v[3] * wmul);
     rec[pos] = r;
   }
 }
@@ -512,64 +544,72 @@ void launch_occupancy(hipStream_t s, int N, const int *rowmask, int *rowlist, in
                      zlist, norm);
 }
 
-// Particles per workgroup of the sort kernels.  Their LDS histogram of every tile allows one
-// workgroup per CU, so a launch is sized as whole rounds of one workgroup per CU (at most 128 Ki
-// particles per chunk, at least 4096, a multiple of the workgroup size).
-static int64_t sort_chunk(int64_t n) {
-  static thread_local int ncu = 0;
-  if (ncu <= 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      ncu = v;
-    else
-      ncu = 256;
-  }
-  const int64_t per_round = (int64_t)ncu * 131072;
-  const int64_t rounds = (n + per_round - 1) / per_round;
-  int64_t c = (n + rounds * ncu - 1) / (rounds * ncu);
+SortLayout sort_layout(int N, int64_t n_gal, int64_t n_ran) {
+  SortLayout L;
+  const int64_t n = n_gal + n_ran;
+  // one chunk size for both catalogs: about one workgroup per CU of a 256-CU device for up to
+  // 2^25 particles, chunks of 2^17 beyond, and never more than kScalarBlocks chunks per catalog
+  int64_t c = (n + kSortNominalCUs - 1) / kSortNominalCUs;
+  if (c > 131072) c = 131072;
+  const int64_t cmin = (n + kScalarBlocks - 1) / kScalarBlocks;
+  if (c < cmin) c = cmin;
   c = (c + kAggThreads - 1) / kAggThreads * kAggThreads;
-  return c < 4096 ? 4096 : c;
+  if (c < 4096) c = 4096;
+  L.chunk = c;
+  L.nblk_g = (int)((n_gal + c - 1) / c);
+  L.nblk_r = (int)((n_ran + c - 1) / c);
+  const int ts = tile_size(N), nt = N / ts;
+  L.ntiles = nt * nt * nt;
+  L.hist_bytes = (size_t)(L.nblk_g + L.nblk_r) * L.ntiles * sizeof(int);
+  return L;
 }
 
-void launch_tile_count(hipStream_t s, const void *xyzw, int64_t n, int dtype, int N,
-                       const double *b0, double H, int assign, int *counts) {
-  if (n <= 0) return;
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+void launch_sort_count(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx, int rdtype,
+                       const void *rnbar, int64_t ng, int64_t nr, int N, const double *b0, double H, int assign,
+                       int *chunk_hist, int *counts, double *part_g, double *part_r) {
+  const unsigned nblk = (unsigned)(L.nblk_g + L.nblk_r);
+  if (nblk == 0) return;
+  static_assert(kSortLdsExtra == (size_t)kSortWaves * kScalarCols * sizeof(double), "LDS rows");
+  const size_t lds = kSortLdsExtra + (size_t)L.ntiles * sizeof(int);
   const int ts = tile_size(N);
-  const int nt = N / ts, ntiles = nt * nt * nt;
-  const size_t lds = (size_t)ntiles * sizeof(int);
-  const int64_t chunk = sort_chunk(n);
-  const unsigned chunks = (unsigned)((n + chunk - 1) / chunk);
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_tile_count<float>, dim3(chunks), dim3(kAggThreads), lds, s, (const float *)xyzw, n, chunk,
-                       N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
-  else
-    hipLaunchKernelGGL(k_tile_count<double>, dim3(chunks), dim3(kAggThreads), lds, s, (const double *)xyzw, n,
-                       chunk, N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, counts);
+  const int vg = aligned16(gx), vr = aligned16(rx);
+#define PW_SC(RG, RR)                                                                                         \
+  hipLaunchKernelGGL((k_sort_count<RG, RR>), dim3(nblk), dim3(kAggThreads), lds, s, (const RG *)gx, (const RR *)rx, \
+                     (const RR *)rnbar, ng, nr, L.chunk, L.nblk_g, vg, vr, N, b0[0], b0[1], b0[2], H, assign, ts,    \
+                     L.ntiles, chunk_hist, counts, part_g, part_r)
+  if (gdtype == 0 && rdtype == 0) PW_SC(float, float);
+  else if (gdtype == 0) PW_SC(float, double);
+  else if (rdtype == 0) PW_SC(double, float);
+  else PW_SC(double, double);
+#undef PW_SC
+}
+
+void launch_sort_scatter(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx,
+                         int rdtype, int64_t ng, int64_t nr, int prec, int N, const double *b0, double H,
+                         int assign, const DevNorm *norm, const int *chunk_hist, int *cursor, void *records) {
+  const unsigned nblk = (unsigned)(L.nblk_g + L.nblk_r);
+  if (nblk == 0) return;
+  const size_t lds = (size_t)L.ntiles * sizeof(int);
+  const int ts = tile_size(N);
+  const int vg = aligned16(gx), vr = aligned16(rx);
+#define PW_SS(RG, RR, RM)                                                                                   \
+  hipLaunchKernelGGL((k_sort_scatter<RG, RR, RM>), dim3(nblk), dim3(kAggThreads), lds, s, (const RG *)gx,     \
+                     (const RR *)rx, ng, nr, L.chunk, L.nblk_g, vg, vr, N, b0[0], b0[1], b0[2], H, assign, ts, \
+                     L.ntiles, norm, chunk_hist, cursor, (typename Rec4<RM>::T *)records)
+#define PW_SS_M(RG, RR) \
+  if (prec == 0) PW_SS(RG, RR, float); else PW_SS(RG, RR, double);
+  if (gdtype == 0 && rdtype == 0) { PW_SS_M(float, float) }
+  else if (gdtype == 0) { PW_SS_M(float, double) }
+  else if (rdtype == 0) { PW_SS_M(double, float) }
+  else { PW_SS_M(double, double) }
+#undef PW_SS_M
+#undef PW_SS
 }
 
 void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot) {
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, offsets, cursor, slot);
-}
-
-void launch_tile_scatter(hipStream_t s, const void *xyzw, int64_t n, int dtype, int prec, int N,
-                         const double *b0, double H, int assign, const DevNorm *norm,
-                         int is_random, int *cursor, void *records) {
-  if (n <= 0) return;
-  const int ts = tile_size(N);
-  const int nt = N / ts, ntiles = nt * nt * nt;
-  const size_t lds = (size_t)ntiles * sizeof(int);
-  const int64_t chunk = sort_chunk(n);
-  const unsigned chunks = (unsigned)((n + chunk - 1) / chunk);
-#define PW_SCAT(RI, RM)                                                                            \
-  hipLaunchKernelGGL((k_tile_scatter<RI, RM>), dim3(chunks), dim3(kAggThreads), lds, s, (const RI *)xyzw, \
-                     n, chunk, N, b0[0], b0[1], b0[2], H, assign, ts, ntiles, norm, is_random, cursor, \
-                     (typename Rec4<RM>::T *)records)
-  if (dtype == 0 && prec == 0) PW_SCAT(float, float);
-  else if (dtype == 0) PW_SCAT(float, double);
-  else if (prec == 0) PW_SCAT(double, float);
-  else PW_SCAT(double, double);
-#undef PW_SCAT
 }
 
 static int ilog2(int v) {

@@ -521,16 +521,21 @@ size_t plan_bytes(const pw_config &c) {
   return table_bytes(h) + work_layout(h).total;
 }
 
+size_t records_bytes(int prec, int64_t n_gal, int64_t n_ran) {
+  const size_t rsz = prec == PW_FP32 ? 4 : 8;
+  return ((size_t)(n_gal + n_ran) * 4 * rsz + 255) & ~(size_t)255;
+}
+
 size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran) {
   const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
-  // tile-sorted records + staging of host catalogs (+ nbar)
-  return (size_t)(n_gal + n_ran) * 4 * rsz * 2 + (size_t)n_ran * rsz;
+  // tile-sorted records and the sort's chunk histograms + staging of host catalogs (+ nbar)
+  return records_bytes(c.prec, n_gal, n_ran) + sort_layout(c.n_mesh, n_gal, n_ran).hist_bytes +
+         (size_t)(n_gal + n_ran) * 4 * rsz + (size_t)n_ran * rsz;
 }
 
 size_t catalog_bytes(const pw_config &c, const pw_catalog &gal, const pw_catalog &ran) {
-  const size_t rsz = c.prec == PW_FP32 ? 4 : 8;
   auto isz = [](const pw_catalog &k) -> size_t { return k.dtype == PW_FP32 ? 4 : 8; };
-  size_t b = (size_t)(gal.n + ran.n) * 4 * rsz;  // tile-sorted records
+  size_t b = records_bytes(c.prec, gal.n, ran.n) + sort_layout(c.n_mesh, gal.n, ran.n).hist_bytes;
   if (!gal.on_device) b += (size_t)gal.n * 4 * isz(gal);
   if (!ran.on_device) b += (size_t)ran.n * 4 * isz(ran) + (ran.nbar ? (size_t)ran.n * isz(ran) : 0);
   return b;

@@ -138,6 +138,9 @@ size_t table_bytes(const HostPlan &h);
 // host catalogs of the mesh precision with nbar (pw_footprint)
 size_t catalog_bytes(const pw_config &c, int64_t n_gal, int64_t n_ran);
 size_t catalog_bytes(const pw_config &c, const pw_catalog &gal, const pw_catalog &ran);
+// tile-sorted particle records in the mesh precision, padded to 256 bytes (the sort's chunk
+// histograms follow them in the same buffer)
+size_t records_bytes(int prec, int64_t n_gal, int64_t n_ran);
 // bytes of each of the two spectrum buffers (memory-lean: of the k-sphere buffer)
 size_t spectrum_buffer_bytes(const HostPlan &h);
 // memory-lean bisector: x-pass and y-pass work buffers of one field group

@@ -82,7 +82,8 @@ def main(case):
         "values": res.values.tolist(), "bin_mean": res.bin_mean.tolist(),
         "counts": res.counts.tolist(), "norm": [res.alpha_r, res.I, res.S],
         "oracle": fn.__name__, "command": f"python tests/golden/make_full_size.py {case}",
-        "seconds": time.time() - t0,
+        "seconds": time.time() - t0, "host_cores": len(os.sched_getaffinity(0)),
+        "host": f"{len(os.sched_getaffinity(0))}-core host without a GPU (the build container)",
     }
     path = os.path.join(HERE, f"full_{case}.json")
     with open(path, "w") as fh:

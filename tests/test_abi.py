@@ -235,11 +235,12 @@ def test_tune_cache_file_is_loaded(tmp_path):
 def test_footprint_counts_records_and_staging_per_particle():
     """pw_footprint grows per particle by the tile-sorted record (4 values in the mesh
     precision) plus the host staging of its (x, y, z, w) record, and per random also by its
-    nbar staging."""
+    nbar staging (steps of 16 particles keep the records' 256-byte padding and the sort's
+    chunk count unchanged)."""
     for prec, rsz in ((pw.PW_FP32, 4), (pw.PW_FP64, 8)):
         cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, prec=prec, n_mesh=64, box_len=1000.0,
                         box_origin=(-500.0, -500.0, 500.0), ell_max=4, order=4, bin_lo=0.01,
                         bin_width=0.01, n_bins=10)
         base = pw.footprint(cfg, 1000, 5000)
-        assert pw.footprint(cfg, 1001, 5000) - base == 8 * rsz
-        assert pw.footprint(cfg, 1000, 5001) - base == 9 * rsz
+        assert pw.footprint(cfg, 1016, 5000) - base == 16 * 8 * rsz
+        assert pw.footprint(cfg, 1000, 5016) - base == 16 * 9 * rsz
