@@ -796,6 +796,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const double x3 = (double)h.nfields * modes_real * csz;
   char *A = (char *)dp->bufA, *B = (char *)dp->bufB;
   const bool mid = h.path == PATH_MID_PK || h.path == PATH_MID_XI;
+  const int fx_kind = mid ? FX_RADIAL : FX_HARMONIC;  // midpoint fields carry (u/2r)^alpha
   if (h.lean) {
     // groups of fields through the x, y and z passes; the z pass writes each field's k-sphere
     // into A at its own index (fmap), so the contraction below sees the usual layout
@@ -804,7 +805,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     for (int g = 0; g < ng; ++g) {
       const int j0 = h.lean_jstart[g], nj = h.lean_jstart[g + 1] - j0;
       const int f0 = h.lean_fstart[g], nf = h.lean_fstart[g + 1] - f0;
-      launch_fx(s, h.prec, N, false, dp->mesh, B, dp->lean_jobs + j0, nj, F.nkx, F.rs, cfg->box_origin, h.H,
+      launch_fx(s, h.prec, N, fx_kind, dp->mesh, B, dp->lean_jobs + j0, nj, F.nkx, F.rs, cfg->box_origin, h.H,
                 h.unit, dp->tw, dp->rowlist, dp->norm);
       launch_fy(s, h.prec, N, 0, B, dp->bufC, nf, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
                 dp->rowmask, dp->zlist, dp->norm);
@@ -813,7 +814,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     }
   } else {
     mark("fx", ncell * rsz + x1);
-    launch_fx(s, h.prec, N, false, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
+    launch_fx(s, h.prec, N, fx_kind, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
               h.unit, dp->tw, dp->rowlist, dp->norm);
     mark("fy", x1 + x2);
     if (F.npen > 0)
@@ -920,7 +921,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
                      a3 = (double)h.n_a * P.nretained * csz;
         mark("afx", (double)h.n_a * ncell * rsz + a1);
-        launch_fx(s, h.prec, N, true, B, Aoff, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
+        launch_fx(s, h.prec, N, FX_PLAIN, B, Aoff, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
                   h.unit, dp->tw, nullptr, nullptr);
         mark("afy", a1 + a2);
         if (P.npen > 0)
@@ -1843,6 +1844,13 @@ int pw_inspect(pw_ctx *ctx, int what, void *dst, size_t dst_bytes, size_t *neede
                              hipMemcpyDeviceToHost));
       } else {
         HIPCHECK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+      }
+      if (what == 0) {
+        // rows outside the occupied-row mask hold no value: the gather leaves them unwritten
+        std::vector<int> mask((size_t)h.N * h.N);
+        HIPCHECK(hipMemcpy(mask.data(), dp->rowmask, mask.size() * sizeof(int), hipMemcpyDeviceToHost));
+        for (size_t r = 0; r < mask.size(); ++r)
+          if (!mask[r]) std::memset((char *)dst + r * h.N * rsz, 0, (size_t)h.N * rsz);
       }
     }
   } catch (const Fail &f) {

@@ -110,8 +110,11 @@ inline int row_stride(int nkx, int prec) {
 // product (2r)^-alpha |D|^alpha is unchanged while fields of every alpha stay O(1)).
 // rowlist (may be null: every row) restricts the pass to the non-empty rows; the output rows of
 // empty ones are not written (the y pass reads them as zeros).
-// plain: every job is kind 2 (pairs of real input fields, no weighting); else kinds 0 and 1.
-void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, void *out, const FieldJob *jobs,
+// kind FX_PLAIN: every job is kind 2 (pairs of real input fields, no weighting); else kinds 0 and 1.
+// x-pass inputs: FX_HARMONIC generates y_J^mu(x^) F (bisector), FX_RADIAL also (u/2r)^alpha
+// (midpoint), FX_PLAIN transforms real input fields of a stack (midpoint A fields)
+enum { FX_HARMONIC = 0, FX_RADIAL = 1, FX_PLAIN = 2 };
+void launch_fx(hipStream_t s, int prec, int N, int kind, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                const int *rowlist, const DevNorm *norm);
 // Launch shape of a column pass, as picked by the autotuner: fields per workgroup (fpb; 0 = the

@@ -81,6 +81,22 @@ struct ShPair8 {
       b_cur = !b_cur;
     }
   }
+  // the same with z / r of each value given (uz; +z at the origin)
+  __device__ __forceinline__ void advance_uz(const ShConst &c, int Jt, const R *uz) {
+    if (Jt < J_cur) restart_q();
+    while (J_cur < Jt) {
+      ++J_cur;
+      const R a = sh_a<R>(c, J_cur, m_cur), b = sh_b<R>(c, J_cur, m_cur);
+      if (b_cur) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) qa[s] = a * uz[s] * qb[s] - b * qa[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) qb[s] = a * uz[s] * qa[s] - b * qb[s];
+      }
+      b_cur = !b_cur;
+    }
+  }
   template <typename Fn>
   __device__ __forceinline__ void with_cur(Fn &&fn) const {
     if (b_cur) fn(qb); else fn(qa);
@@ -120,7 +136,11 @@ __device__ __forceinline__ cplx<R> lane_fetch(int src, cplx<R> v) {
 // exchanges need only wavefront ordering and Z(N-k) comes from the partner lane by a cross-lane
 // permute; otherwise the rows of the block share barriers and the separation reads LDS.
 // FP32 at N = 512 fits three wavefronts per SIMD without spills (FP64 would spill).
-template <typename R, int N, bool PLAIN>
+// RADIAL: jobs may carry radial weights (u/2r)^alpha (midpoint fields), so each value keeps
+// 1/r; otherwise (bisector fields) it keeps z/r, the only radial quantity the harmonics need,
+// and 1/r is recomputed when the recurrence changes m.  Both fields of a job enter the
+// transform scaled by 1/2 (exactly), which is the factor of the two-real-field separation.
+template <typename R, int N, bool PLAIN, bool RADIAL>
 __global__ void __launch_bounds__(FxShape<N>::THREADS)
 __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && N == 512) ? 3 : 1, 8)))
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
@@ -150,17 +170,21 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
     if constexpr (WAVE) wave_lds_sync(); else __syncthreads();
   };
 
-  // per value: density and 1/r (the direction is rebuilt from the position where needed)
-  R f[8], ir[8];
+  // per value: density and 1/r (RADIAL) or z/r (the direction is rebuilt from the position
+  // where needed)
+  R f[8], g[8];
   const R py = b0y + (R)y * H, pz = b0z + (R)z * H;
+  auto inv_r = [&](int s) -> R {
+    const R px = b0x + (R)(t + s * T) * H;
+    const R r = sqrt(px * px + py * py + pz * pz);
+    return (r > (R)0) ? (R)1 / r : (R)0;
+  };
   if constexpr (!PLAIN) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      const int x = t + s * T;
-      f[s] = live ? mesh[(size_t)row * N + x] : (R)0;
-      const R px = b0x + (R)x * H;
-      const R r = sqrt(px * px + py * py + pz * pz);
-      ir[s] = (r > (R)0) ? (R)1 / r : (R)0;
+      f[s] = live ? mesh[(size_t)row * N + t + s * T] : (R)0;
+      const R ir = inv_r(s);
+      g[s] = RADIAL ? ir : (ir > (R)0 ? pz * ir : (R)1);
     }
   }
   const size_t fstride = (size_t)N * N * rs;  // rows padded to rs (128-byte aligned)
@@ -174,56 +198,93 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
       const R *fa = mesh + (size_t)J.Ja * N * N * N + (size_t)row * N;
       const R *fb = mesh + (size_t)(J.Jb < 0 ? 0 : J.Jb) * N * N * N + (size_t)row * N;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) v[s] = mk<R>(fa[t + s * T], J.Jb >= 0 ? fb[t + s * T] : (R)0);
+      for (int s = 0; s < 8; ++s)
+        v[s] = mk<R>((R)0.5 * fa[t + s * T], J.Jb >= 0 ? (R)0.5 * fb[t + s * T] : (R)0);
     } else {
       // kind 0: (J, +m) and (J, -m) at one alpha: norm Q_J^m {Re, Im}(x + iy)^m;
       // kind 1: (Ja, 0) and (Jb, 0) (Jb < 0: none), each at its own alpha.
       // Written as one branch-free form: the second field uses ci + 1 = 1 when m = 0.
       const bool k0 = (J.kind == 0);
       const int Jb = (k0 || J.Jb < 0) ? J.Ja : J.Jb;
-      const R na = sh_n<R>(c_sh, J.Ja, J.m);
-      const R nb = k0 ? na : (J.Jb >= 0 ? sh_n<R>(c_sh, Jb, 0) : (R)0);
+      const R na = (R)0.5 * sh_n<R>(c_sh, J.Ja, J.m);
+      const R nb = k0 ? na : (J.Jb >= 0 ? (R)0.5 * sh_n<R>(c_sh, Jb, 0) : (R)0);
       const R dci = k0 ? (R)0 : (R)1;
       R wa[8];
 #pragma unroll
       for (int s = 0; s < 8; ++s) wa[s] = f[s] * na;
-      for (int a = 0; a < J.alpha; ++a) {
+      if constexpr (RADIAL) {
+        for (int a = 0; a < J.alpha; ++a) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) wa[s] *= uhalf * ir[s];  // u / (2r): lengths in the unit u
+          for (int s = 0; s < 8; ++s) wa[s] *= uhalf * g[s];  // u / (2r): lengths in the unit u
+        }
       }
       if (J.m != rec.m_cur) {
         R ux[8], uy[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          ux[s] = (b0x + (R)(t + s * T) * H) * ir[s];
-          uy[s] = py * ir[s];
+          const R ir = RADIAL ? g[s] : inv_r(s);
+          ux[s] = (b0x + (R)(t + s * T) * H) * ir;
+          uy[s] = py * ir;
         }
         rec.set_m(J.m, ux, uy);
       }
-      rec.advance(c_sh, J.Ja, pz, ir);
-      rec.with_cur([&](const R *q) {
+      if constexpr (!RADIAL) {
+        rec.advance_uz(c_sh, J.Ja, g);
+        if (k0) {
+          // (J, +m) and (J, -m): one Legendre factor, the real and imaginary parts of (x + iy)^m
+          rec.with_cur([&](const R *q) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) v[s].x = wa[s] * q[s] * rec.cr[s];
-      });
-      rec.advance(c_sh, Jb, pz, ir);
-      if (J.alpha_b == J.alpha) {
-        const R rb = nb / na;  // na > 0 always
-        rec.with_cur([&](const R *q) {
+            for (int s = 0; s < 8; ++s) {
+              const R tq = wa[s] * q[s];
+              v[s].x = tq * rec.cr[s];
+              v[s].y = tq * rec.ci[s];
+            }
+          });
+        } else {
+          // (Ja, 0) and (Jb, 0): m = 0, so (x + iy)^0 = 1
+          rec.with_cur([&](const R *q) {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) v[s].y = wa[s] * rb * q[s] * (rec.ci[s] + dci);
-        });
-      } else {
-        R wb[8];
+            for (int s = 0; s < 8; ++s) v[s].x = wa[s] * q[s];
+          });
+          if (J.Jb >= 0) {
+            rec.advance_uz(c_sh, J.Jb, g);
+            rec.with_cur([&](const R *q) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) wb[s] = f[s] * nb;
-        for (int a = 0; a < J.alpha_b; ++a) {
+              for (int s = 0; s < 8; ++s) v[s].y = f[s] * nb * q[s];
+            });
+          } else {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) wb[s] *= uhalf * ir[s];
+            for (int s = 0; s < 8; ++s) v[s].y = (R)0;
+          }
         }
+      } else {
+        rec.advance(c_sh, J.Ja, pz, g);
         rec.with_cur([&](const R *q) {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) v[s].y = wb[s] * q[s] * (rec.ci[s] + dci);
+          for (int s = 0; s < 8; ++s) v[s].x = wa[s] * q[s] * rec.cr[s];
         });
+        rec.advance(c_sh, Jb, pz, g);
+        if (J.alpha_b == J.alpha) {
+          const R rb = nb / na;  // na > 0 always
+          rec.with_cur([&](const R *q) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v[s].y = wa[s] * rb * q[s] * (rec.ci[s] + dci);
+          });
+        } else {
+          R wb[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) wb[s] = f[s] * nb;
+          if constexpr (RADIAL) {
+            for (int a = 0; a < J.alpha_b; ++a) {
+#pragma unroll
+              for (int s = 0; s < 8; ++s) wb[s] *= uhalf * g[s];
+            }
+          }
+          rec.with_cur([&](const R *q) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v[s].y = wb[s] * q[s] * (rec.ci[s] + dci);
+          });
+        }
       }
     }
     fft_pencil<R, N, false>(v, t, tw, at, sync);
@@ -234,25 +295,27 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
       // lane t holds Z(t + 64 s).  Z(N - k) for k = t + 64 s, s < 4: lane (64 - t) & 63, its
       // v[7 - s] (t > 0) or v[(8 - s) & 7] (lane 0); every lane publishes the value its
       // partner needs.  k = 256 (s = 4) is lane 0's own v[4]; 256 < k < rs is padding.
+      // (the inputs carry the separation's factor 1/2)
       const int partner = (64 - t) & 63;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
+        if (64 * s >= rs) break;  // uniform: no lane stores at or beyond the padded row
         const cplx<R> pub = (t == 0) ? v[(8 - s) & 7] : v[7 - s];
         const cplx<R> b = lane_fetch<R>(partner, pub);
         const cplx<R> a = v[s];
         const int kx = t + 64 * s;
         if (kx < rs) {
           const bool keep = kx < nkx;
-          oa[kx] = keep ? mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y)) : mk<R>(0, 0);
-          if (hb) ob[kx] = keep ? mk<R>((R)0.5 * (a.y + b.y), (R)0.5 * (b.x - a.x)) : mk<R>(0, 0);
+          oa[kx] = keep ? mk<R>(a.x + b.x, a.y - b.y) : mk<R>(0, 0);
+          if (hb) ob[kx] = keep ? mk<R>(a.y + b.y, b.x - a.x) : mk<R>(0, 0);
         }
       }
       const int kx = 256 + t;
-      if (kx < rs) {
+      if (256 < rs && kx < rs) {
         const bool keep = (t == 0) && kx < nkx;  // Z(256) pairs with itself
         const cplx<R> a = v[4];
-        oa[kx] = keep ? mk<R>(a.x, (R)0) : mk<R>(0, 0);
-        if (hb) ob[kx] = keep ? mk<R>(a.y, (R)0) : mk<R>(0, 0);
+        oa[kx] = keep ? mk<R>(a.x + a.x, (R)0) : mk<R>(0, 0);
+        if (hb) ob[kx] = keep ? mk<R>(a.y + a.y, (R)0) : mk<R>(0, 0);
       }
     } else {
 #pragma unroll
@@ -265,8 +328,8 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
           continue;
         }
         const cplx<R> a = at(kx), b = at((N - kx) & (N - 1));
-        oa[kx] = mk<R>((R)0.5 * (a.x + b.x), (R)0.5 * (a.y - b.y));
-        if (hb) ob[kx] = mk<R>((R)0.5 * (a.y + b.y), (R)0.5 * (b.x - a.x));
+        oa[kx] = mk<R>(a.x + b.x, a.y - b.y);
+        if (hb) ob[kx] = mk<R>(a.y + b.y, b.x - a.x);
       }
       __syncthreads();
     }
@@ -274,26 +337,26 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 }
 
 template <typename R, int N>
-static void fx_launch(hipStream_t s, bool plain, const void *mesh, void *out, const FieldJob *jobs, int njobs,
+static void fx_launch(hipStream_t s, int kind, const void *mesh, void *out, const FieldJob *jobs, int njobs,
                       int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                       const int *rowlist, const DevNorm *norm) {
   constexpr int ROWS = FxShape<N>::ROWS;
   unsigned blocks = (unsigned)((size_t)N * N / ROWS);
-  if (plain)
-    hipLaunchKernelGGL((k_fx<R, N, true>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
-                       (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
-                       (const cplx<R> *)tw, rowlist, norm);
-  else
-    hipLaunchKernelGGL((k_fx<R, N, false>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,
-                       (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),
-                       (const cplx<R> *)tw, rowlist, norm);
+#define PW_FX(PL, RAD)                                                                                           \
+  hipLaunchKernelGGL((k_fx<R, N, PL, RAD>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,      \
+                     (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),  \
+                     (const cplx<R> *)tw, rowlist, norm)
+  if (kind == FX_PLAIN) PW_FX(true, false);
+  else if (kind == FX_RADIAL) PW_FX(false, true);
+  else PW_FX(false, false);
+#undef PW_FX
 }
 
-void launch_fx(hipStream_t s, int prec, int N, bool plain, const void *mesh, void *out, const FieldJob *jobs,
+void launch_fx(hipStream_t s, int prec, int N, int kind, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
                const int *rowlist, const DevNorm *norm) {
-  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, plain, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
-  else { PW_DISPATCH_N(fx_launch, double, s, plain, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
+  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
+  else { PW_DISPATCH_N(fx_launch, double, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
 }
 
 // ------------------------------------------------------------------------------ fy / fz

@@ -426,6 +426,9 @@ __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restric
 // One workgroup per group of GX tiles along x (GX = 2 for FP32 with at least two tiles per
 // axis, so mesh rows are written as whole 128-byte lines); the slots of the group's
 // neighbourhood are read into LDS once.  N and ts are powers of two.
+// A workgroup whose whole row of tiles (every tx at its ty, tz) has no occupied tile within
+// one tile in y and z writes nothing: every x-row it covers is zero, stays out of rowmask, and
+// no kernel reads mesh rows outside the occupied-row list.
 template <typename RM>
 __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx, const int *__restrict__ slot,
                                                      const RM *__restrict__ blocks, RM *__restrict__ mesh,
@@ -436,6 +439,12 @@ __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx
   const int ngx = nt >> lggx;
   const int gx = (int)blockIdx.x % ngx, ty = ((int)blockIdx.x / ngx) % nt, tz = (int)blockIdx.x / (ngx * nt);
   const int tx0 = gx << lggx;
+  int occ = 0;
+  for (int i = threadIdx.x; i < 9 * nt; i += blockDim.x) {
+    const int tx = i % nt, dy = (i / nt) % 3 - 1, dz = i / (3 * nt) - 1;
+    occ |= slot[(((tz + dz + nt) & (nt - 1)) * nt + ((ty + dy + nt) & (nt - 1))) * nt + tx] >= 0;
+  }
+  if (!__syncthreads_or(occ)) return;  // uniform for the workgroup
   if ((int)threadIdx.x < 9 * (GX + 2)) {
     const int i = threadIdx.x;
     const int dxi = i % (GX + 2), dy = (i / (GX + 2)) % 3 - 1, dz = i / (3 * (GX + 2)) - 1;
