@@ -15,9 +15,10 @@ pytestmark = pytest.mark.gpu
 pw = pytest.importorskip("paper_2102_08384_amd.pw")
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = ["c3_bisector_pk", "c2_midpoint_pk", "c4_midpoint_xi", "c4_bisector_xi_256"]
+CASES = ["c3_bisector_pk", "c2_midpoint_pk", "c4_midpoint_xi", "c4_bisector_xi", "c4_bisector_xi_256"]
 STAT = {"c3_bisector_pk": (pw.PW_PK, pw.PW_BISECTOR), "c2_midpoint_pk": (pw.PW_PK, pw.PW_MIDPOINT),
-        "c4_midpoint_xi": (pw.PW_XI, pw.PW_MIDPOINT), "c4_bisector_xi_256": (pw.PW_XI, pw.PW_BISECTOR)}
+        "c4_midpoint_xi": (pw.PW_XI, pw.PW_MIDPOINT), "c4_bisector_xi": (pw.PW_XI, pw.PW_BISECTOR),
+        "c4_bisector_xi_256": (pw.PW_XI, pw.PW_BISECTOR)}
 
 
 @pytest.fixture(scope="module")
