@@ -288,6 +288,36 @@ def _pct(v):
     return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99))} if len(v) else None
 
 
+def batch_gain(pw, torch, ctx, reqs, n=8):
+    """Batched launches against one estimate after another: n bisector requests of one mesh from
+    the stream (pinned host inputs), as n pw_estimate calls and as one pw_estimate_batch call
+    (each forward pass and the contraction once over the n catalogs)."""
+    out = {}
+    for N in (128, 256):
+        sel = [q for q in reqs if q[1].los == pw.PW_BISECTOR and q[1].n_mesh == N][:n]
+        if len(sel) < 2:
+            continue
+        cfg = sel[0][1]
+        cats = [(g, r, nb) for _, _, g, r, nb in sel]
+        ctx.estimate_batch(cfg, cats)        # warm: batch plans and workspace
+        reps = 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for g, r, nb in cats:
+                ctx.estimate(cfg, g, r, ran_nbar=nb)
+        seq = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.estimate_batch(cfg, cats)
+        bat = (time.perf_counter() - t0) / reps
+        out[f"bisector_{N}"] = {"catalogs": len(cats), "one_after_another_ms": seq * 1e3, "batched_ms": bat * 1e3,
+                                "speedup": seq / bat,
+                                "galaxies": [int(g.shape[0]) for g, _, _ in cats]}
+        log(f"batched {len(cats)} x bisector {N}^3: {seq * 1e3:.1f} ms one after another, {bat * 1e3:.1f} ms batched")
+    return out
+
+
 def serving_stream(pw, torch, n_req, lanes, loads=(0.7, 1.5)):
     """Capacity from one plain pass over the stream (one pw_estimate after another), then, after
     one untimed served pass that warms the lanes, the same requests at exponential
@@ -325,11 +355,13 @@ def serving_stream(pw, torch, n_req, lanes, loads=(0.7, 1.5)):
     warm = [ctx.submit(cfg, g, r, ran_nbar=n) for lab, cfg, g, r, n in reqs]
     for t in warm:
         t.wait()
+    out["batched"] = batch_gain(pw, torch, ctx, reqs)
     rng = np.random.default_rng(11)
     for load in loads:
         gaps = rng.exponential(1.0 / (load * cap), len(reqs))
         arrivals = np.cumsum(gaps) - gaps[0]
         torch.cuda.synchronize()
+        l0, q0 = ctx.serving_stats()
         t0 = time.perf_counter()
         tickets, sub = [], []
         done = [None] * len(reqs)
@@ -362,9 +394,10 @@ def serving_stream(pw, torch, n_req, lanes, loads=(0.7, 1.5)):
             time.sleep(1e-4)
         el = max(done) - t0
         lat = [(d - s_) * 1e3 for s_, d, t in zip(sub, done, tickets) if t is not None]
+        l1, q1 = ctx.serving_stats()
         out[f"at_{load}x"] = {"offered": load * cap, "value": (len(reqs) - len(failed)) / el,
                               "unit": "requests/s", "failed": len(failed), "failures": failed[:5],
-                              "latency_ms": _pct(lat)}
+                              "latency_ms": _pct(lat), "launches": l1 - l0, "requests_launched": q1 - q0}
         log(f"serving at {load}x: {(len(reqs) - len(failed)) / el:.2f} requests/s, p50 {np.percentile(lat, 50):.1f} "
             f"ms, p99 {np.percentile(lat, 99):.1f} ms, {len(failed)} failed")
     ctx.close()

@@ -144,6 +144,20 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal,
                 const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
                 int64_t *counts);
 
+/* n catalogs of one configuration at once (1 <= n <= 8): gal[i], ran[i] (and norm[i] when norm
+ * is not NULL) describe catalog i; out holds [n][n_ell][n_bins], bin_mean and counts (may be
+ * NULL) [n][n_bins].  For the bisector P_l (Section 5.2) with the default plan, each forward
+ * pass and the contraction run once over every catalog's fields (a launch grid of fields x
+ * catalogs; each catalog is painted into its own buffers), so n small meshes cost far fewer
+ * launches than n estimates; other configurations run the catalogs one after another.  Each
+ * catalog's result equals its pw_estimate result (to FP64 rounding of the shell sums).  Errors as
+ * pw_estimate; every catalog's range and extent checks pass before any output is written.
+ * The serving loop (pw_submit) batches pending requests the same way: requests of one such
+ * configuration at n_mesh <= 256 that are pending together share one launch. */
+int pw_estimate_batch(pw_ctx *ctx, const pw_config *cfg, int n, const pw_catalog *gal,
+                      const pw_catalog *ran, pw_norm *norm, double *out, double *bin_mean,
+                      int64_t *counts);
+
 /* pw_estimate for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  It allocates no device memory and no
  * pinned host memory: every device buffer of the estimate (plan tables, mesh, spectrum buffers,
@@ -235,6 +249,9 @@ int pw_cancel(pw_ctx *ctx, uint64_t ticket);
 /* Number of serving lanes (1..8, default 2); only before the first pw_submit (PW_EBUSY
  * after). */
 int pw_set_lanes(pw_ctx *ctx, int n_lanes);
+/* Serving launches made so far and the requests they carried (a batched launch carries
+ * several); either pointer may be NULL. */
+int pw_serving_stats(pw_ctx *ctx, uint64_t *launches, uint64_t *requests);
 /* Backpressure: pw_submit returns PW_EBUSY while max_in_flight requests of the context are
  * pending or running (1..2^30, default 1024; PW_EINVAL otherwise).  A lower limit applies to
  * later submissions only; requests already queued stay queued. */

@@ -94,6 +94,13 @@ struct Lane {
   struct Req *cur = nullptr;  // serving lanes: the request in flight
   int occ_rows = 0, occ_planes = 0;  // occupancy of the most recent estimate (lane 0)
   std::vector<double> noalloc_res;   // lane 0: pageable results of pw_estimate_noalloc
+  // batched launches (bisector P_l, one configuration): the plans of catalogs 1 .. n-1 (catalog
+  // 0 runs in the lane's own plan and workspace) and their workspaces, one after another
+  std::map<PlanKey, std::vector<std::unique_ptr<DevPlan>>> bplans;
+  void *bwork = nullptr;
+  size_t bwork_bytes = 0;
+  std::vector<struct Req *> batch;  // serving lanes: every request of the launch in flight
+  size_t res_slice = 0;             // bytes of one catalog's results in host_res
 };
 
 struct Req {
@@ -151,6 +158,8 @@ struct pw_ctx {
   size_t reserved = 0;
   // pw_submit refuses a request (PW_EBUSY) while this many are pending or running
   size_t queue_limit = 1024;
+  // serving launches made and the requests they carried (batched launches carry several)
+  uint64_t served_launches = 0, served_requests = 0;
   // pinned host buffers holding copies of pageable host catalogs of submitted requests
   // (guarded by pin_mu): the free ones, and the bytes held in all (free and in use)
   std::mutex pin_mu;
@@ -564,9 +573,17 @@ void evict_work(pw_ctx *ctx, Lane &ln) {
   dev_free(ctx, ln.work, ln.work_bytes);
   ln.work = nullptr;
   ln.work_bytes = 0;
+  dev_free(ctx, ln.bwork, ln.bwork_bytes);
+  ln.bwork = nullptr;
+  ln.bwork_bytes = 0;
 }
 
 void evict_plan(pw_ctx *ctx, Lane &ln, const PlanKey &key) {
+  auto bt = ln.bplans.find(key);
+  if (bt != ln.bplans.end()) {
+    for (auto &p : bt->second) free_plan(ctx, p.get());
+    ln.bplans.erase(bt);
+  }
   auto it = ln.plans.find(key);
   if (it == ln.plans.end()) return;
   if (ln.last == it->second.get()) ln.last = nullptr;
@@ -729,6 +746,30 @@ std::vector<ColTune> fz_candidates(int nfields) {
   return c;
 }
 
+// a1 + a2 for one catalog on stream s: FP64 scalars and the tile sort (two passes over the
+// particles), paint, gather and occupancy into dp's mesh, masks and norm.  gx / rx / rnb: the
+// catalogs' device arrays; records: the sort's buffer (records_bytes + the chunk histograms).
+void enqueue_paint(hipStream_t s, const DevPlan *dp, const pw_config *cfg, const pw_catalog *gal, const void *gx,
+                   const pw_catalog *ran, const void *rx, const void *rnb, const pw_norm *norm, void *records) {
+  const HostPlan &h = *dp->host;
+  const SortLayout SL = sort_layout(h.N, gal->n, ran->n);
+  int *chunk_hist = (int *)((char *)records + records_bytes(h.prec, gal->n, ran->n));
+  launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
+  launch_fill(s, dp->rowmask, (size_t)h.N * h.N, 0);
+  launch_sort_count(s, SL, gx, gal->dtype, rx, ran->dtype, rnb, gal->n, ran->n, h.N, cfg->box_origin, h.H,
+                    cfg->assign, chunk_hist, dp->tile_counts, dp->part_g, dp->part_r);
+  const bool use_given = norm && norm->use_given;
+  launch_finalize_norm(s, dp->part_g, SL.nblk_g, dp->part_r, SL.nblk_r, dp->norm, cfg->box_origin, cfg->box_len,
+                       h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
+                       use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
+  launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
+  launch_sort_scatter(s, SL, gx, gal->dtype, rx, ran->dtype, gal->n, ran->n, h.prec, h.N, cfg->box_origin, h.H,
+                      cfg->assign, dp->norm, chunk_hist, dp->tile_cursor, records);
+  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records,
+                    dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
+  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->occ_blockcnt, dp->norm);
+}
+
 // An estimate whose device memory is all in place (pw_estimate_noalloc): the plan with its
 // tables and workspace, the particle records, and a host buffer for the results.
 struct Placed {
@@ -767,25 +808,10 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   // a1 + a2: FP64 scalars and the tile sort (two passes over the particles), paint, gather and
   // occupancy; algorithmic bytes: particles (and the randoms' nbar) read once, mesh written once
   mark("paint", 4.0 * isz_g * gal->n + 5.0 * isz_r * ran->n + ncell * rsz);
-  const SortLayout SL = sort_layout(h.N, gal->n, ran->n);
-  const size_t rec_pad = records_bytes(h.prec, gal->n, ran->n);
-  if (!placed) ensure_buffer(ctx, &ln.records, &ln.records_bytes, rec_pad + SL.hist_bytes);
-  void *records = placed ? placed->records : ln.records;
-  int *chunk_hist = (int *)((char *)records + rec_pad);
-  launch_fill(s, dp->tile_counts, (size_t)dp->ntiles, 0);
-  launch_fill(s, dp->rowmask, (size_t)h.N * h.N, 0);
-  launch_sort_count(s, SL, gx, gal->dtype, rx, ran->dtype, rnb, gal->n, ran->n, h.N, cfg->box_origin, h.H,
-                    cfg->assign, chunk_hist, dp->tile_counts, dp->part_g, dp->part_r);
-  const bool use_given = norm && norm->use_given;
-  launch_finalize_norm(s, dp->part_g, SL.nblk_g, dp->part_r, SL.nblk_r, dp->norm, cfg->box_origin, cfg->box_len,
-                       h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
-                       use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
-  launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
-  launch_sort_scatter(s, SL, gx, gal->dtype, rx, ran->dtype, gal->n, ran->n, h.prec, h.N, cfg->box_origin, h.H,
-                      cfg->assign, dp->norm, chunk_hist, dp->tile_cursor, records);
-  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records,
-                    dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
-  launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->occ_blockcnt, dp->norm);
+  if (!placed)
+    ensure_buffer(ctx, &ln.records, &ln.records_bytes,
+                  records_bytes(h.prec, gal->n, ran->n) + sort_layout(h.N, gal->n, ran->n).hist_bytes);
+  enqueue_paint(s, dp, cfg, gal, gx, ran, rx, rnb, norm, placed ? placed->records : ln.records);
   // a3 + a4: weighted fields and the forward transforms
   const int N = h.N;
   const Prune &F = h.fwd;
@@ -957,8 +983,134 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   HIPCHECK(hipMemcpyAsync(res_host, dp->out, nres * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync((char *)res_host + nres * sizeof(double), dp->norm, sizeof(DevNorm),
                           hipMemcpyDeviceToHost, s));
+  ln.res_slice = need;
   HIPCHECK(hipEventRecord(ln.done, s));
   return dp;
+}
+
+// Launch shape of a column pass as the autotuner settled it (no timing here: a key not yet
+// settled uses the default shape).
+ColTune tuned_choice(pw_ctx *ctx, const std::string &key, const std::vector<ColTune> &cands) {
+  const int mode = ctx->tune_mode;
+  if (mode == 0) return cands[0];
+  if (mode >= 2) return cands[(size_t)(mode - 2) < cands.size() ? (size_t)(mode - 2) : 0];
+  const int k = tune_lookup(key);
+  return (k >= 0 && k < (int)cands.size()) ? cands[(size_t)k] : cands[0];
+}
+
+// Whether a configuration has the batched path: the bisector P_l with a generated contraction,
+// default plan (several catalogs of one configuration in each forward pass and contraction).
+bool batchable(const pw_config &c) {
+  return c.stat == PW_PK && c.los == PW_BISECTOR && !c.memory_lean && bis_contract_generated(c.ell_max, c.order / 2);
+}
+
+// Enqueue the estimates of n catalogs of one batchable configuration on the lane's stream:
+// each catalog is painted into its own plan buffers and workspace, then the x, y and z passes
+// and the contraction each run once over all n catalogs (grid z = catalog).  Catalog 0 uses
+// the lane's plan and workspace; catalogs 1 .. n-1 the lane's batch plans and batch workspace.
+// Results go to slices of res_slice bytes of the lane's pinned buffer.  Returns catalog 0's plan.
+DevPlan *launch_batch(pw_ctx *ctx, Lane &ln, const pw_config *cfg, int n, const pw_catalog *const *gals,
+                      const pw_catalog *const *rans, const pw_norm *const *norms) {
+  if (n < 1 || n > kMaxBatch || !batchable(*cfg)) fail(PW_EINVAL, "internal: not a batchable launch");
+  HIPCHECK(hipSetDevice(ctx->device));
+  ensure_sh(ctx->device);
+  DevPlan *dp0 = get_plan(ctx, ln, cfg);
+  bind_work(ctx, ln, dp0);
+  const HostPlan &h = *dp0->host;
+  auto &extra = ln.bplans[make_key(*cfg)];
+  while ((int)extra.size() < n - 1) extra.push_back(build_dev_plan(ctx, cfg));
+  const size_t per = (dp0->work.total + 255) & ~(size_t)255;
+  if (n > 1) ensure_buffer(ctx, &ln.bwork, &ln.bwork_bytes, per * (size_t)(n - 1));
+  std::vector<DevPlan *> plans((size_t)n);
+  plans[0] = dp0;
+  for (int i = 1; i < n; ++i) {
+    DevPlan *p = extra[(size_t)i - 1].get();
+    char *w = (char *)ln.bwork + (size_t)(i - 1) * per;
+    p->mesh = w + p->work.mesh;
+    p->bufA = w + p->work.bufA;
+    p->bufB = w + p->work.bufB;
+    p->bufC = nullptr;
+    p->tile_blocks = w + p->work.tiles;
+    plans[(size_t)i] = p;
+  }
+  ln.last = dp0;
+  ln.n_stages = 0;  // no stage timing for batched launches
+  hipStream_t s = ln.stream;
+  // a1 + a2 per catalog, one after another through the lane's staging and sort buffers
+  size_t rec = 0;
+  for (int i = 0; i < n; ++i)
+    rec = std::max(rec, records_bytes(h.prec, gals[i]->n, rans[i]->n) +
+                            sort_layout(h.N, gals[i]->n, rans[i]->n).hist_bytes);
+  ensure_buffer(ctx, &ln.records, &ln.records_bytes, rec);
+  for (int i = 0; i < n; ++i) {
+    const void *gnb = nullptr, *rnb = nullptr;
+    const void *gx = stage_catalog(ctx, ln, gals[i], 0, &gnb);
+    const void *rx = stage_catalog(ctx, ln, rans[i], 1, &rnb);
+    enqueue_paint(s, plans[(size_t)i], cfg, gals[i], gx, rans[i], rx, rnb, norms[i], ln.records);
+  }
+  // a3 + a4 + a7: one launch per pass over every catalog
+  Batch ba;
+  std::memset(&ba, 0, sizeof(ba));
+  ba.n = n;
+  for (int i = 0; i < n; ++i) {
+    const DevPlan *p = plans[(size_t)i];
+    ba.s[i] = BatchSlot{p->mesh, p->bufA, p->bufB, p->rowlist, p->rowmask, p->zlist, p->planemask, p->norm, p->acc};
+  }
+  const int N = h.N;
+  const Prune &F = h.fwd;
+  launch_fx(s, h.prec, N, FX_HARMONIC, dp0->mesh, dp0->bufA, dp0->jobs, (int)h.jobs.size(), F.nkx, F.rs,
+            cfg->box_origin, h.H, h.unit, dp0->tw, dp0->rowlist, dp0->norm, &ba);
+  if (F.npen > 0) {
+    launch_fy(s, h.prec, N, 0, dp0->bufA, dp0->bufB, h.nfields, N, F.nkx, F.rs, dp0->fwd.ycnt, dp0->fwd.yoff,
+              F.npen, dp0->tw, dp0->rowmask, dp0->zlist, dp0->norm,
+              tuned_choice(ctx, tune_key("fy", h, h.nfields, F.nkx, F.npen), fy_candidates(h.prec, h.nfields)), &ba);
+    launch_fz(s, h.prec, N, dp0->bufB, dp0->bufA, h.nfields, F.npen, dp0->fwd.pinfo, dp0->fwd.moff, dp0->fwd.goff,
+              dp0->fwd.gsize, F.mstride, dp0->tw, dp0->planemask, nullptr,
+              tuned_choice(ctx, tune_key("fz", h, h.nfields, F.npen, F.goff.empty() ? 0 : 1),
+                           fz_candidates(h.nfields)),
+              &ba);
+  }
+  ln.res_rows = h.nell;
+  const size_t nacc = (size_t)(h.nell + 2) * h.n_bins;
+  for (int i = 0; i < n; ++i) launch_fill(s, plans[(size_t)i]->acc, nacc, 1);
+  if (!launch_contract_bis_generated(s, h.prec, h.ell_max, h.order / 2, dp0->bufA, F.nmodes, F.mstride,
+                                     dp0->fwd.modecoord, N, dp0->bin_of_s2, (int64_t)h.bin_of_s2.size(), h.n_bins,
+                                     h.kf, dp0->winv, dp0->acc, 0, &ba))
+    fail(PW_EINVAL, "internal: no generated contraction for a batched launch");
+  for (int i = 0; i < n; ++i)
+    launch_finalize_pk(s, plans[(size_t)i]->acc, h.nell, h.n_bins, dp0->ells, plans[(size_t)i]->norm,
+                       plans[(size_t)i]->out);
+  HIPCHECK(hipGetLastError());
+  const size_t nres = (size_t)(h.nell + 2) * h.n_bins;
+  const size_t slice = (nres * sizeof(double) + sizeof(DevNorm) + 255) & ~(size_t)255;
+  if (ln.host_res_bytes < slice * (size_t)n) {
+    if (ln.host_res) (void)hipHostFree(ln.host_res);
+    ln.host_res = nullptr;
+    ln.host_res_bytes = 0;
+    HIPCHECK(hipHostMalloc((void **)&ln.host_res, slice * (size_t)n, hipHostMallocDefault));
+    ln.host_res_bytes = slice * (size_t)n;
+  }
+  for (int i = 0; i < n; ++i) {
+    char *dst = (char *)ln.host_res + (size_t)i * slice;
+    HIPCHECK(hipMemcpyAsync(dst, plans[(size_t)i]->out, nres * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(dst + nres * sizeof(double), plans[(size_t)i]->norm, sizeof(DevNorm),
+                            hipMemcpyDeviceToHost, s));
+  }
+  ln.res_slice = slice;
+  HIPCHECK(hipEventRecord(ln.done, s));
+  return dp0;
+}
+
+// Results of catalog i of the launch in flight on the lane (host copy).
+const double *lane_result(const Lane &ln, int i) {
+  return (const double *)((const char *)ln.host_res + (size_t)i * ln.res_slice);
+}
+
+// The error flags an estimate raised on the device (PW_ERANGE, PW_EINVAL), as a failure.
+void check_flags(const DevNorm &dn) {
+  if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
+  if (dn.flags & 2)
+    fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
 }
 
 // After the lane's completion event: check the flags and write the caller's outputs from the
@@ -970,9 +1122,7 @@ void finish_estimate(Lane &ln, const DevPlan *dp, const double *res, pw_norm *no
   const size_t nres = (size_t)(rows + 2) * h.n_bins;
   DevNorm dn;
   std::memcpy(&dn, (const char *)res + nres * sizeof(double), sizeof(DevNorm));
-  if (dn.flags & 1) fail(PW_ERANGE, "a particle lies outside [box_origin, box_origin + box_len)");
-  if (dn.flags & 2)
-    fail(PW_EINVAL, "midpoint P_l with order > 0 needs the catalog extent <= box_len / 2 on every axis");
+  check_flags(dn);
   std::memcpy(out, res, (size_t)rows * h.n_bins * sizeof(double));
   if (bin_mean) std::memcpy(bin_mean, res + (size_t)rows * h.n_bins, h.n_bins * sizeof(double));
   if (counts)
@@ -987,19 +1137,31 @@ void finish_estimate(Lane &ln, const DevPlan *dp, const double *res, pw_norm *no
 // Make room on lane 0 for cfg's plan tables, workspace and catalogs by evicting idle serving
 // lanes' workspaces, then cached plans (lane 0's other ones, idle serving lanes'), least
 // recently used first.
+// (n catalogs gal[0 .. n), ran[0 .. n) of one configuration: a batched launch also needs the
+// lane's batch plans and batch workspace)
 void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
-                    Reservation &res) {
+                    Reservation &res, int nb = 1) {
   Lane &ln = *ctx->main;
   const PlanKey key = make_key(*cfg);
   std::shared_ptr<const HostPlan> hp = host_plan(ctx, *cfg);
   const size_t tables = table_bytes(*hp), work = work_layout(*hp).total;
+  const size_t per = (work + 255) & ~(size_t)255;
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto need = [&]() -> size_t {
     size_t n = ln.plans.count(key) ? 0 : tables;
-    return n + (work > ln.work_bytes ? work - ln.work_bytes : 0);
+    n += work > ln.work_bytes ? work - ln.work_bytes : 0;
+    if (nb > 1) {
+      auto it = ln.bplans.find(key);
+      const size_t have = it == ln.bplans.end() ? 0 : it->second.size();
+      n += have < (size_t)(nb - 1) ? ((size_t)(nb - 1) - have) * tables : 0;
+      const size_t bw = per * (size_t)(nb - 1);
+      n += bw > ln.bwork_bytes ? bw - ln.bwork_bytes : 0;
+    }
+    return n;
   };
   if (need() == 0) return;
-  const size_t cat = catalog_bytes(*cfg, *gal, *ran);
+  size_t cat = 0;  // catalogs are staged and sorted one at a time: the largest one's buffers
+  for (int i = 0; i < nb; ++i) cat = std::max(cat, catalog_bytes(*cfg, gal[i], ran[i]));
   while (mem_used(ctx) + ctx->reserved + need() + cat > ctx->budget) {
     Lane *wl = nullptr;
     uint64_t oldest = (uint64_t)-1;
@@ -1038,6 +1200,47 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm, orders);
   res.release();
   complete_main(ln, dp, ln.host_res, norm, out, bin_mean, counts);
+}
+
+// pw_estimate_batch: n catalogs of one configuration (arrays gal[n], ran[n], norm[n] or NULL;
+// outputs [n][...]), in batched launches when the configuration has them, else one estimate
+// after another.
+void run_estimate_batch(pw_ctx *ctx, const pw_config *cfg, int n, const pw_catalog *gal, const pw_catalog *ran,
+                        pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  if (!cfg || !gal || !ran || !out) fail(PW_EINVAL, "null configuration, catalogs or output");
+  if (n < 1 || n > kMaxBatch) fail(PW_EINVAL, "pw_estimate_batch: n must be in 1..%d", kMaxBatch);
+  validate_config(*cfg);
+  const size_t nb = (size_t)cfg->n_bins, so = (size_t)(cfg->ell_max / 2 + 1) * nb;
+  for (int i = 0; i < n; ++i) check_request(cfg, &gal[i], &ran[i], norm ? &norm[i] : nullptr, out + i * so);
+  if (!batchable(*cfg) || n == 1) {
+    for (int i = 0; i < n; ++i)
+      run_estimate(ctx, cfg, &gal[i], &ran[i], norm ? &norm[i] : nullptr, out + i * so,
+                   bin_mean ? bin_mean + i * nb : nullptr, counts ? counts + i * nb : nullptr);
+    return;
+  }
+  MainBusy busy(ctx);
+  Reservation res(ctx);
+  make_room_main(ctx, cfg, gal, ran, res, n);
+  Lane &ln = *ctx->main;
+  std::vector<const pw_catalog *> gp((size_t)n), rp((size_t)n);
+  std::vector<const pw_norm *> np((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    gp[(size_t)i] = &gal[i];
+    rp[(size_t)i] = &ran[i];
+    np[(size_t)i] = norm ? &norm[i] : nullptr;
+  }
+  DevPlan *dp = launch_batch(ctx, ln, cfg, n, gp.data(), rp.data(), np.data());
+  res.release();
+  HIPCHECK(hipEventSynchronize(ln.done));
+  const size_t nres = (size_t)(ln.res_rows + 2) * nb;
+  for (int i = 0; i < n; ++i) {  // every catalog's flags before any output is written
+    DevNorm dn;
+    std::memcpy(&dn, (const char *)lane_result(ln, i) + nres * sizeof(double), sizeof(DevNorm));
+    check_flags(dn);
+  }
+  for (int i = 0; i < n; ++i)
+    finish_estimate(ln, dp, lane_result(ln, i), norm ? &norm[i] : nullptr, out + i * so,
+                    bin_mean ? bin_mean + i * nb : nullptr, counts ? counts + i * nb : nullptr);
 }
 
 // Lane 0 after launch_estimate: wait, read the stage times, scale the forward passes'
@@ -1169,6 +1372,9 @@ void destroy_lane(pw_ctx *ctx, Lane *ln) {
   if (ln->stream) (void)hipStreamSynchronize(ln->stream);
   for (auto &kv : ln->plans) free_plan(ctx, kv.second.get());
   ln->plans.clear();
+  for (auto &kv : ln->bplans)
+    for (auto &p : kv.second) free_plan(ctx, p.get());
+  ln->bplans.clear();
   for (int i = 0; i < 2; ++i) dev_free(ctx, ln->stage[i], ln->stage_bytes[i]);
   dev_free(ctx, ln->stage_nbar, ln->stage_nbar_bytes);
   dev_free(ctx, ln->records, ln->records_bytes);
@@ -1202,6 +1408,38 @@ size_t lane_extra_bytes(const Lane &ln, const Req &r) {
     if (ln.stage_nbar_bytes < nb) extra += nb;
   }
   return extra;
+}
+
+// Meshes up to this size batch pending requests of one configuration into one launch (at 512^3
+// one catalog already fills the device).
+constexpr int kBatchMaxMesh = 256;
+
+// Batching in the serving loop: after `lead` is admitted on `ln`, later pending requests of the
+// same batchable configuration join its launch (up to kMaxBatch catalogs) while the memory they
+// add fits the budget: a batch plan's tables when the lane holds too few, a workspace slot,
+// their sort buffers and staging.  Called with ctx->mu held.
+void add_followers(pw_ctx *ctx, Lane &ln, Req *lead) {
+  if (!batchable(lead->cfg) || lead->cfg.n_mesh > kBatchMaxMesh) return;
+  const PlanKey key = make_key(lead->cfg);
+  auto bt = ln.bplans.find(key);
+  const size_t have = bt == ln.bplans.end() ? 0 : bt->second.size();
+  const size_t per = (lead->need_work + 255) & ~(size_t)255;
+  for (auto jt = ctx->pending.begin(); jt != ctx->pending.end() && (int)ln.batch.size() < kMaxBatch;) {
+    Req *q = *jt;
+    if (make_key(q->cfg) != key) {
+      ++jt;
+      continue;
+    }
+    const size_t slot = ln.batch.size();  // catalog index of q in the launch (>= 1)
+    size_t add = (slot - 1 < have) ? 0 : q->need_tables;
+    if (per * slot > ln.bwork_bytes) add += per;
+    add += catalog_bytes(q->cfg, q->gal, q->ran);
+    if (mem_used(ctx) + ctx->reserved + add > ctx->budget) break;
+    q->reserved = add;
+    ctx->reserved += add;
+    ln.batch.push_back(q);
+    jt = ctx->pending.erase(jt);
+  }
 }
 
 // Try to admit the oldest pending request that can run now.  Called with ctx->mu held.
@@ -1256,6 +1494,8 @@ std::pair<Req *, Lane *> pick_admission(pw_ctx *ctx) {
       ctx->pending.erase(it);
       r->reserved = best_extra;  // released once the launch has made its allocations
       ctx->reserved += best_extra;
+      best->batch.assign(1, r);
+      add_followers(ctx, *best, r);
       return {r, best};
     }
     bool running = ctx->main_busy;  // lane 0 may still release memory
@@ -1286,20 +1526,23 @@ void worker_loop(pw_ctx *ctx) {
       if (!ln.cur) continue;
       hipError_t q = hipEventQuery(ln.done);
       if (q == hipErrorNotReady) { any_running = true; continue; }
-      Req *r = ln.cur;
-      if (q != hipSuccess) {
-        r->status = PW_EDEVICE;
-        r->err = std::string("device error: ") + hipGetErrorString(q);
-      } else {
-        try {
-          finish_estimate(ln, r->dp, ln.host_res, r->norm_out, r->out, r->bin_mean, r->counts);
-          r->status = PW_OK;
-        } catch (const Fail &f) {
-          r->status = f.code;
-          r->err = f.msg;
+      for (size_t i = 0; i < ln.batch.size(); ++i) {
+        Req *r = ln.batch[i];
+        if (q != hipSuccess) {
+          r->status = PW_EDEVICE;
+          r->err = std::string("device error: ") + hipGetErrorString(q);
+        } else {
+          try {
+            finish_estimate(ln, r->dp, lane_result(ln, (int)i), r->norm_out, r->out, r->bin_mean, r->counts);
+            r->status = PW_OK;
+          } catch (const Fail &f) {
+            r->status = f.code;
+            r->err = f.msg;
+          }
         }
+        pin_release(ctx, r);  // the lane's copies out of it are complete
       }
-      pin_release(ctx, r);  // the lane's copies out of it are complete
+      ln.batch.clear();
       ln.cur = nullptr;
       ctx->cv.notify_all();
     }
@@ -1310,11 +1553,26 @@ void worker_loop(pw_ctx *ctx) {
       Req *r = a.first;
       Lane &ln = *a.second;
       ln.cur = r;
+      const std::vector<Req *> batch = ln.batch;  // r first (pick_admission)
+      ctx->served_launches += 1;
+      ctx->served_requests += batch.size();
       lk.unlock();
       int code = PW_OK;
       std::string msg;
       try {
-        r->dp = launch_estimate(ctx, ln, &r->cfg, &r->gal, &r->ran, &r->norm_in);
+        if (batch.size() > 1) {
+          std::vector<const pw_catalog *> gp, rp;
+          std::vector<const pw_norm *> np;
+          for (Req *q : batch) {
+            gp.push_back(&q->gal);
+            rp.push_back(&q->ran);
+            np.push_back(&q->norm_in);
+          }
+          DevPlan *dp = launch_batch(ctx, ln, &r->cfg, (int)batch.size(), gp.data(), rp.data(), np.data());
+          for (Req *q : batch) q->dp = dp;
+        } else {
+          r->dp = launch_estimate(ctx, ln, &r->cfg, &r->gal, &r->ran, &r->norm_in);
+        }
       } catch (const Fail &f) {
         code = f.code;
         msg = f.msg;
@@ -1322,16 +1580,23 @@ void worker_loop(pw_ctx *ctx) {
         code = PW_EINVAL;
         msg = e.what();
       }
-      if (code != PW_OK && r->pin) {
-        (void)hipStreamSynchronize(ln.stream);  // staging copies enqueued before the failure
-        pin_release(ctx, r);
+      if (code != PW_OK) {
+        bool pinned = false;
+        for (Req *q : batch) pinned = pinned || q->pin;
+        if (pinned) (void)hipStreamSynchronize(ln.stream);  // staging copies enqueued before the failure
+        for (Req *q : batch) pin_release(ctx, q);
       }
       lk.lock();
-      ctx->reserved -= r->reserved;
-      r->reserved = 0;
+      for (Req *q : batch) {
+        ctx->reserved -= q->reserved;
+        q->reserved = 0;
+      }
       if (code != PW_OK) {
-        r->status = code;
-        r->err = msg;
+        for (Req *q : batch) {
+          q->status = code;
+          q->err = msg;
+        }
+        ln.batch.clear();
         ln.cur = nullptr;
         ctx->cv.notify_all();
       } else {
@@ -1441,6 +1706,30 @@ int pw_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const 
     return PW_EINVAL;
   }
   set_err(ctx, std::string());
+  return PW_OK;
+}
+
+int pw_estimate_batch(pw_ctx *ctx, const pw_config *cfg, int n, const pw_catalog *gal, const pw_catalog *ran,
+                      pw_norm *norm, double *out, double *bin_mean, int64_t *counts) {
+  if (!ctx) return PW_EINVAL;
+  try {
+    run_estimate_batch(ctx, cfg, n, gal, ran, norm, out, bin_mean, counts);
+  } catch (const Fail &f) {
+    set_err(ctx, f.msg);
+    return f.code;
+  } catch (const std::exception &e) {
+    set_err(ctx, e.what());
+    return PW_EINVAL;
+  }
+  set_err(ctx, std::string());
+  return PW_OK;
+}
+
+int pw_serving_stats(pw_ctx *ctx, uint64_t *launches, uint64_t *requests) {
+  if (!ctx) return PW_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (launches) *launches = ctx->served_launches;
+  if (requests) *requests = ctx->served_requests;
   return PW_OK;
 }
 

@@ -37,8 +37,13 @@ __global__ void __launch_bounds__(256)
 k_contract_bis_reg(const cplx<R> *__restrict__ spec, int64_t nmodes, int64_t mstride,
                    const uint32_t *__restrict__ modecoord,
                    int N, const int *__restrict__ bin_of_s2, int64_t n_s2, int nbins, double kf,
-                   const R *__restrict__ winv, double *__restrict__ acc) {
+                   const R *__restrict__ winv, double *__restrict__ acc, const Batch ba) {
   using CT = BisContract<LMAX, BMAX, R>;
+  if (ba.n) {  // catalog blockIdx.z of a batch
+    const BatchSlot &bs = ba.s[blockIdx.z];
+    spec = (const cplx<R> *)bs.A;
+    acc = bs.acc;
+  }
   constexpr int NF = CT::NF;
   constexpr int NSH = (LMAX + 1) * (LMAX + 1);
   constexpr int NE = ORD ? CT::NO * (LMAX / 2 + 1) : LMAX / 2 + 1;
@@ -107,20 +112,25 @@ template <typename R, int L, int B>
 static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, int64_t mstride,
                                 const uint32_t *modecoord,
                                 int N, const int *bin_of_s2, int64_t n_s2, int nbins, double kf,
-                                const void *winv, double *acc, int orders) {
+                                const void *winv, double *acc, int orders, const Batch *batch) {
   if constexpr (BisContract<L, B, R>::kGenerated) {
+    Batch ba;
+    ba.n = 0;
+    if (batch) ba = *batch;
+    const int nb = ba.n ? ba.n : 1;
     int64_t want = (nmodes + 255) / 256;
-    unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    const int64_t cap = 4096 / nb > 0 ? 4096 / nb : 1;
+    unsigned blocks = (unsigned)(want < cap ? (want > 0 ? want : 1) : cap);
     const int ne = (orders ? B + 1 : 1) * (L / 2 + 1);
     size_t sh = (size_t)(ne + 2) * nbins * sizeof(double);
     if (orders)
-      hipLaunchKernelGGL((k_contract_bis_reg<R, L, B, true>), dim3(blocks), dim3(256), sh, s,
+      hipLaunchKernelGGL((k_contract_bis_reg<R, L, B, true>), dim3(blocks, 1, nb), dim3(256), sh, s,
                          (const cplx<R> *)spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf,
-                         (const R *)winv, acc);
+                         (const R *)winv, acc, ba);
     else
-      hipLaunchKernelGGL((k_contract_bis_reg<R, L, B, false>), dim3(blocks), dim3(256), sh, s,
+      hipLaunchKernelGGL((k_contract_bis_reg<R, L, B, false>), dim3(blocks, 1, nb), dim3(256), sh, s,
                          (const cplx<R> *)spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf,
-                         (const R *)winv, acc);
+                         (const R *)winv, acc, ba);
     return true;
   } else {
     return false;
@@ -131,11 +141,12 @@ template <typename R>
 static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void *spec, int64_t nmodes,
                                   int64_t mstride,
                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                  int nbins, double kf, const void *winv, double *acc, int orders) {
+                                  int nbins, double kf, const void *winv, double *acc, int orders,
+                                  const Batch *batch) {
 #define PW_CR(L, B)                                                                                \
   if (lmax == L && bmax == B)                                                                      \
     return contract_reg_launch<R, L, B>(s, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, \
-                                        acc, orders);
+                                        acc, orders, batch);
   PW_CR(0, 0) PW_CR(0, 1) PW_CR(0, 2) PW_CR(2, 0) PW_CR(2, 1) PW_CR(2, 2)
   PW_CR(4, 0) PW_CR(4, 1) PW_CR(4, 2) PW_CR(6, 0) PW_CR(6, 1) PW_CR(6, 2)
 #undef PW_CR
@@ -144,11 +155,12 @@ static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void 
 
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
                                    int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                   int nbins, double kf, const void *winv, double *acc, int orders) {
+                                   int nbins, double kf, const void *winv, double *acc, int orders,
+                                   const Batch *batch) {
   return prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
-                                                  n_s2, nbins, kf, winv, acc, orders)
+                                                  n_s2, nbins, kf, winv, acc, orders, batch)
                    : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
-                                                   n_s2, nbins, kf, winv, acc, orders);
+                                                   n_s2, nbins, kf, winv, acc, orders, batch);
 }
 
 // ------------------------------------------------------------------------------ generated

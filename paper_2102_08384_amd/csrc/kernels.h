@@ -42,6 +42,23 @@ struct PencilInfo {   // a retained (kx, ky) pencil of the z pass
   int kx, ky, kzcnt, pad;
 };
 
+// Catalogs of one batched launch of the bisector P_l passes (same configuration, so the
+// plan's tables are shared): each catalog's own buffers.  Kernels take the table by value and
+// work on catalog blockIdx.z; n = 0 (the default) means no batch, and the kernels use their
+// pointer arguments.
+constexpr int kMaxBatch = 8;
+struct BatchSlot {
+  const void *mesh;
+  void *A, *B;  // spectrum buffers: x- and z-pass output (A), y-pass output (B)
+  const int *rowlist, *rowmask, *zlist, *planemask;
+  const DevNorm *norm;
+  double *acc;
+};
+struct Batch {
+  int n;
+  BatchSlot s[kMaxBatch];
+};
+
 void upload_sh_const(const ShConst &c);
 void upload_sh_const_inverse(const ShConst &c);
 void upload_sh_const_generated(const ShConst &c);
@@ -116,7 +133,7 @@ inline int row_stride(int nkx, int prec) {
 enum { FX_HARMONIC = 0, FX_RADIAL = 1, FX_PLAIN = 2 };
 void launch_fx(hipStream_t s, int prec, int N, int kind, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
-               const int *rowlist, const DevNorm *norm);
+               const int *rowlist, const DevNorm *norm, const Batch *batch = nullptr);
 // Launch shape of a column pass, as picked by the autotuner: fields per workgroup (fpb; 0 = the
 // default, which aims at about 4096 workgroups per launch) and, for the y pass, adjacent
 // columns per workgroup (cols: 0 = one 128-byte row segment, 8 = half of one in FP32).  Every
@@ -135,7 +152,7 @@ struct ColTune {
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields,
                int nplanes, int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen,
                const void *tw, const int *rowmask, const int *zlist, const DevNorm *norm,
-               ColTune tune = ColTune());
+               ColTune tune = ColTune(), const Batch *batch = nullptr);
 // c2c along z.  Full sets (goff null): out[p][moff[q] + kz], all N kz of every pencil.
 // Sphere-pruned sets: out[p][goff[g] + slot * C + c] for pencil q = g C + c, slot as in Prune
 // (C = 128 bytes / complex size, the pencils per workgroup).  Field stride mstride.
@@ -144,7 +161,7 @@ void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *ou
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields,
                int64_t npen, const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff,
                const int *gsize, int64_t mstride, const void *tw, const int *planemask,
-               const int *fmap = nullptr, ColTune tune = ColTune());
+               const int *fmap = nullptr, ColTune tune = ColTune(), const Batch *batch = nullptr);
 
 // Bisector contraction + FP64 k-binning.
 struct TermTable {
@@ -176,7 +193,7 @@ void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, c
 // and the |k| sum ((bmax + 1) * nell + 2 rows of nbins).
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
                                    int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                   int nbins, double kf, const void *winv, double *acc, int orders);
+                                   int nbins, double kf, const void *winv, double *acc, int orders, const Batch *batch = nullptr);
 // Which (ell_max, beta_max) / (ell_max, order) have build-time generated couplings.
 bool bis_contract_generated(int lmax, int bmax);
 bool mid_reweight_generated(int lmax, int order, int all_parity);

@@ -145,8 +145,15 @@ __global__ void __launch_bounds__(FxShape<N>::THREADS)
 __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && N == 512) ? 3 : 1, 8)))
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
      int njobs, int nkx, int rs, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw,
-     const int *__restrict__ rowlist, const DevNorm *__restrict__ norm) {
+     const int *__restrict__ rowlist, const DevNorm *__restrict__ norm, const Batch ba) {
   constexpr int T = FxShape<N>::T, ROWS = FxShape<N>::ROWS;
+  if (ba.n) {  // catalog blockIdx.z of a batch
+    const BatchSlot &bs = ba.s[blockIdx.z];
+    mesh = (const R *)bs.mesh;
+    out = (cplx<R> *)bs.A;
+    rowlist = bs.rowlist;
+    norm = bs.norm;
+  }
   constexpr bool WAVE = (T == 64);
   constexpr int LN = N + N / 8;
   __shared__ cplx<R> lds[ROWS * LN];
@@ -339,13 +346,17 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 template <typename R, int N>
 static void fx_launch(hipStream_t s, int kind, const void *mesh, void *out, const FieldJob *jobs, int njobs,
                       int nkx, int rs, const double *b0, double H, double unit, const void *tw,
-                      const int *rowlist, const DevNorm *norm) {
+                      const int *rowlist, const DevNorm *norm, const Batch *batch) {
   constexpr int ROWS = FxShape<N>::ROWS;
   unsigned blocks = (unsigned)((size_t)N * N / ROWS);
+  Batch ba;
+  ba.n = 0;
+  if (batch) ba = *batch;
+  const dim3 grid(blocks, 1, ba.n ? ba.n : 1);
 #define PW_FX(PL, RAD)                                                                                           \
-  hipLaunchKernelGGL((k_fx<R, N, PL, RAD>), dim3(blocks), dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,      \
+  hipLaunchKernelGGL((k_fx<R, N, PL, RAD>), grid, dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,              \
                      (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),  \
-                     (const cplx<R> *)tw, rowlist, norm)
+                     (const cplx<R> *)tw, rowlist, norm, ba)
   if (kind == FX_PLAIN) PW_FX(true, false);
   else if (kind == FX_RADIAL) PW_FX(false, true);
   else PW_FX(false, false);
@@ -354,9 +365,9 @@ static void fx_launch(hipStream_t s, int kind, const void *mesh, void *out, cons
 
 void launch_fx(hipStream_t s, int prec, int N, int kind, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
-               const int *rowlist, const DevNorm *norm) {
-  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
-  else { PW_DISPATCH_N(fx_launch, double, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm) }
+               const int *rowlist, const DevNorm *norm, const Batch *batch) {
+  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm, batch) }
+  else { PW_DISPATCH_N(fx_launch, double, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm, batch) }
 }
 
 // ------------------------------------------------------------------------------ fy / fz
@@ -370,8 +381,17 @@ template <typename R, int N, bool INV, int CC>
 __global__ void __launch_bounds__(CC * (N / 8))
 k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int fpb, int nplanes, int nkx, int rs,
      const int *__restrict__ ycnt, const int64_t *__restrict__ yoff, int64_t npen, const cplx<R> *__restrict__ tw,
-     const int *__restrict__ rowmask, const int *__restrict__ zlist, const DevNorm *__restrict__ norm) {
+     const int *__restrict__ rowmask, const int *__restrict__ zlist, const DevNorm *__restrict__ norm,
+     const Batch ba) {
   constexpr int T = N / 8, C = CC, NT = CC * T;
+  if (ba.n) {  // catalog blockIdx.z of a batch
+    const BatchSlot &bs = ba.s[blockIdx.z];
+    in = (const cplx<R> *)bs.A;
+    out = (cplx<R> *)bs.B;
+    rowmask = bs.rowmask;
+    zlist = bs.zlist;
+    norm = bs.norm;
+  }
   constexpr int Q = 128 / (int)sizeof(cplx<R>);
   constexpr int LB = N * (C + 1);  // one exchange buffer; two alternate (one barrier per exchange)
   __shared__ cplx<R> lds[2 * LB];
@@ -434,25 +454,30 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
 template <typename R, int N>
 static void fy_launch(hipStream_t s, int inv, const void *in, void *out, int nfields, int nplanes, int nkx,
                       int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
-                      const int *rowmask, const int *zlist, const DevNorm *norm, ColTune tune) {
+                      const int *rowmask, const int *zlist, const DevNorm *norm, ColTune tune,
+                      const Batch *batch) {
   constexpr int CY = ColShape<R, N>::C;  // 128-byte row segments
+  Batch ba;
+  ba.n = 0;
+  if (batch) ba = *batch;
+  const int nb = ba.n ? ba.n : 1;
   int fpb = tune.fpb;
   if (fpb <= 0) {
-    const int G = field_groups(nfields, nplanes);
+    const int G = field_groups(nfields, nplanes * nb);
     fpb = (nfields + G - 1) / G;
   }
   fpb = std::min(fpb, nfields);
-  dim3 grid(nplanes, (nfields + fpb - 1) / fpb);
+  dim3 grid(nplanes, (nfields + fpb - 1) / fpb, nb);
 #define PW_FY(CC)                                                                                  \
   do {                                                                                             \
     if (inv)                                                                                       \
       hipLaunchKernelGGL((k_fy<R, N, true, CC>), grid, dim3((CC) * (N / 8)), 0, s, (const cplx<R> *)in, \
                          (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen,          \
-                         (const cplx<R> *)tw, rowmask, zlist, norm);                                \
+                         (const cplx<R> *)tw, rowmask, zlist, norm, ba);                            \
     else                                                                                           \
       hipLaunchKernelGGL((k_fy<R, N, false, CC>), grid, dim3((CC) * (N / 8)), 0, s, (const cplx<R> *)in, \
                          (cplx<R> *)out, nfields, fpb, nplanes, nkx, rs, ycnt, yoff, npen,          \
-                         (const cplx<R> *)tw, rowmask, zlist, norm);                                \
+                         (const cplx<R> *)tw, rowmask, zlist, norm, ba);                            \
   } while (0)
   // half-segment columns (8 per workgroup) only where a full segment holds 16 (FP32)
   if constexpr (CY == 16) {
@@ -467,14 +492,14 @@ static void fy_launch(hipStream_t s, int inv, const void *in, void *out, int nfi
 
 void launch_fy(hipStream_t s, int prec, int N, int inv, const void *in, void *out, int nfields, int nplanes,
                int nkx, int rs, const int *ycnt, const int64_t *yoff, int64_t npen, const void *tw,
-               const int *rowmask, const int *zlist, const DevNorm *norm, ColTune tune) {
+               const int *rowmask, const int *zlist, const DevNorm *norm, ColTune tune, const Batch *batch) {
   if (nfields <= 0 || nplanes <= 0) return;
   if (prec == 0) {
     PW_DISPATCH_N(fy_launch, float, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
-                  zlist, norm, tune)
+                  zlist, norm, tune, batch)
   } else {
     PW_DISPATCH_N(fy_launch, double, s, inv, in, out, nfields, nplanes, nkx, rs, ycnt, yoff, npen, tw, rowmask,
-                  zlist, norm, tune)
+                  zlist, norm, tune, batch)
   }
 }
 
@@ -486,8 +511,14 @@ __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_fz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int fpb, int64_t npen,
      const PencilInfo *__restrict__ pinfo, const int64_t *__restrict__ moff, const int64_t *__restrict__ goff,
      const int *__restrict__ gsize, int64_t mstride, const cplx<R> *__restrict__ tw,
-     const int *__restrict__ planemask, const int *__restrict__ fmap) {
+     const int *__restrict__ planemask, const int *__restrict__ fmap, const Batch ba) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
+  if (ba.n) {  // catalog blockIdx.z of a batch
+    const BatchSlot &bs = ba.s[blockIdx.z];
+    in = (const cplx<R> *)bs.B;
+    out = (cplx<R> *)bs.A;
+    planemask = bs.planemask;
+  }
   constexpr int LB = N * (C + 1);  // one exchange buffer; grouped: two alternate
   __shared__ cplx<R> lds[GROUPED ? 2 * LB : LB];
   __shared__ int st[C + 1];                      // full sets: first output mode of each pencil
@@ -574,37 +605,42 @@ template <typename R, int N>
 static void fz_launch(hipStream_t s, const void *in, void *out, int nfields, int64_t npen,
                       const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
                       int64_t mstride, const void *tw, const int *planemask, const int *fmap,
-                      ColTune tune) {
+                      ColTune tune, const Batch *batch) {
   constexpr int C = ColShape<R, N>::C;
   static_assert(C == 128 / (int)sizeof(cplx<R>), "z-pass groups must match 128-byte slot rows");
   const unsigned ng = (unsigned)((npen + C - 1) / C);
+  Batch ba;
+  ba.n = 0;
+  if (batch) ba = *batch;
+  const int nb = ba.n ? ba.n : 1;
   int fpb = tune.fpb;
   if (fpb <= 0) {
-    const int G = field_groups(nfields, (int)std::min<int64_t>(ng, 1 << 20));
+    const int G = field_groups(nfields, (int)std::min<int64_t>((int64_t)ng * nb, 1 << 20));
     fpb = (nfields + G - 1) / G;
   }
   fpb = std::min(fpb, nfields);
-  dim3 grid(ng, (nfields + fpb - 1) / fpb);
+  dim3 grid(ng, (nfields + fpb - 1) / fpb, nb);
   if (goff)
     hipLaunchKernelGGL((k_fz<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
                        (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, goff, gsize, mstride, (const cplx<R> *)tw,
-                       planemask, fmap);
+                       planemask, fmap, ba);
   else
     hipLaunchKernelGGL((k_fz<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (const cplx<R> *)in,
                        (cplx<R> *)out, nfields, fpb, npen, pinfo, moff, goff, gsize, mstride, (const cplx<R> *)tw,
-                       planemask, (const int *)nullptr);
+                       planemask, (const int *)nullptr, ba);
 }
 
 void launch_fz(hipStream_t s, int prec, int N, const void *in, void *out, int nfields, int64_t npen,
                const PencilInfo *pinfo, const int64_t *moff, const int64_t *goff, const int *gsize,
-               int64_t mstride, const void *tw, const int *planemask, const int *fmap, ColTune tune) {
+               int64_t mstride, const void *tw, const int *planemask, const int *fmap, ColTune tune,
+               const Batch *batch) {
   if (nfields <= 0 || npen <= 0) return;
   if (prec == 0) {
     PW_DISPATCH_N(fz_launch, float, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask,
-                  fmap, tune)
+                  fmap, tune, batch)
   } else {
     PW_DISPATCH_N(fz_launch, double, s, in, out, nfields, npen, pinfo, moff, goff, gsize, mstride, tw, planemask,
-                  fmap, tune)
+                  fmap, tune, batch)
   }
 }
 

@@ -70,6 +70,10 @@ def _load():
     lib.pw_estimate.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                                 C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_int64)]
+    lib.pw_estimate_batch.argtypes = [P, C.POINTER(_Config), C.c_int, C.POINTER(_Catalog), C.POINTER(_Catalog),
+                                      C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64)]
+    lib.pw_serving_stats.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     lib.pw_estimate_noalloc.argtypes = [P, C.POINTER(_Config), C.POINTER(_Catalog), C.POINTER(_Catalog),
                                         C.POINTER(_Norm), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_int64)]
@@ -262,6 +266,38 @@ class Context:
     def estimate(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """Run one estimate.  norm = (alpha_r, I, S) to impose the normalisation."""
         return self._run(_lib.pw_estimate, (cfg.n_ell, cfg.n_bins), cfg, gal_xyzw, ran_xyzw, ran_nbar, norm)
+
+    def estimate_batch(self, cfg: Config, cats):
+        """pw_estimate_batch over cats = [(gal_xyzw, ran_xyzw, ran_nbar), ...] of one configuration;
+        returns one result dict per catalog."""
+        keep = []
+        n = len(cats)
+        gals = (_Catalog * n)()
+        rans = (_Catalog * n)()
+        for i, (g, r, nb) in enumerate(cats):
+            gals[i] = _catalog(g, None, keep)
+            rans[i] = _catalog(r, nb, keep)
+        norms = (_Norm * n)()
+        out = np.zeros((n, cfg.n_ell, cfg.n_bins))
+        bm = np.zeros((n, cfg.n_bins))
+        cnt = np.zeros((n, cfg.n_bins), dtype=np.int64)
+        c = cfg._c()
+        rc = _lib.pw_estimate_batch(self._h, C.byref(c), n, gals, rans, norms,
+                                    out.ctypes.data_as(C.POINTER(C.c_double)),
+                                    bm.ctypes.data_as(C.POINTER(C.c_double)),
+                                    cnt.ctypes.data_as(C.POINTER(C.c_int64)))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        return [{"values": out[i], "bin_mean": bm[i], "counts": cnt[i],
+                 "norm": (norms[i].alpha_r, norms[i].I, norms[i].S)} for i in range(n)]
+
+    def serving_stats(self):
+        """(launches, requests) of the serving loop so far."""
+        a, b = C.c_uint64(), C.c_uint64()
+        rc = _lib.pw_serving_stats(self._h, C.byref(a), C.byref(b))
+        if rc != PW_OK:
+            raise PwError(rc, self.last_error())
+        return a.value, b.value
 
     def estimate_noalloc(self, cfg: Config, gal_xyzw, ran_xyzw, ran_nbar=None, norm=None):
         """pw_estimate_noalloc: the estimate in the library's static device scratch (device
