@@ -289,16 +289,31 @@ def _pct(v):
 
 
 def batch_gain(pw, torch, ctx, reqs, n=8):
-    """Batched launches against one estimate after another: n bisector requests of one mesh from
-    the stream (pinned host inputs), as n pw_estimate calls and as one pw_estimate_batch call
-    (each forward pass and the contraction once over the n catalogs)."""
+    """Batched launches against one estimate after another: n bisector catalogs of one mesh, as
+    n pw_estimate calls and as one pw_estimate_batch call (each forward pass and the contraction
+    once over the n catalogs).  Cases: the stream's own requests at 128^3 and 256^3 (pinned host
+    inputs, so every catalog is copied to the device), the same catalogs device-resident, and
+    small device-resident catalogs (windows of 1e5 galaxies) at 64^3 and 128^3."""
     out = {}
+    cases = []
     for N in (128, 256):
         sel = [q for q in reqs if q[1].los == pw.PW_BISECTOR and q[1].n_mesh == N][:n]
-        if len(sel) < 2:
-            continue
-        cfg = sel[0][1]
-        cats = [(g, r, nb) for _, _, g, r, nb in sel]
+        if len(sel) >= 2:
+            cats = [(g, r, nb) for _, _, g, r, nb in sel]
+            cases.append((f"bisector_{N}_host_inputs", sel[0][1], cats))
+            cases.append((f"bisector_{N}_device_inputs", sel[0][1], [tuple(a.cuda() for a in c) for c in cats]))
+    bis = [q for q in reqs if q[1].los == pw.PW_BISECTOR]
+    if bis:
+        g, r, nb = bis[0][2], bis[0][3], bis[0][4]
+        small = [(g[i * 100_000:(i + 1) * 100_000].cuda(), r[i * 500_000:(i + 1) * 500_000].cuda(),
+                  nb[i * 500_000:(i + 1) * 500_000].cuda()) for i in range(n)
+                 if (i + 1) * 100_000 <= len(g) and (i + 1) * 500_000 <= len(r)]
+        for N in (64, 128):
+            cfg = pw.Config(**{**bis[0][1].__dict__, "n_mesh": N,
+                               "n_bins": int((min(0.40, np.pi * N / bis[0][1].box_len) - 0.005) / 0.005)})
+            if len(small) >= 2:
+                cases.append((f"bisector_{N}_small_device_inputs", cfg, small))
+    for name, cfg, cats in cases:
         ctx.estimate_batch(cfg, cats)        # warm: batch plans and workspace
         reps = 3
         torch.cuda.synchronize()
@@ -311,10 +326,11 @@ def batch_gain(pw, torch, ctx, reqs, n=8):
         for _ in range(reps):
             ctx.estimate_batch(cfg, cats)
         bat = (time.perf_counter() - t0) / reps
-        out[f"bisector_{N}"] = {"catalogs": len(cats), "one_after_another_ms": seq * 1e3, "batched_ms": bat * 1e3,
-                                "speedup": seq / bat,
-                                "galaxies": [int(g.shape[0]) for g, _, _ in cats]}
-        log(f"batched {len(cats)} x bisector {N}^3: {seq * 1e3:.1f} ms one after another, {bat * 1e3:.1f} ms batched")
+        out[name] = {"catalogs": len(cats), "n_mesh": cfg.n_mesh, "one_after_another_ms": seq * 1e3,
+                     "batched_ms": bat * 1e3, "speedup": seq / bat,
+                     "galaxies": [int(g.shape[0]) for g, _, _ in cats]}
+        log(f"batched {name}: {seq * 1e3:.1f} ms one after another, {bat * 1e3:.1f} ms batched")
+        del cats
     return out
 
 
@@ -355,7 +371,6 @@ def serving_stream(pw, torch, n_req, lanes, loads=(0.7, 1.5)):
     warm = [ctx.submit(cfg, g, r, ran_nbar=n) for lab, cfg, g, r, n in reqs]
     for t in warm:
         t.wait()
-    out["batched"] = batch_gain(pw, torch, ctx, reqs)
     rng = np.random.default_rng(11)
     for load in loads:
         gaps = rng.exponential(1.0 / (load * cap), len(reqs))
@@ -400,6 +415,7 @@ def serving_stream(pw, torch, n_req, lanes, loads=(0.7, 1.5)):
                               "latency_ms": _pct(lat), "launches": l1 - l0, "requests_launched": q1 - q0}
         log(f"serving at {load}x: {(len(reqs) - len(failed)) / el:.2f} requests/s, p50 {np.percentile(lat, 50):.1f} "
             f"ms, p99 {np.percentile(lat, 99):.1f} ms, {len(failed)} failed")
+    out["batched"] = batch_gain(pw, torch, ctx, reqs)
     ctx.close()
     return out
 

@@ -1417,14 +1417,17 @@ constexpr int kBatchMaxMesh = 256;
 // Batching in the serving loop: after `lead` is admitted on `ln`, later pending requests of the
 // same batchable configuration join its launch (up to kMaxBatch catalogs) while the memory they
 // add fits the budget: a batch plan's tables when the lane holds too few, a workspace slot,
-// their sort buffers and staging.  Called with ctx->mu held.
+// their sort buffers and staging.  A lane's batch workspace stays within 1/16 of the budget, so
+// batching never crowds out other lanes' workspaces.  Called with ctx->mu held.
 void add_followers(pw_ctx *ctx, Lane &ln, Req *lead) {
   if (!batchable(lead->cfg) || lead->cfg.n_mesh > kBatchMaxMesh) return;
   const PlanKey key = make_key(lead->cfg);
   auto bt = ln.bplans.find(key);
   const size_t have = bt == ln.bplans.end() ? 0 : bt->second.size();
   const size_t per = (lead->need_work + 255) & ~(size_t)255;
-  for (auto jt = ctx->pending.begin(); jt != ctx->pending.end() && (int)ln.batch.size() < kMaxBatch;) {
+  const size_t max_slots = per > 0 ? (ctx->budget / 16) / per : 0;  // catalogs beyond the lead
+  for (auto jt = ctx->pending.begin();
+       jt != ctx->pending.end() && (int)ln.batch.size() < kMaxBatch && ln.batch.size() <= max_slots;) {
     Req *q = *jt;
     if (make_key(q->cfg) != key) {
       ++jt;
