@@ -405,48 +405,57 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
   FftTw<R, N> twr;
   twr.load(t, tw);
   // output rows of this lane (ky = t + s*T) and their padded lengths, fixed for the block
-  int64_t yo[8];
-  int yl[8];
+  // (offsets within one output plane: below 2^31 for every supported mesh)
+  int yo[8], yl[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
-    yo[s] = yoff[t + s * T];
+    yo[s] = (int)yoff[t + s * T];
     yl[s] = (ycnt[t + s * T] + Q - 1) / Q * Q;
   }
   for (int i = threadIdx.x; i < N; i += NT) msk[i] = rowmask ? rowmask[z * N + i] : 1;
   wait_vmem();
   __syncthreads();
+  // input rows of this lane (y = t + s*T): bit s set when the row holds data; row offsets
+  unsigned live = 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) live |= (msk[t + s * T] ? 1u : 0u) << s;
   const int ncb = (nkx + C - 1) / C;
   const int p0 = blockIdx.y * fpb;
   const int p1 = min(nfields, p0 + fpb);
   const int nitems = (p1 - p0) * ncb;
   if (nitems <= 0) return;
-  auto load = [&](int it, cplx<R> *v) {
-    const int p = p0 + it / ncb, kx = (it % ncb) * C + c;
-    const cplx<R> *src = in + ((size_t)p * nplanes + z) * N * rs;
+  const size_t plane = (size_t)N * rs;  // one input plane of one field
+  auto load = [&](int p, int cb, cplx<R> *v) {
+    const int kx = cb * C + c;
+    const cplx<R> *src = in + ((size_t)p * nplanes + z) * plane + kx;
+    const unsigned lv = kx < nkx ? live : 0u;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int y = t + s * T;
-      v[s] = (kx < nkx && msk[y]) ? src[(size_t)y * rs + kx] : mk<R>(0, 0);
-    }
+    for (int s = 0; s < 8; ++s) v[s] = ((lv >> s) & 1u) ? src[(t + s * T) * rs] : mk<R>(0, 0);
   };
   int lb = 0;
   auto at = [c, &lb](int i) -> cplx<R> & { return lds[lb * LB + i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
   auto flip = [&lb]() { lb ^= 1; };
+  // items (field p, column group cb) in order, stepped without division
+  int p = p0, cb = 0;
   cplx<R> nxt[8];
-  load(0, nxt);
+  load(p, cb, nxt);
   for (int it = 0; it < nitems; ++it) {
     cplx<R> v[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
-    if (it + 1 < nitems) load(it + 1, nxt);
+    const int pc = p, kx = cb * C + c;
+    if (++cb == ncb) {
+      cb = 0;
+      ++p;
+    }
+    if (it + 1 < nitems) load(p, cb, nxt);
     fft_pencil_db<R, N, INV>(v, t, twr, at, sync, flip);
-    const int p = p0 + it / ncb, kx = (it % ncb) * C + c;
-    cplx<R> *dst = out + ((size_t)p * nplanes + z) * npen;
+    cplx<R> *dst = out + ((size_t)pc * nplanes + z) * npen + kx;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       // whole 128-byte lines: the row's padding slots are written too (never read as modes)
-      if (kx < yl[s]) dst[yo[s] + kx] = v[s];
+      if (kx < yl[s]) dst[yo[s]] = v[s];
     }
   }
 }

@@ -170,6 +170,7 @@ __device__ __forceinline__ bool particle_tile(const double v[4], int N, double b
 }
 
 constexpr int kSortWaves = kAggThreads / 64;
+constexpr int kSortUnroll = 4;  // particles per thread whose loads are issued together
 
 __device__ __forceinline__ double wave_combine(int c, double v) {
 #pragma unroll
@@ -200,24 +201,37 @@ k_sort_count(const RG *__restrict__ gx, const RR *__restrict__ rx, const RR *__r
   const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
   double sw = 0, sw2 = 0, swn = 0, swa = 0, cnt = 0;
   double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-    double v[4];
-    if (ran) load_record(rx, i, vec_r != 0, v);
-    else load_record(gx, i, vec_g != 0, v);
-    const double w = v[3];
-    sw += w;
-    sw2 += w * w;
-    swa += fabs(w);
-    if (ran && rnbar) swn += w * w * (double)rnbar[i];
+  // kSortUnroll records per thread in flight (thread order of the particles unchanged)
+  for (int64_t ib = c0 + threadIdx.x; ib < c1; ib += kSortUnroll * (int64_t)blockDim.x) {
+    double v[kSortUnroll][4], nb[kSortUnroll];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = fmin(mn[a], v[a]);
-      mx[a] = fmax(mx[a], v[a]);
+    for (int k = 0; k < kSortUnroll; ++k) {
+      const int64_t i = ib + k * (int64_t)blockDim.x;
+      nb[k] = 0.0;
+      if (i < c1) {
+        if (ran) load_record(rx, i, vec_r != 0, v[k]);
+        else load_record(gx, i, vec_g != 0, v[k]);
+        if (ran && rnbar) nb[k] = (double)rnbar[i];
+      }
     }
-    cnt += 1;
-    int i0[3], tile;
-    double d[3];
-    if (particle_tile(v, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
+#pragma unroll
+    for (int k = 0; k < kSortUnroll; ++k) {
+      if (ib + k * (int64_t)blockDim.x >= c1) break;
+      const double w = v[k][3];
+      sw += w;
+      sw2 += w * w;
+      swa += fabs(w);
+      if (ran && rnbar) swn += w * w * nb[k];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        mn[a] = fmin(mn[a], v[k][a]);
+        mx[a] = fmax(mx[a], v[k][a]);
+      }
+      cnt += 1;
+      int i0[3], tile;
+      double d[3];
+      if (particle_tile(v[k], N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) atomicAdd(&hist[tile], 1);
+    }
   }
   double vals[kScalarCols] = {sw, sw2, swn, mn[0], mn[1], mn[2], mx[0], mx[1], mx[2], cnt, swa};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -336,20 +350,30 @@ k_sort_scatter(const RG *__restrict__ gx, const RR *__restrict__ rx, int64_t ng,
   const int64_t c0 = (int64_t)b * chunk;
   const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
   const double wmul = ran ? -norm->alpha_r : 1.0;
-  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-    double v[4];
-    if (ran) load_record(rx, i, vec_r != 0, v);
-    else load_record(gx, i, vec_g != 0, v);
-    int i0[3], tile;
-    double d[3];
-    if (!particle_tile(v, N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) continue;
-    const int pos = atomicAdd(&hist[tile], 1);
-    typename Rec4<RM>::T r;
-    r.x = (RM)((double)(i0[0] % ts) + d[0]);
-    r.y = (RM)((double)(i0[1] % ts) + d[1]);
-    r.z = (RM)((double)(i0[2] % ts) + d[2]);
-    r.w = (RM)(v[3] * wmul);
-    rec[pos] = r;
+  for (int64_t ib = c0 + threadIdx.x; ib < c1; ib += kSortUnroll * (int64_t)blockDim.x) {
+    double v[kSortUnroll][4];
+#pragma unroll
+    for (int k = 0; k < kSortUnroll; ++k) {
+      const int64_t i = ib + k * (int64_t)blockDim.x;
+      if (i < c1) {
+        if (ran) load_record(rx, i, vec_r != 0, v[k]);
+        else load_record(gx, i, vec_g != 0, v[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSortUnroll; ++k) {
+      if (ib + k * (int64_t)blockDim.x >= c1) break;
+      int i0[3], tile;
+      double d[3];
+      if (!particle_tile(v[k], N, b0x, b0y, b0z, H, assign, ts, i0, d, &tile)) continue;
+      const int pos = atomicAdd(&hist[tile], 1);
+      typename Rec4<RM>::T r;
+      r.x = (RM)((double)(i0[0] % ts) + d[0]);
+      r.y = (RM)((double)(i0[1] % ts) + d[1]);
+      r.z = (RM)((double)(i0[2] % ts) + d[2]);
+      r.w = (RM)(v[k][3] * wmul);
+      rec[pos] = r;
+    }
   }
 }
 
@@ -376,8 +400,12 @@ __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restric
   __syncthreads();
   constexpr int NTAP = (ASSIGN == 2) ? 2 : 3;
   constexpr int O0 = (ASSIGN == 2) ? 1 : 0;   // LDS index of tap a on an axis: l + a + O0
+  // each thread's records in turn, the next one loaded while the current one is deposited
+  typename Rec4<RM>::T nxt;
+  if (beg + (int)threadIdx.x < end) nxt = rec[beg + threadIdx.x];
   for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
-    const typename Rec4<RM>::T r = rec[p];
+    const typename Rec4<RM>::T r = nxt;
+    if (p + (int)blockDim.x < end) nxt = rec[p + blockDim.x];
     const RM v[3] = {r.x, r.y, r.z};
     int l[3];
     RM wt[3][3];
@@ -420,12 +448,15 @@ __global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restric
 
 // Node (x, y, z) of tile T at local (lx, ly, lz) is covered by the block of tile T + d for
 // d in {-1, 0, 1}^3 where d_a = -1 needs l_a = 0 and d_a = +1 needs l_a = ts - 1; inside that
-// block it sits at local l - d ts, block index l - d ts + 1.  Empty tiles have no block.  The
-// (at most eight) block values are summed in FP64 in the fixed order of d, so the mesh is the
-// same on every run.
+// block it sits at local l - d ts, block index l - d ts + 1.  Empty tiles have no block.
 // One workgroup per group of GX tiles along x (GX = 2 for FP32 with at least two tiles per
 // axis, so mesh rows are written as whole 128-byte lines); the slots of the group's
-// neighbourhood are read into LDS once.  N and ts are powers of two.
+// neighbourhood are read into LDS once.  Every thread first loads all the block values it
+// will need (its nodes' own values and its share of the neighbours' halo values), so a
+// workgroup waits on memory about twice; the values are then summed in LDS: each node takes
+// its own block's value, then the halo values in a fixed order of classes (x faces, y faces,
+// z faces, xy / xz / yz edges, corners).  Within one class a node receives at most one value
+// (ts > 1), so the mesh is the same on every run.  N and ts are powers of two, ts = 16 (or N).
 // A workgroup whose whole row of tiles (every tx at its ty, tz) has no occupied tile within
 // one tile in y and z writes nothing: every x-row it covers is zero, stays out of rowmask, and
 // no kernel reads mesh rows outside the occupied-row list.
@@ -433,51 +464,123 @@ template <typename RM>
 __global__ void __launch_bounds__(256) k_tile_gather(int lgN, int lgts, int lggx, const int *__restrict__ slot,
                                                      const RM *__restrict__ blocks, RM *__restrict__ mesh,
                                                      int *__restrict__ rowmask) {
+  constexpr int kNodes = 32768 / (int)sizeof(RM);  // GX * ts^3 nodes: 8192 FP32 (GX 2), 4096 FP64
+  constexpr int kOwn = kNodes / 256;               // nodes per thread, at most
   const int N = 1 << lgN, ts = 1 << lgts, nt = N >> lgts, E = ts + 2, GX = 1 << lggx;
   const size_t E3 = (size_t)E * E * E;
   __shared__ int sl[3][3][4];  // [dz + 1][dy + 1][tile offset along x + 1], offsets -1 .. GX
+  __shared__ RM acc[kNodes];   // node lxg + W (ly + ts lz) of the group, W = GX ts
   const int ngx = nt >> lggx;
   const int gx = (int)blockIdx.x % ngx, ty = ((int)blockIdx.x / ngx) % nt, tz = (int)blockIdx.x / (ngx * nt);
   const int tx0 = gx << lggx;
+  const int tid = threadIdx.x;
+  // occupancy of the tile row's neighbourhood (9 nt <= 288 slots) and the group's slots
   int occ = 0;
-  for (int i = threadIdx.x; i < 9 * nt; i += blockDim.x) {
-    const int tx = i % nt, dy = (i / nt) % 3 - 1, dz = i / (3 * nt) - 1;
-    occ |= slot[(((tz + dz + nt) & (nt - 1)) * nt + ((ty + dy + nt) & (nt - 1))) * nt + tx] >= 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int i = tid + 256 * k;
+    if (i < 9 * nt) {
+      const int tx = i % nt, dy = (i / nt) % 3 - 1, dz = i / (3 * nt) - 1;
+      occ |= slot[(((tz + dz + nt) & (nt - 1)) * nt + ((ty + dy + nt) & (nt - 1))) * nt + tx] >= 0;
+    }
   }
-  if (!__syncthreads_or(occ)) return;  // uniform for the workgroup
-  if ((int)threadIdx.x < 9 * (GX + 2)) {
-    const int i = threadIdx.x;
-    const int dxi = i % (GX + 2), dy = (i / (GX + 2)) % 3 - 1, dz = i / (3 * (GX + 2)) - 1;
+  if (tid < 9 * (GX + 2)) {
+    const int dxi = tid % (GX + 2), dy = (tid / (GX + 2)) % 3 - 1, dz = tid / (3 * (GX + 2)) - 1;
     const int tx = (tx0 + dxi - 1 + nt) & (nt - 1), tyy = (ty + dy + nt) & (nt - 1), tzz = (tz + dz + nt) & (nt - 1);
     sl[dz + 1][dy + 1][dxi] = slot[(tzz * nt + tyy) * nt + tx];
   }
-  __syncthreads();
+  if (!__syncthreads_or(occ)) return;  // uniform for the workgroup
   const int lgW = lggx + lgts;  // nodes per row of the group: W = GX * ts
-  const int nnode = 1 << (lgW + 2 * lgts);
-#pragma unroll 4
-  for (int n = threadIdx.x; n < nnode; n += 256) {
-    const int lxg = n & ((1 << lgW) - 1), ly = (n >> lgW) & (ts - 1), lz = n >> (lgW + lgts);
-    const int txl = lxg >> lgts, lx = lxg & (ts - 1);
-    const int l[3] = {lx, ly, lz};
-    int dlo[3], dhi[3];
+  const int W = 1 << lgW;
+  const int nown = 1 << (lgW + 2 * lgts - 8);  // nodes per thread (the group has a multiple of 256)
+  const int hi = ts - 1;
+  // the value of neighbour d at node (lxg, ly, lz) and the node's index (-1: no block)
+  auto fetch = [&](int dx, int dy, int dz, int lxg, int ly, int lz, int &node) -> RM {
+    const int s = sl[dz + 1][dy + 1][(lxg >> lgts) + dx + 1];
+    node = s < 0 ? -1 : lxg + ((ly + (lz << lgts)) << lgW);
+    if (s < 0) return (RM)0;
+    const int ex = (lxg & hi) - dx * ts + 1, ey = ly - dy * ts + 1, ez = lz - dz * ts + 1;
+    return blocks[(size_t)s * E3 + (size_t)((ez * E + ey) * E + ex)];
+  };
+  // own values: node tid + 256 k, block index l + 1
+  RM own[kOwn];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      dlo[a] = (l[a] == 0) ? -1 : 0;
-      dhi[a] = (l[a] == ts - 1) ? 1 : 0;
+  for (int k = 0; k < kOwn; ++k) {
+    if (k < nown) {
+      const int n = tid + (k << 8);
+      const int lxg = n & (W - 1), ly = (n >> lgW) & hi, lz = n >> (lgW + lgts);
+      const int s = sl[1][1][(lxg >> lgts) + 1];
+      own[k] = s < 0 ? (RM)0 : blocks[(size_t)s * E3 + (size_t)(((lz + 1) * E + ly + 1) * E + (lxg & hi) + 1)];
     }
-    double v = 0.0;
-    for (int dz = dlo[2]; dz <= dhi[2]; ++dz)
-      for (int dy = dlo[1]; dy <= dhi[1]; ++dy)
-        for (int dx = dlo[0]; dx <= dhi[0]; ++dx) {
-          const int s = sl[dz + 1][dy + 1][txl + dx + 1];
-          if (s < 0) continue;
-          const int ex = lx - dx * ts + 1, ey = ly - dy * ts + 1, ez = lz - dz * ts + 1;
-          v += (double)blocks[(size_t)s * E3 + ((size_t)ez * E + ey) * E + ex];
-        }
-    const int x = (tx0 << lgts) + lxg, y = (ty << lgts) + ly, z = (tz << lgts) + lz;
-    const size_t g = ((size_t)z * N + y) * N + x;
-    mesh[g] = (RM)v;
-    if (rowmask && v != 0.0) rowmask[g >> lgN] = 1;  // every writer stores the same value
+  }
+  // faces: item i = 2 r + f, f the face (0: low, 1: high); x: r -> (tile, ly, lz);
+  // y: r -> (lxg, lz); z: r -> (lxg, ly).  At most 4 items of each per thread.
+  RM fv[3][4];
+  int fn[3][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = tid + (k << 8), f = i & 1, r = i >> 1;
+    fn[0][k] = fn[1][k] = fn[2][k] = -1;
+    if (i < 2 * GX * ts * ts)
+      fv[0][k] = fetch(f ? 1 : -1, 0, 0, ((r & (GX - 1)) << lgts) + (f ? hi : 0), (r >> lggx) & hi,
+                       r >> (lggx + lgts), fn[0][k]);
+    if (i < 2 * W * ts) {
+      fv[1][k] = fetch(0, f ? 1 : -1, 0, r & (W - 1), f ? hi : 0, r >> lgW, fn[1][k]);
+      fv[2][k] = fetch(0, 0, f ? 1 : -1, r & (W - 1), r >> lgW, f ? hi : 0, fn[2][k]);
+    }
+  }
+  // edges: item i = 4 r + f, f the two signs; xy: r -> (tile, lz); xz: r -> (tile, ly);
+  // yz: r -> lxg.  Corners: item i = 8 tile + f, f the three signs.
+  RM ev[3], cv = (RM)0;
+  int en[3] = {-1, -1, -1}, cn = -1;
+  {
+    const int f = tid & 3, r = tid >> 2;
+    const int sa = (f & 1) ? 1 : -1, sb = (f & 2) ? 1 : -1;
+    if (tid < 4 * GX * ts) {
+      const int lx = ((r & (GX - 1)) << lgts) + (sa > 0 ? hi : 0);
+      ev[0] = fetch(sa, sb, 0, lx, sb > 0 ? hi : 0, r >> lggx, en[0]);
+      ev[1] = fetch(sa, 0, sb, lx, r >> lggx, sb > 0 ? hi : 0, en[1]);
+    }
+    if (tid < 4 * W) ev[2] = fetch(0, sa, sb, r, sa > 0 ? hi : 0, sb > 0 ? hi : 0, en[2]);
+    if (tid < 8 * GX) {
+      const int c = tid & 7, dx = (c & 1) ? 1 : -1, dy = (c & 2) ? 1 : -1, dz = (c & 4) ? 1 : -1;
+      cv = fetch(dx, dy, dz, ((tid >> 3) << lgts) + (dx > 0 ? hi : 0), dy > 0 ? hi : 0, dz > 0 ? hi : 0, cn);
+    }
+  }
+  // sums in LDS, class by class
+#pragma unroll
+  for (int k = 0; k < kOwn; ++k)
+    if (k < nown) acc[tid + (k << 8)] = own[k];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (fn[c][k] >= 0) acc[fn[c][k]] += fv[c][k];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (en[c] >= 0) acc[en[c]] += ev[c];
+    __syncthreads();
+  }
+  if (cn >= 0) acc[cn] += cv;
+  __syncthreads();
+  // store: each row segment is W adjacent lanes (W divides 64); its first lane marks the row
+  const int lane = tid & 63;
+  const unsigned long long seg = (1ull << W) - 1;  // W <= 32
+#pragma unroll 8
+  for (int k = 0; k < kOwn; ++k) {
+    if (k < nown) {  // uniform: whole waves
+      const int n = tid + (k << 8);
+      const int lxg = n & (W - 1), ly = (n >> lgW) & hi, lz = n >> (lgW + lgts);
+      const RM v = acc[n];
+      const int x = (tx0 << lgts) + lxg, y = (ty << lgts) + ly, z = (tz << lgts) + lz;
+      const size_t g = ((size_t)z * N + y) * N + x;
+      mesh[g] = v;
+      const unsigned long long nz = __ballot(v != (RM)0);
+      if (rowmask && (lane & (W - 1)) == 0 && ((nz >> lane) & seg)) rowmask[g >> lgN] = 1;
+    }
   }
 }
 
