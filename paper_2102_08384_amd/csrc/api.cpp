@@ -630,11 +630,12 @@ void check_request(const pw_config *cfg, const pw_catalog *gal, const pw_catalog
 }
 
 // ------------------------------------------------------------------------------ autotuner
-// Launch shapes (ColTune) of the column passes are picked per shape key, once per process: on
-// the first launch of a key, every candidate runs twice on the lane's stream, on the estimate's
-// own data, timed with events, and the fastest is kept.  Each candidate reads one buffer and
-// writes another, so a repeat recomputes the same output and the estimate goes on from there.
-// Candidate 0 is the default shape.  PW_TUNE=0 in the environment turns the timing off (the
+// Launch shapes (ColTune) of the x pass, the column passes, the tile paint and gather and the
+// bisector contraction are picked per shape key, once per process: on the first launch of a
+// key, every candidate runs twice on the lane's stream, on the estimate's own data, timed with
+// events, the fastest is kept and run once more unless it ran last.  Each candidate reads one
+// buffer and writes another (the contraction clears its sums first), so a repeat recomputes the
+// same output and the estimate goes on from there.  Candidate 0 is the default shape.  PW_TUNE=0 in the environment turns the timing off (the
 // defaults are used); PW_TUNE_CACHE names a file of "key choice" lines read at first use and
 // appended to with each new choice.
 struct TuneEntry {
@@ -707,7 +708,20 @@ void tuned_launch(pw_ctx *ctx, Lane &ln, const std::string &key, const std::vect
       ms[i] = std::min(ms[i], t);
     }
   const size_t best = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+  // the estimate goes on from the chosen shape's output, as every later launch of the key will
+  // (shapes that sum in another order, like the contraction's workgroup count, round otherwise)
+  if (best + 1 != cands.size()) run(cands[best]);
   tune_store(key, (int)best, ms[best], ms[0]);
+}
+
+// Launch shape of a pass as the autotuner settled it (no timing here: a key not yet
+// settled uses the default shape).
+ColTune tuned_choice(pw_ctx *ctx, const std::string &key, const std::vector<ColTune> &cands) {
+  const int mode = ctx->tune_mode;
+  if (mode == 0) return cands[0];
+  if (mode >= 2) return cands[(size_t)(mode - 2) < cands.size() ? (size_t)(mode - 2) : 0];
+  const int k = tune_lookup(key);
+  return (k >= 0 && k < (int)cands.size()) ? cands[(size_t)k] : cands[0];
 }
 
 std::string tune_key(const char *pass, const HostPlan &h, int nfields, int64_t a, int64_t b) {
@@ -746,11 +760,62 @@ std::vector<ColTune> fz_candidates(int nfields) {
   return c;
 }
 
+// x pass: rows (wavefronts) per workgroup where a row is one wavefront (FP32 at N = 512)
+std::vector<ColTune> fx_candidates(int prec, int N) {
+  std::vector<ColTune> c(1);
+  if (prec == PW_FP32 && N == 512) {
+    for (int r : {1, 2, 8}) {
+      ColTune t;
+      t.rows = r;
+      c.push_back(t);
+    }
+  }
+  return c;
+}
+
+// tile paint: threads per workgroup
+std::vector<ColTune> paint_candidates() {
+  std::vector<ColTune> c(1);
+  for (int n : {128, 512}) {
+    ColTune t;
+    t.threads = n;
+    c.push_back(t);
+  }
+  return c;
+}
+
+// gather: one tile per workgroup as well as the default two (FP32 with two tiles or more a side)
+std::vector<ColTune> gather_candidates(int prec, int N) {
+  std::vector<ColTune> c(1);
+  if (prec == PW_FP32 && N / tile_size(N) >= 2) {
+    ColTune t;
+    t.gx = 1;
+    c.push_back(t);
+  }
+  return c;
+}
+
+// bisector contraction: a quarter, half and twice the default workgroup count (one per 256
+// modes, at most 4096)
+std::vector<ColTune> contract_candidates(int64_t nmodes) {
+  std::vector<ColTune> c(1);
+  const int64_t d = std::max<int64_t>(1, std::min<int64_t>((nmodes + 255) / 256, 4096));
+  for (int64_t b : {d / 4, d / 2, 2 * d}) {
+    if (b < 1 || b == d || b == c.back().blocks) continue;
+    ColTune t;
+    t.blocks = (int)b;
+    c.push_back(t);
+  }
+  return c;
+}
+
 // a1 + a2 for one catalog on stream s: FP64 scalars and the tile sort (two passes over the
 // particles), paint, gather and occupancy into dp's mesh, masks and norm.  gx / rx / rnb: the
 // catalogs' device arrays; records: the sort's buffer (records_bytes + the chunk histograms).
-void enqueue_paint(hipStream_t s, const DevPlan *dp, const pw_config *cfg, const pw_catalog *gal, const void *gx,
-                   const pw_catalog *ran, const void *rx, const void *rnb, const pw_norm *norm, void *records) {
+// The paint and gather shapes are autotuned on ln's stream, or (ln null) taken as settled.
+void enqueue_paint(pw_ctx *ctx, Lane *ln, hipStream_t s, const DevPlan *dp, const pw_config *cfg,
+                   const pw_catalog *gal, const void *gx, const pw_catalog *ran, const void *rx, const void *rnb,
+                   const pw_norm *norm, void *records) {
   const HostPlan &h = *dp->host;
   const SortLayout SL = sort_layout(h.N, gal->n, ran->n);
   int *chunk_hist = (int *)((char *)records + records_bytes(h.prec, gal->n, ran->n));
@@ -765,8 +830,22 @@ void enqueue_paint(hipStream_t s, const DevPlan *dp, const pw_config *cfg, const
   launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
   launch_sort_scatter(s, SL, gx, gal->dtype, rx, ran->dtype, gal->n, ran->n, h.prec, h.N, cfg->box_origin, h.H,
                       cfg->assign, dp->norm, chunk_hist, dp->tile_cursor, records);
-  launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records,
-                    dp->norm, dp->tile_blocks, dp->mesh, dp->rowmask);
+  auto paint = [&](ColTune t) {
+    launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records, dp->norm,
+                      dp->tile_blocks, t);
+  };
+  auto gather = [&](ColTune t) {
+    launch_tile_gather(s, h.prec, h.N, dp->tile_slot, dp->tile_blocks, dp->mesh, dp->rowmask, t);
+  };
+  const std::string pkey = tune_key("paint", h, cfg->assign, dp->ntiles, 0);
+  const std::string gkey = tune_key("gather", h, 0, dp->ntiles, 0);
+  if (ln) {
+    tuned_launch(ctx, *ln, pkey, paint_candidates(), paint);
+    tuned_launch(ctx, *ln, gkey, gather_candidates(h.prec, h.N), gather);
+  } else {
+    paint(tuned_choice(ctx, pkey, paint_candidates()));
+    gather(tuned_choice(ctx, gkey, gather_candidates(h.prec, h.N)));
+  }
   launch_occupancy(s, h.N, dp->rowmask, dp->rowlist, dp->planemask, dp->zlist, dp->occ_blockcnt, dp->norm);
 }
 
@@ -811,7 +890,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   if (!placed)
     ensure_buffer(ctx, &ln.records, &ln.records_bytes,
                   records_bytes(h.prec, gal->n, ran->n) + sort_layout(h.N, gal->n, ran->n).hist_bytes);
-  enqueue_paint(s, dp, cfg, gal, gx, ran, rx, rnb, norm, placed ? placed->records : ln.records);
+  enqueue_paint(ctx, &ln, s, dp, cfg, gal, gx, ran, rx, rnb, norm, placed ? placed->records : ln.records);
   // a3 + a4: weighted fields and the forward transforms
   const int N = h.N;
   const Prune &F = h.fwd;
@@ -831,8 +910,10 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     for (int g = 0; g < ng; ++g) {
       const int j0 = h.lean_jstart[g], nj = h.lean_jstart[g + 1] - j0;
       const int f0 = h.lean_fstart[g], nf = h.lean_fstart[g + 1] - f0;
-      launch_fx(s, h.prec, N, fx_kind, dp->mesh, B, dp->lean_jobs + j0, nj, F.nkx, F.rs, cfg->box_origin, h.H,
-                h.unit, dp->tw, dp->rowlist, dp->norm);
+      tuned_launch(ctx, ln, tune_key("fx", h, nj, fx_kind, F.nkx), fx_candidates(h.prec, N), [&](ColTune t) {
+        launch_fx(s, h.prec, N, fx_kind, dp->mesh, B, dp->lean_jobs + j0, nj, F.nkx, F.rs, cfg->box_origin, h.H,
+                  h.unit, dp->tw, dp->rowlist, dp->norm, nullptr, t);
+      });
       launch_fy(s, h.prec, N, 0, B, dp->bufC, nf, N, F.nkx, F.rs, dp->fwd.ycnt, dp->fwd.yoff, F.npen, dp->tw,
                 dp->rowmask, dp->zlist, dp->norm);
       launch_fz(s, h.prec, N, dp->bufC, A, nf, F.npen, dp->fwd.pinfo, dp->fwd.moff, dp->fwd.goff, dp->fwd.gsize,
@@ -840,8 +921,11 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
     }
   } else {
     mark("fx", ncell * rsz + x1);
-    launch_fx(s, h.prec, N, fx_kind, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs, cfg->box_origin, h.H,
-              h.unit, dp->tw, dp->rowlist, dp->norm);
+    tuned_launch(ctx, ln, tune_key("fx", h, (int)h.jobs.size(), fx_kind, F.nkx), fx_candidates(h.prec, N),
+                 [&](ColTune t) {
+                   launch_fx(s, h.prec, N, fx_kind, dp->mesh, A, dp->jobs, (int)h.jobs.size(), F.nkx, F.rs,
+                             cfg->box_origin, h.H, h.unit, dp->tw, dp->rowlist, dp->norm, nullptr, t);
+                 });
     mark("fy", x1 + x2);
     if (F.npen > 0)
       tuned_launch(ctx, ln, tune_key("fy", h, h.nfields, F.nkx, F.npen), fy_candidates(h.prec, h.nfields),
@@ -868,11 +952,15 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   if (h.path == PATH_BIS_PK) {
     // a7: contraction and FP64 binning
     mark("contract", x3 + 4.0 * F.nretained);
-    launch_fill(s, dp->acc, nacc, 1);
+    // (the shell sums accumulate: every autotuning run clears them first)
+    const std::string ckey = tune_key(orders ? "contract_orders" : "contract", h, h.nfields, F.nmodes, 0);
     if (orders) {
       // every order's terms into accumulators of their own (one pass over the spectra)
-      launch_contract_bis_generated(s, h.prec, h.ell_max, h.order / 2, A, F.nmodes, F.mstride, dp->fwd.modecoord,
-                                    N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->winv, dp->acc, 1);
+      tuned_launch(ctx, ln, ckey, contract_candidates(F.nmodes), [&](ColTune t) {
+        launch_fill(s, dp->acc, nacc, 1);
+        launch_contract_bis_generated(s, h.prec, h.ell_max, h.order / 2, A, F.nmodes, F.mstride, dp->fwd.modecoord,
+                                      N, dp->bin_of_s2, n_s2, h.n_bins, h.kf, dp->winv, dp->acc, 1, nullptr, t);
+      });
       mark("finalize", 0.0);
       launch_finalize_pk(s, dp->acc, ln.res_rows, h.n_bins, dp->ells_orders, dp->norm, dp->out);
     } else {
@@ -880,8 +968,12 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
       tab.tstart = dp->t_start; tab.tsh = dp->t_sh; tab.tell = dp->t_ell;
       tab.p1 = dp->t_p1; tab.p2 = dp->t_p2; tab.coef = dp->t_coef;
       tab.ntargets = (int)h.t_sh.size();
-      launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, F.mstride, dp->fwd.modecoord,
-                          N, dp->bin_of_s2, n_s2, h.n_bins, h.nell, tab, h.kf, dp->winv, dp->acc);
+      tuned_launch(ctx, ln, ckey, contract_candidates(F.nmodes), [&](ColTune t) {
+        launch_fill(s, dp->acc, nacc, 1);
+        launch_contract_bis(s, h.prec, h.ell_max, h.order / 2, A, h.nfields, F.nmodes, F.mstride,
+                            dp->fwd.modecoord, N, dp->bin_of_s2, n_s2, h.n_bins, h.nell, tab, h.kf, dp->winv,
+                            dp->acc, t);
+      });
       mark("finalize", 0.0);
       launch_finalize_pk(s, dp->acc, h.nell, h.n_bins, dp->ells, dp->norm, dp->out);
     }
@@ -947,8 +1039,11 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
         const double a1 = (double)h.n_a * N * N * P.nkx * csz, a2 = (double)h.n_a * N * P.npen * csz,
                      a3 = (double)h.n_a * P.nretained * csz;
         mark("afx", (double)h.n_a * ncell * rsz + a1);
-        launch_fx(s, h.prec, N, FX_PLAIN, B, Aoff, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs, cfg->box_origin, h.H,
-                  h.unit, dp->tw, nullptr, nullptr);
+        tuned_launch(ctx, ln, tune_key("fx", h, (int)h.ajobs.size(), FX_PLAIN, P.nkx), fx_candidates(h.prec, N),
+                     [&](ColTune t) {
+                       launch_fx(s, h.prec, N, FX_PLAIN, B, Aoff, dp->ajobs, (int)h.ajobs.size(), P.nkx, P.rs,
+                                 cfg->box_origin, h.H, h.unit, dp->tw, nullptr, nullptr, nullptr, t);
+                     });
         mark("afy", a1 + a2);
         if (P.npen > 0)
           launch_fy(s, h.prec, N, 0, Aoff, B, h.n_a, N, P.nkx, P.rs, dp->sph.ycnt, dp->sph.yoff, P.npen, dp->tw,
@@ -986,16 +1081,6 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   ln.res_slice = need;
   HIPCHECK(hipEventRecord(ln.done, s));
   return dp;
-}
-
-// Launch shape of a column pass as the autotuner settled it (no timing here: a key not yet
-// settled uses the default shape).
-ColTune tuned_choice(pw_ctx *ctx, const std::string &key, const std::vector<ColTune> &cands) {
-  const int mode = ctx->tune_mode;
-  if (mode == 0) return cands[0];
-  if (mode >= 2) return cands[(size_t)(mode - 2) < cands.size() ? (size_t)(mode - 2) : 0];
-  const int k = tune_lookup(key);
-  return (k >= 0 && k < (int)cands.size()) ? cands[(size_t)k] : cands[0];
 }
 
 // Whether a configuration has the batched path: the bisector P_l with a generated contraction,
@@ -1046,7 +1131,7 @@ DevPlan *launch_batch(pw_ctx *ctx, Lane &ln, const pw_config *cfg, int n, const 
     const void *gnb = nullptr, *rnb = nullptr;
     const void *gx = stage_catalog(ctx, ln, gals[i], 0, &gnb);
     const void *rx = stage_catalog(ctx, ln, rans[i], 1, &rnb);
-    enqueue_paint(s, plans[(size_t)i], cfg, gals[i], gx, rans[i], rx, rnb, norms[i], ln.records);
+    enqueue_paint(ctx, nullptr, s, plans[(size_t)i], cfg, gals[i], gx, rans[i], rx, rnb, norms[i], ln.records);
   }
   // a3 + a4 + a7: one launch per pass over every catalog
   Batch ba;
@@ -1059,7 +1144,8 @@ DevPlan *launch_batch(pw_ctx *ctx, Lane &ln, const pw_config *cfg, int n, const 
   const int N = h.N;
   const Prune &F = h.fwd;
   launch_fx(s, h.prec, N, FX_HARMONIC, dp0->mesh, dp0->bufA, dp0->jobs, (int)h.jobs.size(), F.nkx, F.rs,
-            cfg->box_origin, h.H, h.unit, dp0->tw, dp0->rowlist, dp0->norm, &ba);
+            cfg->box_origin, h.H, h.unit, dp0->tw, dp0->rowlist, dp0->norm, &ba,
+            tuned_choice(ctx, tune_key("fx", h, (int)h.jobs.size(), FX_HARMONIC, F.nkx), fx_candidates(h.prec, N)));
   if (F.npen > 0) {
     launch_fy(s, h.prec, N, 0, dp0->bufA, dp0->bufB, h.nfields, N, F.nkx, F.rs, dp0->fwd.ycnt, dp0->fwd.yoff,
               F.npen, dp0->tw, dp0->rowmask, dp0->zlist, dp0->norm,

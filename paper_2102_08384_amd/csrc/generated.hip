@@ -112,14 +112,15 @@ template <typename R, int L, int B>
 static bool contract_reg_launch(hipStream_t s, const void *spec, int64_t nmodes, int64_t mstride,
                                 const uint32_t *modecoord,
                                 int N, const int *bin_of_s2, int64_t n_s2, int nbins, double kf,
-                                const void *winv, double *acc, int orders, const Batch *batch) {
+                                const void *winv, double *acc, int orders, const Batch *batch, ColTune tune) {
   if constexpr (BisContract<L, B, R>::kGenerated) {
     Batch ba;
     ba.n = 0;
     if (batch) ba = *batch;
     const int nb = ba.n ? ba.n : 1;
     int64_t want = (nmodes + 255) / 256;
-    const int64_t cap = 4096 / nb > 0 ? 4096 / nb : 1;
+    // workgroups per catalog: the tuned count, else up to 4096 over all catalogs
+    const int64_t cap = tune.blocks > 0 ? tune.blocks : (4096 / nb > 0 ? 4096 / nb : 1);
     unsigned blocks = (unsigned)(want < cap ? (want > 0 ? want : 1) : cap);
     const int ne = (orders ? B + 1 : 1) * (L / 2 + 1);
     size_t sh = (size_t)(ne + 2) * nbins * sizeof(double);
@@ -142,11 +143,11 @@ static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void 
                                   int64_t mstride,
                                   const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
                                   int nbins, double kf, const void *winv, double *acc, int orders,
-                                  const Batch *batch) {
+                                  const Batch *batch, ColTune tune) {
 #define PW_CR(L, B)                                                                                \
   if (lmax == L && bmax == B)                                                                      \
     return contract_reg_launch<R, L, B>(s, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins, kf, winv, \
-                                        acc, orders, batch);
+                                        acc, orders, batch, tune);
   PW_CR(0, 0) PW_CR(0, 1) PW_CR(0, 2) PW_CR(2, 0) PW_CR(2, 1) PW_CR(2, 2)
   PW_CR(4, 0) PW_CR(4, 1) PW_CR(4, 2) PW_CR(6, 0) PW_CR(6, 1) PW_CR(6, 2)
 #undef PW_CR
@@ -156,11 +157,11 @@ static bool contract_reg_dispatch(int lmax, int bmax, hipStream_t s, const void 
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
                                    int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
                                    int nbins, double kf, const void *winv, double *acc, int orders,
-                                   const Batch *batch) {
+                                   const Batch *batch, ColTune tune) {
   return prec == 0 ? contract_reg_dispatch<float>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
-                                                  n_s2, nbins, kf, winv, acc, orders, batch)
+                                                  n_s2, nbins, kf, winv, acc, orders, batch, tune)
                    : contract_reg_dispatch<double>(lmax, bmax, s, spec, nmodes, mstride, modecoord, N, bin_of_s2,
-                                                   n_s2, nbins, kf, winv, acc, orders, batch);
+                                                   n_s2, nbins, kf, winv, acc, orders, batch, tune);
 }
 
 // ------------------------------------------------------------------------------ generated

@@ -79,6 +79,18 @@ void launch_fill(hipStream_t s, void *p, size_t n_elems, int prec);
 // kernels keep one LDS counter per tile (ntiles * 4 bytes per workgroup).
 constexpr int kTile = 16;
 inline int tile_size(int N) { return N < kTile ? N : kTile; }
+// Launch shape of a pass, as picked by the autotuner (0 everywhere: the defaults).  Every shape
+// computes the same values; only the speed differs.
+struct ColTune {
+  int fpb = 0;      // column passes: fields per workgroup (0: about 4096 workgroups per launch)
+  int cols = 0;     // y pass: adjacent columns (0: one 128-byte row segment; 8: half of one, FP32)
+  int rows = 0;     // x pass, FP32 at N = 512: rows (wavefronts) per workgroup (0: 4; 1, 2 or 8)
+  int threads = 0;  // tile paint: threads per workgroup (0: 256; 128 or 512)
+  int gx = 0;       // gather: tiles per workgroup along x (0: two in FP32 where N allows; 1: one)
+  int blocks = 0;   // bisector contraction: workgroups per catalog (0: one per 256 modes, at most
+                    // 4096 in all)
+};
+
 // The sort reads the particles twice.  Both catalogs are cut into chunks of `chunk` particles,
 // one workgroup each (galaxy chunks first), a layout fixed by the mesh and the catalog sizes.
 constexpr int kSortNominalCUs = 256;
@@ -100,11 +112,14 @@ void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets
 void launch_sort_scatter(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx,
                          int rdtype, int64_t ng, int64_t nr, int prec, int N, const double *b0, double H,
                          int assign, const DevNorm *norm, const int *chunk_hist, int *cursor, void *records);
-// blocks: scratch of ntiles * (TS+2)^3 int64 values; slot: [ntiles + 1] from the scan.
-// rowmask (N*N ints, zeroed by the caller; may be null) receives 1 for every x-row (z, y)
-// holding a non-zero node.
+// blocks: scratch of ntiles * (TS+2)^3 values of the mesh precision, one block per occupied tile
+// (slot: [ntiles + 1] from the scan).
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
-                       const void *records, const DevNorm *norm, void *blocks, void *mesh, int *rowmask);
+                       const void *records, const DevNorm *norm, void *blocks, ColTune tune = ColTune());
+// Every mesh node = the sum of the blocks covering it.  rowmask (N*N ints, zeroed by the
+// caller; may be null) receives 1 for every x-row (z, y) holding a non-zero node.
+void launch_tile_gather(hipStream_t s, int prec, int N, const int *slot, const void *blocks, void *mesh,
+                        int *rowmask, ColTune tune = ColTune());
 // Survey occupancy: rowlist = the non-empty rows in increasing order, planemask[z] = 1 for
 // z-planes with a non-empty row, zlist = those planes in increasing order; counts into
 // norm->nrows_occ / nplanes_occ.  Every field of the forward transforms is the mesh times a
@@ -133,16 +148,8 @@ inline int row_stride(int nkx, int prec) {
 enum { FX_HARMONIC = 0, FX_RADIAL = 1, FX_PLAIN = 2 };
 void launch_fx(hipStream_t s, int prec, int N, int kind, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
-               const int *rowlist, const DevNorm *norm, const Batch *batch = nullptr);
-// Launch shape of a column pass, as picked by the autotuner: fields per workgroup (fpb; 0 = the
-// default, which aims at about 4096 workgroups per launch) and, for the y pass, adjacent
-// columns per workgroup (cols: 0 = one 128-byte row segment, 8 = half of one in FP32).  Every
-// shape computes the same values; only the speed differs.
-struct ColTune {
-  int fpb = 0;
-  int cols = 0;
-};
-
+               const int *rowlist, const DevNorm *norm, const Batch *batch = nullptr,
+               ColTune tune = ColTune());
 // c2c along y (forward, or inverse when inv), on nplanes planes per field:
 // in[p][plane][y * rs + kx] -> out[p][plane][yoff[y'] + kx] for kx < ycnt[y'] (y' the output
 // index, npen values per output plane).
@@ -184,7 +191,7 @@ inline int contract_bis_threads(int prec, int nfields, int nell, int nbins) {
 void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
                          int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
-                         const void *winv, double *acc);
+                         const void *winv, double *acc, ColTune tune = ColTune());
 void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, const int *ells,
                         const DevNorm *norm, double *out);
 
@@ -193,7 +200,8 @@ void launch_finalize_pk(hipStream_t s, const double *acc, int nell, int nbins, c
 // and the |k| sum ((bmax + 1) * nell + 2 rows of nbins).
 bool launch_contract_bis_generated(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int64_t nmodes,
                                    int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2, int64_t n_s2,
-                                   int nbins, double kf, const void *winv, double *acc, int orders, const Batch *batch = nullptr);
+                                   int nbins, double kf, const void *winv, double *acc, int orders, const Batch *batch = nullptr,
+                                   ColTune tune = ColTune());
 // Which (ell_max, beta_max) / (ell_max, order) have build-time generated couplings.
 bool bis_contract_generated(int lmax, int bmax);
 bool mid_reweight_generated(int lmax, int order, int all_parity);

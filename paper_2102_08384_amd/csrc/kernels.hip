@@ -140,13 +140,13 @@ __device__ __forceinline__ cplx<R> lane_fetch(int src, cplx<R> v) {
 // 1/r; otherwise (bisector fields) it keeps z/r, the only radial quantity the harmonics need,
 // and 1/r is recomputed when the recurrence changes m.  Both fields of a job enter the
 // transform scaled by 1/2 (exactly), which is the factor of the two-real-field separation.
-template <typename R, int N, bool PLAIN, bool RADIAL>
-__global__ void __launch_bounds__(FxShape<N>::THREADS)
+template <typename R, int N, bool PLAIN, bool RADIAL, int ROWS = FxShape<N>::ROWS>
+__global__ void __launch_bounds__(ROWS * FxShape<N>::T)
 __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && N == 512) ? 3 : 1, 8)))
 k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__restrict__ jobs,
      int njobs, int nkx, int rs, R b0x, R b0y, R b0z, R H, R uhalf, const cplx<R> *__restrict__ tw,
      const int *__restrict__ rowlist, const DevNorm *__restrict__ norm, const Batch ba) {
-  constexpr int T = FxShape<N>::T, ROWS = FxShape<N>::ROWS;
+  constexpr int T = FxShape<N>::T;
   if (ba.n) {  // catalog blockIdx.z of a batch
     const BatchSlot &bs = ba.s[blockIdx.z];
     mesh = (const R *)bs.mesh;
@@ -346,28 +346,37 @@ k_fx(const R *__restrict__ mesh, cplx<R> *__restrict__ out, const FieldJob *__re
 template <typename R, int N>
 static void fx_launch(hipStream_t s, int kind, const void *mesh, void *out, const FieldJob *jobs, int njobs,
                       int nkx, int rs, const double *b0, double H, double unit, const void *tw,
-                      const int *rowlist, const DevNorm *norm, const Batch *batch) {
-  constexpr int ROWS = FxShape<N>::ROWS;
-  unsigned blocks = (unsigned)((size_t)N * N / ROWS);
+                      const int *rowlist, const DevNorm *norm, const Batch *batch, ColTune tune) {
   Batch ba;
   ba.n = 0;
   if (batch) ba = *batch;
-  const dim3 grid(blocks, 1, ba.n ? ba.n : 1);
-#define PW_FX(PL, RAD)                                                                                           \
-  hipLaunchKernelGGL((k_fx<R, N, PL, RAD>), grid, dim3(FxShape<N>::THREADS), 0, s, (const R *)mesh,              \
-                     (cplx<R> *)out, jobs, njobs, nkx, rs, (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit),  \
-                     (const cplx<R> *)tw, rowlist, norm, ba)
-  if (kind == FX_PLAIN) PW_FX(true, false);
-  else if (kind == FX_RADIAL) PW_FX(false, true);
-  else PW_FX(false, false);
+  const unsigned nb = ba.n ? ba.n : 1;
+#define PW_FX(PL, RAD, RW)                                                                                       \
+  hipLaunchKernelGGL((k_fx<R, N, PL, RAD, RW>), dim3((unsigned)((size_t)N * N / (RW)), 1, nb),                  \
+                     dim3((RW) * FxShape<N>::T), 0, s, (const R *)mesh, (cplx<R> *)out, jobs, njobs, nkx, rs,    \
+                     (R)b0[0], (R)b0[1], (R)b0[2], (R)H, (R)(0.5 * unit), (const cplx<R> *)tw, rowlist, norm, ba)
+#define PW_FX_KIND(RW)                                                                                           \
+  do {                                                                                                           \
+    if (kind == FX_PLAIN) PW_FX(true, false, RW);                                                                \
+    else if (kind == FX_RADIAL) PW_FX(false, true, RW);                                                          \
+    else PW_FX(false, false, RW);                                                                                \
+  } while (0)
+  // other row counts per workgroup where a row is one wavefront (FP32 at N = 512)
+  if constexpr (sizeof(R) == 4 && FxShape<N>::T == 64) {
+    if (tune.rows == 1) { PW_FX_KIND(1); return; }
+    if (tune.rows == 2) { PW_FX_KIND(2); return; }
+    if (tune.rows == 8) { PW_FX_KIND(8); return; }
+  }
+  PW_FX_KIND(FxShape<N>::ROWS);
+#undef PW_FX_KIND
 #undef PW_FX
 }
 
 void launch_fx(hipStream_t s, int prec, int N, int kind, const void *mesh, void *out, const FieldJob *jobs,
                int njobs, int nkx, int rs, const double *b0, double H, double unit, const void *tw,
-               const int *rowlist, const DevNorm *norm, const Batch *batch) {
-  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm, batch) }
-  else { PW_DISPATCH_N(fx_launch, double, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm, batch) }
+               const int *rowlist, const DevNorm *norm, const Batch *batch, ColTune tune) {
+  if (prec == 0) { PW_DISPATCH_N(fx_launch, float, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm, batch, tune) }
+  else { PW_DISPATCH_N(fx_launch, double, s, kind, mesh, out, jobs, njobs, nkx, rs, b0, H, unit, tw, rowlist, norm, batch, tune) }
 }
 
 // ------------------------------------------------------------------------------ fy / fz
@@ -751,10 +760,10 @@ k_contract_bis(const cplx<R> *__restrict__ spec, int nfields, int64_t nmodes, in
 void launch_contract_bis(hipStream_t s, int prec, int lmax, int bmax, const void *spec, int nfields,
                          int64_t nmodes, int64_t mstride, const uint32_t *modecoord, int N, const int *bin_of_s2,
                          int64_t n_s2, int nbins, int nell, TermTable tab, double kf,
-                         const void *winv, double *acc) {
+                         const void *winv, double *acc, ColTune tune) {
   if (nmodes <= 0) return;
   if (launch_contract_bis_generated(s, prec, lmax, bmax, spec, nmodes, mstride, modecoord, N, bin_of_s2, n_s2, nbins,
-                                    kf, winv, acc, 0))
+                                    kf, winv, acc, 0, nullptr, tune))
     return;
   const int nth = contract_bis_threads(prec, nfields, nell, nbins);  // validated by the planner
   int64_t want = (nmodes + nth - 1) / nth;

@@ -384,7 +384,7 @@ k_sort_scatter(const RG *__restrict__ gx, const RR *__restrict__ rx, int64_t ng,
 // atomics are serialised per lane); integer sums are exact, so a block does not depend on the
 // order of its particles.
 template <typename RM, int ASSIGN>
-__global__ void __launch_bounds__(256) k_tile_paint(int ts, const int *__restrict__ offsets,
+__global__ void __launch_bounds__(512) k_tile_paint(int ts, const int *__restrict__ offsets,
                                                     const int *__restrict__ slot,
                                                     const typename Rec4<RM>::T *__restrict__ rec,
                                                     const DevNorm *__restrict__ norm,
@@ -731,18 +731,27 @@ static int ilog2(int v) {
 }
 
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,
-                       const void *records, const DevNorm *norm, void *blocks, void *mesh, int *rowmask) {
+                       const void *records, const DevNorm *norm, void *blocks, ColTune tune) {
   const int ts = tile_size(N);
   const int nt = N / ts;
   const unsigned ntiles = (unsigned)(nt * nt * nt);
   const size_t E3 = (size_t)(ts + 2) * (ts + 2) * (ts + 2);
-  const int lggx_f = nt >= 2 ? 1 : 0;  // FP32: two tiles per workgroup along x (128-byte rows)
+  const int threads = (tune.threads == 128 || tune.threads == 512) ? tune.threads : 256;
 #define PW_TP(RM, A)                                                                              \
-  hipLaunchKernelGGL((k_tile_paint<RM, A>), dim3(ntiles), dim3(256), E3 * sizeof(unsigned long long), s, \
+  hipLaunchKernelGGL((k_tile_paint<RM, A>), dim3(ntiles), dim3(threads), E3 * sizeof(unsigned long long), s, \
                      ts, offsets, slot, (const typename Rec4<RM>::T *)records, norm, (RM *)blocks)
   if (prec == 0) { if (assign == 2) PW_TP(float, 2); else PW_TP(float, 3); }
   else { if (assign == 2) PW_TP(double, 2); else PW_TP(double, 3); }
 #undef PW_TP
+}
+
+void launch_tile_gather(hipStream_t s, int prec, int N, const int *slot, const void *blocks, void *mesh,
+                        int *rowmask, ColTune tune) {
+  const int ts = tile_size(N);
+  const int nt = N / ts;
+  const unsigned ntiles = (unsigned)(nt * nt * nt);
+  // FP32: two tiles per workgroup along x (128-byte rows) unless tuned to one
+  const int lggx_f = (nt >= 2 && tune.gx != 1) ? 1 : 0;
   if (prec == 0)
     hipLaunchKernelGGL(k_tile_gather<float>, dim3(ntiles >> lggx_f), dim3(256), 0, s, ilog2(N), ilog2(ts), lggx_f,
                        slot, (const float *)blocks, (float *)mesh, rowmask);

@@ -1,7 +1,8 @@
-"""Autotuned launch shapes of the column passes (pw_set_tuning, pw_tune_entry): every candidate
-shape computes the same values as the default one, bit for bit on the transforms, and the
-autotuner's first launch (which times every candidate on the estimate's own data) leaves a
-correct estimate and a table entry per pass."""
+"""Autotuned launch shapes (pw_set_tuning, pw_tune_entry) of the x pass, the column passes, the
+tile paint and gather and the bisector contraction: every candidate shape computes the same
+values as the default one, bit for bit on the mesh and the transforms, and the autotuner's first
+launch (which times every candidate on the estimate's own data) leaves a correct estimate and a
+table entry per pass."""
 import numpy as np
 import pytest
 
@@ -80,6 +81,43 @@ def test_midpoint_every_shape_same_values(stat):
             assert _close(res["values"], base["values"]), mode
     ref = (pk_midpoint if stat == pw.PW_PK else xi_midpoint)(g64, r64, oracle_cfg(cfg))
     assert np.all(max_err_per_ell(base["values"], ref.values) < 1e-10)
+
+
+def test_bisector_512_every_shape_same_mesh_and_spectra():
+    """FP32 bisector P_l at N = 512, where the x pass has its row-count candidates: under every
+    candidate shape (x pass rows, paint threads, gather tiles per workgroup, contraction
+    workgroups, column passes) the painted mesh and the k-sphere spectra equal the default's bit
+    for bit, and the multipoles agree to FP64 rounding of the shell sums.  (The default path is
+    held to the oracle at N = 512 by the full-size tests; an oracle run here would take minutes.)"""
+    say("tune: bisector P N=512 fp32 every shape (x pass, paint, gather, contraction)")
+    gal, ran = uniform_catalog(421, 60000, 180000, (0, 0, 1100), 400)
+    gx, _ = rounded(gal, np.float32)
+    rx, _ = rounded(ran, np.float32)
+    nb = ran["nbar"].astype(np.float32)
+    # a small k-sphere (|n| <= 5) keeps the spectra copied to the host small
+    cfg = pw.Config(stat=pw.PW_PK, los=pw.PW_BISECTOR, assign=pw.PW_TSC, prec=pw.PW_FP32, n_mesh=512,
+                    box_len=800.0, box_origin=(-400.0, -400.0, 700.0), ell_max=4, order=2, compensate=1,
+                    bin_lo=0.004, bin_width=0.008, n_bins=4)
+    with pw.Context(0) as ctx:
+        ctx.set_tuning(0)
+        base = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
+        mesh = ctx.inspect(0, np.float32).copy()
+        sph = ctx.inspect(1, np.float32).copy()
+        for mode in range(2, 7):   # candidates 0..4 of every pass (past a pass's last: its default)
+            say("shape candidate", mode - 2)
+            ctx.set_tuning(mode)
+            res = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
+            assert np.array_equal(ctx.inspect(0, np.float32), mesh), mode
+            assert np.array_equal(ctx.inspect(1, np.float32), sph), mode
+            assert _close(res["values"], base["values"]), mode
+        say("autotuned")
+        ctx.set_tuning(1)
+        tuned = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
+        assert np.array_equal(ctx.inspect(1, np.float32), sph)
+    assert _close(tuned["values"], base["values"])
+    entries = {e["key"].split(":")[0] for e in pw.tune_entries()}
+    say("tuned passes", sorted(entries))
+    assert {"fx", "fy", "fz", "paint", "gather", "contract"} <= entries
 
 
 def test_tuning_mode_validation():
