@@ -75,7 +75,7 @@ WORKLOADS = {
     # bisector P_l, the headline workload
     "C3": Workload(3, "lognormal_cone", 4_000_000, 5.0, 400.0, 2000.0, 512, 2700.0,
                    _cone_box(400.0, 2000.0, 2700.0), 3, (0, 2, 4), 4, "pk", "bisector",
-                   0.005, 0.005, 79, 256, True),
+                   0.005, 0.005, 79, 512, True),
     # xi_l via the inverse FFT (midpoint and bisector), 25 bins over 0-200
     "C4": Workload(4, "lognormal_cone", 4_000_000, 5.0, 400.0, 2000.0, 512, 2900.0,
                    _cone_box(400.0, 2000.0, 2900.0), 2, (0, 2, 4), 4, "xi", "midpoint",
