@@ -68,13 +68,16 @@ def config(name, n_mesh=None):
 
 def main(case):
     name, n_mesh, fn = CASES[case]
-    t0 = time.time()
+    t_cat = time.time()
     gal, ran = make_workload_catalog(name, index=0)
     g, r = fp32_catalog(gal), fp32_catalog(ran)
     del gal, ran
+    t_cat = time.time() - t_cat
     cfg = config(name, n_mesh)
     print(f"[golden] {case}: {len(g['w'])} + {len(r['w'])} particles, N={cfg.N}", flush=True)
+    t0 = time.time()
     res = fn(g, r, cfg)
+    seconds = time.time() - t0
     out = {
         "case": case, "workload": name, "n_mesh": cfg.N, "box_len": cfg.L, "box_origin": list(cfg.b0),
         "assign": cfg.assign, "ells": list(cfg.ells), "order": cfg.order, "bin_lo": cfg.bin_lo,
@@ -82,13 +85,13 @@ def main(case):
         "values": res.values.tolist(), "bin_mean": res.bin_mean.tolist(),
         "counts": res.counts.tolist(), "norm": [res.alpha_r, res.I, res.S],
         "oracle": fn.__name__, "command": f"python tests/golden/make_full_size.py {case}",
-        "seconds": time.time() - t0, "host_cores": len(os.sched_getaffinity(0)),
+        "seconds": seconds, "catalog_seconds": t_cat, "host_cores": len(os.sched_getaffinity(0)),
         "host": f"{len(os.sched_getaffinity(0))}-core host without a GPU (the build container)",
     }
     path = os.path.join(HERE, f"full_{case}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print(f"[golden] wrote {path} in {time.time() - t0:.0f}s", flush=True)
+    print(f"[golden] wrote {path}: oracle {seconds:.0f}s, catalog {t_cat:.0f}s", flush=True)
 
 
 if __name__ == "__main__":
