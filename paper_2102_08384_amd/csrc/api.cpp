@@ -523,7 +523,6 @@ std::unique_ptr<DevPlan> build_dev_plan(pw_ctx *ctx, const pw_config *cfg, char 
       dp->ntiles = nt * nt * nt;
       dp->tile_counts = (int *)M.get((size_t)dp->ntiles * sizeof(int));
       dp->tile_offsets = (int *)M.get((size_t)(dp->ntiles + 1) * sizeof(int));
-      dp->tile_cursor = (int *)M.get((size_t)dp->ntiles * sizeof(int));
       dp->tile_slot = (int *)M.get((size_t)(dp->ntiles + 1) * sizeof(int));
       dp->rowmask = (int *)M.get((size_t)h.N * h.N * sizeof(int));
       dp->rowlist = (int *)M.get((size_t)h.N * h.N * sizeof(int));
@@ -827,9 +826,9 @@ void enqueue_paint(pw_ctx *ctx, Lane *ln, hipStream_t s, const DevPlan *dp, cons
   launch_finalize_norm(s, dp->part_g, SL.nblk_g, dp->part_r, SL.nblk_r, dp->norm, cfg->box_origin, cfg->box_len,
                        h.check_extent, use_given ? 1 : 0, use_given ? norm->alpha_r : 0.0,
                        use_given ? norm->I : 0.0, use_given ? norm->S : 0.0);
-  launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_cursor, dp->tile_slot);
+  launch_tile_scan(s, dp->tile_counts, dp->ntiles, dp->tile_offsets, dp->tile_slot);
   launch_sort_scatter(s, SL, gx, gal->dtype, rx, ran->dtype, gal->n, ran->n, h.prec, h.N, cfg->box_origin, h.H,
-                      cfg->assign, dp->norm, chunk_hist, dp->tile_cursor, records);
+                      cfg->assign, dp->norm, chunk_hist, dp->tile_offsets, records);
   auto paint = [&](ColTune t) {
     launch_tile_paint(s, h.prec, h.N, cfg->assign, dp->tile_offsets, dp->tile_slot, records, dp->norm,
                       dp->tile_blocks, t);

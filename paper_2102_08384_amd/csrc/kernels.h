@@ -107,11 +107,12 @@ SortLayout sort_layout(int N, int64_t n_gal, int64_t n_ran);
 void launch_sort_count(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx, int rdtype,
                        const void *rnbar, int64_t ng, int64_t nr, int N, const double *b0, double H, int assign,
                        int *chunk_hist, int *counts, double *part_g, double *part_r);
-void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot);
+void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *slot);
 // Pass 2: tile-sorted records in the mesh precision (prec), randoms weighted by -alpha_r.
+// chunk_hist's counts become run bases in place (offsets: the tile offsets of the scan).
 void launch_sort_scatter(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx,
                          int rdtype, int64_t ng, int64_t nr, int prec, int N, const double *b0, double H,
-                         int assign, const DevNorm *norm, const int *chunk_hist, int *cursor, void *records);
+                         int assign, const DevNorm *norm, int *chunk_hist, const int *offsets, void *records);
 // blocks: scratch of ntiles * (TS+2)^3 values of the mesh precision, one block per occupied tile
 // (slot: [ntiles + 1] from the scan).
 void launch_tile_paint(hipStream_t s, int prec, int N, int assign, const int *offsets, const int *slot,

@@ -7,9 +7,10 @@
 //   norm          alpha_r = sum w_g / sum w_r, I = alpha_r sum_r w_r^2 nbar_r,
 //                 S = sum_g w_g^2 + alpha_r^2 sum_r w_r^2 (Section 2.1), range / extent flags
 //   tile_scan     exclusive scan of the tile counts, compact slots of the occupied tiles
-//   sort_scatter  second (last) pass over the particles: each chunk reserves its runs from its
-//                 stored histogram and writes tile-sorted records (node offset inside the
-//                 tile, signed weight)
+//   chunk_bases   each chunk's run base in every tile (the tile offset plus the earlier
+//                 chunks' counts), in place of the stored histograms
+//   sort_scatter  second (last) pass over the particles: each chunk writes tile-sorted records
+//                 (node offset inside the tile, signed weight) into its runs
 //   tile_paint    CIC / TSC taps of one tile's particles accumulated in LDS (tile + halo),
 //                 written as a block to the tile's scratch slot
 //   tile_gather   every mesh node = sum of the (at most eight) blocks that cover it
@@ -255,12 +256,12 @@ k_sort_count(const RG *__restrict__ gx, const RR *__restrict__ rx, const RR *__r
   }
 }
 
-// offsets = exclusive scan of counts (offsets[ntiles] = total), cursor = offsets,
+// offsets = exclusive scan of counts (offsets[ntiles] = total),
 // slot[t] = rank of tile t among the occupied tiles (-1 if empty), slots[ntiles] = count.
 // Thread i owns the run [i * per, (i + 1) * per); when ntiles is a multiple of 4 * 1024 (and
 // per <= 64) the runs are read and written as 16-byte vectors.
 __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ counts, int ntiles,
-                                                    int *__restrict__ offsets, int *__restrict__ cursor,
+                                                    int *__restrict__ offsets,
                                                     int *__restrict__ slot) {
   __shared__ int part[1024];
   __shared__ int occ[1024];
@@ -309,14 +310,12 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ coun
         of.z = run; run += c[k + 2]; sl.z = c[k + 2] > 0 ? orun++ : -1;
         of.w = run; run += c[k + 3]; sl.w = c[k + 3] > 0 ? orun++ : -1;
         *reinterpret_cast<int4 *>(offsets + b + k) = of;
-        *reinterpret_cast<int4 *>(cursor + b + k) = of;
         *reinterpret_cast<int4 *>(slot + b + k) = sl;
       }
     }
   } else {
     for (int i = b; i < e; ++i) {
       offsets[i] = run;
-      cursor[i] = run;
       run += counts[i];
       slot[i] = counts[i] > 0 ? orun++ : -1;
     }
@@ -327,21 +326,56 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int *__restrict__ coun
   }
 }
 
-// Second pass, same chunks as k_sort_count: reserve one run per (chunk, tile) from the stored
-// histogram (one global atomic per occupied tile), then rank the chunk's particles inside their
-// runs with LDS atomics and write their records (randoms carry -alpha_r w).
+// Run bases of the sort: chunk b's records of tile t start at offsets[t] plus the counts of tile
+// t in the chunks before b.  One thread per tile turns its column of the per-chunk histograms
+// into those bases in place (kBaseUnroll loads in flight), so the scatter reserves its runs
+// without atomics and a tile's runs follow the chunk order.
+constexpr int kBaseUnroll = 32;
+__global__ void __launch_bounds__(256) k_chunk_bases(const int *__restrict__ offsets, int ntiles, int nchunks,
+                                                     int *__restrict__ hist) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int base = offsets[t];
+  for (int b0 = 0; b0 < nchunks; b0 += kBaseUnroll) {
+    int v[kBaseUnroll];
+#pragma unroll
+    for (int k = 0; k < kBaseUnroll; ++k)
+      v[k] = b0 + k < nchunks ? hist[(size_t)(b0 + k) * ntiles + t] : 0;
+#pragma unroll
+    for (int k = 0; k < kBaseUnroll; ++k) {
+      if (b0 + k < nchunks) {
+        hist[(size_t)(b0 + k) * ntiles + t] = base;
+        base += v[k];
+      }
+    }
+  }
+}
+
+// Second pass, same chunks as k_sort_count: the chunk's run bases (its row of chunk_hist, turned
+// into bases by k_chunk_bases) go to LDS, then the chunk's particles are ranked inside their
+// runs with LDS atomics and their records written (randoms carry -alpha_r w).
 template <typename RG, typename RR, typename RM>
 __global__ void __launch_bounds__(kAggThreads)
 k_sort_scatter(const RG *__restrict__ gx, const RR *__restrict__ rx, int64_t ng, int64_t nr, int64_t chunk,
                int nblk_g, int vec_g, int vec_r, int N, double b0x, double b0y, double b0z, double H, int assign,
-               int ts, int ntiles, const DevNorm *__restrict__ norm, const int *__restrict__ chunk_hist,
-               int *__restrict__ cursor, typename Rec4<RM>::T *__restrict__ rec) {
+               int ts, int ntiles, const DevNorm *__restrict__ norm, const int *__restrict__ chunk_base,
+               typename Rec4<RM>::T *__restrict__ rec) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int *hist = reinterpret_cast<int *>(smem_raw);
-  const int *row = chunk_hist + (size_t)blockIdx.x * ntiles;
-  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    const int c = row[t];
-    hist[t] = c ? atomicAdd(&cursor[t], c) : 0;  // base of this chunk's run in tile t
+  const int *row = chunk_base + (size_t)blockIdx.x * ntiles;
+  // base of this chunk's run in every tile, eight loads per thread in flight
+  for (int t0 = threadIdx.x; t0 < ntiles; t0 += 8 * (int)blockDim.x) {
+    int v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int t = t0 + k * (int)blockDim.x;
+      v[k] = t < ntiles ? row[t] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int t = t0 + k * (int)blockDim.x;
+      if (t < ntiles) hist[t] = v[k];
+    }
   }
   __syncthreads();
   const bool ran = (int)blockIdx.x >= nblk_g;
@@ -700,16 +734,18 @@ void launch_sort_count(hipStream_t s, const SortLayout &L, const void *gx, int g
 
 void launch_sort_scatter(hipStream_t s, const SortLayout &L, const void *gx, int gdtype, const void *rx,
                          int rdtype, int64_t ng, int64_t nr, int prec, int N, const double *b0, double H,
-                         int assign, const DevNorm *norm, const int *chunk_hist, int *cursor, void *records) {
+                         int assign, const DevNorm *norm, int *chunk_hist, const int *offsets, void *records) {
   const unsigned nblk = (unsigned)(L.nblk_g + L.nblk_r);
   if (nblk == 0) return;
+  hipLaunchKernelGGL(k_chunk_bases, dim3((unsigned)((L.ntiles + 255) / 256)), dim3(256), 0, s, offsets, L.ntiles,
+                     (int)nblk, chunk_hist);
   const size_t lds = (size_t)L.ntiles * sizeof(int);
   const int ts = tile_size(N);
   const int vg = aligned16(gx), vr = aligned16(rx);
 #define PW_SS(RG, RR, RM)                                                                                   \
   hipLaunchKernelGGL((k_sort_scatter<RG, RR, RM>), dim3(nblk), dim3(kAggThreads), lds, s, (const RG *)gx,     \
                      (const RR *)rx, ng, nr, L.chunk, L.nblk_g, vg, vr, N, b0[0], b0[1], b0[2], H, assign, ts, \
-                     L.ntiles, norm, chunk_hist, cursor, (typename Rec4<RM>::T *)records)
+                     L.ntiles, norm, chunk_hist, (typename Rec4<RM>::T *)records)
 #define PW_SS_M(RG, RR) \
   if (prec == 0) PW_SS(RG, RR, float); else PW_SS(RG, RR, double);
   if (gdtype == 0 && rdtype == 0) { PW_SS_M(float, float) }
@@ -720,8 +756,8 @@ void launch_sort_scatter(hipStream_t s, const SortLayout &L, const void *gx, int
 #undef PW_SS
 }
 
-void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *cursor, int *slot) {
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, offsets, cursor, slot);
+void launch_tile_scan(hipStream_t s, const int *counts, int ntiles, int *offsets, int *slot) {
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, offsets, slot);
 }
 
 static int ilog2(int v) {

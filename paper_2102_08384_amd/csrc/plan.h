@@ -177,7 +177,7 @@ struct DevPlan {
   void *mesh = nullptr, *bufA = nullptr, *bufB = nullptr;
   double *acc = nullptr, *out = nullptr, *part_g = nullptr, *part_r = nullptr;
   DevNorm *norm = nullptr;
-  int *tile_counts = nullptr, *tile_offsets = nullptr, *tile_cursor = nullptr, *tile_slot = nullptr;
+  int *tile_counts = nullptr, *tile_offsets = nullptr, *tile_slot = nullptr;
   void *tile_blocks = nullptr;
   int ntiles = 0;
   int *rowmask = nullptr, *rowlist = nullptr, *planemask = nullptr, *zlist = nullptr;  // survey occupancy
