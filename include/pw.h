@@ -122,7 +122,19 @@ typedef struct {
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device memory the
  * context may hold (0 = 90% of the device's free memory).  hip_stream (a hipStream_t, or
- * NULL) is the stream pw_estimate runs on; NULL makes the context create its own. */
+ * NULL) is the stream pw_estimate runs on; NULL makes the context create its own.
+ * Tracing: with PW_TRACE=<file> in the environment when the context is created, every
+ * completed estimate (pw_estimate, pw_estimate_orders, pw_estimate_batch, pw_estimate_noalloc
+ * and served requests) appends one JSON line to <file>:
+ *   {"t_ms": end, ms since pw_create; "kind": "estimate" | "orders" | "batch" | "noalloc" |
+ *    "served"; "ticket": pw_submit's ticket (0 otherwise); "lane": 0 for pw_estimate-family
+ *    calls, 1.. for serving lanes; "status": the request's code; "stat", "los", "n_mesh",
+ *    "prec"; "n_gal", "n_ran"; "batch": catalogs in its launch; "queued_ms": submission to
+ *    admission; "run_ms": admission (or the call) to completion, on the host's clock;
+ *    "stages_ms": {stage: ms} from HIP events on the lane's stream, for launches of one
+ *    catalog}.
+ * Every lane then records stage events, which costs a few microseconds per estimate.  An
+ * unwritable file fails pw_create with PW_EINVAL. */
 int pw_create(pw_ctx **ctx, int device, size_t hbm_budget_bytes, void *hip_stream);
 
 /* Release every device allocation, stream and host resource of the context.  Pending

@@ -84,7 +84,7 @@ struct Lane {
   hipEvent_t done = nullptr;
   hipEvent_t tev[2] = {nullptr, nullptr};  // autotuning: around one candidate launch
   DevPlan *last = nullptr;
-  // stage timing (lane 0)
+  // stage timing (lane 0 on request; every lane while the context traces)
   bool timing = false;
   hipEvent_t ev[kMaxStages + 1] = {};
   int n_stages = 0;
@@ -118,6 +118,7 @@ struct Req {
   DevPlan *dp = nullptr;
   void *pin = nullptr;  // context-owned pinned copy of the host catalogs (pw_submit), or NULL
   size_t pin_bytes = 0;
+  double t_submit = 0.0, t_start = 0.0;  // ms since the context's creation (tracing)
 };
 
 }  // namespace
@@ -166,6 +167,10 @@ struct pw_ctx {
   std::vector<std::pair<void *, size_t>> pin_free;
   size_t pin_held = 0;
   size_t pin_cap = (size_t)8 << 30;
+  // PW_TRACE=<file> at pw_create: one JSON line per completed estimate (guarded by trace_mu)
+  std::FILE *trace = nullptr;
+  std::mutex trace_mu;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
 
 // ------------------------------------------------------------------------------ static scratch
@@ -872,7 +877,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
   const void *gnb = nullptr, *rnb = nullptr;
   const void *gx = stage_catalog(ctx, ln, gal, 0, &gnb);
   const void *rx = stage_catalog(ctx, ln, ran, 1, &rnb);
-  const bool timing = ln.timing;
+  const bool timing = ln.timing || ctx->trace != nullptr;
   int ns = 0;
   auto mark = [&](const char *name, double bytes) {
     if (ns > kMaxStages) fail(PW_EINVAL, "internal: too many stages");
@@ -1275,9 +1280,48 @@ void make_room_main(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, co
 void complete_main(Lane &ln, const DevPlan *dp, const double *res_host, pw_norm *norm, double *out,
                    double *bin_mean, int64_t *counts);
 
+// ------------------------------------------------------------------------------ tracing
+double ms_since_create(const pw_ctx *ctx) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ctx->t0).count();
+}
+
+// One JSON line per completed estimate into the PW_TRACE file: when it ended (ms since
+// pw_create), what ran (kind, ticket, lane, configuration, catalog sizes, catalogs in its
+// launch), how long it waited for admission and ran on the host's clock, and the stage times
+// from the lane's events (launches of one catalog only; a batched launch has none).
+void trace_write(pw_ctx *ctx, const Lane &ln, const char *kind, uint64_t ticket, const pw_config &c, int64_t n_gal,
+                 int64_t n_ran, size_t batch, double t_submit, double t_start, int status) {
+  if (!ctx->trace) return;
+  std::lock_guard<std::mutex> lk(ctx->trace_mu);  // (lines in the order of their end times)
+  const double t_end = ms_since_create(ctx);
+  std::string stages;
+  if (batch == 1 && status == PW_OK) {
+    for (int i = 0; i < ln.n_stages; ++i) {
+      float ms = -1.0f;
+      if (hipEventElapsedTime(&ms, ln.ev[i], ln.ev[i + 1]) != hipSuccess) ms = -1.0f;
+      char b[96];
+      std::snprintf(b, sizeof(b), "%s\"%s\": %.4f", i ? ", " : "", ln.st_name[i] ? ln.st_name[i] : "?", (double)ms);
+      stages += b;
+    }
+  }
+  char line[768];
+  std::snprintf(line, sizeof(line),
+                "{\"t_ms\": %.3f, \"kind\": \"%s\", \"ticket\": %llu, \"lane\": %d, \"status\": %d, "
+                "\"stat\": \"%s\", \"los\": \"%s\", \"n_mesh\": %d, \"prec\": \"%s\", \"n_gal\": %lld, "
+                "\"n_ran\": %lld, \"batch\": %zu, \"queued_ms\": %.3f, \"run_ms\": %.3f, \"stages_ms\": {",
+                t_end, kind, (unsigned long long)ticket, ln.id, status, c.stat == PW_PK ? "pk" : "xi",
+                c.los == PW_BISECTOR ? "bisector" : "midpoint", c.n_mesh, c.prec == PW_FP32 ? "fp32" : "fp64",
+                (long long)n_gal, (long long)n_ran, batch, t_start - t_submit, t_end - t_start);
+  std::fputs(line, ctx->trace);
+  std::fputs(stages.c_str(), ctx->trace);
+  std::fputs("}}\n", ctx->trace);
+  std::fflush(ctx->trace);
+}
+
 void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw_catalog *ran,
                   pw_norm *norm, double *out, double *bin_mean, int64_t *counts, bool orders = false) {
   check_request(cfg, gal, ran, norm, out);
+  const double t_start = ms_since_create(ctx);
   MainBusy busy(ctx);
   Reservation res(ctx);
   make_room_main(ctx, cfg, gal, ran, res);
@@ -1285,6 +1329,7 @@ void run_estimate(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, cons
   DevPlan *dp = launch_estimate(ctx, ln, cfg, gal, ran, norm, orders);
   res.release();
   complete_main(ln, dp, ln.host_res, norm, out, bin_mean, counts);
+  trace_write(ctx, ln, orders ? "orders" : "estimate", 0, *cfg, gal->n, ran->n, 1, t_start, t_start, PW_OK);
 }
 
 // pw_estimate_batch: n catalogs of one configuration (arrays gal[n], ran[n], norm[n] or NULL;
@@ -1303,6 +1348,7 @@ void run_estimate_batch(pw_ctx *ctx, const pw_config *cfg, int n, const pw_catal
                    bin_mean ? bin_mean + i * nb : nullptr, counts ? counts + i * nb : nullptr);
     return;
   }
+  const double t_start = ms_since_create(ctx);
   MainBusy busy(ctx);
   Reservation res(ctx);
   make_room_main(ctx, cfg, gal, ran, res, n);
@@ -1323,9 +1369,11 @@ void run_estimate_batch(pw_ctx *ctx, const pw_config *cfg, int n, const pw_catal
     std::memcpy(&dn, (const char *)lane_result(ln, i) + nres * sizeof(double), sizeof(DevNorm));
     check_flags(dn);
   }
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     finish_estimate(ln, dp, lane_result(ln, i), norm ? &norm[i] : nullptr, out + i * so,
                     bin_mean ? bin_mean + i * nb : nullptr, counts ? counts + i * nb : nullptr);
+    trace_write(ctx, ln, "batch", 0, *cfg, gal[i].n, ran[i].n, (size_t)n, t_start, t_start, PW_OK);
+  }
 }
 
 // Lane 0 after launch_estimate: wait, read the stage times, scale the forward passes'
@@ -1432,11 +1480,13 @@ void run_estimate_noalloc(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *g
   const size_t words = (size_t)(hp->nell + 2) * hp->n_bins + (sizeof(DevNorm) + 7) / 8;
   if (ln.noalloc_res.size() < words) ln.noalloc_res.resize(words);
   Placed pl{dp.get(), records, ln.noalloc_res.data()};
+  const double t_start = ms_since_create(ctx);
   launch_estimate(ctx, ln, cfg, gal, ran, norm, false, &pl);
   complete_main(ln, dp.get(), pl.host_res, norm, out, bin_mean, counts);
+  trace_write(ctx, ln, "noalloc", 0, *cfg, gal->n, ran->n, 1, t_start, t_start, PW_OK);
 }
 
-Lane *make_lane(int id, hipStream_t user_stream) {
+Lane *make_lane(int id, hipStream_t user_stream, bool stage_events) {
   std::unique_ptr<Lane> ln(new Lane());
   ln->id = id;
   if (user_stream) {
@@ -1447,8 +1497,9 @@ Lane *make_lane(int id, hipStream_t user_stream) {
   }
   HIPCHECK(hipEventCreateWithFlags(&ln->done, hipEventDisableTiming));
   for (int i = 0; i < 2; ++i) HIPCHECK(hipEventCreate(&ln->tev[i]));
-  if (id == 0)
+  if (id == 0 || stage_events)
     for (int i = 0; i <= kMaxStages; ++i) HIPCHECK(hipEventCreate(&ln->ev[i]));
+  ln->timing = id != 0 && stage_events;  // lane 0: pw_set_timing, or tracing (launch_estimate)
   return ln.release();
 }
 
@@ -1628,6 +1679,8 @@ void worker_loop(pw_ctx *ctx) {
             r->err = f.msg;
           }
         }
+        trace_write(ctx, ln, "served", r->ticket, r->cfg, r->gal.n, r->ran.n, ln.batch.size(), r->t_submit,
+                    r->t_start, r->status);
         pin_release(ctx, r);  // the lane's copies out of it are complete
       }
       ln.batch.clear();
@@ -1642,6 +1695,8 @@ void worker_loop(pw_ctx *ctx) {
       Lane &ln = *a.second;
       ln.cur = r;
       const std::vector<Req *> batch = ln.batch;  // r first (pick_admission)
+      const double t_adm = ms_since_create(ctx);
+      for (Req *q : batch) q->t_start = t_adm;
       ctx->served_launches += 1;
       ctx->served_requests += batch.size();
       lk.unlock();
@@ -1702,7 +1757,7 @@ void worker_loop(pw_ctx *ctx) {
 
 void start_worker(pw_ctx *ctx) {
   if (ctx->worker_started) return;
-  for (int i = 0; i < ctx->n_lanes; ++i) ctx->lanes.emplace_back(make_lane(i + 1, nullptr));
+  for (int i = 0; i < ctx->n_lanes; ++i) ctx->lanes.emplace_back(make_lane(i + 1, nullptr, ctx->trace != nullptr));
   ctx->worker = std::thread(worker_loop, ctx);
   ctx->worker_started = true;
 }
@@ -1742,7 +1797,12 @@ int pw_create(pw_ctx **out, int device, size_t hbm_budget_bytes, void *hip_strea
       HIPCHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
       ctx->lds_per_block = (size_t)lds;
     }
-    ctx->main.reset(make_lane(0, (hipStream_t)hip_stream));
+    ctx->main.reset(make_lane(0, (hipStream_t)hip_stream, false));
+    const char *tp = std::getenv("PW_TRACE");
+    if (tp && *tp) {
+      ctx->trace = std::fopen(tp, "a");
+      if (!ctx->trace) fail(PW_EINVAL, "PW_TRACE: cannot open %s for appending", tp);
+    }
   } catch (const Fail &f) {
     if (ctx->main) destroy_lane(ctx, ctx->main.release());
     delete ctx;
@@ -1777,6 +1837,7 @@ int pw_destroy(pw_ctx *ctx) {
   ctx->main.reset();
   for (auto &b : ctx->pin_free) (void)hipHostFree(b.first);
   ctx->pin_free.clear();
+  if (ctx->trace) std::fclose(ctx->trace);
   delete ctx;
   return PW_OK;
 }
@@ -2027,6 +2088,7 @@ int pw_submit(pw_ctx *ctx, const pw_config *cfg, const pw_catalog *gal, const pw
     std::lock_guard<std::mutex> lk(ctx->mu);
     start_worker(ctx);
     r->ticket = ctx->next_ticket++;
+    r->t_submit = ms_since_create(ctx);
     *ticket = r->ticket;
     ctx->pending.push_back(r.get());
     ctx->reqs[r->ticket] = std::move(r);
