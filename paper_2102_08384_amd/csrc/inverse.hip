@@ -13,6 +13,8 @@
 //   finalize_xi    xi_l = (4 pi / I) sum / (N_a H^3)
 #include "kernels.h"
 
+#include <type_traits>
+
 #include "dev_core.h"
 
 namespace pw {
@@ -24,7 +26,7 @@ void upload_sh_const_inverse(const ShConst &c) {
 }
 
 // ------------------------------------------------------------------------------ iz
-template <typename R, int N>
+template <typename R, int N, bool REAL_IN>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int n_inplace, int64_t npen,
      int nkx, int rs, const cplx<R> *D, R d_scale, const R *__restrict__ winv, const int *__restrict__ zrank, int nz,
@@ -55,7 +57,7 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
   const int64_t qo = q;
   const int64_t plane_o = npen;
   cplx<R> dv[8];
-  if (D) {
+  if (!REAL_IN && D) {
     load_chunk(D);
     sync();
     R iwxy = (R)1;
@@ -73,25 +75,51 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
     }
     sync();
   }
-  for (int p = 0; p < nfields; ++p) {
-    if (in_real) {
-      const R *src = in_real + (size_t)p * fstride;
-      for (int e = threadIdx.x; e < C * N; e += NT) {
-        const int cc = e >> LOGN, kz = e & (N - 1);
-        lds[kz * (C + 1) + cc] = mk<R>((e < nval) ? src[(size_t)q0 * N + e] : (R)0, (R)0);
+  // each field's chunk: PER values per thread, loaded together into registers, then placed in
+  // LDS; real inputs (held as reals: half the registers) load the next field's chunk while the
+  // current one is transformed
+  constexpr int PER = C * N / NT;
+  typedef typename std::conditional<REAL_IN, R, cplx<R>>::type In;
+  auto fetch = [&](int p, In *x) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if constexpr (REAL_IN) {
+        const R *src = in_real + (size_t)p * fstride;
+        x[k] = (e < nval) ? src[(size_t)q0 * N + e] : (R)0;
+      } else {
+        const cplx<R> *src = in + (size_t)p * fstride;
+        x[k] = (e < nval) ? src[(size_t)q0 * N + e] : mk<R>(0, 0);
       }
-    } else {
-      load_chunk(in + (size_t)p * fstride);
+    }
+  };
+  // output plane of every kz (-1: not kept), read once into LDS
+  __shared__ int zsh[N];
+  for (int i = threadIdx.x; i < N; i += NT) zsh[i] = zrank[i];
+  In xb[PER];
+  if constexpr (REAL_IN) {
+    if (nfields > 0) fetch(0, xb);
+  }
+  for (int p = 0; p < nfields; ++p) {
+    if constexpr (!REAL_IN) fetch(p, xb);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if constexpr (REAL_IN) lds[(e & (N - 1)) * (C + 1) + (e >> LOGN)] = mk<R>(xb[k], (R)0);
+      else lds[(e & (N - 1)) * (C + 1) + (e >> LOGN)] = xb[k];
     }
     sync();
     cplx<R> v[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = at(t + s * T);
-    if (D) {
+    if (!REAL_IN && D) {
 #pragma unroll
       for (int s = 0; s < 8; ++s) v[s] = cmul(dv[s], v[s]);
     }
     sync();
+    if constexpr (REAL_IN) {
+      if (p + 1 < nfields) fetch(p + 1, xb);
+    }
     if (p < n_inplace) {
       // the product stays in k-space: store it back in place, coalesced through LDS
 #pragma unroll
@@ -110,7 +138,7 @@ k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int 
       cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * plane_o;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const int zr = zrank[t + s * T];
+        const int zr = zsh[t + s * T];
         if (zr >= 0) dst[(size_t)zr * plane_o + qo] = v[s];
       }
     }
@@ -123,10 +151,14 @@ static void iz_launch(hipStream_t s, void *in, void *out, int nfields, int n_inp
                       const void *tw) {
   constexpr int C = ColShape<R, N>::C;
   dim3 grid((unsigned)((npen + C - 1) / C));
-  hipLaunchKernelGGL((k_iz<R, N>), grid, dim3(ColShape<R, N>::THREADS), 0, s,
-                     real_in ? (cplx<R> *)nullptr : (cplx<R> *)in, real_in ? (const R *)in : (const R *)nullptr,
-                     (cplx<R> *)out, nfields, n_inplace, npen, nkx, rs, (const cplx<R> *)D, (R)d_scale,
-                     (const R *)winv, zrank, nz, (const cplx<R> *)tw);
+  if (real_in)
+    hipLaunchKernelGGL((k_iz<R, N, true>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (cplx<R> *)nullptr,
+                       (const R *)in, (cplx<R> *)out, nfields, n_inplace, npen, nkx, rs, (const cplx<R> *)D,
+                       (R)d_scale, (const R *)winv, zrank, nz, (const cplx<R> *)tw);
+  else
+    hipLaunchKernelGGL((k_iz<R, N, false>), grid, dim3(ColShape<R, N>::THREADS), 0, s, (cplx<R> *)in,
+                       (const R *)nullptr, (cplx<R> *)out, nfields, n_inplace, npen, nkx, rs, (const cplx<R> *)D,
+                       (R)d_scale, (const R *)winv, zrank, nz, (const cplx<R> *)tw);
 }
 
 void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields, int n_inplace, int real_in,
