@@ -1008,6 +1008,9 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
       // from the y-pass output (B): the alpha = 0 products of P_l stay in k-space at the front
       // of A, the retained z planes of the others follow them
       zout = A + (size_t)h.n_inplace * sfull_b;
+      // the fused kernel addresses one field with 32-bit byte offsets below 2^31 (its masked
+      // lanes use offset 2^31); with N <= 512 a field is at most 1.2 GB
+      if ((double)N * F.npen * csz >= 2147483648.0) fail(PW_EINVAL, "field too large for the fused z pass");
       mark("fziz", x2 + (double)h.n_inplace * sfull + zpart);
       tuned_launch(ctx, ln, tune_key("fziz", h, h.nfields, h.n_inplace, npl), fz_candidates(h.nfields),
                    [&](ColTune t) {

@@ -25,8 +25,41 @@ void upload_sh_const_inverse(const ShConst &c) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_sh_inv), &c, sizeof(ShConst));
 }
 
+// Raw buffer access with byte offsets.  The hardware checks each lane's vector offset against
+// the resource's byte count: a lane given kOob reads zeros and its stores are dropped, so masked
+// lanes need no branch.  The uniform part of an address goes in the scalar offset.
+constexpr uint32_t kOob = 0x80000000u;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(R) == 4) {
+    const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return mk<R>(v.x, v.y);
+  } else {
+    const f64x2 v = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return mk<R>(v.x, v.y);
+  }
+}
+template <typename R>
+__device__ __forceinline__ void buf_store(cplx<R> x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(R) == 4) {
+    const f32x2 v = {x.x, x.y};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  } else {
+    const f64x2 v = {x.x, x.y};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+  }
+}
+
 // ------------------------------------------------------------------------------ iz
 template <typename R, int N, bool REAL_IN>
+
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_iz(cplx<R> *in, const R *in_real, cplx<R> *__restrict__ out, int nfields, int n_inplace, int64_t npen,
      int nkx, int rs, const cplx<R> *D, R d_scale, const R *__restrict__ winv, const int *__restrict__ zrank, int nz,
@@ -184,7 +217,9 @@ void launch_iz(hipStream_t s, int prec, int N, void *in, void *out, int nfields,
 // at out[p - n_inplace][zrank[z]][q].  A block owns C adjacent pencils and one group of fields
 // [p0, p1); it transforms field 0 first (every group does) and prefetches the next field's
 // loads across each transform.  conj(D) / W^2 waits in LDS (each lane its own 8 values), which
-// keeps the N = 512 FP32 form within 128 VGPRs.
+// keeps the N = 512 FP32 form within 128 VGPRs.  Loads and the z-side stores are raw buffer
+// accesses whose per-lane offsets (empty planes, padding pencils and planes outside the
+// r-bins masked out) are fixed for the whole kernel, so the per-field work is the transforms.
 template <typename R, int N>
 __global__ void __launch_bounds__((ColShape<R, N>::THREADS))
 k_fziz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ prod, cplx<R> *__restrict__ out, int nfields,
@@ -192,10 +227,9 @@ k_fziz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ prod, cplx<R> *__re
        const int *__restrict__ zrank, int nz, const cplx<R> *__restrict__ tw, const int *__restrict__ planemask) {
   constexpr int T = ColShape<R, N>::T, C = ColShape<R, N>::C, NT = ColShape<R, N>::THREADS;
   constexpr int LOGN = log2i(N);
+  constexpr int64_t E = sizeof(cplx<R>);
   __shared__ cplx<R> lds[N * (C + 1)];
   __shared__ cplx<R> dls[8 * NT];
-  __shared__ int msk[N];
-  __shared__ int zrk[N];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int64_t q0 = (int64_t)blockIdx.x * C;
   const int64_t q = q0 + c;
@@ -204,25 +238,36 @@ k_fziz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ prod, cplx<R> *__re
   if (p0 >= p1) return;  // uniform
   FftTw<R, N> twr;
   twr.load(t, tw);
-  for (int i = threadIdx.x; i < N; i += NT) {
-    msk[i] = planemask ? planemask[i] : 1;
-    zrk[i] = zrank ? zrank[i] : -1;
-  }
   const bool has = q < npen;
+  // byte offsets: input plane z = t + s T of pencil q sits at lo[s] + s * sT in its field, and
+  // the output row of a retained plane z at zo[s] in its output field
+  const uint32_t sT = (uint32_t)(T * npen * E);
+  const uint32_t lane_in = (uint32_t)((t * npen + q) * E);
+  // wave-uniform bit s of wload / wstore: some lane of the wave loads / stores plane t + s T (a
+  // wave spans 4 adjacent planes, so empty planes and planes outside the r-bins skip whole
+  // instructions, not only lanes)
+  uint32_t lo[8], zo[8], wload = 0, wstore = 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int z = t + s * T;
+    lo[s] = (has && (!planemask || planemask[z])) ? lane_in : kOob;
+    const int zr = zrank ? zrank[z] : -1;
+    zo[s] = (has && zr >= 0) ? (uint32_t)((zr * npen + q) * E) : kOob;
+    if (__builtin_amdgcn_ballot_w64(lo[s] != kOob)) wload |= 1u << s;
+    if (__builtin_amdgcn_ballot_w64(zo[s] != kOob)) wstore |= 1u << s;
+  }
+  const uint32_t in_bytes = (uint32_t)(N * npen * E);
+  const uint32_t out_bytes = (uint32_t)(nz * npen * E);
   R iwxy = (R)1;
   if (winv && has) {
     const int qky = (int)(q / rs), qkx = (int)(q - (int64_t)qky * rs);
     iwxy = winv[qkx] * winv[qky];
   }
   wait_vmem();
-  __syncthreads();
   auto load = [&](int p, cplx<R> *v) {
-    const cplx<R> *src = in + (size_t)p * N * npen;
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(in + (size_t)p * N * npen, in_bytes);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int z = t + s * T;
-      v[s] = (has && msk[z]) ? src[(size_t)z * npen + q] : mk<R>(0, 0);
-    }
+    for (int s = 0; s < 8; ++s) v[s] = (wload >> s & 1) ? buf_load<R>(r, lo[s], (uint32_t)s * sT) : mk<R>(0, 0);
   };
   auto at = [c](int i) -> cplx<R> & { return lds[i * (C + 1) + c]; };
   auto sync = []() { __syncthreads(); };
@@ -244,14 +289,10 @@ k_fziz(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ prod, cplx<R> *__re
       __syncthreads();
     } else {
       fft_pencil<R, N, true>(v, t, twr, at, sync);
-      if (has) {
-        cplx<R> *dst = out + (size_t)(p - n_inplace) * nz * npen;
+      const __amdgpu_buffer_rsrc_t r = buf_rsrc(out + (size_t)(p - n_inplace) * nz * npen, out_bytes);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int zr = zrk[t + s * T];
-          if (zr >= 0) dst[(size_t)zr * npen + q] = v[s];
-        }
-      }
+      for (int s = 0; s < 8; ++s)
+        if (wstore >> s & 1) buf_store<R>(v[s], r, zo[s], 0);
     }
   };
   // conj(D) / W^2 on every mode, D = d_scale Q_000~; field 0's own product is then
