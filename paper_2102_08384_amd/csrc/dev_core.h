@@ -194,6 +194,38 @@ __device__ __forceinline__ void fft_pencil_db(cplx<R> v[8], int t, const FftTw<R
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt not waited on)
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Raw buffer access with byte offsets.  The hardware checks each lane's vector offset against
+// the resource's byte count: a lane given kOob reads zeros and its stores are dropped, so masked
+// lanes need no branch.  The uniform part of an address goes in the scalar offset.
+constexpr uint32_t kOob = 0x80000000u;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(R) == 4) {
+    const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return mk<R>(v.x, v.y);
+  } else {
+    const f64x2 v = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return mk<R>(v.x, v.y);
+  }
+}
+template <typename R>
+__device__ __forceinline__ void buf_store(cplx<R> x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(R) == 4) {
+    const f32x2 v = {x.x, x.y};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  } else {
+    const f64x2 v = {x.x, x.y};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+  }
+}
+
 // Groups of fields per block (grid.y) for column passes, so that a launch has about 4096
 // blocks when the pencil dimension alone gives fewer.
 inline int field_groups(int nfields, int nblocks_other) {

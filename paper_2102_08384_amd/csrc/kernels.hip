@@ -424,22 +424,34 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
   for (int i = threadIdx.x; i < N; i += NT) msk[i] = rowmask ? rowmask[z * N + i] : 1;
   wait_vmem();
   __syncthreads();
-  // input rows of this lane (y = t + s*T): bit s set when the row holds data; row offsets
-  unsigned live = 0;
+  // Raw buffer accesses with byte offsets fixed for the block: input row y = t + s*T of this
+  // lane's column sits at lo[s] + s * sT from the column group's base (kOob where the row is
+  // empty), output row ky = t + s*T at so[s] from the output group's base.  Bit s of wlive is
+  // set when some lane of the wave loads row t + s*T (a wave spans 4 adjacent rows, so empty
+  // rows skip whole load instructions).
+  constexpr uint32_t E = sizeof(cplx<R>);
+  const uint32_t sT = (uint32_t)(T * rs) * E;
+  uint32_t lo[8], so[8], wlive = 0;
 #pragma unroll
-  for (int s = 0; s < 8; ++s) live |= (msk[t + s * T] ? 1u : 0u) << s;
+  for (int s = 0; s < 8; ++s) {
+    const bool live = msk[t + s * T] != 0;
+    lo[s] = live ? (uint32_t)(t * rs + c) * E : kOob;
+    so[s] = (uint32_t)(yo[s] + c) * E;
+    if (__builtin_amdgcn_ballot_w64(live)) wlive |= 1u << s;
+  }
   const int ncb = (nkx + C - 1) / C;
   const int p0 = blockIdx.y * fpb;
   const int p1 = min(nfields, p0 + fpb);
   const int nitems = (p1 - p0) * ncb;
   if (nitems <= 0) return;
   const size_t plane = (size_t)N * rs;  // one input plane of one field
+  const uint32_t in_bytes = (uint32_t)(plane * E), out_bytes = (uint32_t)(npen * E);
   auto load = [&](int p, int cb, cplx<R> *v) {
-    const int kx = cb * C + c;
-    const cplx<R> *src = in + ((size_t)p * nplanes + z) * plane + kx;
-    const unsigned lv = kx < nkx ? live : 0u;
+    const bool colok = cb * C + c < nkx;
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(in + ((size_t)p * nplanes + z) * plane + cb * C, in_bytes);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) v[s] = ((lv >> s) & 1u) ? src[(t + s * T) * rs] : mk<R>(0, 0);
+    for (int s = 0; s < 8; ++s)
+      v[s] = ((wlive >> s) & 1u) ? buf_load<R>(r, colok ? lo[s] : kOob, (uint32_t)s * sT) : mk<R>(0, 0);
   };
   int lb = 0;
   auto at = [c, &lb](int i) -> cplx<R> & { return lds[lb * LB + i * (C + 1) + c]; };
@@ -453,18 +465,19 @@ k_fy(const cplx<R> *__restrict__ in, cplx<R> *__restrict__ out, int nfields, int
     cplx<R> v[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) v[s] = nxt[s];
-    const int pc = p, kx = cb * C + c;
+    const int pc = p, cbc = cb, kx = cb * C + c;
     if (++cb == ncb) {
       cb = 0;
       ++p;
     }
     if (it + 1 < nitems) load(p, cb, nxt);
     fft_pencil_db<R, N, INV>(v, t, twr, at, sync, flip);
-    cplx<R> *dst = out + ((size_t)pc * nplanes + z) * npen + kx;
+    const __amdgpu_buffer_rsrc_t w = buf_rsrc(out + ((size_t)pc * nplanes + z) * npen + cbc * C, out_bytes);
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       // whole 128-byte lines: the row's padding slots are written too (never read as modes)
-      if (kx < yl[s]) dst[yo[s]] = v[s];
+      const bool keep = kx < yl[s];
+      if (__builtin_amdgcn_ballot_w64(keep)) buf_store<R>(v[s], w, keep ? so[s] : kOob, 0);
     }
   }
 }
