@@ -998,7 +998,7 @@ DevPlan *launch_estimate(pw_ctx *ctx, Lane &ln, const pw_config *cfg, const pw_c
       // a8 (bisector): T_{l nu}(k) = sum S Re(conj R_p1 R_p2) / W^2 on every mode, then the
       // inverse z pass of the real targets
       mark("targets", x3 + (double)h.n_targets * modes_real * rsz);
-      launch_targets(s, h.prec, N, h.ell_max, h.order / 2, A, F.nmodes, F.rs, dp->winv, B);
+      launch_targets(s, h.prec, N, h.ell_max, h.order / 2, A, F.nmodes, F.mstride, F.rs, dp->winv, B);
       zout = A;
       mark("iz", (double)h.n_targets * modes_real * rsz + zpart);
       launch_iz(s, h.prec, N, B, zout, h.n_targets, 0, 1, F.npen, F.nkx, F.rs, nullptr, sqrt4pi, nullptr,

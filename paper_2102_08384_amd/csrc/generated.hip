@@ -190,8 +190,8 @@ bool mid_reweight_generated(int lmax, int order, int all_parity) {
 // Bisector xi targets over the full pencil-major spectra: one thread per mode.
 template <typename R, int LMAX, int BMAX>
 __global__ void __launch_bounds__(256)
-k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int rs, const R *__restrict__ winv,
-          R *__restrict__ T) {
+k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int64_t mstride, int N, int rs,
+          const R *__restrict__ winv, R *__restrict__ T) {
   using CT = BisContract<LMAX, BMAX, R>;
   constexpr int NF = CT::NF;
   constexpr int NT = (LMAX + 1) * (LMAX + 2) / 2;   // targets of even l <= LMAX
@@ -200,7 +200,7 @@ k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int rs, const
        i += (int64_t)gridDim.x * blockDim.x) {
     cplx<R> a[NF];
 #pragma unroll
-    for (int p = 0; p < NF; ++p) a[p] = spec[(size_t)p * nmodes + i];
+    for (int p = 0; p < NF; ++p) a[p] = spec[(size_t)p * mstride + i];
     R full[NSH];
     CT::targets(a, full);
     R iw2 = (R)1;
@@ -219,12 +219,12 @@ k_targets(const cplx<R> *__restrict__ spec, int64_t nmodes, int N, int rs, const
 }
 
 template <typename R, int L, int B>
-static bool targets_launch(hipStream_t s, const void *spec, int64_t nmodes, int N, int rs, const void *winv,
-                           void *T) {
+static bool targets_launch(hipStream_t s, const void *spec, int64_t nmodes, int64_t mstride, int N, int rs,
+                           const void *winv, void *T) {
   if constexpr (BisContract<L, B, R>::kGenerated) {
     int64_t want = (nmodes + 255) / 256;
     unsigned blocks = (unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536);
-    hipLaunchKernelGGL((k_targets<R, L, B>), dim3(blocks), dim3(256), 0, s, (const cplx<R> *)spec, nmodes, N,
+    hipLaunchKernelGGL((k_targets<R, L, B>), dim3(blocks), dim3(256), 0, s, (const cplx<R> *)spec, nmodes, mstride, N,
                        rs, (const R *)winv, (R *)T);
     return true;
   } else {
@@ -233,11 +233,11 @@ static bool targets_launch(hipStream_t s, const void *spec, int64_t nmodes, int 
 }
 
 void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const void *spec, int64_t nmodes,
-                    int rs, const void *winv, void *T) {
+                    int64_t mstride, int rs, const void *winv, void *T) {
 #define PW_TG(L, B)                                                                               \
   if (lmax == L && bmax == B) {                                                                   \
-    if (prec == 0) targets_launch<float, L, B>(s, spec, nmodes, N, rs, winv, T);                  \
-    else targets_launch<double, L, B>(s, spec, nmodes, N, rs, winv, T);                           \
+    if (prec == 0) targets_launch<float, L, B>(s, spec, nmodes, mstride, N, rs, winv, T);         \
+    else targets_launch<double, L, B>(s, spec, nmodes, mstride, N, rs, winv, T);                  \
     return;                                                                                       \
   }
   PW_TG(0, 0) PW_TG(0, 1) PW_TG(0, 2) PW_TG(2, 0) PW_TG(2, 1) PW_TG(2, 2)

@@ -241,8 +241,9 @@ void launch_reweight(hipStream_t s, int prec, int N, int lmax, int order, int al
                      double Hu);
 // Bisector xi targets: T[t][i] = sum S Re(conj(R_p1) R_p2) / W(k)^2 over the full
 // pencil-major spectra (i = q * N + kz, q = ky * rs + kx), written as real values (generated).
+// Field p of spec starts at p * mstride; target t of T at t * nmodes.
 void launch_targets(hipStream_t s, int prec, int N, int lmax, int bmax, const void *spec, int64_t nmodes,
-                    int rs, const void *winv, void *T);
+                    int64_t mstride, int rs, const void *winv, void *T);
 // Midpoint P contraction: E_l = sum_nu y_l^nu(k^) Re[G_{l nu}(k) + A_{l nu}(k)] on the k-sphere
 // modes; G: full pencil-major products (alpha = 0 fields, index even_index(l, nu)); A: pruned
 // spectra of the A fields (l >= 2, index even_index(l, nu) - 1; null when absent).
