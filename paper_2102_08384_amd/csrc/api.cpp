@@ -739,7 +739,7 @@ std::string tune_key(const char *pass, const HostPlan &h, int nfields, int64_t a
 // in FP32).
 std::vector<ColTune> fy_candidates(int prec, int nfields) {
   std::vector<ColTune> c(1);
-  for (int f : {1, 4}) {
+  for (int f : {1, 2, 4, 7}) {
     if (f >= nfields) continue;
     ColTune t;
     t.fpb = f;

@@ -43,7 +43,7 @@ def test_bisector_every_shape_same_spectra(prec):
         ctx.set_tuning(0)
         base = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
         sph = ctx.inspect(1, dt).copy()
-        for mode in range(2, 7):   # candidates 0..4 (past the last one: the default)
+        for mode in range(2, 8):   # candidates 0..5 (past the last one: the default)
             ctx.set_tuning(mode)
             res = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
             assert np.array_equal(ctx.inspect(1, dt), sph), mode
@@ -103,7 +103,7 @@ def test_bisector_512_every_shape_same_mesh_and_spectra():
         base = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
         mesh = ctx.inspect(0, np.float32).copy()
         sph = ctx.inspect(1, np.float32).copy()
-        for mode in range(2, 7):   # candidates 0..4 of every pass (past a pass's last: its default)
+        for mode in range(2, 8):   # candidates 0..5 of every pass (past a pass's last: its default)
             say("shape candidate", mode - 2)
             ctx.set_tuning(mode)
             res = ctx.estimate(cfg, gx, rx, ran_nbar=nb)
