@@ -413,10 +413,15 @@ k_sort_scatter(const RG *__restrict__ gx, const RR *__restrict__ rx, int64_t ng,
 
 // One workgroup per tile: the tile's nodes plus a one-node halo (local index -1 .. ts on each
 // axis, E = ts + 2) accumulated in LDS, then stored as block `slot[tile]` of the scratch in the
-// mesh precision.  Contributions are accumulated as 64-bit fixed point, round(c * fix_scale)
-// with fix_scale a power of two (integer LDS atomics run at full rate where floating-point LDS
-// atomics are serialised per lane); integer sums are exact, so a block does not depend on the
-// order of its particles.
+// mesh precision.  Contributions are accumulated as 64-bit fixed point, round(c * scale) with
+// scale a power of two (integer LDS atomics run at full rate where floating-point LDS atomics
+// are serialised per lane); integer sums are exact, so a block does not depend on the order of
+// its particles.  FP64 meshes use scale = fix_scale (node sums below 2^62).  FP32 meshes use
+// scale = fix_scale / 2^11, so every contribution is below 2^50 in magnitude and converts to
+// int64 by adding 1.5 * 2^52 in double (the sum lands in [2^52, 2^53), where the ulp is 1 and
+// the bit pattern minus that of 1.5 * 2^52 is the rounded integer in two's complement): three
+// operations in place of the dozen of a general float-to-int64 conversion.  The quantum, 2^-50
+// of the catalog's total |weight|, stays far below FP32 resolution.
 template <typename RM, int ASSIGN>
 __global__ void __launch_bounds__(512) k_tile_paint(int ts, const int *__restrict__ offsets,
                                                     const int *__restrict__ slot,
@@ -430,7 +435,9 @@ __global__ void __launch_bounds__(512) k_tile_paint(int ts, const int *__restric
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
   const int E = ts + 2, E3 = E * E * E;
   for (int c = threadIdx.x; c < E3; c += blockDim.x) acc[c] = 0ull;
-  const RM scale = (RM)norm->fix_scale;
+  constexpr bool MAGIC = sizeof(RM) == 4;
+  const double qscale = MAGIC ? norm->fix_scale * (1.0 / 2048.0) : norm->fix_scale;
+  const RM scale = (RM)qscale;
   __syncthreads();
   constexpr int NTAP = (ASSIGN == 2) ? 2 : 3;
   constexpr int O0 = (ASSIGN == 2) ? 1 : 0;   // LDS index of tap a on an axis: l + a + O0
@@ -468,14 +475,18 @@ __global__ void __launch_bounds__(512) k_tile_paint(int ts, const int *__restric
         const int base = (zz * E + l[1] + b + O0) * E + l[0] + O0;
 #pragma unroll
         for (int c = 0; c < NTAP; ++c) {
-          const long long q = (long long)rint(wt[0][c] * wyz);
+          long long q;
+          if constexpr (MAGIC)
+            q = __double_as_longlong((double)(wt[0][c] * wyz) + 6755399441055744.0) - 0x4338000000000000LL;
+          else
+            q = (long long)rint(wt[0][c] * wyz);
           atomicAdd(&acc[base + c], (unsigned long long)q);
         }
       }
     }
   }
   __syncthreads();
-  const double inv = 1.0 / norm->fix_scale;
+  const double inv = 1.0 / qscale;
   RM *dst = blocks + (size_t)slot[tile] * E3;
   for (int c = threadIdx.x; c < E3; c += blockDim.x) dst[c] = (RM)((double)(long long)acc[c] * inv);
 }

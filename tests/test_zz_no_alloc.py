@@ -35,7 +35,10 @@ def _dev(seed, n_gal, n_ran, side):
 
 def _same(a, b):
     assert np.array_equal(a["counts"], b["counts"])
-    assert np.allclose(a["bin_mean"], b["bin_mean"], rtol=1e-15, atol=0)
+    # FP64 sums over a bin's modes: the two calls may run the contraction with different
+    # workgroup counts (the estimate's autotuned choice, the scratch call's settled one or the
+    # default), which adds the same terms in another order
+    assert np.allclose(a["bin_mean"], b["bin_mean"], rtol=1e-13, atol=0)
     assert np.allclose(a["norm"], b["norm"], rtol=1e-14, atol=0)
     err = max_err_per_ell(a["values"], b["values"])
     assert np.all(err < SAME), err
