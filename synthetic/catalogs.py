@@ -79,11 +79,11 @@ WORKLOADS = {
     # xi_l via the inverse FFT (midpoint and bisector), 25 bins over 0-200
     "C4": Workload(4, "lognormal_cone", 4_000_000, 5.0, 400.0, 2000.0, 512, 2900.0,
                    _cone_box(400.0, 2000.0, 2900.0), 2, (0, 2, 4), 4, "xi", "midpoint",
-                   0.0, 8.0, 25, 256, True),
+                   0.0, 8.0, 25, 512, True),
     # the same catalog (same workload id, same seeds) with the bisector xi_l (Section 6)
     "C4B": Workload(4, "lognormal_cone", 4_000_000, 5.0, 400.0, 2000.0, 512, 2900.0,
                     _cone_box(400.0, 2000.0, 2900.0), 2, (0, 2, 4), 4, "xi", "bisector",
-                    0.0, 8.0, 25, 256, True),
+                    0.0, 8.0, 25, 512, True),
 }
 
 
