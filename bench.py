@@ -158,6 +158,31 @@ def _profile_text(name):
     return open(path).read(), path
 
 
+def copy_bandwidth(torch, dev, nbytes=COPY_BYTES, reps=10):
+    """Rate of torch's device-to-device copy (bytes read + written per second, in GB/s) on a
+    1 GiB buffer, four times the Infinity Cache: what a plain library streaming kernel reaches
+    on this device, reported beside the 8 TB/s peak (context, not the roofline's peak).  Timed
+    with events on torch's current stream, outside every timed region of the estimates."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(3):   # the best of three batches
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def counter_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
     summary is missing or was taken on other kernel sources."""
@@ -671,6 +696,9 @@ def main():
                 "kernel": knames[dom], "algorithmic_bytes_per_launch": stage_bytes[dom],
                 "avg_ms": stages[dom]["ms"], "timing": f"HIP events on the library's stream, {n_stage} estimates",
                 "traffic_source": tsrc}
+    if headline:
+        roofline["copy_GBps"] = copy_bandwidth(torch, dev)
+        roofline["frac_of_copy"] = ach / roofline["copy_GBps"]
     if rp_us:
         roofline["rocprof"] = {"avg_ms": rp_us / 1e3, "frac": stage_bytes[dom] / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                                "source": rp_src}
