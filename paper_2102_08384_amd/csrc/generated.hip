@@ -255,7 +255,12 @@ k_reweight(const R *__restrict__ g, R *__restrict__ A, int N, R Hu) {
   constexpr int NSH = (K + 1) * (K + 1);
   constexpr int NDP = ALLP ? K + 1 : K / 2 + 1;
   const size_t ncell = (size_t)N * N * N;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
+  // one cell per thread, no grid-stride loop: the fields' base addresses are then formed next
+  // to their loads instead of being kept live across a loop (up to 130 fields: more scalar
+  // registers than there are, spilled into vector lanes)
+  {
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
     const int x = (int)(c % N), y = (int)((c / N) % N), z = (int)(c / ((size_t)N * N));
     const int sx = x < N / 2 ? x : x - N, sy = y < N / 2 ? y : y - N, sz = z < N / 2 ? z : z - N;
     const R dx = (R)sx * Hu, dy = (R)sy * Hu, dz = (R)sz * Hu;  // D / unit
@@ -290,8 +295,7 @@ static void reweight_launch(hipStream_t s, int N, const void *g, void *A, double
   using MR = typename std::conditional<ALLP, MidReweightAll<L, K, R>, MidReweight<L, K, R>>::type;
   if constexpr (MR::kGenerated) {
     const size_t ncell = (size_t)N * N * N;
-    size_t want = (ncell + 255) / 256;
-    unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+    const unsigned blocks = (unsigned)((ncell + 255) / 256);  // at most 2^19 (N <= 512)
     hipLaunchKernelGGL((k_reweight<R, L, K, ALLP>), dim3(blocks), dim3(256), 0, s, (const R *)g, (R *)A, N,
                        (R)Hu);
   }
